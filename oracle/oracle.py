@@ -1,0 +1,315 @@
+"""CPU oracle for the LFDPR hot path: Python front end of ``lfdpr_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY.  Imported by the test-suite, by the smoke check and
+by the benchmark's CPU-baseline leg; never by the product path.  It shares no
+code with the HIP path: the rig/lens tables below are computed here, in
+double, from the paper's description (Sec. 3.1, Sec. 4, Sec. 5.1), and the
+HIP library computes its own copies independently.
+
+Functions and what pins them (see tests/test_oracle_pins.py):
+  view_table        -- camera rig (parallel off-axis eyes, shared focal plane)
+  lens_constants    -- tilted-lens phase constants (prototype geometry, Sec. 5.1)
+  angular_table     -- Gaussian weights for the angular supersampling filter
+  build_textures    -- box mip chains                      [pinned: numpy box mean]
+  render            -- point generation + splatting         [pinned: brute-force lattice
+                       counts, closest-point brute force, reverse-projection geometry,
+                       rasteriser coverage identity, constant-texture identity]
+  interleave        -- panel interleave + reconstruction    [pinned: index-map readout,
+                       lens-independence, slope-0 closed form]
+  angular_filter    -- 4x angular SS -> V views             [pinned: focal-plane identity,
+                       constant input, weight normalisation]
+  rasterise         -- conventional z-buffer multiview renderer (gold standard)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lfdpr_oracle.c")
+_LIB = os.path.join(_HERE, "liblfdpr_oracle.so")
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _lib.orc_lattice_cells.restype = C.c_int
+        _lib.orc_trilinear.restype = C.c_uint32
+        _lib.orc_lod_q8.restype = C.c_int
+        _lib.orc_lod_q8.argtypes = [C.c_float]
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# ctypes mirrors of the oracle's own structs
+
+
+class _Scene(C.Structure):
+    _fields_ = [("nv", C.c_int), ("nt", C.c_int), ("pos", C.c_void_p), ("uv", C.c_void_p),
+                ("idx", C.c_void_p), ("tex", C.c_void_p), ("ntex", C.c_int),
+                ("tex_size", C.c_void_p), ("tex_levels", C.c_void_p), ("tex_level_off", C.c_void_p),
+                ("texels", C.c_void_p)]
+
+
+class _Frame(C.Structure):
+    _fields_ = [("n_views", C.c_int), ("W", C.c_int), ("H", C.c_int), ("mip", C.c_int),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("rD", C.c_float), ("znear", C.c_float), ("eye", C.c_void_p), ("kshift", C.c_void_p),
+                ("model", C.c_float * 12)]
+
+
+class _Out(C.Structure):
+    _fields_ = [("count", C.c_void_p), ("trif", C.c_void_p), ("trii", C.c_void_p),
+                ("point_cap", C.c_int64), ("p_tri", C.c_void_p), ("p_i", C.c_void_p), ("p_j", C.c_void_p),
+                ("p_flags", C.c_void_p), ("p_tvmin", C.c_void_p), ("p_tvmax", C.c_void_p),
+                ("keys", C.c_void_p), ("stats", C.c_void_p), ("unused", C.c_void_p)]
+
+
+class _Lens(C.Structure):
+    _fields_ = [("Wp", C.c_int), ("Hp", C.c_int), ("mode", C.c_int), ("K1", C.c_uint32),
+                ("Ky", C.c_uint32), ("K0", C.c_uint32), ("taps", C.c_void_p)]
+
+
+def _p(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+# ---------------------------------------------------------------------------
+# rig, lens and filter tables (double precision, rounded once)
+
+
+def subview_positions(vp) -> np.ndarray:
+    """Position q of every rendered (sub-)view on the view axis, in view
+    intervals: plain views sit at interval centres v + 0.5; with angular
+    supersampling factor S, sub-view k of view v sits at v + (k + 0.5 + j)/S
+    with a random jitter j in [-0.5, 0.5) (Sec. 4: random angles in view
+    intervals)."""
+    q = np.empty(vp.V * vp.S, np.float64)
+    for v in range(vp.V):
+        for k in range(vp.S):
+            j = float(vp.jitter[v * vp.S + k]) if (vp.S > 1 and vp.jitter is not None) else 0.0
+            q[v * vp.S + k] = v + 0.5 if vp.S == 1 else v + (k + 0.5 + j) / vp.S
+    return q
+
+
+def view_table(vp) -> Dict[str, object]:
+    """Parallel off-axis cameras sharing one orientation and the focal plane
+    Z = D; eye r sits at (b_r, 0, 0) with b = D tan(cone/2) (2q/V - 1)."""
+    B = vp.D * math.tan(math.radians(vp.cone_deg) / 2.0)
+    q = subview_positions(vp)
+    b = B * (2.0 * q / vp.V - 1.0)
+    t = math.tan(math.radians(vp.fovy_deg) / 2.0)
+    return dict(
+        fx=np.float32((vp.W / 2.0) / (vp.aspect * t)), fy=np.float32((vp.H / 2.0) / t),
+        cx=np.float32(vp.W / 2.0), cy=np.float32(vp.H / 2.0), rD=np.float32(1.0 / vp.D),
+        znear=np.float32(vp.znear), eye=b.astype(np.float32), kshift=(b / vp.D).astype(np.float32),
+        q=q)
+
+
+def lens_constants(lp, V: int):
+    """Q32 lens-phase constants: phase = (subpixel - 3*slope*row)/pitch + offset."""
+    two32 = 2.0 ** 32
+    K1 = int(round(two32 / lp.pitch_subpx)) % (1 << 32)
+    Ky = int(round(-3.0 * lp.slope * two32 / lp.pitch_subpx)) % (1 << 32)
+    K0 = int(round(lp.offset * two32)) % (1 << 32)
+    return K1, Ky, K0
+
+
+def angular_table(vp):
+    """For output view v: sub-views within one view interval of its centre,
+    weighted by round(65535 exp(-d^2 / (2 * 0.5^2)))."""
+    q = subview_positions(vp)
+    maxe = 3 * vp.S
+    cnt = np.zeros(vp.V, np.int32)
+    src = np.zeros((vp.V, maxe), np.int32)
+    wt = np.zeros((vp.V, maxe), np.uint32)
+    for v in range(vp.V):
+        for r in range(vp.V * vp.S):
+            d = q[r] - (v + 0.5)
+            if abs(d) < 1.0:
+                src[v, cnt[v]] = r
+                wt[v, cnt[v]] = int(round(65535.0 * math.exp(-d * d / (2.0 * 0.25))))
+                cnt[v] += 1
+    return cnt, src, wt, maxe
+
+
+# ---------------------------------------------------------------------------
+
+
+class Textures:
+    def __init__(self, scene):
+        self.ntex = len(scene.textures)
+        self.size = np.array([t.shape[0] for t in scene.textures], np.int32)
+        self.levels = np.array([int(math.log2(s)) + 1 for s in self.size], np.int32)
+        self.off = np.zeros((max(1, self.ntex), 16), np.int64)
+        total = 0
+        for k, s in enumerate(self.size):
+            o = total
+            for lvl in range(self.levels[k]):
+                self.off[k, lvl] = o
+                o += (int(s) >> lvl) ** 2 * 4
+            total = o
+        self.texels = np.zeros(max(total, 4), np.uint8)
+        for k, t in enumerate(scene.textures):
+            s = int(self.size[k])
+            chain = np.zeros(sum((s >> l) ** 2 * 4 for l in range(self.levels[k])), np.uint8)
+            lib().orc_build_mips(C.c_void_p(_p(np.ascontiguousarray(t))), C.c_int(s), C.c_void_p(_p(chain)))
+            self.texels[self.off[k, 0]:self.off[k, 0] + chain.size] = chain
+
+    def level(self, k: int, lvl: int) -> np.ndarray:
+        s = int(self.size[k]) >> lvl
+        o = int(self.off[k, lvl])
+        return self.texels[o:o + s * s * 4].reshape(s, s, 4)
+
+
+def build_textures(scene) -> Textures:
+    return Textures(scene)
+
+
+def _scene_struct(scene, tx: Textures, keep: list) -> _Scene:
+    arrs = [np.ascontiguousarray(scene.pos, np.float32), np.ascontiguousarray(scene.uv, np.float32),
+            np.ascontiguousarray(scene.idx, np.uint32), np.ascontiguousarray(scene.tex, np.uint16)]
+    keep += arrs
+    return _Scene(scene.n_verts, scene.n_tris, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]),
+                  tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels))
+
+
+def _frame_struct(vp, vt, model, keep: list) -> _Frame:
+    eye = np.ascontiguousarray(vt["eye"], np.float32)
+    ks = np.ascontiguousarray(vt["kshift"], np.float32)
+    keep += [eye, ks]
+    f = _Frame()
+    f.n_views, f.W, f.H, f.mip = vp.V * vp.S, vp.W, vp.H, int(vp.mip)
+    f.fx, f.fy, f.cx, f.cy = float(vt["fx"]), float(vt["fy"]), float(vt["cx"]), float(vt["cy"])
+    f.rD, f.znear = float(vt["rD"]), float(vt["znear"])
+    f.eye, f.kshift = _p(eye), _p(ks)
+    m = np.ascontiguousarray(model, np.float32).reshape(12)
+    for k in range(12):
+        f.model[k] = float(m[k])
+    return f
+
+
+def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_cap: Optional[int] = None):
+    """Point generation + splatting of one frame into all V*S rendered views.
+
+    Returns a dict with per-triangle counts and records, the point buffer in
+    emission order, RGBA8 views (n_views, H, W) as uint32, FP32 depth and stats."""
+    tx = tx or build_textures(scene)
+    vt = view_table(vp)
+    keep: list = []
+    sc = _scene_struct(scene, tx, keep)
+    fr = _frame_struct(vp, vt, model, keep)
+    nt = scene.n_tris
+    nviews = vp.V * vp.S
+    cap = point_cap if point_cap is not None else max(64, 24 * nt)
+    o = dict(count=np.zeros(nt, np.int32), trif=np.zeros((nt, 8), np.float32), trii=np.zeros((nt, 8), np.int32),
+             p_tri=np.zeros(cap, np.uint32), p_i=np.zeros(cap, np.int16), p_j=np.zeros(cap, np.int16),
+             p_flags=np.zeros(cap, np.uint8), p_tvmin=np.zeros(cap, np.uint32), p_tvmax=np.zeros(cap, np.uint32),
+             keys=np.full((nviews, vp.H, vp.W), np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64),
+             stats=np.zeros(8, np.int64))
+    out = _Out(_p(o["count"]), _p(o["trif"]), _p(o["trii"]), cap, _p(o["p_tri"]), _p(o["p_i"]), _p(o["p_j"]),
+               _p(o["p_flags"]), _p(o["p_tvmin"]), _p(o["p_tvmax"]), _p(o["keys"]), _p(o["stats"]), None)
+    lib().orc_render(C.byref(sc), C.byref(fr), C.byref(out))
+    n = int(o["stats"][0])
+    if n > cap:
+        return render(scene, vp, model, tx, point_cap=n)
+    rgba = np.zeros((nviews, vp.H, vp.W), np.uint32)
+    depth = np.zeros((nviews, vp.H, vp.W), np.float32)
+    lib().orc_resolve(C.c_void_p(_p(o["keys"])), C.c_int64(o["keys"].size), C.c_void_p(_p(rgba)), C.c_void_p(_p(depth)))
+    st = o["stats"]
+    return dict(count=o["count"], trif=o["trif"], trii=o["trii"], n_points=n,
+                points=dict(tri=o["p_tri"][:n], i=o["p_i"][:n], j=o["p_j"][:n], flags=o["p_flags"][:n],
+                            tvmin=o["p_tvmin"][:n], tvmax=o["p_tvmax"][:n]),
+                keys=o["keys"], rgba=rgba, depth=depth,
+                stats=dict(points=int(st[0]), active_tris=int(st[1]), point_views=int(st[2]), orphans=int(st[3]),
+                           misses=int(st[4]), overflow_tris=int(st[5]), fragments=int(st[6])),
+                view_table=vt)
+
+
+def rasterise(scene, vp, model: np.ndarray, tx: Optional[Textures] = None):
+    """Conventional multiview rendering: one z-buffer pass per view, same vertex
+    projection and coverage rule, perspective-correct attributes and per-pixel
+    trilinear mipmapping in double."""
+    tx = tx or build_textures(scene)
+    vt = view_table(vp)
+    keep: list = []
+    sc = _scene_struct(scene, tx, keep)
+    fr = _frame_struct(vp, vt, model, keep)
+    nviews = vp.V * vp.S
+    rgba = np.zeros((nviews, vp.H, vp.W), np.uint32)
+    depth = np.zeros((nviews, vp.H, vp.W), np.float32)
+    lib().orc_rasterise(C.byref(sc), C.byref(fr), C.c_void_p(_p(rgba)), C.c_void_p(_p(depth)))
+    return rgba, depth
+
+
+def interleave(views: np.ndarray, lp, taps: Optional[np.ndarray] = None, mode: Optional[int] = None) -> np.ndarray:
+    """Interleave V views (V, H, W) RGBA8-as-uint32 into the Hp x Wp x 3 panel."""
+    views = np.ascontiguousarray(views, np.uint32)
+    V, Hv, Wv = views.shape
+    K1, Ky, K0 = lens_constants(lp, V)
+    t = np.ascontiguousarray(taps if taps is not None else (lp.taps if lp.taps is not None else np.zeros((8, 3))), np.int64)
+    ln = _Lens(lp.Wp, lp.Hp, int(lp.mode if mode is None else mode), K1, Ky, K0, _p(t))
+    panel = np.zeros((lp.Hp, lp.Wp, 3), np.uint8)
+    lib().orc_interleave(C.c_void_p(_p(views)), C.c_int(V), C.c_int(Wv), C.c_int(Hv), C.byref(ln), C.c_void_p(_p(panel)))
+    return panel
+
+
+def angular_filter(sub_views: np.ndarray, vp) -> np.ndarray:
+    sub_views = np.ascontiguousarray(sub_views, np.uint32)
+    cnt, src, wt, maxe = angular_table(vp)
+    out = np.zeros((vp.V, vp.H, vp.W), np.uint32)
+    lib().orc_angular_filter(C.c_void_p(_p(sub_views)), C.c_int(vp.V), C.c_int(vp.W), C.c_int(vp.H),
+                             C.c_void_p(_p(cnt)), C.c_void_p(_p(src)), C.c_void_p(_p(wt)), C.c_int(maxe),
+                             C.c_void_p(_p(out)))
+    return out
+
+
+def lattice_cells(S, T, cap: int = 1 << 20):
+    S = np.ascontiguousarray(S, np.int64)
+    T = np.ascontiguousarray(T, np.int64)
+    ci = np.zeros(cap, np.int32)
+    cj = np.zeros(cap, np.int32)
+    n = lib().orc_lattice_cells(C.c_void_p(_p(S)), C.c_void_p(_p(T)), C.c_int(cap), C.c_void_p(_p(ci)), C.c_void_p(_p(cj)))
+    if n < 0:
+        raise ValueError("cell cap exceeded")
+    return ci[:n].copy(), cj[:n].copy()
+
+
+def closest_point(p, a, b, c) -> np.ndarray:
+    arrs = [np.ascontiguousarray(x, np.float32) for x in (p, a, b, c)]
+    out = np.zeros(3, np.float32)
+    lib().orc_closest_point(*[C.c_void_p(_p(x)) for x in arrs], C.c_void_p(_p(out)))
+    return out
+
+
+def trilinear(tx: Textures, t: int, u: float, v: float, kc: int) -> int:
+    keep: list = []
+    sc = _Scene(0, 0, None, None, None, None, tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels))
+    return int(lib().orc_trilinear(C.byref(sc), C.c_int(t), C.c_float(u), C.c_float(v), C.c_int(kc)))
+
+
+def lod_q8(a: float) -> int:
+    return int(lib().orc_lod_q8(float(a)))
+
+
+def unpack_rgba(u32: np.ndarray) -> np.ndarray:
+    return u32.view(np.uint8).reshape(*u32.shape, 4)
