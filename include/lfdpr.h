@@ -1,0 +1,186 @@
+/*
+ * lfdpr.h — C ABI of the light field display point rendering (LFDPR) hot path
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * One frame (Gavane & Watson, Light Field Display Point Rendering, Sec. 3-4):
+ *   1. point generation from textured triangles with LFD-biased horizontal /
+ *      vertical sampling densities and texture-based coarsening (Sec. 3.1,
+ *      Eqs. 1-3), multiview-mip set-up and two mip fetches per point
+ *      (Sec. 3.3, Eqs. 4-7);
+ *   2. splatting of every point into every light-field view with per-view
+ *      texture interpolation (Sec. 3.2, Eqs. 8-9) and a 64-bit (depth,
+ *      colour) minimum per pixel (Sec. 5.1);
+ *   3. interleaving of the views into the tilted-lenticular panel with
+ *      optional Gaussian reconstruction, and the angular supersampling filter
+ *      (Sec. 4).
+ *
+ * Conventions shared by every entry point:
+ *   - Every function returns an int status: LFDPR_OK (0) or a negative
+ *     LFDPR_E* code.  lfdpr_strerror() names a code; lfdpr_last_error() gives
+ *     the message of the context's last failure.  Nothing else crosses the ABI
+ *     on error (no exceptions, no aborts); a failed call leaves the context
+ *     usable unless it returned LFDPR_EDEVICE.
+ *   - "device" pointers are HIP device memory on the context's device, owned
+ *     by the caller; "host" pointers are ordinary process memory, owned by the
+ *     caller and only read during the call.  Memory the library allocates
+ *     (scene copies, mip chains, per-triangle records, the point buffer, the
+ *     64-bit key buffer) belongs to the context and is freed by lfdpr_destroy.
+ *   - Work is enqueued on the stream given to lfdpr_create and is asynchronous
+ *     unless stated otherwise; device outputs are valid once that stream has
+ *     been synchronised.  A context is used from one host thread at a time.
+ *   - Images: views are RGBA8 packed in uint32 (R in the low byte), laid out
+ *     [view][row][column]; depth is FP32 camera-space Z, +inf where empty;
+ *     the panel is RGB8, [row][column][3].
+ */
+#ifndef LFDPR_H
+#define LFDPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LFDPR_ABI_VERSION 1
+
+enum {
+  LFDPR_OK = 0,
+  LFDPR_EINVAL = -1,    /* bad argument (null pointer, size out of range, unknown id) */
+  LFDPR_ENOMEM = -2,    /* device allocation failed */
+  LFDPR_EOVERFLOW = -3, /* point capacity exceeded in the last frame (reported by lfdpr_get_stats) */
+  LFDPR_EDEVICE = -4,   /* a HIP runtime call failed */
+  LFDPR_ESTATE = -5     /* call out of order (e.g. render before lfdpr_set_views) */
+};
+
+enum { LFDPR_RECON_NONE = 0, LFDPR_RECON_SPATIAL = 1, LFDPR_RECON_ANGULAR = 2, LFDPR_RECON_BOTH = 3 };
+
+typedef struct lfdpr_ctx lfdpr_ctx;
+
+/* Scene: a flat indexed triangle mesh in scene coordinates with one RGBA8
+ * albedo texture per triangle (Sec. 3.1, Eq. 1 with |T| = 1).  Triangles are
+ * wound so that (P1-P0) x (P2-P0) points out of the surface.  All pointers
+ * are host pointers; the data is copied. */
+typedef struct {
+  int32_t n_verts, n_tris;
+  const float* pos;            /* host, n_verts*3 (x, y, z) */
+  const float* uv;             /* host, n_verts*2 */
+  const uint32_t* idx;         /* host, n_tris*3, each < n_verts */
+  const uint16_t* tex_id;      /* host, n_tris, each < n_tex */
+  int32_t n_tex;               /* 1..65535 */
+  const int32_t* tex_size;     /* host, n_tex; square edge, power of two in [1, 16384] */
+  const uint8_t* const* tex_rgba8; /* host, n_tex pointers to level-0 RGBA8 texels, row-major */
+} lfdpr_scene_desc;
+
+/* Light-field rig (Sec. 3.1: centres of projection distributed horizontally;
+ * Sec. 4: angular supersampling).  V views of W x H pixels, rendered as V*S
+ * sub-views; parallel off-axis cameras sharing the focal plane Z = D; eye r at
+ * x = D tan(cone/2) (2 q_r / V - 1) with q = v + 0.5 (S = 1) or
+ * q = v + (k + 0.5 + jitter[v*S+k]) / S.  Pixels are `aspect` times wider than
+ * tall (the LFD anisotropy of Sec. 3.1). */
+typedef struct {
+  int32_t V, S, W, H;          /* V*S in [1, 256]; W, H in [1, 8192] */
+  float fovy_deg, aspect, D, cone_deg, znear;
+  const float* jitter;         /* host, V*S values in [-0.5, 0.5); may be NULL when S == 1 */
+  int32_t mip;                 /* multiview mipmapping (Sec. 3.3) on (1) or off (0) */
+  int64_t point_capacity;      /* points per frame the context reserves; 0 = 8M */
+} lfdpr_view_params;
+
+/* Tilted lenticular panel (Sec. 4, prototype of Sec. 5.1): Wp x Hp RGB
+ * pixels; lens phase of subpixel X' in row Y is frac((X' - 3*slope*Y)/pitch +
+ * offset).  Reconstruction taps (Sec. 4: Gaussian, 8 random samples): du in
+ * Q32 view intervals, dx/dy in Q8 view pixels. */
+typedef struct {
+  int32_t Wp, Hp;              /* in [1, 16384] */
+  double pitch_subpx, slope, offset;
+  int32_t mode;                /* LFDPR_RECON_* */
+  int64_t taps[8][3];
+} lfdpr_lens_params;
+
+typedef struct {
+  int64_t points;          /* points emitted by the last frame (may exceed capacity) */
+  int64_t active_tris;     /* triangles visible in at least one view */
+  int64_t point_views;     /* sum over points of the views their triangle is active in */
+  int64_t overflow_tris;   /* triangles whose lattice exceeded the cell caps (no points) */
+  int64_t capacity;        /* point capacity of the context */
+  int32_t point_overflow;  /* 1 when points > capacity (frame incomplete) */
+  int32_t n_views;         /* rendered (sub-)views */
+} lfdpr_stats;
+
+/* Version of this ABI (LFDPR_ABI_VERSION). */
+int lfdpr_abi_version(void);
+
+/* Static text for a status code; never NULL. */
+const char* lfdpr_strerror(int code);
+
+/* Creates a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the null stream).  *out receives the context. */
+int lfdpr_create(int device, void* stream, lfdpr_ctx** out);
+
+/* Frees the context and every device buffer it owns.  NULL is accepted. */
+int lfdpr_destroy(lfdpr_ctx* ctx);
+
+/* Message of the last failure on this context (empty when none); the string
+ * is owned by the context and valid until its next call. */
+const char* lfdpr_last_error(lfdpr_ctx* ctx);
+
+/* Copies a scene into device memory and builds its box mip chains on the
+ * device (the "hardware mipmap" of Sec. 3.3).  *scene_id receives a handle.
+ * Synchronises the stream before returning (host buffers are then free). */
+int lfdpr_scene_upload(lfdpr_ctx* ctx, const lfdpr_scene_desc* desc, int32_t* scene_id);
+
+/* Releases a scene's device memory. */
+int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id);
+
+/* Sets the rig and (re)allocates the per-view key buffer (8 B per pixel of
+ * every rendered view, the 64-bit view buffer of Sec. 5.1) and the point
+ * buffer (16 B per point).  Synchronous. */
+int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* views);
+
+/* Sets the panel and reconstruction parameters used by lfdpr_reconstruct. */
+int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* lens);
+
+/* Renders one frame of a scene into all V*S rendered views (Sec. 3):
+ *   model      host, 12 floats, row-major 3x4 camera-from-scene transform;
+ *   views_rgba device, V*S*H*W uint32 (RGBA8);
+ *   depth      device, V*S*H*W float, or NULL.
+ * Asynchronous.  A point-capacity overflow is reported by lfdpr_get_stats
+ * (the frame's views are then incomplete). */
+int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views_rgba, float* depth);
+
+/* Interleaves n_views views of W x H (device, [view][row][col] RGBA8) into the
+ * lenticular panel (device, Hp*Wp*3 bytes) with the lens and reconstruction
+ * mode of lfdpr_set_lens (Sec. 4).  Asynchronous. */
+int lfdpr_reconstruct(lfdpr_ctx* ctx, const uint32_t* views_rgba, int32_t n_views, int32_t W, int32_t H,
+                      uint8_t* panel_rgb);
+
+/* Angular supersampling filter (Sec. 4): V*S sub-views (device, as rendered
+ * by lfdpr_render_frame with S > 1) to V views (device, V*H*W) with Gaussian
+ * weights over sub-views within one view interval.  Asynchronous. */
+int lfdpr_angular_filter(lfdpr_ctx* ctx, const uint32_t* sub_views, uint32_t* views_out);
+
+/* Statistics of the last rendered frame.  Synchronises the stream.  Returns
+ * LFDPR_EOVERFLOW (with *stats filled) when the point capacity overflowed. */
+int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* stats);
+
+/* Copies the last frame's point buffer (device, 16 B per point:
+ * tri | flags<<28, (u16)i | (u16)j<<16, tv_min, tv_max) into dst (device,
+ * room for cap points) and its length into *n_points (host).  Synchronises. */
+int lfdpr_copy_points(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points);
+
+/* Copies the last frame's per-triangle point counts (device, uint32 per
+ * triangle of the scene last rendered) into dst.  Synchronises. */
+int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n);
+
+/* Enables (dst_f/dst_i non-NULL, device, 8 values per triangle each for up to
+ * n_tris triangles) or disables (both NULL) the per-triangle set-up record
+ * written by the next frames; rendering a scene with more than n_tris
+ * triangles while enabled fails with LFDPR_EINVAL.  Record:
+ * f = {Sx, Sy, size_min, size_max, A_ts/A_ws, n.P0, size_xy, active views},
+ * i = {lattice s1, t1, s2, t2 (Q8), LOD_min, LOD_max (1/256), active, overflow}. */
+int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* dst_f, int32_t* dst_i, int64_t n_tris);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFDPR_H */

@@ -38,6 +38,7 @@
 #define F_JHI 8u
 #define CELL_CAP 65536
 #define EPS_Q8 4
+#define BOX_CAP (1 << 22)
 
 typedef struct {
     int nv, nt;
@@ -489,10 +490,11 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         if (ts.area2 != 0) {
             int64_t mins = imin64(ts.S[0], imin64(ts.S[1], ts.S[2])), maxs = imax64(ts.S[0], imax64(ts.S[1], ts.S[2]));
             int64_t mint = imin64(ts.T[0], imin64(ts.T[1], ts.T[2])), maxt = imax64(ts.T[0], imax64(ts.T[1], ts.T[2]));
-            int64_t i0 = floordiv64(mins, 256) - 1, i1 = floordiv64(maxs, 256) + 1;
-            int64_t j0 = floordiv64(mint, 256) - 1, j1 = floordiv64(maxt, 256) + 1;
+            /* cells whose dilated box overlaps the lattice bounding box with positive length */
+            int64_t i0 = floordiv64(mins - EPS_Q8, 256), i1 = floordiv64(maxs + EPS_Q8 - 1, 256);
+            int64_t j0 = floordiv64(mint - EPS_Q8, 256), j1 = floordiv64(maxt + EPS_Q8 - 1, 256);
             int64_t nb = (i1 - i0 + 1) * (j1 - j0 + 1);
-            if (nb > 64 * (int64_t)CELL_CAP) overflow = 1;
+            if (nb > BOX_CAP) overflow = 1;
             else {
                 int cap = 1024;
                 cells_i = (int *)malloc(sizeof(int) * cap);

@@ -1,0 +1,531 @@
+// C ABI of the LFDPR hot path: context, scene store, rig/lens tables and the
+// per-frame launch sequence.  See include/lfdpr.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lfdpr.h"
+#include "lfdpr_internal.h"
+
+using namespace lfdpr;
+
+namespace {
+
+struct SceneDev {
+  int32_t nv = 0, nt = 0, ntex = 0;
+  float* pos = nullptr;
+  float* uv = nullptr;
+  uint32_t* idx = nullptr;
+  uint16_t* tex = nullptr;
+  TexInfo* texinfo = nullptr;
+  uint8_t* texels = nullptr;
+};
+
+template <class T>
+void dfree(T*& p) {
+  if (p) hipFree((void*)p);
+  p = nullptr;
+}
+
+}  // namespace
+
+struct lfdpr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::map<int32_t, SceneDev> scenes;
+  int32_t next_scene = 1;
+  // rig
+  bool views_set = false;
+  lfdpr_view_params vp{};
+  std::vector<float> jitter;
+  Rig rig{};
+  float* d_eye = nullptr;
+  float* d_kshift = nullptr;
+  float* d_lod_thr = nullptr;
+  int64_t cap = 0;
+  Point* d_points = nullptr;
+  uint64_t* d_keys = nullptr;
+  int64_t n_keys = 0;
+  // angular supersampling filter table
+  int32_t* d_acnt = nullptr;
+  int32_t* d_asrc = nullptr;
+  uint32_t* d_awt = nullptr;
+  int32_t amaxe = 0;
+  // per-triangle buffers
+  int64_t tri_cap = 0;
+  uint32_t* d_counts = nullptr;
+  uint64_t* d_offsets = nullptr;
+  TriRec* d_rec = nullptr;
+  TriEmit* d_em = nullptr;
+  uint64_t* d_tiles = nullptr;
+  uint64_t* d_stats = nullptr;
+  int64_t last_nt = 0;
+  // lens
+  bool lens_set = false;
+  lfdpr_lens_params lens{};
+  // debug records
+  float* dbgf = nullptr;
+  int32_t* dbgi = nullptr;
+  int64_t dbg_cap = 0;
+  // launch shape of the splat kernel
+  int splat_blocks = 4096;
+};
+
+namespace {
+
+int fail(lfdpr_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPOK(call)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (call);                                                                      \
+    if (e_ != hipSuccess) return fail(ctx, LFDPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T*& p, size_t n) {
+  p = nullptr;
+  if (n == 0) n = 1;
+  return hipMalloc((void**)&p, n * sizeof(T));
+}
+
+void free_scene(SceneDev& s) {
+  dfree(s.pos);
+  dfree(s.uv);
+  dfree(s.idx);
+  dfree(s.tex);
+  dfree(s.texinfo);
+  dfree(s.texels);
+}
+
+int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
+  if (nt <= ctx->tri_cap && ctx->d_counts) return LFDPR_OK;
+  int64_t n = nt > 1024 ? nt : 1024;
+  dfree(ctx->d_counts);
+  dfree(ctx->d_offsets);
+  dfree(ctx->d_rec);
+  dfree(ctx->d_em);
+  dfree(ctx->d_tiles);
+  if (dalloc(ctx->d_counts, n) != hipSuccess || dalloc(ctx->d_offsets, n) != hipSuccess ||
+      dalloc(ctx->d_rec, n) != hipSuccess || dalloc(ctx->d_em, n) != hipSuccess ||
+      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess) {
+    ctx->tri_cap = 0;
+    return fail(ctx, LFDPR_ENOMEM, "per-triangle buffers");
+  }
+  ctx->tri_cap = n;
+  return LFDPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lfdpr_abi_version(void) { return LFDPR_ABI_VERSION; }
+
+const char* lfdpr_strerror(int code) {
+  switch (code) {
+    case LFDPR_OK: return "ok";
+    case LFDPR_EINVAL: return "invalid argument";
+    case LFDPR_ENOMEM: return "out of device memory";
+    case LFDPR_EOVERFLOW: return "point capacity exceeded";
+    case LFDPR_EDEVICE: return "HIP runtime error";
+    case LFDPR_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
+  lfdpr_ctx* ctx = nullptr;
+  if (!out) return LFDPR_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LFDPR_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return LFDPR_EDEVICE;
+  ctx = new lfdpr_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess) {
+    delete ctx;
+    return LFDPR_ENOMEM;
+  }
+  // LOD thresholds: 2^((k - 127.5)/128) rounded up to the next float
+  float thr[128];
+  for (int k = 0; k < 128; ++k) {
+    double t = std::exp2((k - 127.5) / 128.0);
+    float f = (float)t;
+    if ((double)f < t) f = std::nextafter(f, INFINITY);
+    thr[k] = f;
+  }
+  if (dalloc(ctx->d_lod_thr, 128) != hipSuccess ||
+      hipMemcpy(ctx->d_lod_thr, thr, sizeof thr, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(ctx->d_stats, 0, STAT_SLOTS * sizeof(uint64_t)) != hipSuccess) {
+    lfdpr_destroy(ctx);
+    return LFDPR_EDEVICE;
+  }
+  *out = ctx;
+  return LFDPR_OK;
+}
+
+int lfdpr_destroy(lfdpr_ctx* ctx) {
+  if (!ctx) return LFDPR_OK;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->scenes) free_scene(kv.second);
+  dfree(ctx->d_eye);
+  dfree(ctx->d_kshift);
+  dfree(ctx->d_lod_thr);
+  dfree(ctx->d_points);
+  dfree(ctx->d_keys);
+  dfree(ctx->d_acnt);
+  dfree(ctx->d_asrc);
+  dfree(ctx->d_awt);
+  dfree(ctx->d_counts);
+  dfree(ctx->d_offsets);
+  dfree(ctx->d_rec);
+  dfree(ctx->d_em);
+  dfree(ctx->d_tiles);
+  dfree(ctx->d_stats);
+  delete ctx;
+  return LFDPR_OK;
+}
+
+const char* lfdpr_last_error(lfdpr_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int lfdpr_scene_upload(lfdpr_ctx* ctx, const lfdpr_scene_desc* d, int32_t* scene_id) {
+  if (!ctx || !d || !scene_id) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (d->n_verts < 3 || d->n_tris < 0 || d->n_tris > (1 << 28) - 1 || d->n_tex < 1 || d->n_tex > 65535 ||
+      !d->pos || !d->uv || (d->n_tris > 0 && (!d->idx || !d->tex_id)) || !d->tex_size || !d->tex_rgba8)
+    return fail(ctx, LFDPR_EINVAL, "scene descriptor out of range");
+  for (int64_t k = 0; k < 3ll * d->n_tris; ++k)
+    if (d->idx[k] >= (uint32_t)d->n_verts) return fail(ctx, LFDPR_EINVAL, "vertex index out of range");
+  for (int64_t k = 0; k < d->n_tris; ++k)
+    if (d->tex_id[k] >= d->n_tex) return fail(ctx, LFDPR_EINVAL, "texture id out of range");
+  std::vector<TexInfo> ti(d->n_tex);
+  int64_t pool = 0;
+  for (int k = 0; k < d->n_tex; ++k) {
+    int s = d->tex_size[k];
+    if (s < 1 || s > 16384 || (s & (s - 1)) || !d->tex_rgba8[k]) return fail(ctx, LFDPR_EINVAL, "texture size");
+    ti[k].size = s;
+    ti[k].levels = 0;
+    for (int q = s; q >= 1; q >>= 1) {
+      ti[k].off[ti[k].levels++] = pool;
+      pool += (int64_t)q * q * 4;
+    }
+    for (int l = ti[k].levels; l < 16; ++l) ti[k].off[l] = 0;
+  }
+  HIPOK(hipSetDevice(ctx->device));
+  SceneDev s;
+  s.nv = d->n_verts;
+  s.nt = d->n_tris;
+  s.ntex = d->n_tex;
+  if (dalloc(s.pos, 3ll * s.nv) != hipSuccess || dalloc(s.uv, 2ll * s.nv) != hipSuccess ||
+      dalloc(s.idx, 3ll * s.nt) != hipSuccess || dalloc(s.tex, (size_t)s.nt) != hipSuccess ||
+      dalloc(s.texinfo, (size_t)s.ntex) != hipSuccess || dalloc(s.texels, (size_t)pool) != hipSuccess) {
+    free_scene(s);
+    return fail(ctx, LFDPR_ENOMEM, "scene buffers");
+  }
+  hipError_t e = hipMemcpyAsync(s.pos, d->pos, 12ll * s.nv, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s.uv, d->uv, 8ll * s.nv, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && s.nt) e = hipMemcpyAsync(s.idx, d->idx, 12ll * s.nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && s.nt) e = hipMemcpyAsync(s.tex, d->tex_id, 2ll * s.nt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s.texinfo, ti.data(), sizeof(TexInfo) * s.ntex, hipMemcpyHostToDevice, ctx->stream);
+  for (int k = 0; k < s.ntex && e == hipSuccess; ++k) {
+    int sz = ti[k].size;
+    e = hipMemcpyAsync(s.texels + ti[k].off[0], d->tex_rgba8[k], (size_t)sz * sz * 4, hipMemcpyHostToDevice, ctx->stream);
+    for (int l = 1; l < ti[k].levels && e == hipSuccess; ++l) {
+      launch_build_mip((const uint32_t*)(s.texels + ti[k].off[l - 1]), (uint32_t*)(s.texels + ti[k].off[l]),
+                       sz >> (l - 1), ctx->stream);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    free_scene(s);
+    return fail(ctx, LFDPR_EDEVICE, std::string("scene upload: ") + hipGetErrorString(e));
+  }
+  int32_t id = ctx->next_scene++;
+  ctx->scenes[id] = s;
+  *scene_id = id;
+  return LFDPR_OK;
+}
+
+int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
+  if (!ctx) return LFDPR_EINVAL;
+  auto it = ctx->scenes.find(scene_id);
+  if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  free_scene(it->second);
+  ctx->scenes.erase(it);
+  return LFDPR_OK;
+}
+
+int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
+  if (!ctx || !v) return fail(ctx, LFDPR_EINVAL, "null argument");
+  int64_t nviews = (int64_t)v->V * v->S;
+  if (v->V < 1 || v->S < 1 || nviews > 256 || v->W < 1 || v->H < 1 || v->W > 8192 || v->H > 8192 ||
+      !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) || !(v->aspect > 0.0f) || !(v->D > 0.0f) ||
+      !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f) || !(v->znear > 0.0f) || (v->S > 1 && !v->jitter) ||
+      v->point_capacity < 0 || v->point_capacity > (1ll << 31))
+    return fail(ctx, LFDPR_EINVAL, "view parameters out of range");
+  if (v->S > 1)
+    for (int64_t k = 0; k < nviews; ++k)
+      if (!(v->jitter[k] >= -0.5f && v->jitter[k] < 0.5f)) return fail(ctx, LFDPR_EINVAL, "jitter out of range");
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  // rig in double, rounded once
+  const double D = v->D;
+  const double B = D * std::tan((double)v->cone_deg * M_PI / 180.0 / 2.0);
+  const double tf = std::tan((double)v->fovy_deg * M_PI / 180.0 / 2.0);
+  std::vector<float> eye(nviews), ks(nviews);
+  std::vector<double> q(nviews);
+  for (int vv = 0; vv < v->V; ++vv)
+    for (int k = 0; k < v->S; ++k) {
+      int r = vv * v->S + k;
+      q[r] = v->S == 1 ? vv + 0.5 : vv + (k + 0.5 + (double)v->jitter[r]) / v->S;
+      double b = B * (2.0 * q[r] / v->V - 1.0);
+      eye[r] = (float)b;
+      ks[r] = (float)(b / D);
+    }
+  Rig rg{};
+  rg.n_views = (int32_t)nviews;
+  rg.W = v->W;
+  rg.H = v->H;
+  rg.mip = v->mip ? 1 : 0;
+  rg.fx = (float)((v->W / 2.0) / ((double)v->aspect * tf));
+  rg.fy = (float)((v->H / 2.0) / tf);
+  rg.cx = (float)(v->W / 2.0);
+  rg.cy = (float)(v->H / 2.0);
+  rg.rD = (float)(1.0 / D);
+  rg.znear = v->znear;
+  rg.fxfy = rg.fx * rg.fy;
+  // angular filter table: sub-views within one interval of each view centre
+  int32_t maxe = 3 * v->S;
+  std::vector<int32_t> acnt(v->V, 0), asrc((size_t)v->V * maxe, 0);
+  std::vector<uint32_t> awt((size_t)v->V * maxe, 0);
+  for (int vv = 0; vv < v->V; ++vv)
+    for (int r = 0; r < nviews; ++r) {
+      double dlt = q[r] - (vv + 0.5);
+      if (std::fabs(dlt) < 1.0 && acnt[vv] < maxe) {
+        asrc[(size_t)vv * maxe + acnt[vv]] = r;
+        awt[(size_t)vv * maxe + acnt[vv]] = (uint32_t)std::llround(65535.0 * std::exp(-dlt * dlt / (2.0 * 0.25)));
+        ++acnt[vv];
+      }
+    }
+  int64_t cap = v->point_capacity ? v->point_capacity : (8ll << 20);
+  int64_t nkeys = nviews * (int64_t)v->W * v->H;
+  dfree(ctx->d_eye);
+  dfree(ctx->d_kshift);
+  dfree(ctx->d_acnt);
+  dfree(ctx->d_asrc);
+  dfree(ctx->d_awt);
+  if (dalloc(ctx->d_eye, nviews) != hipSuccess || dalloc(ctx->d_kshift, nviews) != hipSuccess ||
+      dalloc(ctx->d_acnt, v->V) != hipSuccess || dalloc(ctx->d_asrc, (size_t)v->V * maxe) != hipSuccess ||
+      dalloc(ctx->d_awt, (size_t)v->V * maxe) != hipSuccess)
+    return fail(ctx, LFDPR_ENOMEM, "rig tables");
+  if (cap != ctx->cap || !ctx->d_points) {
+    dfree(ctx->d_points);
+    ctx->cap = 0;
+    if (dalloc(ctx->d_points, (size_t)cap) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "point buffer");
+    ctx->cap = cap;
+  }
+  if (nkeys != ctx->n_keys || !ctx->d_keys) {
+    dfree(ctx->d_keys);
+    ctx->n_keys = 0;
+    if (dalloc(ctx->d_keys, (size_t)nkeys) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "key buffer");
+    ctx->n_keys = nkeys;
+  }
+  HIPOK(hipMemcpy(ctx->d_eye, eye.data(), 4 * nviews, hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(ctx->d_kshift, ks.data(), 4 * nviews, hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(ctx->d_acnt, acnt.data(), 4 * acnt.size(), hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(ctx->d_asrc, asrc.data(), 4 * asrc.size(), hipMemcpyHostToDevice));
+  HIPOK(hipMemcpy(ctx->d_awt, awt.data(), 4 * awt.size(), hipMemcpyHostToDevice));
+  launch_fill_u64(ctx->d_keys, nkeys, ~0ull, ctx->stream);
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  rg.eye = ctx->d_eye;
+  rg.kshift = ctx->d_kshift;
+  ctx->rig = rg;
+  ctx->vp = *v;
+  ctx->amaxe = maxe;
+  ctx->views_set = true;
+  return LFDPR_OK;
+}
+
+int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* l) {
+  if (!ctx || !l) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (l->Wp < 1 || l->Hp < 1 || l->Wp > 16384 || l->Hp > 16384 || !(l->pitch_subpx > 0.0) || l->mode < 0 ||
+      l->mode > 3 || !std::isfinite(l->slope) || !std::isfinite(l->offset))
+    return fail(ctx, LFDPR_EINVAL, "lens parameters out of range");
+  for (int k = 0; k < 8; ++k)
+    if (l->taps[k][0] <= -(1ll << 34) || l->taps[k][0] >= (1ll << 34) || l->taps[k][1] < -65536 ||
+        l->taps[k][1] > 65536 || l->taps[k][2] < -65536 || l->taps[k][2] > 65536)
+      return fail(ctx, LFDPR_EINVAL, "reconstruction tap out of range");
+  ctx->lens = *l;
+  ctx->lens_set = true;
+  return LFDPR_OK;
+}
+
+int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* f, int32_t* i, int64_t n_tris) {
+  if (!ctx) return LFDPR_EINVAL;
+  if ((f == nullptr) != (i == nullptr)) return fail(ctx, LFDPR_EINVAL, "both or neither debug buffers");
+  if (f && n_tris < 0) return fail(ctx, LFDPR_EINVAL, "negative debug record capacity");
+  ctx->dbgf = f;
+  ctx->dbgi = i;
+  ctx->dbg_cap = f ? n_tris : 0;
+  return LFDPR_OK;
+}
+
+int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, float* depth) {
+  if (!ctx || !model || !views) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (!ctx->views_set) return fail(ctx, LFDPR_ESTATE, "lfdpr_set_views first");
+  auto it = ctx->scenes.find(scene_id);
+  if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(model[k])) return fail(ctx, LFDPR_EINVAL, "non-finite model matrix");
+  const SceneDev& s = it->second;
+  if (ctx->dbgf && s.nt > ctx->dbg_cap) return fail(ctx, LFDPR_EINVAL, "debug record buffers smaller than the scene");
+  HIPOK(hipSetDevice(ctx->device));
+  int rc = ensure_tri_buffers(ctx, s.nt);
+  if (rc) return rc;
+  hipStream_t st = ctx->stream;
+  launch_fill_u64(ctx->d_stats, STAT_SLOTS, 0ull, st);
+  SetupArgs sa{};
+  sa.pos = s.pos;
+  sa.uv = s.uv;
+  sa.idx = s.idx;
+  sa.tex = s.tex;
+  sa.nt = s.nt;
+  std::memcpy(sa.model.m, model, sizeof sa.model.m);
+  sa.rig = ctx->rig;
+  sa.texinfo = s.texinfo;
+  sa.lod_thr = ctx->d_lod_thr;
+  sa.counts = ctx->d_counts;
+  sa.rec = ctx->d_rec;
+  sa.em = ctx->d_em;
+  sa.dbgf = ctx->dbgf;
+  sa.dbgi = ctx->dbgi;
+  sa.stats = ctx->d_stats;
+  launch_tri_setup(sa, st);
+  launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, st);
+  EmitArgs ea{};
+  ea.nt = s.nt;
+  ea.counts = ctx->d_counts;
+  ea.offsets = ctx->d_offsets;
+  ea.em = ctx->d_em;
+  ea.texinfo = s.texinfo;
+  ea.texels = s.texels;
+  ea.points = ctx->d_points;
+  ea.cap = ctx->cap;
+  launch_emit(ea, st);
+  SplatArgs pa{};
+  pa.rig = ctx->rig;
+  pa.points = ctx->d_points;
+  pa.n_points = ctx->d_stats + STAT_TOTAL;
+  pa.cap = ctx->cap;
+  pa.rec = ctx->d_rec;
+  pa.keys = ctx->d_keys;
+  launch_splat(pa, ctx->splat_blocks, st);
+  launch_resolve(ctx->d_keys, ctx->n_keys, views, depth, st);
+  HIPOK(hipGetLastError());
+  ctx->last_nt = s.nt;
+  return LFDPR_OK;
+}
+
+int lfdpr_reconstruct(lfdpr_ctx* ctx, const uint32_t* views, int32_t n_views, int32_t W, int32_t H, uint8_t* panel) {
+  if (!ctx || !views || !panel) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (!ctx->lens_set) return fail(ctx, LFDPR_ESTATE, "lfdpr_set_lens first");
+  if (n_views < 1 || n_views > 4096 || W < 1 || H < 1 || W > 16384 || H > 16384)
+    return fail(ctx, LFDPR_EINVAL, "view stack size out of range");
+  const lfdpr_lens_params& l = ctx->lens;
+  const double two32 = 4294967296.0;
+  auto mod32 = [](long long v) { return (uint32_t)((unsigned long long)v & 0xFFFFFFFFull); };
+  InterleaveArgs a{};
+  a.views = views;
+  a.V = n_views;
+  a.Wv = W;
+  a.Hv = H;
+  a.Wp = l.Wp;
+  a.Hp = l.Hp;
+  a.mode = l.mode;
+  a.K1 = mod32(std::llround(two32 / l.pitch_subpx));
+  a.Ky = mod32(std::llround(-3.0 * l.slope * two32 / l.pitch_subpx));
+  a.K0 = mod32(std::llround(l.offset * two32));
+  for (int k = 0; k < 8; ++k) {
+    a.du[k] = (l.mode & LFDPR_RECON_ANGULAR) ? l.taps[k][0] : 0;
+    a.dx[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][1] : 0;
+    a.dy[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][2] : 0;
+  }
+  a.panel = panel;
+  HIPOK(hipSetDevice(ctx->device));
+  launch_interleave(a, ctx->stream);
+  HIPOK(hipGetLastError());
+  return LFDPR_OK;
+}
+
+int lfdpr_angular_filter(lfdpr_ctx* ctx, const uint32_t* sub, uint32_t* out) {
+  if (!ctx || !sub || !out) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (!ctx->views_set) return fail(ctx, LFDPR_ESTATE, "lfdpr_set_views first");
+  AngularArgs a{};
+  a.sub = sub;
+  a.out = out;
+  a.V = ctx->vp.V;
+  a.W = ctx->vp.W;
+  a.H = ctx->vp.H;
+  a.maxe = ctx->amaxe;
+  a.cnt = ctx->d_acnt;
+  a.src = ctx->d_asrc;
+  a.wt = ctx->d_awt;
+  HIPOK(hipSetDevice(ctx->device));
+  launch_angular_filter(a, ctx->stream);
+  HIPOK(hipGetLastError());
+  return LFDPR_OK;
+}
+
+int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
+  if (!ctx || !out) return fail(ctx, LFDPR_EINVAL, "null argument");
+  uint64_t st[STAT_SLOTS];
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(hipMemcpy(st, ctx->d_stats, sizeof st, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->points = (int64_t)st[STAT_TOTAL];
+  out->active_tris = (int64_t)st[STAT_ACTIVE];
+  out->point_views = (int64_t)st[STAT_POINT_VIEWS];
+  out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
+  out->capacity = ctx->cap;
+  out->point_overflow = out->points > ctx->cap ? 1 : 0;
+  out->n_views = ctx->rig.n_views;
+  return out->point_overflow ? LFDPR_EOVERFLOW : LFDPR_OK;
+}
+
+int lfdpr_copy_points(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points) {
+  if (!ctx || !dst || !n_points || cap < 0) return fail(ctx, LFDPR_EINVAL, "null argument");
+  uint64_t total = 0;
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(hipMemcpy(&total, ctx->d_stats + STAT_TOTAL, 8, hipMemcpyDeviceToHost));
+  int64_t n = (int64_t)total < ctx->cap ? (int64_t)total : ctx->cap;
+  *n_points = (int64_t)total;
+  if (n > cap) n = cap;
+  if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_points, (size_t)n * sizeof(Point), hipMemcpyDeviceToDevice));
+  return LFDPR_OK;
+}
+
+int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n) {
+  if (!ctx || !dst || n < 0) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (n > ctx->last_nt) return fail(ctx, LFDPR_EINVAL, "more counts than triangles");
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_counts, (size_t)n * 4, hipMemcpyDeviceToDevice));
+  return LFDPR_OK;
+}
+
+}  // extern "C"

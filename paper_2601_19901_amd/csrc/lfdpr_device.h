@@ -1,0 +1,277 @@
+// Device-side arithmetic of the LFDPR hot path for gfx950.
+//
+// Every floating-point expression is binary32 with round-to-nearest-even, no
+// contraction (the library is built with -ffp-contract=off and correctly
+// rounded division/sqrt), evaluated exactly as parenthesised, so that point
+// counts, point attributes and per-pixel keys are reproducible bit for bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LF_HD __host__ __device__ __forceinline__
+
+namespace lfdpr {
+
+constexpr uint32_t F_ILO = 1u, F_IHI = 2u, F_JLO = 4u, F_JHI = 8u;
+constexpr int kCellCap = 65536;          // cells per triangle before overflow
+constexpr int64_t kBoxCap = 1ll << 22;   // lattice bounding-box cells before overflow
+constexpr int64_t kEpsQ8 = 4;            // cell dilation, 4/256 of a cell
+constexpr float kGuard = 32768.0f;       // screen guard band, pixels
+
+// Per-triangle record read by the splat kernel (112 B, 7 x float4).
+struct alignas(16) TriRec {
+  float p0x, p0y, p0z, h;      // camera-space vertex 0; plane offset n.P0
+  float nx, ny, nz, sx;        // unit normal; horizontal sampling density
+  float ux, uy, uz, sy;        // lattice s axis; vertical sampling density
+  float wx, wy, wz, ruv;       // lattice t axis; texture/world area ratio
+  float a0, c0, y0, smin;      // projected vertex 0 (x = a - b*c), Eqs. 4-5 minimum
+  float a1, c1, y1, smax;      // projected vertex 1, Eqs. 4-5 maximum
+  float a2, c2, y2, pad;       // projected vertex 2
+};
+
+// Per-triangle emission data (64 B).
+struct alignas(16) TriEmit {
+  float uv0u, uv0v, du1, dv1;
+  float du2, dv2;
+  int32_t s1, t1;
+  int32_t s2, t2, kmin, kmax;
+  int32_t tex, pad0, pad1, pad2;
+};
+
+// One point: 16 B.  tri | flags<<28, (u16)i | (u16)j<<16, tv_min, tv_max (RGBA8).
+struct alignas(16) Point {
+  uint32_t tri_flags, ij, tvmin, tvmax;
+};
+
+struct TexInfo {
+  int32_t size, levels;
+  int64_t off[16];  // byte offset of each level in the texel pool
+};
+
+struct Rig {
+  int32_t n_views, W, H, mip;
+  float fx, fy, cx, cy, rD, znear, fxfy;
+  const float* eye;     // n_views
+  const float* kshift;  // n_views
+};
+
+struct Model {
+  float m[12];
+};
+
+LF_HD float clamp_big(float x) {
+  if (!(x > -1073741824.0f)) return -1073741824.0f;
+  if (x > 1073741824.0f) return 1073741824.0f;
+  return x;
+}
+
+LF_HD int64_t floor_div(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  if ((a % b) != 0 && a < 0) q -= 1;
+  return q;
+}
+
+LF_HD int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
+LF_HD int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------- projection
+// x = A - b*C with A = cx + fx*(X/Z), C = fx*(1/Z - 1/D); y = cy + fy*(Y/Z).
+LF_HD void vertex_proj(const Rig& rg, float X, float Y, float Z, float& A, float& C, float& Yp) {
+  A = rg.cx + rg.fx * (X / Z);
+  C = rg.fx * (1.0f / Z - rg.rD);
+  Yp = rg.cy + rg.fy * (Y / Z);
+}
+
+LF_HD bool q8_xy(float A, float C, float Yp, float b, int32_t& qx, int32_t& qy) {
+  float x = A - b * C;
+  if (!(fabsf(x) < kGuard) || !(fabsf(Yp) < kGuard)) return false;
+  qx = (int32_t)rintf(x * 256.0f);
+  qy = (int32_t)rintf(Yp * 256.0f);
+  return true;
+}
+
+// View r is active for the triangle: front facing, inside the guard band, and
+// not entirely beyond one screen edge.  Fills the Q8 vertices on success.
+LF_HD bool view_active(const Rig& rg, const TriRec& t, float b, int32_t qx[3], int32_t qy[3]) {
+  float delta = t.h - t.nx * b;
+  if (!(delta < 0.0f)) return false;
+  if (!q8_xy(t.a0, t.c0, t.y0, b, qx[0], qy[0])) return false;
+  if (!q8_xy(t.a1, t.c1, t.y1, b, qx[1], qy[1])) return false;
+  if (!q8_xy(t.a2, t.c2, t.y2, b, qx[2], qy[2])) return false;
+  int32_t W8 = 256 * rg.W, H8 = 256 * rg.H;
+  if (qx[0] < 0 && qx[1] < 0 && qx[2] < 0) return false;
+  if (qx[0] > W8 && qx[1] > W8 && qx[2] > W8) return false;
+  if (qy[0] < 0 && qy[1] < 0 && qy[2] < 0) return false;
+  if (qy[0] > H8 && qy[1] > H8 && qy[2] > H8) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------- geometry
+struct F3 {
+  float x, y, z;
+};
+LF_HD F3 sub3(F3 a, F3 b) { return F3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+LF_HD float dot3(F3 a, F3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+LF_HD F3 axpy3(F3 a, float s, F3 d) { return F3{a.x + s * d.x, a.y + s * d.y, a.z + s * d.z}; }
+
+// Point of triangle abc nearest to p, by the Voronoi regions of its vertices,
+// edges and face (Ericson, Real-Time Collision Detection, Sec. 5.1.5).
+LF_HD F3 nearest_on_triangle(F3 p, F3 a, F3 b, F3 c) {
+  F3 ab = sub3(b, a), ac = sub3(c, a);
+  F3 ap = sub3(p, a);
+  float d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+  if (d1 <= 0.0f && d2 <= 0.0f) return a;
+  F3 bp = sub3(p, b);
+  float d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+  if (d3 >= 0.0f && d4 <= d3) return b;
+  float vc = d1 * d4 - d3 * d2;
+  if (vc <= 0.0f && d1 >= 0.0f && d3 <= 0.0f) return axpy3(a, d1 / (d1 - d3), ab);
+  F3 cp = sub3(p, c);
+  float d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+  if (d6 >= 0.0f && d5 <= d6) return c;
+  float vb = d5 * d2 - d1 * d6;
+  if (vb <= 0.0f && d2 >= 0.0f && d6 <= 0.0f) return axpy3(a, d2 / (d2 - d6), ac);
+  float va = d3 * d6 - d5 * d4;
+  float e43 = d4 - d3, e56 = d5 - d6;
+  if (va <= 0.0f && e43 >= 0.0f && e56 >= 0.0f) return axpy3(b, e43 / (e43 + e56), sub3(c, b));
+  float inv = 1.0f / ((va + vb) + vc);
+  return axpy3(axpy3(a, vb * inv, ab), vc * inv, ac);
+}
+
+// ---------------------------------------------------------------- lattice
+// Conservative cell rule: cell (i,j)'s box [256i-4, 256i+260] x [256j-4, 256j+260]
+// (Q8) overlaps the snapped triangle with positive area.  The two box axes give
+// the bounding ranges below; each of the three edges bounds i within a row.
+struct Lattice {
+  int64_t S[3], T[3];
+  int64_t sg;                 // sign of the doubled area
+  int64_t iA, iB, jA, jB;     // cells passing the box-axis test
+};
+
+LF_HD bool lattice_init(Lattice& L, int32_t s1, int32_t t1, int32_t s2, int32_t t2) {
+  L.S[0] = 128; L.T[0] = 128;
+  L.S[1] = s1; L.T[1] = t1;
+  L.S[2] = s2; L.T[2] = t2;
+  int64_t a2 = (L.S[1] - L.S[0]) * (L.T[2] - L.T[0]) - (L.T[1] - L.T[0]) * (L.S[2] - L.S[0]);
+  if (a2 == 0) return false;
+  L.sg = a2 > 0 ? 1 : -1;
+  int64_t mins = imin(L.S[0], imin(L.S[1], L.S[2])), maxs = imax(L.S[0], imax(L.S[1], L.S[2]));
+  int64_t mint = imin(L.T[0], imin(L.T[1], L.T[2])), maxt = imax(L.T[0], imax(L.T[1], L.T[2]));
+  L.iA = floor_div(mins - kEpsQ8, 256);
+  L.iB = floor_div(maxs + kEpsQ8 - 1, 256);
+  L.jA = floor_div(mint - kEpsQ8, 256);
+  L.jB = floor_div(maxt + kEpsQ8 - 1, 256);
+  return true;
+}
+
+// Emitted i-range [lo, hi] of row j (empty when lo > hi).
+LF_HD void lattice_row(const Lattice& L, int64_t j, int64_t& lo, int64_t& hi) {
+  lo = L.iA;
+  hi = L.iB;
+  int64_t y0 = 256 * j - kEpsQ8, y1 = 256 * j + 256 + kEpsQ8;
+  for (int e = 0; e < 3; ++e) {
+    int a = e, b = e == 2 ? 0 : e + 1;
+    int64_t dx = L.S[b] - L.S[a], dy = L.T[b] - L.T[a];
+    // E(x,y) = alpha*x + beta*y + gamma, interior positive
+    int64_t alpha = -L.sg * dy, beta = L.sg * dx;
+    int64_t gamma = L.sg * (dy * L.S[a] - dx * L.T[a]);
+    int64_t c = beta * (beta > 0 ? y1 : y0) + gamma;
+    if (alpha > 0) {
+      // alpha*(256 i + 260) + c > 0
+      lo = imax(lo, floor_div(-c - (256 + kEpsQ8) * alpha, 256 * alpha) + 1);
+    } else if (alpha < 0) {
+      // -a'*(256 i - 4) + c > 0  <=>  256 a' i < c + 4 a'
+      int64_t ap = -alpha;
+      int64_t num = c + kEpsQ8 * ap;
+      // i < num / (256 ap)  <=>  i <= ceil(num / (256 ap)) - 1
+      hi = imin(hi, floor_div(num - 1, 256 * ap));
+    } else if (!(c > 0)) {
+      lo = 1;
+      hi = 0;
+      return;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- level of detail
+// Eqs. 6-7: LOD = 0.5 log2(a), in units of 1/256 level, rounded to nearest:
+// round(128 log2 a) = 128 e - 128 + #{k : thr[k] <= m} for a = m 2^e with
+// m in [0.5, 1), where thr[k] is 2^((k - 127.5)/128) rounded up to a float
+// (so the comparison with the float m is exact).
+LF_HD int32_t lod_q8(const float* thr, float a) {
+  if (!(a > 0.0f)) return -(1 << 30);
+  if (__builtin_isinf(a)) return 1 << 30;
+  int e;
+  float m = frexpf(a, &e);
+  int lo = 0, hi = 128;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (thr[mid] <= m) lo = mid + 1; else hi = mid;
+  }
+  return 128 * e - 128 + lo;
+}
+
+// ---------------------------------------------------------------- textures
+LF_HD void bilinear_q16(const uint8_t* lev, int Wl, float u, float v, uint32_t out[4]) {
+  float sc = (float)(Wl * 256);
+  float tx = clamp_big(u * sc - 128.0f);
+  float ty = clamp_big(v * sc - 128.0f);
+  int32_t ix = (int32_t)floorf(tx), iy = (int32_t)floorf(ty);
+  int32_t m = Wl - 1;
+  int32_t x0 = (ix >> 8) & m, y0 = (iy >> 8) & m;
+  int32_t x1 = (x0 + 1) & m, y1 = (y0 + 1) & m;
+  uint32_t ax = (uint32_t)(ix & 255), ay = (uint32_t)(iy & 255);
+  uint32_t w00 = (256u - ax) * (256u - ay), w10 = ax * (256u - ay);
+  uint32_t w01 = (256u - ax) * ay, w11 = ax * ay;
+  const uint32_t* t = reinterpret_cast<const uint32_t*>(lev);
+  uint32_t t00 = t[(int64_t)y0 * Wl + x0], t10 = t[(int64_t)y0 * Wl + x1];
+  uint32_t t01 = t[(int64_t)y1 * Wl + x0], t11 = t[(int64_t)y1 * Wl + x1];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int sh = 8 * c;
+    out[c] = w00 * ((t00 >> sh) & 255u) + w10 * ((t10 >> sh) & 255u) + w01 * ((t01 >> sh) & 255u) +
+             w11 * ((t11 >> sh) & 255u);
+  }
+}
+
+LF_HD uint32_t trilinear(const uint8_t* pool, const TexInfo& ti, float u, float v, int32_t kc) {
+  int32_t l0 = kc >> 8, f = kc & 255;
+  int32_t l1 = l0 + 1 < ti.levels ? l0 + 1 : ti.levels - 1;
+  uint32_t c0[4], c1[4] = {0u, 0u, 0u, 0u};
+  bilinear_q16(pool + ti.off[l0], ti.size >> l0, u, v, c0);
+  if (l1 != l0 && f != 0) bilinear_q16(pool + ti.off[l1], ti.size >> l1, u, v, c1);
+  uint32_t r = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    uint32_t acc = (uint32_t)(256 - f) * c0[c] + (uint32_t)f * c1[c];
+    r |= ((acc + (1u << 23)) >> 24) << (8 * c);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------- splat colour
+// Eqs. 8-9 for point (i, j) of the triangle in a view with plane distance delta.
+LF_HD uint32_t splat_colour(const Rig& rg, const TriRec& t, float delta, int32_t i, int32_t j, uint32_t tvmin,
+                            uint32_t tvmax) {
+  float cs = (float)i / t.sx, ct = (float)j / t.sy;
+  float Zc = (t.p0z + cs * t.uz) + ct * t.wz;
+  float ad = fabsf(delta);
+  float Ar = ((Zc * Zc) * Zc) / (rg.fxfy * ad);
+  float Acell = 1.0f / (t.sx * t.sy);
+  float ar = Acell / Ar;
+  float suv = Acell * t.ruv;
+  float vse = ar < 1.0f ? suv / ar : suv;
+  float vs = vse < t.smin ? t.smin : (vse > t.smax ? t.smax : vse);
+  float tau = t.smax > t.smin ? (vs - t.smin) / (t.smax - t.smin) : 0.0f;
+  int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
+  tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
+  uint32_t r = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    uint32_t a = (tvmin >> (8 * c)) & 255u, z = (tvmax >> (8 * c)) & 255u;
+    r |= ((a * (uint32_t)(256 - tq) + z * (uint32_t)tq + 128u) >> 8) << (8 * c);
+  }
+  return r;
+}
+
+}  // namespace lfdpr

@@ -1,0 +1,79 @@
+// Internal interface between the C ABI and the kernels (not exported).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lfdpr_device.h"
+
+namespace lfdpr {
+
+enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_SLOTS = 8 };
+
+struct SetupArgs {
+  const float* pos;
+  const float* uv;
+  const uint32_t* idx;
+  const uint16_t* tex;
+  int32_t nt;
+  Model model;
+  Rig rig;
+  const TexInfo* texinfo;
+  const float* lod_thr;  // 128 mantissa thresholds
+  uint32_t* counts;
+  TriRec* rec;
+  TriEmit* em;
+  float* dbgf;     // optional nt*8
+  int32_t* dbgi;   // optional nt*8
+  uint64_t* stats;
+};
+
+struct EmitArgs {
+  int32_t nt;
+  const uint32_t* counts;
+  const uint64_t* offsets;
+  const TriEmit* em;
+  const TexInfo* texinfo;
+  const uint8_t* texels;
+  Point* points;
+  int64_t cap;
+};
+
+struct SplatArgs {
+  Rig rig;
+  const Point* points;
+  const uint64_t* n_points;  // device count (total emitted)
+  int64_t cap;
+  const TriRec* rec;
+  uint64_t* keys;            // n_views * H * W
+};
+
+struct InterleaveArgs {
+  const uint32_t* views;
+  int32_t V, Wv, Hv, Wp, Hp, mode;
+  uint32_t K1, Ky, K0;
+  int64_t du[8];
+  int32_t dx[8], dy[8];
+  uint8_t* panel;
+};
+
+struct AngularArgs {
+  const uint32_t* sub;
+  uint32_t* out;
+  int32_t V, W, H, maxe;
+  const int32_t* cnt;
+  const int32_t* src;
+  const uint32_t* wt;
+};
+
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st);
+void launch_tri_setup(const SetupArgs& a, hipStream_t s);
+void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
+                 hipStream_t s);
+void launch_emit(const EmitArgs& a, hipStream_t s);
+void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
+void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s);
+void launch_interleave(const InterleaveArgs& a, hipStream_t s);
+void launch_angular_filter(const AngularArgs& a, hipStream_t s);
+
+}  // namespace lfdpr

@@ -1,0 +1,601 @@
+// HIP kernels of the LFDPR hot path for gfx950 (wave64).
+//
+//   k_tri_setup   one lane per triangle: frame transform, visibility in every
+//                 LFD view, T_align frame, LFD-biased H/V densities, Eqs. 1-7,
+//                 lattice snap and cell count                (Sec. 3, 3.1, 3.3)
+//   k_scan_*      wave64 prefix sum of the counts -> point offsets
+//   k_emit        one lane per triangle: cells in deterministic order, UV,
+//                 two trilinear mip fetches per point         (Sec. 3.3)
+//   k_splat_*     one lane per (point, view): splat box, inside-triangle
+//                 test, cell ownership, Eqs. 8-9, 64-bit atomicMin of
+//                 (depth, colour)                             (Sec. 3.2, 3.3, 5.1)
+//   k_resolve     keys -> RGBA8 (+ depth), keys re-cleared for the next frame
+//   k_interleave  one lane per panel pixel: tilted-lens phase, view and pixel
+//                 index, optional 8-tap Gaussian reconstruction (Sec. 4)
+//   k_angular_filter  sub-views -> views (angular supersampling, Sec. 4)
+#include "lfdpr_device.h"
+#include "lfdpr_internal.h"
+
+namespace lfdpr {
+
+// ------------------------------------------------------------------ utilities
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_build_mip(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int s) {
+  int h = s >> 1;
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)h * h) return;
+  int y = (int)(k / h), x = (int)(k % h);
+  uint32_t a = src[(int64_t)(2 * y) * s + 2 * x], b = src[(int64_t)(2 * y) * s + 2 * x + 1];
+  uint32_t c = src[(int64_t)(2 * y + 1) * s + 2 * x], d = src[(int64_t)(2 * y + 1) * s + 2 * x + 1];
+  uint32_t r = 0;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) {
+    int sh = 8 * ch;
+    uint32_t m = (((a >> sh) & 255u) + ((b >> sh) & 255u) + ((c >> sh) & 255u) + ((d >> sh) & 255u) + 2u) >> 2;
+    r |= m << sh;
+  }
+  dst[k] = r;
+}
+
+// wave64 inclusive scan of one uint64 per lane
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ a1/a2: triangle setup
+
+__global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t act_cnt = 0, ovf_cnt = 0, pv_cnt = 0;
+  if (t < a.nt) {
+    uint32_t cnt = 0;
+    if (a.dbgf) {
+      for (int k = 0; k < 8; ++k) { a.dbgf[t * 8 + k] = 0.0f; a.dbgi[t * 8 + k] = 0; }
+    }
+    const Rig& rg = a.rig;
+    const float* m = a.model.m;
+    float P[3][3];
+    bool ok = true;
+    uint32_t vi[3];
+    for (int k = 0; k < 3; ++k) {
+      vi[k] = a.idx[(int64_t)t * 3 + k];
+      float px = a.pos[(int64_t)vi[k] * 3], py = a.pos[(int64_t)vi[k] * 3 + 1], pz = a.pos[(int64_t)vi[k] * 3 + 2];
+      P[k][0] = ((m[0] * px + m[1] * py) + m[2] * pz) + m[3];
+      P[k][1] = ((m[4] * px + m[5] * py) + m[6] * pz) + m[7];
+      P[k][2] = ((m[8] * px + m[9] * py) + m[10] * pz) + m[11];
+      if (!(P[k][2] >= rg.znear)) ok = false;
+    }
+    F3 P0{P[0][0], P[0][1], P[0][2]}, P1{P[1][0], P[1][1], P[1][2]}, P2{P[2][0], P[2][1], P[2][2]};
+    F3 e1 = sub3(P1, P0), e2 = sub3(P2, P0);
+    F3 n{e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x};
+    float nl = sqrtf((n.x * n.x + n.y * n.y) + n.z * n.z);
+    if (ok && (!(nl > 0.0f) || isinf(nl))) ok = false;
+    TriRec R;
+    if (ok) {
+      R.nx = n.x / nl; R.ny = n.y / nl; R.nz = n.z / nl;
+      R.p0x = P0.x; R.p0y = P0.y; R.p0z = P0.z;
+      R.h = (R.nx * P0.x + R.ny * P0.y) + R.nz * P0.z;
+      vertex_proj(rg, P0.x, P0.y, P0.z, R.a0, R.c0, R.y0);
+      vertex_proj(rg, P1.x, P1.y, P1.z, R.a1, R.c1, R.y1);
+      vertex_proj(rg, P2.x, P2.y, P2.z, R.a2, R.c2, R.y2);
+    }
+    // visibility in each view + LFD-biased densities over the active views
+    int nact = 0;
+    float lxmin = INFINITY, lymin = INFINITY, Amin = INFINITY, admin = INFINITY, admax = 0.0f;
+    if (ok) {
+      for (int r = 0; r < rg.n_views; ++r) {
+        float b = rg.eye[r];
+        int32_t qx[3], qy[3];
+        if (!view_active(rg, R, b, qx, qy)) continue;
+        ++nact;
+        F3 e{b, 0.0f, 0.0f};
+        F3 Ps = nearest_on_triangle(e, P0, P1, P2);
+        F3 d = sub3(Ps, e);
+        float delta = R.h - R.nx * b;
+        float ad = fabsf(delta);
+        float Zs = Ps.z;
+        float g = R.nx / delta;
+        float vx = 1.0f - d.x * g, vy = 0.0f - d.y * g, vz = 0.0f - d.z * g;
+        float lx = (Zs / rg.fx) * sqrtf((vx * vx + vy * vy) + vz * vz);
+        float g2 = R.ny / delta;
+        float wx = 0.0f - d.x * g2, wy = 1.0f - d.y * g2, wz = 0.0f - d.z * g2;
+        float ly = (Zs / rg.fy) * sqrtf((wx * wx + wy * wy) + wz * wz);
+        float A = ((Zs * Zs) * Zs) / (rg.fxfy * ad);
+        lxmin = lx < lxmin ? lx : lxmin;
+        lymin = ly < lymin ? ly : lymin;
+        Amin = A < Amin ? A : Amin;
+        admin = ad < admin ? ad : admin;
+        admax = ad > admax ? ad : admax;
+      }
+    }
+    if (ok && nact > 0) {
+      act_cnt = 1;
+      // T_align: s axis = camera X projected into the plane, t axis = n x s
+      float upx, upy, upz;
+      if (fabsf(R.nx) > 0.99999f) {
+        upx = 0.0f - R.nx * R.ny; upy = 1.0f - R.ny * R.ny; upz = 0.0f - R.nz * R.ny;
+      } else {
+        upx = 1.0f - R.nx * R.nx; upy = 0.0f - R.ny * R.nx; upz = 0.0f - R.nz * R.nx;
+      }
+      float ul = sqrtf((upx * upx + upy * upy) + upz * upz);
+      R.ux = upx / ul; R.uy = upy / ul; R.uz = upz / ul;
+      R.wx = R.ny * R.uz - R.nz * R.uy;
+      R.wy = R.nz * R.ux - R.nx * R.uz;
+      R.wz = R.nx * R.uy - R.ny * R.ux;
+      float Sx = 1.0f / lxmin, Sy = 1.0f / lymin;
+      float size_xy = Amin;
+      // texture-based sampling, Eqs. 1-3
+      const int tex = a.tex[t];
+      const TexInfo& ti = a.texinfo[tex];
+      float uv0u = a.uv[(int64_t)vi[0] * 2], uv0v = a.uv[(int64_t)vi[0] * 2 + 1];
+      float du1 = a.uv[(int64_t)vi[1] * 2] - uv0u, dv1 = a.uv[(int64_t)vi[1] * 2 + 1] - uv0v;
+      float du2 = a.uv[(int64_t)vi[2] * 2] - uv0u, dv2 = a.uv[(int64_t)vi[2] * 2 + 1] - uv0v;
+      float Ats = 0.5f * fabsf(du1 * dv2 - dv1 * du2);
+      float Aws = 0.5f * nl;
+      float Xt = (float)ti.size;
+      float ntex = (Ats * Xt) * Xt;
+      if (ntex > 0.0f) {
+        float size_uv = Aws / ntex;
+        if (size_uv > size_xy) {
+          float f = sqrtf(size_xy / size_uv);
+          Sx = Sx * f;
+          Sy = Sy * f;
+        }
+      }
+      R.sx = Sx; R.sy = Sy;
+      R.ruv = Ats / Aws;
+      // multiview-mip setup, Eqs. 4-7
+      float Zmin = P0.z, Zmax = P0.z;
+      Zmin = P1.z < Zmin ? P1.z : Zmin; Zmax = P1.z > Zmax ? P1.z : Zmax;
+      Zmin = P2.z < Zmin ? P2.z : Zmin; Zmax = P2.z > Zmax ? P2.z : Zmax;
+      R.smin = (((Zmin * Zmin) * Zmin) / (rg.fxfy * admax)) * R.ruv;
+      R.smax = (((Zmax * Zmax) * Zmax) / (rg.fxfy * admin)) * R.ruv;
+      R.pad = 0.0f;
+      int32_t kmin = 0, kmax = 0;
+      if (rg.mip) {
+        int32_t top = 256 * (ti.levels - 1);
+        kmin = lod_q8(a.lod_thr, (R.smin * Xt) * Xt);
+        kmax = lod_q8(a.lod_thr, (R.smax * Xt) * Xt);
+        kmin = kmin < 0 ? 0 : (kmin > top ? top : kmin);
+        kmax = kmax < 0 ? 0 : (kmax > top ? top : kmax);
+      }
+      // sample lattice, vertex 0 at the centre of cell (0,0)
+      bool ovf = false;
+      int32_t sq[3] = {128, 0, 0}, tq[3] = {128, 0, 0};
+      F3 ek[2] = {e1, e2};
+      F3 uh{R.ux, R.uy, R.uz}, wh{R.wx, R.wy, R.wz};
+      for (int k = 0; k < 2; ++k) {
+        float s = Sx * dot3(uh, ek[k]) + 0.5f;
+        float tt = Sy * dot3(wh, ek[k]) + 0.5f;
+        if (!(fabsf(s) < 16384.0f) || !(fabsf(tt) < 16384.0f)) { ovf = true; break; }
+        sq[k + 1] = (int32_t)rintf(s * 256.0f);
+        tq[k + 1] = (int32_t)rintf(tt * 256.0f);
+      }
+      if (a.dbgf) {
+        float* df = a.dbgf + t * 8;
+        int32_t* di = a.dbgi + t * 8;
+        df[0] = Sx; df[1] = Sy; df[2] = R.smin; df[3] = R.smax; df[4] = R.ruv; df[5] = R.h;
+        df[6] = size_xy; df[7] = (float)nact;
+        if (!ovf) { di[0] = sq[1]; di[1] = tq[1]; di[2] = sq[2]; di[3] = tq[2]; }
+        di[4] = kmin; di[5] = kmax; di[6] = 1;
+      }
+      int64_t count = 0;
+      Lattice L;
+      if (!ovf && lattice_init(L, sq[1], tq[1], sq[2], tq[2])) {
+        int64_t nb = (L.iB - L.iA + 1) * (L.jB - L.jA + 1);
+        if (nb > kBoxCap) {
+          ovf = true;
+        } else {
+          for (int64_t j = L.jA; j <= L.jB; ++j) {
+            int64_t lo, hi;
+            lattice_row(L, j, lo, hi);
+            if (hi >= lo) count += hi - lo + 1;
+          }
+          if (count > kCellCap) ovf = true;
+        }
+      }
+      if (ovf) {
+        count = 0;
+        ovf_cnt = 1;
+        if (a.dbgi) a.dbgi[t * 8 + 7] = 1;
+      }
+      cnt = (uint32_t)count;
+      pv_cnt = (uint64_t)count * (uint64_t)nact;
+      if (cnt > 0) {
+        a.rec[t] = R;
+        TriEmit E;
+        E.uv0u = uv0u; E.uv0v = uv0v; E.du1 = du1; E.dv1 = dv1; E.du2 = du2; E.dv2 = dv2;
+        E.s1 = sq[1]; E.t1 = tq[1]; E.s2 = sq[2]; E.t2 = tq[2];
+        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.pad0 = E.pad1 = E.pad2 = 0;
+        a.em[t] = E;
+      }
+    }
+    a.counts[t] = cnt;
+  }
+  // per-wave statistics, one atomic per wave
+  act_cnt = wave_sum(act_cnt);
+  ovf_cnt = wave_sum(ovf_cnt);
+  pv_cnt = wave_sum(pv_cnt);
+  if ((threadIdx.x & 63) == 0) {
+    if (act_cnt) atomicAdd((unsigned long long*)&a.stats[STAT_ACTIVE], (unsigned long long)act_cnt);
+    if (ovf_cnt) atomicAdd((unsigned long long*)&a.stats[STAT_OVERFLOW], (unsigned long long)ovf_cnt);
+    if (pv_cnt) atomicAdd((unsigned long long*)&a.stats[STAT_POINT_VIEWS], (unsigned long long)pv_cnt);
+  }
+}
+
+// ------------------------------------------------------------------ scan (counts -> offsets)
+// Three passes over 1024-element tiles: tile sums, one-block scan of the tile
+// sums (also writes the grand total), tile-local scans plus the tile base.
+
+constexpr int kScanTile = 1024;  // 256 lanes x 4 items
+
+__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
+                                                      uint64_t* __restrict__ tile_sum) {
+  __shared__ uint64_t ws[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s += base + k < n ? cnt[base + k] : 0u;
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(uint64_t* __restrict__ tile_sum, int64_t ntiles,
+                                                    uint64_t* __restrict__ total) {
+  __shared__ uint64_t ws[16];
+  __shared__ uint64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < ntiles; b0 += 1024) {
+    int64_t i = b0 + threadIdx.x;
+    uint64_t v = i < ntiles ? tile_sum[i] : 0;
+    uint64_t inc = wave_incl_scan(v);
+    if ((threadIdx.x & 63) == 63) ws[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    uint64_t wbase = 0;
+    for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += ws[w];
+    uint64_t excl = carry + wbase + inc - v;
+    __syncthreads();
+    if (i < ntiles) tile_sum[i] = excl;
+    if (threadIdx.x == 1023) carry = excl + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ cnt, int64_t n,
+                                                     const uint64_t* __restrict__ tile_base,
+                                                     uint64_t* __restrict__ off) {
+  __shared__ uint64_t ws[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+  uint64_t v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) { v[k] = base + k < n ? cnt[base + k] : 0u; s += v[k]; }
+  uint64_t inc = wave_incl_scan(s);
+  if ((threadIdx.x & 63) == 63) ws[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint64_t wbase = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += ws[w];
+  uint64_t run = tile_base[blockIdx.x] + wbase + inc - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) off[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ------------------------------------------------------------------ a1/a2: emission
+
+__global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.nt) return;
+  uint32_t cnt = a.counts[t];
+  if (cnt == 0) return;
+  const TriEmit E = a.em[t];
+  const TexInfo& ti = a.texinfo[E.tex];
+  uint64_t base = a.offsets[t];
+  Lattice L;
+  lattice_init(L, E.s1, E.t1, E.s2, E.t2);
+  int64_t jlo = L.jB + 1, jhi = L.jA - 1;
+  for (int64_t j = L.jA; j <= L.jB; ++j) {
+    int64_t lo, hi;
+    lattice_row(L, j, lo, hi);
+    if (hi >= lo) {
+      if (jlo > L.jB) jlo = j;
+      jhi = j;
+    }
+  }
+  const int64_t area2 = (L.S[1] - L.S[0]) * (L.T[2] - L.T[0]) - (L.T[1] - L.T[0]) * (L.S[2] - L.S[0]);
+  const double darea = (double)area2;
+  uint64_t k = 0;
+  for (int64_t j = jlo; j <= jhi; ++j) {
+    int64_t lo, hi;
+    lattice_row(L, j, lo, hi);
+    for (int64_t i = lo; i <= hi; ++i, ++k) {
+      uint64_t gi = base + k;
+      if (gi >= (uint64_t)a.cap) continue;
+      uint32_t f = 0;
+      if (i == lo) f |= F_ILO;
+      if (i == hi) f |= F_IHI;
+      if (j == jlo) f |= F_JLO;
+      if (j == jhi) f |= F_JHI;
+      int64_t cxq = 256 * i + 128, cyq = 256 * j + 128;
+      int64_t w1 = (cxq - L.S[0]) * (L.T[2] - L.T[0]) - (cyq - L.T[0]) * (L.S[2] - L.S[0]);
+      int64_t w2 = (L.S[1] - L.S[0]) * (cyq - L.T[0]) - (L.T[1] - L.T[0]) * (cxq - L.S[0]);
+      float b1 = (float)((double)w1 / darea);
+      float b2 = (float)((double)w2 / darea);
+      float u = (E.uv0u + b1 * E.du1) + b2 * E.du2;
+      float v = (E.uv0v + b1 * E.dv1) + b2 * E.dv2;
+      Point p;
+      p.tri_flags = (uint32_t)t | (f << 28);
+      p.ij = (uint32_t)(uint16_t)(int16_t)i | ((uint32_t)(uint16_t)(int16_t)j << 16);
+      p.tvmin = trilinear(a.texels, ti, u, v, E.kmin);
+      p.tvmax = E.kmax == E.kmin ? p.tvmin : trilinear(a.texels, ti, u, v, E.kmax);
+      a.points[gi] = p;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ a3: splat
+
+struct SplatSetup {
+  int32_t bx0, bx1, by0, by1;
+  int32_t qx[3], qy[3];
+  float b, ks, delta;
+  uint32_t col;
+};
+
+// Per (point, view) set-up: visibility, triangle pixel range, splat box, colour.
+// Returns false when the point writes nothing in this view.
+__device__ __forceinline__ bool splat_setup(const Rig& rg, const TriRec& T, int r, int32_t i, int32_t j,
+                                            uint32_t flags, uint32_t tvmin, uint32_t tvmax, SplatSetup& S) {
+  S.b = rg.eye[r];
+  if (!view_active(rg, T, S.b, S.qx, S.qy)) return false;
+  int64_t a2 = (int64_t)(S.qx[1] - S.qx[0]) * (S.qy[2] - S.qy[0]) - (int64_t)(S.qy[1] - S.qy[0]) * (S.qx[2] - S.qx[0]);
+  if (a2 == 0) return false;
+  if (a2 < 0) {
+    int32_t tx = S.qx[1]; S.qx[1] = S.qx[2]; S.qx[2] = tx;
+    int32_t ty = S.qy[1]; S.qy[1] = S.qy[2]; S.qy[2] = ty;
+  }
+  int64_t xmin = imin(S.qx[0], imin(S.qx[1], S.qx[2])), xmax = imax(S.qx[0], imax(S.qx[1], S.qx[2]));
+  int64_t ymin = imin(S.qy[0], imin(S.qy[1], S.qy[2])), ymax = imax(S.qy[0], imax(S.qy[1], S.qy[2]));
+  int64_t X0 = imax(0, -floor_div(-(xmin - 128), 256)), X1 = imin(rg.W - 1, floor_div(xmax - 128, 256));
+  int64_t Y0 = imax(0, -floor_div(-(ymin - 128), 256)), Y1 = imin(rg.H - 1, floor_div(ymax - 128, 256));
+  if (X0 > X1 || Y0 > Y1) return false;
+  // splat box: the (row-end extended) cell projected into this view
+  int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
+  int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
+  int32_t bx0 = (int32_t)X0, bx1 = (int32_t)X1, by0 = (int32_t)Y0, by1 = (int32_t)Y1;
+  float xmn = 0.0f, xmx = 0.0f, ymn = 0.0f, ymx = 0.0f;
+  bool full = false;
+  const float zlim = 0.5f * rg.znear;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float a = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
+    float c = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
+    float X = (T.p0x + a * T.ux) + c * T.wx;
+    float Y = (T.p0y + a * T.uy) + c * T.wy;
+    float Z = (T.p0z + a * T.uz) + c * T.wz;
+    if (!(Z >= zlim)) { full = true; break; }
+    float A, C, Yp;
+    vertex_proj(rg, X, Y, Z, A, C, Yp);
+    float x = A - S.b * C;
+    if (k == 0) { xmn = xmx = x; ymn = ymx = Yp; }
+    else {
+      xmn = x < xmn ? x : xmn; xmx = x > xmx ? x : xmx;
+      ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx;
+    }
+  }
+  if (!full) {
+    int32_t c0 = (int32_t)ceilf(clamp_big(xmn - 0.515625f)), c1 = (int32_t)floorf(clamp_big(xmx - 0.484375f));
+    int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
+    bx0 = c0 > bx0 ? c0 : bx0; bx1 = c1 < bx1 ? c1 : bx1;
+    by0 = r0 > by0 ? r0 : by0; by1 = r1 < by1 ? r1 : by1;
+  }
+  if (bx0 > bx1 || by0 > by1) return false;
+  S.bx0 = bx0; S.bx1 = bx1; S.by0 = by0; S.by1 = by1;
+  S.ks = rg.kshift[r];
+  S.delta = T.h - T.nx * S.b;
+  S.col = splat_colour(rg, T, S.delta, i, j, tvmin, tvmax);
+  return true;
+}
+
+// Inside-triangle test (Q8 edge functions, tie ownership) + ray-plane depth and
+// cell ownership for pixel (x, y).  Returns the key, or ~0 when not written.
+__device__ __forceinline__ uint64_t splat_pixel(const Rig& rg, const TriRec& T, const SplatSetup& S, int32_t i,
+                                                int32_t j, uint32_t flags, int32_t x, int32_t y) {
+  int64_t pxq = 256 * (int64_t)x + 128, pyq = 256 * (int64_t)y + 128;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    int a = e, b = e == 2 ? 0 : e + 1;
+    int64_t dx = S.qx[b] - S.qx[a], dy = S.qy[b] - S.qy[a];
+    int64_t E = dx * (pyq - S.qy[a]) - dy * (pxq - S.qx[a]);
+    bool owns = dy > 0 || (dy == 0 && dx > 0);
+    if (!(E > 0 || (E == 0 && owns))) return ~0ull;
+  }
+  float fxp = (float)x + 0.5f, fyp = (float)y + 0.5f;
+  float rx = (fxp - rg.cx) / rg.fx - S.ks;
+  float ry = (fyp - rg.cy) / rg.fy;
+  float den = (T.nx * rx + T.ny * ry) + T.nz;
+  float Z = S.delta / den;
+  if (!(Z > 0.0f) || isinf(Z)) return ~0ull;
+  float hx = (S.b + Z * rx) - T.p0x;
+  float hy = Z * ry - T.p0y;
+  float hz = Z - T.p0z;
+  float s = T.sx * ((T.ux * hx + T.uy * hy) + T.uz * hz) + 0.5f;
+  float t = T.sy * ((T.wx * hx + T.wy * hy) + T.wz * hz) + 0.5f;
+  int32_t fi = (int32_t)floorf(clamp_big(s)), fj = (int32_t)floorf(clamp_big(t));
+  bool rowok = fj == j || ((flags & F_JLO) && fj < j) || ((flags & F_JHI) && fj > j);
+  bool colok = fi == i || ((flags & F_ILO) && fi < i) || ((flags & F_IHI) && fi > i);
+  if (!(rowok && colok)) return ~0ull;
+  return ((uint64_t)__float_as_uint(Z) << 32) | S.col;
+}
+
+// One lane per (point, view); keys in HBM, 64-bit atomicMin at L2.
+__global__ void __launch_bounds__(256) k_splat_global(SplatArgs a) {
+  const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
+  const uint64_t nv = (uint64_t)a.rig.n_views;
+  const uint64_t total = npts * nv;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const int64_t vpx = (int64_t)a.rig.W * a.rig.H;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    uint64_t p = g / nv;
+    int r = (int)(g - p * nv);
+    const Point pt = a.points[p];
+    const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
+    const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
+    const TriRec T = a.rec[tri];
+    SplatSetup S;
+    if (!splat_setup(a.rig, T, r, i, j, flags, pt.tvmin, pt.tvmax, S)) continue;
+    uint64_t* kv = a.keys + (int64_t)r * vpx;
+    for (int32_t y = S.by0; y <= S.by1; ++y)
+      for (int32_t x = S.bx0; x <= S.bx1; ++x) {
+        uint64_t key = splat_pixel(a.rig, T, S, i, j, flags, x, y);
+        if (key != ~0ull) atomicMin((unsigned long long*)&kv[(int64_t)y * a.rig.W + x], (unsigned long long)key);
+      }
+  }
+}
+
+__global__ void k_resolve(uint64_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ rgba,
+                          float* __restrict__ depth) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    uint64_t k = keys[i];
+    bool empty = k == ~0ull;
+    rgba[i] = empty ? 0u : (uint32_t)k;
+    if (depth) depth[i] = empty ? __uint_as_float(0x7f800000u) : __uint_as_float((uint32_t)(k >> 32));
+    keys[i] = ~0ull;
+  }
+}
+
+// ------------------------------------------------------------------ a4: interleave + reconstruction
+
+__global__ void __launch_bounds__(256) k_interleave(InterleaveArgs a) {
+  int64_t X = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t Y = blockIdx.y;
+  if (X >= a.Wp) return;
+  int64_t xq = ((2 * X + 1) * (int64_t)a.Wv * 128) / a.Wp;
+  int64_t yq = ((2 * Y + 1) * (int64_t)a.Hv * 128) / a.Hp;
+  uint8_t out[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uint32_t phi = (uint32_t)(3 * X + c) * a.K1 + (uint32_t)Y * a.Ky + a.K0;
+    uint64_t U = (uint64_t)phi * (uint64_t)a.V;
+    uint32_t val;
+    if (a.mode == 0) {
+      int64_t v = (int64_t)(U >> 32);
+      val = (a.views[(v * a.Hv + (yq >> 8)) * a.Wv + (xq >> 8)] >> (8 * c)) & 255u;
+    } else {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int64_t v = ((int64_t)U + a.du[k]) >> 32;
+        int64_t x = (xq + a.dx[k]) >> 8, y = (yq + a.dy[k]) >> 8;
+        v = v < 0 ? 0 : (v > a.V - 1 ? a.V - 1 : v);
+        x = x < 0 ? 0 : (x > a.Wv - 1 ? a.Wv - 1 : x);
+        y = y < 0 ? 0 : (y > a.Hv - 1 ? a.Hv - 1 : y);
+        sum += (a.views[(v * a.Hv + y) * a.Wv + x] >> (8 * c)) & 255u;
+      }
+      val = (sum + 4u) >> 3;
+    }
+    out[c] = (uint8_t)val;
+  }
+  uint8_t* dst = a.panel + (Y * a.Wp + X) * 3;
+  dst[0] = out[0]; dst[1] = out[1]; dst[2] = out[2];
+}
+
+__global__ void __launch_bounds__(256) k_angular_filter(AngularArgs a) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = blockIdx.y;
+  int64_t npx = (int64_t)a.W * a.H;
+  if (p >= npx) return;
+  int n = a.cnt[v];
+  uint64_t acc[4] = {0, 0, 0, 0}, ws = 0;
+  for (int e = 0; e < n; ++e) {
+    uint64_t w = a.wt[v * a.maxe + e];
+    uint32_t c = a.sub[(int64_t)a.src[v * a.maxe + e] * npx + p];
+    ws += w;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) acc[ch] += w * ((c >> (8 * ch)) & 255u);
+  }
+  uint32_t o = 0;
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch) o |= (uint32_t)((acc[ch] + ws / 2) / ws) << (8 * ch);
+  a.out[(int64_t)v * npx + p] = o;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = (unsigned)imin(nblk(n, 256), 256 * 64);
+  k_fill_u64<<<g, 256, 0, s>>>(p, n, v);
+}
+
+void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st) {
+  int64_t n = (int64_t)(s >> 1) * (s >> 1);
+  k_build_mip<<<nblk(n, 256), 256, 0, st>>>(src, dst, s);
+}
+
+void launch_tri_setup(const SetupArgs& a, hipStream_t s) {
+  if (a.nt <= 0) return;
+  k_tri_setup<<<nblk(a.nt, 256), 256, 0, s>>>(a);
+}
+
+void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
+                 hipStream_t s) {
+  int64_t ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles == 0) ntiles = 1;
+  k_scan_reduce<<<(unsigned)ntiles, 256, 0, s>>>(cnt, n, tile_scratch);
+  k_scan_top<<<1, 1024, 0, s>>>(tile_scratch, ntiles, total);
+  k_scan_apply<<<(unsigned)ntiles, 256, 0, s>>>(cnt, n, tile_scratch, off);
+}
+
+void launch_emit(const EmitArgs& a, hipStream_t s) {
+  if (a.nt <= 0) return;
+  k_emit<<<nblk(a.nt, 256), 256, 0, s>>>(a);
+}
+
+void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
+  k_splat_global<<<grid_blocks, 256, 0, s>>>(a);
+}
+
+void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s) {
+  unsigned g = (unsigned)imin(nblk(n, 256), 256 * 64);
+  k_resolve<<<g, 256, 0, s>>>(keys, n, rgba, depth);
+}
+
+void launch_interleave(const InterleaveArgs& a, hipStream_t s) {
+  dim3 g(nblk(a.Wp, 256), (unsigned)a.Hp);
+  k_interleave<<<g, 256, 0, s>>>(a);
+}
+
+void launch_angular_filter(const AngularArgs& a, hipStream_t s) {
+  dim3 g(nblk((int64_t)a.W * a.H, 256), (unsigned)a.V);
+  k_angular_filter<<<g, 256, 0, s>>>(a);
+}
+
+}  // namespace lfdpr

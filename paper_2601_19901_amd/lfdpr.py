@@ -1,0 +1,260 @@
+"""Thin ctypes binding of liblfdpr.so (include/lfdpr.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels.  torch supplies device memory (``data_ptr()``) and the stream.
+Raises if the library is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblfdpr.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "lfdpr.h")
+
+LFDPR_OK, LFDPR_EINVAL, LFDPR_ENOMEM, LFDPR_EOVERFLOW, LFDPR_EDEVICE, LFDPR_ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class LfdprError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lfdpr error {code}: {msg}")
+        self.code = code
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("n_verts", C.c_int32), ("n_tris", C.c_int32), ("pos", C.c_void_p), ("uv", C.c_void_p),
+                ("idx", C.c_void_p), ("tex_id", C.c_void_p), ("n_tex", C.c_int32), ("tex_size", C.c_void_p),
+                ("tex_rgba8", C.c_void_p)]
+
+
+class ViewParams(C.Structure):
+    _fields_ = [("V", C.c_int32), ("S", C.c_int32), ("W", C.c_int32), ("H", C.c_int32),
+                ("fovy_deg", C.c_float), ("aspect", C.c_float), ("D", C.c_float), ("cone_deg", C.c_float),
+                ("znear", C.c_float), ("jitter", C.c_void_p), ("mip", C.c_int32), ("point_capacity", C.c_int64)]
+
+
+class LensParams(C.Structure):
+    _fields_ = [("Wp", C.c_int32), ("Hp", C.c_int32), ("pitch_subpx", C.c_double), ("slope", C.c_double),
+                ("offset", C.c_double), ("mode", C.c_int32), ("taps", (C.c_int64 * 3) * 8)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("points", C.c_int64), ("active_tris", C.c_int64), ("point_views", C.c_int64),
+                ("overflow_tris", C.c_int64), ("capacity", C.c_int64), ("point_overflow", C.c_int32),
+                ("n_views", C.c_int32)]
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Function names declared in include/lfdpr.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lfdpr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER
+    sig = {
+        "lfdpr_abi_version": ([], C.c_int),
+        "lfdpr_strerror": ([C.c_int], C.c_char_p),
+        "lfdpr_create": ([C.c_int, vp, p(vp)], C.c_int),
+        "lfdpr_destroy": ([vp], C.c_int),
+        "lfdpr_last_error": ([vp], C.c_char_p),
+        "lfdpr_scene_upload": ([vp, p(SceneDesc), p(i32)], C.c_int),
+        "lfdpr_scene_free": ([vp, i32], C.c_int),
+        "lfdpr_set_views": ([vp, p(ViewParams)], C.c_int),
+        "lfdpr_set_lens": ([vp, p(LensParams)], C.c_int),
+        "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
+        "lfdpr_reconstruct": ([vp, vp, i32, i32, i32, vp], C.c_int),
+        "lfdpr_angular_filter": ([vp, vp, vp], C.c_int),
+        "lfdpr_get_stats": ([vp, p(Stats)], C.c_int),
+        "lfdpr_copy_points": ([vp, vp, i64, p(i64)], C.c_int),
+        "lfdpr_copy_counts": ([vp, vp, i64], C.c_int),
+        "lfdpr_set_debug_records": ([vp, vp, vp, i64], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    if isinstance(t, np.ndarray):
+        assert t.flags["C_CONTIGUOUS"]
+        return t.ctypes.data
+    assert t.is_contiguous(), "tensor must be contiguous"
+    return t.data_ptr()
+
+
+def _check_dev(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{name}: need contiguous {dtype} with >= {numel} elements")
+
+
+class Renderer:
+    """One library context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        self._check(lib().lfdpr_create(device, C.c_void_p(self.stream.cuda_stream), C.byref(h)), ctx=None)
+        self.h = h
+        self.vp = None
+        self.lens = None
+        self._keep = {}
+
+    def _check(self, rc: int, ctx="self"):
+        if rc != LFDPR_OK:
+            msg = lib().lfdpr_strerror(rc).decode()
+            if ctx == "self" and getattr(self, "h", None):
+                last = lib().lfdpr_last_error(self.h)
+                msg += ": " + (last.decode() if last else "")
+            raise LfdprError(rc, msg)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lfdpr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- scene ---------------------------------------------------------------
+    def upload_scene(self, scene) -> int:
+        pos = np.ascontiguousarray(scene.pos, np.float32)
+        uv = np.ascontiguousarray(scene.uv, np.float32)
+        idx = np.ascontiguousarray(scene.idx, np.uint32)
+        tex = np.ascontiguousarray(scene.tex, np.uint16)
+        texs = [np.ascontiguousarray(t, np.uint8) for t in scene.textures]
+        sizes = np.array([t.shape[0] for t in texs], np.int32)
+        ptrs = (C.c_void_p * len(texs))(*[t.ctypes.data for t in texs])
+        d = SceneDesc(pos.shape[0], idx.shape[0], _ptr(pos), _ptr(uv), _ptr(idx) if idx.size else None,
+                      _ptr(tex) if tex.size else None, len(texs), _ptr(sizes), C.cast(ptrs, C.c_void_p))
+        sid = C.c_int32()
+        self._check(lib().lfdpr_scene_upload(self.h, C.byref(d), C.byref(sid)))
+        return sid.value
+
+    def free_scene(self, sid: int):
+        self._check(lib().lfdpr_scene_free(self.h, sid))
+
+    # -- parameters ----------------------------------------------------------
+    def set_views(self, vp, point_capacity: int = 0):
+        jit = None
+        if vp.S > 1:
+            jit = np.ascontiguousarray(vp.jitter, np.float32)
+        p = ViewParams(vp.V, vp.S, vp.W, vp.H, vp.fovy_deg, vp.aspect, vp.D, vp.cone_deg, vp.znear,
+                       _ptr(jit) if jit is not None else None, int(vp.mip), int(point_capacity))
+        self._check(lib().lfdpr_set_views(self.h, C.byref(p)))
+        self.vp = vp
+
+    def set_lens(self, lp, mode: Optional[int] = None):
+        p = LensParams()
+        p.Wp, p.Hp = lp.Wp, lp.Hp
+        p.pitch_subpx, p.slope, p.offset = float(lp.pitch_subpx), float(lp.slope), float(lp.offset)
+        p.mode = int(lp.mode if mode is None else mode)
+        if lp.taps is not None:
+            for k in range(8):
+                for c in range(3):
+                    p.taps[k][c] = int(lp.taps[k][c])
+        self._check(lib().lfdpr_set_lens(self.h, C.byref(p)))
+        self.lens = lp
+
+    # -- per frame -----------------------------------------------------------
+    @property
+    def n_views(self) -> int:
+        return self.vp.V * self.vp.S
+
+    def alloc_views(self, with_depth: bool = False):
+        torch = self._torch
+        n = self.n_views * self.vp.H * self.vp.W
+        v = torch.empty((self.n_views, self.vp.H, self.vp.W), dtype=torch.int32, device=f"cuda:{self.device}")
+        d = torch.empty_like(v, dtype=torch.float32) if with_depth else None
+        assert v.numel() == n
+        return v, d
+
+    def render_frame(self, sid: int, model: np.ndarray, views, depth=None):
+        torch = self._torch
+        if self.vp is not None:  # without a rig the library itself reports LFDPR_ESTATE
+            n = self.n_views * self.vp.H * self.vp.W
+            _check_dev(views, torch.int32, n, "views")
+            if depth is not None:
+                _check_dev(depth, torch.float32, n, "depth")
+        m = np.ascontiguousarray(model, np.float32).reshape(12)
+        self._check(lib().lfdpr_render_frame(self.h, sid, _ptr(m), _ptr(views), _ptr(depth) if depth is not None else None))
+
+    def reconstruct(self, views, panel, n_views: Optional[int] = None, W: Optional[int] = None,
+                    H: Optional[int] = None):
+        torch = self._torch
+        V = n_views if n_views is not None else views.shape[0]
+        Hh = H if H is not None else views.shape[1]
+        Ww = W if W is not None else views.shape[2]
+        _check_dev(views, torch.int32, V * Hh * Ww, "views")
+        _check_dev(panel, torch.uint8, self.lens.Wp * self.lens.Hp * 3, "panel")
+        self._check(lib().lfdpr_reconstruct(self.h, _ptr(views), V, Ww, Hh, _ptr(panel)))
+
+    def angular_filter(self, sub_views, out):
+        torch = self._torch
+        _check_dev(sub_views, torch.int32, self.n_views * self.vp.H * self.vp.W, "sub_views")
+        _check_dev(out, torch.int32, self.vp.V * self.vp.H * self.vp.W, "out")
+        self._check(lib().lfdpr_angular_filter(self.h, _ptr(sub_views), _ptr(out)))
+
+    def stats(self, allow_overflow: bool = False) -> dict:
+        s = Stats()
+        rc = lib().lfdpr_get_stats(self.h, C.byref(s))
+        if rc != LFDPR_OK and not (allow_overflow and rc == LFDPR_EOVERFLOW):
+            self._check(rc)
+        return {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+
+    def points(self) -> dict:
+        """The last frame's point buffer, unpacked into numpy arrays."""
+        torch = self._torch
+        s = self.stats(allow_overflow=True)
+        n = min(s["points"], s["capacity"])
+        buf = torch.empty((max(n, 1), 4), dtype=torch.int32, device=f"cuda:{self.device}")
+        got = C.c_int64()
+        self._check(lib().lfdpr_copy_points(self.h, _ptr(buf), n, C.byref(got)))
+        a = buf[:n].cpu().numpy().view(np.uint32)
+        tri = a[:, 0] & 0x0FFFFFFF
+        return dict(tri=tri, flags=(a[:, 0] >> 28).astype(np.uint8), i=(a[:, 1] & 0xFFFF).astype(np.uint16).view(np.int16),
+                    j=(a[:, 1] >> 16).astype(np.uint16).view(np.int16), tvmin=a[:, 2].copy(), tvmax=a[:, 3].copy(),
+                    n=int(got.value))
+
+    def counts(self, nt: int) -> np.ndarray:
+        torch = self._torch
+        buf = torch.empty(max(nt, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().lfdpr_copy_counts(self.h, _ptr(buf), nt))
+        return buf[:nt].cpu().numpy().view(np.uint32)
+
+    def set_debug_records(self, f=None, i=None):
+        n = 0
+        if f is not None:
+            n = min(f.numel(), i.numel()) // 8
+        self._check(lib().lfdpr_set_debug_records(self.h, _ptr(f) if f is not None else None,
+                                                  _ptr(i) if i is not None else None, n))
