@@ -179,6 +179,17 @@ int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n);
  * i = {lattice s1, t1, s2, t2 (Q8), LOD_min, LOD_max (1/256), active, overflow}. */
 int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* dst_f, int32_t* dst_i, int64_t n_tris);
 
+/* Stage timing with HIP events recorded on the context's stream.
+ * lfdpr_timing(ctx, 1) clears and starts recording; every following
+ * render_frame / reconstruct / angular_filter records one event pair per
+ * stage.  lfdpr_get_timings() synchronises the stream and writes, per stage,
+ * the summed milliseconds and the number of recorded launches (host arrays of
+ * LFDPR_N_STAGES); stages: 0 triangle set-up, 1 scan, 2 emission, 3 splat,
+ * 4 resolve, 5 interleave, 6 angular filter.  lfdpr_timing(ctx, 0) stops. */
+#define LFDPR_N_STAGES 7
+int lfdpr_timing(lfdpr_ctx* ctx, int enable);
+int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n_launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,11 @@ struct lfdpr_ctx {
   int64_t dbg_cap = 0;
   // launch shape of the splat kernel
   int splat_blocks = 4096;
+  // stage timing: event pairs recorded on the stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
 };
 
 namespace {
@@ -122,6 +127,23 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   }
   ctx->tri_cap = n;
   return LFDPR_OK;
+}
+
+// Event recorded on the stream when timing is on (nullptr otherwise).
+hipEvent_t mark(lfdpr_ctx* ctx) {
+  if (!ctx->timing) return nullptr;
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->ev_pool.push_back(e);
+  }
+  hipEvent_t e = ctx->ev_pool[ctx->ev_used++];
+  hipEventRecord(e, ctx->stream);
+  return e;
+}
+
+void stage(lfdpr_ctx* ctx, int id, hipEvent_t a, hipEvent_t b) {
+  if (a && b) ctx->ev_marks.push_back({id, {a, b}});
 }
 
 }  // namespace
@@ -193,6 +215,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_em);
   dfree(ctx->d_tiles);
   dfree(ctx->d_stats);
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   delete ctx;
   return LFDPR_OK;
 }
@@ -413,8 +436,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   sa.dbgf = ctx->dbgf;
   sa.dbgi = ctx->dbgi;
   sa.stats = ctx->d_stats;
+  hipEvent_t e0 = mark(ctx);
   launch_tri_setup(sa, st);
+  hipEvent_t e1 = mark(ctx);
   launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, st);
+  hipEvent_t e2 = mark(ctx);
   EmitArgs ea{};
   ea.nt = s.nt;
   ea.counts = ctx->d_counts;
@@ -425,6 +451,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   ea.points = ctx->d_points;
   ea.cap = ctx->cap;
   launch_emit(ea, st);
+  hipEvent_t e3 = mark(ctx);
   SplatArgs pa{};
   pa.rig = ctx->rig;
   pa.points = ctx->d_points;
@@ -433,8 +460,15 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   pa.rec = ctx->d_rec;
   pa.keys = ctx->d_keys;
   launch_splat(pa, ctx->splat_blocks, st);
+  hipEvent_t e4 = mark(ctx);
   launch_resolve(ctx->d_keys, ctx->n_keys, views, depth, st);
+  hipEvent_t e5 = mark(ctx);
   HIPOK(hipGetLastError());
+  stage(ctx, 0, e0, e1);
+  stage(ctx, 1, e1, e2);
+  stage(ctx, 2, e2, e3);
+  stage(ctx, 3, e3, e4);
+  stage(ctx, 4, e4, e5);
   ctx->last_nt = s.nt;
   return LFDPR_OK;
 }
@@ -465,8 +499,11 @@ int lfdpr_reconstruct(lfdpr_ctx* ctx, const uint32_t* views, int32_t n_views, in
   }
   a.panel = panel;
   HIPOK(hipSetDevice(ctx->device));
+  hipEvent_t e0 = mark(ctx);
   launch_interleave(a, ctx->stream);
+  hipEvent_t e1 = mark(ctx);
   HIPOK(hipGetLastError());
+  stage(ctx, 5, e0, e1);
   return LFDPR_OK;
 }
 
@@ -484,8 +521,11 @@ int lfdpr_angular_filter(lfdpr_ctx* ctx, const uint32_t* sub, uint32_t* out) {
   a.src = ctx->d_asrc;
   a.wt = ctx->d_awt;
   HIPOK(hipSetDevice(ctx->device));
+  hipEvent_t e0 = mark(ctx);
   launch_angular_filter(a, ctx->stream);
+  hipEvent_t e1 = mark(ctx);
   HIPOK(hipGetLastError());
+  stage(ctx, 6, e0, e1);
   return LFDPR_OK;
 }
 
@@ -525,6 +565,28 @@ int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n) {
   HIPOK(hipSetDevice(ctx->device));
   HIPOK(hipStreamSynchronize(ctx->stream));
   if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_counts, (size_t)n * 4, hipMemcpyDeviceToDevice));
+  return LFDPR_OK;
+}
+
+int lfdpr_timing(lfdpr_ctx* ctx, int enable) {
+  if (!ctx) return LFDPR_EINVAL;
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  ctx->timing = enable != 0;
+  ctx->ev_used = 0;
+  ctx->ev_marks.clear();
+  return LFDPR_OK;
+}
+
+int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n) {
+  if (!ctx || !ms_sum || !n) return fail(ctx, LFDPR_EINVAL, "null argument");
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < LFDPR_N_STAGES; ++k) { ms_sum[k] = 0.0; n[k] = 0; }
+  for (auto& m : ctx->ev_marks) {
+    float ms = 0.0f;
+    HIPOK(hipEventElapsedTime(&ms, m.second.first, m.second.second));
+    ms_sum[m.first] += ms;
+    n[m.first] += 1;
+  }
   return LFDPR_OK;
 }
 

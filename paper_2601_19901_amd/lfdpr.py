@@ -84,6 +84,8 @@ def lib():
         "lfdpr_copy_points": ([vp, vp, i64, p(i64)], C.c_int),
         "lfdpr_copy_counts": ([vp, vp, i64], C.c_int),
         "lfdpr_set_debug_records": ([vp, vp, vp, i64], C.c_int),
+        "lfdpr_timing": ([vp, C.c_int], C.c_int),
+        "lfdpr_get_timings": ([vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -251,6 +253,18 @@ class Renderer:
         buf = torch.empty(max(nt, 1), dtype=torch.int32, device=f"cuda:{self.device}")
         self._check(lib().lfdpr_copy_counts(self.h, _ptr(buf), nt))
         return buf[:nt].cpu().numpy().view(np.uint32)
+
+    STAGES = ("setup", "scan", "emit", "splat", "resolve", "interleave", "angular_filter")
+
+    def timing(self, enable: bool):
+        self._check(lib().lfdpr_timing(self.h, int(enable)))
+
+    def timings(self) -> dict:
+        """Per stage: (summed ms, launches) recorded since timing(True)."""
+        ms = np.zeros(len(self.STAGES), np.float64)
+        n = np.zeros(len(self.STAGES), np.int64)
+        self._check(lib().lfdpr_get_timings(self.h, _ptr(ms), _ptr(n)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.STAGES)}
 
     def set_debug_records(self, f=None, i=None):
         n = 0
