@@ -78,7 +78,7 @@ typedef struct {
  * q = v + (k + 0.5 + jitter[v*S+k]) / S.  Pixels are `aspect` times wider than
  * tall (the LFD anisotropy of Sec. 3.1). */
 typedef struct {
-  int32_t V, S, W, H;          /* V*S in [1, 256]; W, H in [1, 8192] */
+  int32_t V, S, W, H;          /* V*S in [1, 256]; W, H in [1, 4096] */
   float fovy_deg, aspect, D, cone_deg, znear;
   const float* jitter;         /* host, V*S values in [-0.5, 0.5); may be NULL when S == 1 */
   int32_t mip;                 /* multiview mipmapping (Sec. 3.3) on (1) or off (0) */

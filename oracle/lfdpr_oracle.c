@@ -285,13 +285,13 @@ static uint32_t splat_colour(const tri_state *ts, const orc_frame *fr, float b, 
     float Zc = (ts->P[0].z + cs * ts->u.z) + ct * ts->w.z;
     float delta = ts->h - ts->nh.x * b;
     float ad = fabsf(delta);
-    float Ar = ((Zc * Zc) * Zc) / (fxfy * ad);
-    float Acell = 1.0f / (ts->Sx * ts->Sy);
-    float ar = Acell / Ar;                 /* splat size in view pixels */
-    float suv = Acell * ts->ruv;           /* splat area in texture space */
-    float vse = ar < 1.0f ? suv / ar : suv;            /* Eq. 8, first line */
+    float Ar = ((Zc * Zc) * Zc) / (fxfy * ad);   /* pixel footprint at the cell centre */
+    float Acell = 1.0f / (ts->Sx * ts->Sy);      /* splat (cell) area */
+    /* Eq. 8: the splat's texture area suv = Acell*ruv, divided by min(1, Acell/Ar) */
+    float vse = Acell < Ar ? ts->ruv * Ar : Acell * ts->ruv;
     float vs = vse < ts->smin ? ts->smin : (vse > ts->smax ? ts->smax : vse); /* clamp */
-    float tau = ts->smax > ts->smin ? (vs - ts->smin) / (ts->smax - ts->smin) : 0.0f; /* Eq. 9 */
+    float irange = ts->smax > ts->smin ? 1.0f / (ts->smax - ts->smin) : 0.0f;
+    float tau = (vs - ts->smin) * irange;          /* Eq. 9 */
     int tq = (int)floorf(tau * 256.0f + 0.5f);
     if (tq < 0) tq = 0;
     if (tq > 256) tq = 256;
@@ -585,6 +585,8 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
             int64_t Y0 = imax64(0, -floordiv64(-(ymin - 128), 256)), Y1 = imin64(fr->H - 1, floordiv64(ymax - 128, 256));
             float ks = fr->kshift[r];
             float delta = ts.h - ts.nh.x * b;
+            float cu = ts.u.x * (b - ts.P[0].x) - (ts.u.y * ts.P[0].y + ts.u.z * ts.P[0].z);
+            float cw = ts.w.x * (b - ts.P[0].x) - (ts.w.y * ts.P[0].y + ts.w.z * ts.P[0].z);
             for (int64_t y = Y0; y <= Y1; ++y)
                 for (int64_t x = X0; x <= X1; ++x) {
                     int64_t pxq = 256 * x + 128, pyq = 256 * y + 128;
@@ -605,11 +607,11 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
                     float den = (ts.nh.x * rx + ts.nh.y * ry) + ts.nh.z;
                     float Z = delta / den;
                     if (!(Z > 0.0f) || isinf(Z)) { out->stats[4] += 1; continue; }
-                    float hx = (b + Z * rx) - ts.P[0].x;
-                    float hy = Z * ry - ts.P[0].y;
-                    float hz = Z - ts.P[0].z;
-                    float s = ts.Sx * ((ts.u.x * hx + ts.u.y * hy) + ts.u.z * hz) + 0.5f;
-                    float tt = ts.Sy * ((ts.w.x * hx + ts.w.y * hy) + ts.w.z * hz) + 0.5f;
+                    /* hit - P0 = (b - P0x, -P0y, -P0z) + Z*(rx, ry, 1), projected on the lattice axes */
+                    float ur = (ts.u.x * rx + ts.u.y * ry) + ts.u.z;
+                    float wr = (ts.w.x * rx + ts.w.y * ry) + ts.w.z;
+                    float s = ts.Sx * (Z * ur + cu) + 0.5f;
+                    float tt = ts.Sy * (Z * wr + cw) + 0.5f;
                     if (ts.count == 0) { out->stats[3] += 1; continue; }
                     int fi = (int)floorf(clampf_big(s)), fj = (int)floorf(clampf_big(tt));
                     int cj = fj < ts.jlo ? ts.jlo : (fj > ts.jhi ? ts.jhi : fj);

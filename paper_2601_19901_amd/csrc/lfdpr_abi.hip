@@ -64,6 +64,7 @@ struct lfdpr_ctx {
   TriRec* d_rec = nullptr;
   TriEmit* d_em = nullptr;
   uint64_t* d_tiles = nullptr;
+  uint32_t* d_big = nullptr;
   uint64_t* d_stats = nullptr;
   int64_t last_nt = 0;
   // lens
@@ -119,9 +120,10 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   dfree(ctx->d_rec);
   dfree(ctx->d_em);
   dfree(ctx->d_tiles);
+  dfree(ctx->d_big);
   if (dalloc(ctx->d_counts, n) != hipSuccess || dalloc(ctx->d_offsets, n) != hipSuccess ||
       dalloc(ctx->d_rec, n) != hipSuccess || dalloc(ctx->d_em, n) != hipSuccess ||
-      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess) {
+      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess || dalloc(ctx->d_big, n) != hipSuccess) {
     ctx->tri_cap = 0;
     return fail(ctx, LFDPR_ENOMEM, "per-triangle buffers");
   }
@@ -214,6 +216,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_rec);
   dfree(ctx->d_em);
   dfree(ctx->d_tiles);
+  dfree(ctx->d_big);
   dfree(ctx->d_stats);
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   delete ctx;
@@ -293,7 +296,7 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
 int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   if (!ctx || !v) return fail(ctx, LFDPR_EINVAL, "null argument");
   int64_t nviews = (int64_t)v->V * v->S;
-  if (v->V < 1 || v->S < 1 || nviews > 256 || v->W < 1 || v->H < 1 || v->W > 8192 || v->H > 8192 ||
+  if (v->V < 1 || v->S < 1 || nviews > 256 || v->W < 1 || v->H < 1 || v->W > 4096 || v->H > 4096 ||
       !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) || !(v->aspect > 0.0f) || !(v->D > 0.0f) ||
       !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f) || !(v->znear > 0.0f) || (v->S > 1 && !v->jitter) ||
       v->point_capacity < 0 || v->point_capacity > (1ll << 31))
@@ -449,8 +452,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   ea.texinfo = s.texinfo;
   ea.texels = s.texels;
   ea.points = ctx->d_points;
+  ea.n_points = ctx->d_stats + STAT_TOTAL;
+  ea.big = ctx->d_big;
+  ea.n_big = ctx->d_stats + STAT_BIG;
   ea.cap = ctx->cap;
-  launch_emit(ea, st);
+  launch_emit(ea, ctx->splat_blocks, st);
   hipEvent_t e3 = mark(ctx);
   SplatArgs pa{};
   pa.rig = ctx->rig;

@@ -14,11 +14,12 @@ namespace lfdpr {
 
 constexpr uint32_t F_ILO = 1u, F_IHI = 2u, F_JLO = 4u, F_JHI = 8u;
 constexpr int kCellCap = 65536;          // cells per triangle before overflow
+constexpr uint32_t kBigCells = 96;       // triangles with more cells are emitted by a whole workgroup
 constexpr int64_t kBoxCap = 1ll << 22;   // lattice bounding-box cells before overflow
 constexpr int64_t kEpsQ8 = 4;            // cell dilation, 4/256 of a cell
 constexpr float kGuard = 32768.0f;       // screen guard band, pixels
 
-// Per-triangle record read by the splat kernel (112 B, 7 x float4).
+// Per-triangle record read by the splat kernel (128 B, 8 x float4).
 struct alignas(16) TriRec {
   float p0x, p0y, p0z, h;      // camera-space vertex 0; plane offset n.P0
   float nx, ny, nz, sx;        // unit normal; horizontal sampling density
@@ -26,7 +27,8 @@ struct alignas(16) TriRec {
   float wx, wy, wz, ruv;       // lattice t axis; texture/world area ratio
   float a0, c0, y0, smin;      // projected vertex 0 (x = a - b*c), Eqs. 4-5 minimum
   float a1, c1, y1, smax;      // projected vertex 1, Eqs. 4-5 maximum
-  float a2, c2, y2, pad;       // projected vertex 2
+  float a2, c2, y2, irange;    // projected vertex 2; 1/(smax - smin) (0 when equal)
+  float cu0, cw0, pad0, pad1;  // u.P0 and w.P0 without their x terms
 };
 
 // Per-triangle emission data (64 B).
@@ -245,31 +247,6 @@ LF_HD uint32_t trilinear(const uint8_t* pool, const TexInfo& ti, float u, float 
   for (int c = 0; c < 4; ++c) {
     uint32_t acc = (uint32_t)(256 - f) * c0[c] + (uint32_t)f * c1[c];
     r |= ((acc + (1u << 23)) >> 24) << (8 * c);
-  }
-  return r;
-}
-
-// ---------------------------------------------------------------- splat colour
-// Eqs. 8-9 for point (i, j) of the triangle in a view with plane distance delta.
-LF_HD uint32_t splat_colour(const Rig& rg, const TriRec& t, float delta, int32_t i, int32_t j, uint32_t tvmin,
-                            uint32_t tvmax) {
-  float cs = (float)i / t.sx, ct = (float)j / t.sy;
-  float Zc = (t.p0z + cs * t.uz) + ct * t.wz;
-  float ad = fabsf(delta);
-  float Ar = ((Zc * Zc) * Zc) / (rg.fxfy * ad);
-  float Acell = 1.0f / (t.sx * t.sy);
-  float ar = Acell / Ar;
-  float suv = Acell * t.ruv;
-  float vse = ar < 1.0f ? suv / ar : suv;
-  float vs = vse < t.smin ? t.smin : (vse > t.smax ? t.smax : vse);
-  float tau = t.smax > t.smin ? (vs - t.smin) / (t.smax - t.smin) : 0.0f;
-  int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
-  tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
-  uint32_t r = 0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    uint32_t a = (tvmin >> (8 * c)) & 255u, z = (tvmax >> (8 * c)) & 255u;
-    r |= ((a * (uint32_t)(256 - tq) + z * (uint32_t)tq + 128u) >> 8) << (8 * c);
   }
   return r;
 }

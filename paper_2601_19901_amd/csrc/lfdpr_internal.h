@@ -7,7 +7,7 @@
 
 namespace lfdpr {
 
-enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_SLOTS = 8 };
+enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_BIG = 4, STAT_SLOTS = 8 };
 
 struct SetupArgs {
   const float* pos;
@@ -29,12 +29,15 @@ struct SetupArgs {
 
 struct EmitArgs {
   int32_t nt;
+  uint32_t* big;             // triangles emitted cooperatively (capacity nt)
+  uint64_t* n_big;
   const uint32_t* counts;
   const uint64_t* offsets;
   const TriEmit* em;
   const TexInfo* texinfo;
   const uint8_t* texels;
   Point* points;
+  const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
 };
 
@@ -70,7 +73,7 @@ void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st)
 void launch_tri_setup(const SetupArgs& a, hipStream_t s);
 void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
                  hipStream_t s);
-void launch_emit(const EmitArgs& a, hipStream_t s);
+void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s);
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
 void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s);
 void launch_interleave(const InterleaveArgs& a, hipStream_t s);

@@ -4,11 +4,13 @@
 //                 LFD view, T_align frame, LFD-biased H/V densities, Eqs. 1-7,
 //                 lattice snap and cell count                (Sec. 3, 3.1, 3.3)
 //   k_scan_*      wave64 prefix sum of the counts -> point offsets
-//   k_emit        one lane per triangle: cells in deterministic order, UV,
-//                 two trilinear mip fetches per point         (Sec. 3.3)
-//   k_splat_*     one lane per (point, view): splat box, inside-triangle
-//                 test, cell ownership, Eqs. 8-9, 64-bit atomicMin of
-//                 (depth, colour)                             (Sec. 3.2, 3.3, 5.1)
+//   k_emit        one lane per triangle: its cells in deterministic order;
+//   k_emit_big    triangles with many cells: one workgroup each, rows over lanes
+//   k_fetch       one lane per point: UV at the cell centre, two trilinear
+//                 mip fetches (tv_min, tv_max)                (Sec. 3.3)
+//   k_splat       one lane per point, looping over the views: splat box,
+//                 inside-triangle test, cell ownership, Eqs. 8-9, 64-bit
+//                 atomicMin of (depth, colour)                (Sec. 3.2, 3.3, 5.1)
 //   k_resolve     keys -> RGBA8 (+ depth), keys re-cleared for the next frame
 //   k_interleave  one lane per panel pixel: tilted-lens phase, view and pixel
 //                 index, optional 8-tap Gaussian reconstruction (Sec. 4)
@@ -168,7 +170,10 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       Zmin = P2.z < Zmin ? P2.z : Zmin; Zmax = P2.z > Zmax ? P2.z : Zmax;
       R.smin = (((Zmin * Zmin) * Zmin) / (rg.fxfy * admax)) * R.ruv;
       R.smax = (((Zmax * Zmax) * Zmax) / (rg.fxfy * admin)) * R.ruv;
-      R.pad = 0.0f;
+      R.irange = R.smax > R.smin ? 1.0f / (R.smax - R.smin) : 0.0f;
+      R.cu0 = R.uy * P0.y + R.uz * P0.z;
+      R.cw0 = R.wy * P0.y + R.wz * P0.z;
+      R.pad0 = R.pad1 = 0.0f;
       int32_t kmin = 0, kmax = 0;
       if (rg.mip) {
         int32_t top = 256 * (ti.levels - 1);
@@ -306,13 +311,26 @@ __global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__
 
 // ------------------------------------------------------------------ a1/a2: emission
 
+__device__ __forceinline__ void write_head(Point* pts, uint64_t gi, uint32_t t, uint32_t f, int64_t i, int64_t j) {
+  uint2 head;
+  head.x = t | (f << 28);
+  head.y = (uint32_t)(uint16_t)(int16_t)i | ((uint32_t)(uint16_t)(int16_t)j << 16);
+  *reinterpret_cast<uint2*>(&pts[gi]) = head;
+}
+
+// One lane per triangle; triangles with more than kBigCells cells are queued
+// for k_emit_big instead.
 __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.nt) return;
   uint32_t cnt = a.counts[t];
   if (cnt == 0) return;
-  const TriEmit E = a.em[t];
-  const TexInfo& ti = a.texinfo[E.tex];
+  if (cnt > kBigCells) {
+    uint64_t slot = atomicAdd((unsigned long long*)a.n_big, 1ull);
+    a.big[slot] = (uint32_t)t;
+    return;
+  }
+  const TriEmit& E = a.em[t];
   uint64_t base = a.offsets[t];
   Lattice L;
   lattice_init(L, E.s1, E.t1, E.s2, E.t2);
@@ -325,154 +343,259 @@ __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
       jhi = j;
     }
   }
-  const int64_t area2 = (L.S[1] - L.S[0]) * (L.T[2] - L.T[0]) - (L.T[1] - L.T[0]) * (L.S[2] - L.S[0]);
-  const double darea = (double)area2;
   uint64_t k = 0;
   for (int64_t j = jlo; j <= jhi; ++j) {
     int64_t lo, hi;
     lattice_row(L, j, lo, hi);
+    uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
     for (int64_t i = lo; i <= hi; ++i, ++k) {
       uint64_t gi = base + k;
-      if (gi >= (uint64_t)a.cap) continue;
-      uint32_t f = 0;
-      if (i == lo) f |= F_ILO;
-      if (i == hi) f |= F_IHI;
-      if (j == jlo) f |= F_JLO;
-      if (j == jhi) f |= F_JHI;
-      int64_t cxq = 256 * i + 128, cyq = 256 * j + 128;
-      int64_t w1 = (cxq - L.S[0]) * (L.T[2] - L.T[0]) - (cyq - L.T[0]) * (L.S[2] - L.S[0]);
-      int64_t w2 = (L.S[1] - L.S[0]) * (cyq - L.T[0]) - (L.T[1] - L.T[0]) * (cxq - L.S[0]);
-      float b1 = (float)((double)w1 / darea);
-      float b2 = (float)((double)w2 / darea);
-      float u = (E.uv0u + b1 * E.du1) + b2 * E.du2;
-      float v = (E.uv0v + b1 * E.dv1) + b2 * E.dv2;
-      Point p;
-      p.tri_flags = (uint32_t)t | (f << 28);
-      p.ij = (uint32_t)(uint16_t)(int16_t)i | ((uint32_t)(uint16_t)(int16_t)j << 16);
-      p.tvmin = trilinear(a.texels, ti, u, v, E.kmin);
-      p.tvmax = E.kmax == E.kmin ? p.tvmin : trilinear(a.texels, ti, u, v, E.kmax);
-      a.points[gi] = p;
+      if (gi >= (uint64_t)a.cap) return;
+      write_head(a.points, gi, (uint32_t)t, fj | (i == lo ? F_ILO : 0u) | (i == hi ? F_IHI : 0u), i, j);
     }
+  }
+}
+
+// One workgroup per queued triangle: lanes take rows, a block scan places them.
+__global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
+  __shared__ uint64_t wsum[4];
+  __shared__ int64_t row_lo_hi[2];
+  const uint64_t nbig = *a.n_big;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (uint64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+    const uint32_t t = a.big[b];
+    const TriEmit& E = a.em[t];
+    const uint64_t base = a.offsets[t];
+    Lattice L;
+    lattice_init(L, E.s1, E.t1, E.s2, E.t2);
+    if (threadIdx.x == 0) { row_lo_hi[0] = L.jB + 1; row_lo_hi[1] = L.jA - 1; }
+    __syncthreads();
+    for (int64_t j = L.jA + threadIdx.x; j <= L.jB; j += blockDim.x) {
+      int64_t lo, hi;
+      lattice_row(L, j, lo, hi);
+      if (hi >= lo) {
+        atomicMin((long long*)&row_lo_hi[0], (long long)j);
+        atomicMax((long long*)&row_lo_hi[1], (long long)j);
+      }
+    }
+    __syncthreads();
+    const int64_t jlo = row_lo_hi[0], jhi = row_lo_hi[1];
+    uint64_t run = 0;
+    for (int64_t j0 = jlo; j0 <= jhi; j0 += blockDim.x) {
+      const int64_t j = j0 + threadIdx.x;
+      int64_t lo = 1, hi = 0;
+      if (j <= jhi) lattice_row(L, j, lo, hi);
+      const uint64_t c = hi >= lo ? (uint64_t)(hi - lo + 1) : 0;
+      uint64_t inc = wave_incl_scan(c);
+      if (lane == 63) wsum[wv] = inc;
+      __syncthreads();
+      uint64_t before = 0, total = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (w < wv) before += wsum[w];
+        total += wsum[w];
+      }
+      const uint64_t start = base + run + before + inc - c;
+      const uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
+      for (int64_t i = lo; i <= hi; ++i) {
+        uint64_t gi = start + (uint64_t)(i - lo);
+        if (gi < (uint64_t)a.cap)
+          write_head(a.points, gi, t, fj | (i == lo ? F_ILO : 0u) | (i == hi ? F_IHI : 0u), i, j);
+      }
+      run += total;
+      __syncthreads();
+    }
+    __syncthreads();  // row bounds are rewritten for the next triangle
+  }
+}
+
+// Per point: UV at the cell centre and the two mip fetches (Eqs. 6-7).
+__global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
+  const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
+    uint2 head = *reinterpret_cast<const uint2*>(&a.points[p]);
+    const uint32_t t = head.x & 0x0FFFFFFFu;
+    const int64_t i = (int16_t)(head.y & 0xFFFFu), j = (int16_t)(head.y >> 16);
+    const TriEmit& E = a.em[t];
+    const int64_t S1 = E.s1, T1 = E.t1, S2 = E.s2, T2 = E.t2;
+    const int64_t area2 = (S1 - 128) * (T2 - 128) - (T1 - 128) * (S2 - 128);
+    int64_t cxq = 256 * i + 128, cyq = 256 * j + 128;
+    int64_t w1 = (cxq - 128) * (T2 - 128) - (cyq - 128) * (S2 - 128);
+    int64_t w2 = (S1 - 128) * (cyq - 128) - (T1 - 128) * (cxq - 128);
+    float b1 = (float)((double)w1 / (double)area2);
+    float b2 = (float)((double)w2 / (double)area2);
+    float u = (E.uv0u + b1 * E.du1) + b2 * E.du2;
+    float v = (E.uv0v + b1 * E.dv1) + b2 * E.dv2;
+    const TexInfo& ti = a.texinfo[E.tex];
+    uint2 tv;
+    tv.x = trilinear(a.texels, ti, u, v, E.kmin);
+    tv.y = E.kmax == E.kmin ? tv.x : trilinear(a.texels, ti, u, v, E.kmax);
+    *reinterpret_cast<uint2*>(&a.points[p].tvmin) = tv;
   }
 }
 
 // ------------------------------------------------------------------ a3: splat
 
-struct SplatSetup {
-  int32_t bx0, bx1, by0, by1;
-  int32_t qx[3], qy[3];
-  float b, ks, delta;
-  uint32_t col;
-};
-
-// Per (point, view) set-up: visibility, triangle pixel range, splat box, colour.
-// Returns false when the point writes nothing in this view.
-__device__ __forceinline__ bool splat_setup(const Rig& rg, const TriRec& T, int r, int32_t i, int32_t j,
-                                            uint32_t flags, uint32_t tvmin, uint32_t tvmax, SplatSetup& S) {
-  S.b = rg.eye[r];
-  if (!view_active(rg, T, S.b, S.qx, S.qy)) return false;
-  int64_t a2 = (int64_t)(S.qx[1] - S.qx[0]) * (S.qy[2] - S.qy[0]) - (int64_t)(S.qy[1] - S.qy[0]) * (S.qx[2] - S.qx[0]);
-  if (a2 == 0) return false;
-  if (a2 < 0) {
-    int32_t tx = S.qx[1]; S.qx[1] = S.qx[2]; S.qx[2] = tx;
-    int32_t ty = S.qy[1]; S.qy[1] = S.qy[2]; S.qy[2] = ty;
-  }
-  int64_t xmin = imin(S.qx[0], imin(S.qx[1], S.qx[2])), xmax = imax(S.qx[0], imax(S.qx[1], S.qx[2]));
-  int64_t ymin = imin(S.qy[0], imin(S.qy[1], S.qy[2])), ymax = imax(S.qy[0], imax(S.qy[1], S.qy[2]));
-  int64_t X0 = imax(0, -floor_div(-(xmin - 128), 256)), X1 = imin(rg.W - 1, floor_div(xmax - 128, 256));
-  int64_t Y0 = imax(0, -floor_div(-(ymin - 128), 256)), Y1 = imin(rg.H - 1, floor_div(ymax - 128, 256));
-  if (X0 > X1 || Y0 > Y1) return false;
-  // splat box: the (row-end extended) cell projected into this view
-  int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
-  int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
-  int32_t bx0 = (int32_t)X0, bx1 = (int32_t)X1, by0 = (int32_t)Y0, by1 = (int32_t)Y1;
-  float xmn = 0.0f, xmx = 0.0f, ymn = 0.0f, ymx = 0.0f;
-  bool full = false;
-  const float zlim = 0.5f * rg.znear;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    float a = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
-    float c = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
-    float X = (T.p0x + a * T.ux) + c * T.wx;
-    float Y = (T.p0y + a * T.uy) + c * T.wy;
-    float Z = (T.p0z + a * T.uz) + c * T.wz;
-    if (!(Z >= zlim)) { full = true; break; }
-    float A, C, Yp;
-    vertex_proj(rg, X, Y, Z, A, C, Yp);
-    float x = A - S.b * C;
-    if (k == 0) { xmn = xmx = x; ymn = ymx = Yp; }
-    else {
-      xmn = x < xmn ? x : xmn; xmx = x > xmx ? x : xmx;
-      ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx;
-    }
-  }
-  if (!full) {
-    int32_t c0 = (int32_t)ceilf(clamp_big(xmn - 0.515625f)), c1 = (int32_t)floorf(clamp_big(xmx - 0.484375f));
-    int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
-    bx0 = c0 > bx0 ? c0 : bx0; bx1 = c1 < bx1 ? c1 : bx1;
-    by0 = r0 > by0 ? r0 : by0; by1 = r1 < by1 ? r1 : by1;
-  }
-  if (bx0 > bx1 || by0 > by1) return false;
-  S.bx0 = bx0; S.bx1 = bx1; S.by0 = by0; S.by1 = by1;
-  S.ks = rg.kshift[r];
-  S.delta = T.h - T.nx * S.b;
-  S.col = splat_colour(rg, T, S.delta, i, j, tvmin, tvmax);
-  return true;
-}
-
-// Inside-triangle test (Q8 edge functions, tie ownership) + ray-plane depth and
-// cell ownership for pixel (x, y).  Returns the key, or ~0 when not written.
-__device__ __forceinline__ uint64_t splat_pixel(const Rig& rg, const TriRec& T, const SplatSetup& S, int32_t i,
-                                                int32_t j, uint32_t flags, int32_t x, int32_t y) {
-  int64_t pxq = 256 * (int64_t)x + 128, pyq = 256 * (int64_t)y + 128;
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    int a = e, b = e == 2 ? 0 : e + 1;
-    int64_t dx = S.qx[b] - S.qx[a], dy = S.qy[b] - S.qy[a];
-    int64_t E = dx * (pyq - S.qy[a]) - dy * (pxq - S.qx[a]);
-    bool owns = dy > 0 || (dy == 0 && dx > 0);
-    if (!(E > 0 || (E == 0 && owns))) return ~0ull;
-  }
-  float fxp = (float)x + 0.5f, fyp = (float)y + 0.5f;
-  float rx = (fxp - rg.cx) / rg.fx - S.ks;
-  float ry = (fyp - rg.cy) / rg.fy;
-  float den = (T.nx * rx + T.ny * ry) + T.nz;
-  float Z = S.delta / den;
-  if (!(Z > 0.0f) || isinf(Z)) return ~0ull;
-  float hx = (S.b + Z * rx) - T.p0x;
-  float hy = Z * ry - T.p0y;
-  float hz = Z - T.p0z;
-  float s = T.sx * ((T.ux * hx + T.uy * hy) + T.uz * hz) + 0.5f;
-  float t = T.sy * ((T.wx * hx + T.wy * hy) + T.wz * hz) + 0.5f;
-  int32_t fi = (int32_t)floorf(clamp_big(s)), fj = (int32_t)floorf(clamp_big(t));
-  bool rowok = fj == j || ((flags & F_JLO) && fj < j) || ((flags & F_JHI) && fj > j);
-  bool colok = fi == i || ((flags & F_ILO) && fi < i) || ((flags & F_IHI) && fi > i);
-  if (!(rowok && colok)) return ~0ull;
-  return ((uint64_t)__float_as_uint(Z) << 32) | S.col;
-}
-
-// One lane per (point, view); keys in HBM, 64-bit atomicMin at L2.
-__global__ void __launch_bounds__(256) k_splat_global(SplatArgs a) {
+// One lane per point, looping over the views.  Everything that does not depend
+// on the eye offset b is computed once per point: the cell's corner projections
+// (x = A - b*C is affine in b), the row range, the cell-centre depth.  Pixel
+// ray slopes (x+0.5-cx)/fx and (y+0.5-cy)/fy come from per-block LDS tables
+// holding exactly the values the inline expressions give.  The integer edge
+// functions are evaluated in double, which represents every value exactly
+// (|E| < 2^50), and stepped along x.
+__global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
+  extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
+  const Rig& rg = a.rig;
+  float* tx = ray_tab;
+  float* ty = ray_tab + rg.W;
+  for (int k = threadIdx.x; k < rg.W; k += blockDim.x) tx[k] = ((float)k + 0.5f - rg.cx) / rg.fx;
+  for (int k = threadIdx.x; k < rg.H; k += blockDim.x) ty[k] = ((float)k + 0.5f - rg.cy) / rg.fy;
+  __syncthreads();
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
-  const uint64_t nv = (uint64_t)a.rig.n_views;
-  const uint64_t total = npts * nv;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const int64_t vpx = (int64_t)a.rig.W * a.rig.H;
-  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    uint64_t p = g / nv;
-    int r = (int)(g - p * nv);
+  const int64_t vpx = (int64_t)rg.W * rg.H;
+  const float zlim = 0.5f * rg.znear;
+  const int32_t H8 = 256 * rg.H, W8 = 256 * rg.W;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
     const Point pt = a.points[p];
     const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
     const TriRec T = a.rec[tri];
-    SplatSetup S;
-    if (!splat_setup(a.rig, T, r, i, j, flags, pt.tvmin, pt.tvmax, S)) continue;
-    uint64_t* kv = a.keys + (int64_t)r * vpx;
-    for (int32_t y = S.by0; y <= S.by1; ++y)
-      for (int32_t x = S.bx0; x <= S.bx1; ++x) {
-        uint64_t key = splat_pixel(a.rig, T, S, i, j, flags, x, y);
-        if (key != ~0ull) atomicMin((unsigned long long*)&kv[(int64_t)y * a.rig.W + x], (unsigned long long)key);
+    // view-independent vertex rows (guard band on y) and triangle row range
+    if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) continue;
+    const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
+                  qy2 = (int32_t)rintf(T.y2 * 256.0f);
+    if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) continue;
+    const int32_t ymin = min(qy0, min(qy1, qy2)), ymax = max(qy0, max(qy1, qy2));
+    const int32_t Y0 = max(0, -((128 - ymin) >> 8));
+    const int32_t Y1 = min(rg.H - 1, (ymax - 128) >> 8);
+    if (Y0 > Y1) continue;
+    // splat box corners (row-end extended cell), projected except for the eye offset
+    const int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
+    const int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
+    float cA[4], cC[4];
+    float ymn = 0.0f, ymx = 0.0f;
+    bool full = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float aa = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
+      float cc = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
+      float X = (T.p0x + aa * T.ux) + cc * T.wx;
+      float Y = (T.p0y + aa * T.uy) + cc * T.wy;
+      float Z = (T.p0z + aa * T.uz) + cc * T.wz;
+      if (!(Z >= zlim)) full = true;
+      float Yp;
+      vertex_proj(rg, X, Y, Z, cA[k], cC[k], Yp);
+      if (k == 0) { ymn = ymx = Yp; }
+      else { ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx; }
+    }
+    int32_t by0 = Y0, by1 = Y1;
+    if (!full) {
+      int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
+      by0 = max(r0, by0);
+      by1 = min(r1, by1);
+    }
+    if (by0 > by1) continue;
+    // cell-centre terms of Eqs. 8-9 and the ownership bounds
+    const float cs = (float)i / T.sx, ct = (float)j / T.sy;
+    const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
+    const float Zc3 = (Zc * Zc) * Zc;
+    const float Acell = 1.0f / (T.sx * T.sy);
+    const float suv = Acell * T.ruv;
+    const float fi0 = (float)i, fi1 = (float)(i + 1), fj0 = (float)j, fj1 = (float)(j + 1);
+    const bool oilo = flags & F_ILO, oihi = flags & F_IHI, ojlo = flags & F_JLO, ojhi = flags & F_JHI;
+    const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
+    const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
+    for (int r = 0; r < rg.n_views; ++r) {
+      const float b = rg.eye[r];
+      const float delta = T.h - T.nx * b;
+      if (!(delta < 0.0f)) continue;
+      const float x0 = T.a0 - b * T.c0, x1 = T.a1 - b * T.c1, x2 = T.a2 - b * T.c2;
+      if (!(fabsf(x0) < kGuard) || !(fabsf(x1) < kGuard) || !(fabsf(x2) < kGuard)) continue;
+      int32_t qx[3] = {(int32_t)rintf(x0 * 256.0f), (int32_t)rintf(x1 * 256.0f), (int32_t)rintf(x2 * 256.0f)};
+      int32_t qy[3] = {qy0, qy1, qy2};
+      if ((qx[0] < 0 && qx[1] < 0 && qx[2] < 0) || (qx[0] > W8 && qx[1] > W8 && qx[2] > W8)) continue;
+      const double a2 = (double)(qx[1] - qx[0]) * (double)(qy[2] - qy[0]) -
+                        (double)(qy[1] - qy[0]) * (double)(qx[2] - qx[0]);
+      if (a2 == 0.0) continue;
+      if (a2 < 0.0) {
+        int32_t u = qx[1]; qx[1] = qx[2]; qx[2] = u;
+        u = qy[1]; qy[1] = qy[2]; qy[2] = u;
       }
+      const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
+      int32_t bx0 = max(0, -((128 - xmin) >> 8));
+      int32_t bx1 = min(rg.W - 1, (xmax - 128) >> 8);
+      int32_t ry0 = by0, ry1 = by1;
+      if (full) {
+        ry0 = Y0;
+        ry1 = Y1;
+      } else {
+        float xmn = cA[0] - b * cC[0], xmx = xmn;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          float xx = cA[k] - b * cC[k];
+          xmn = xx < xmn ? xx : xmn;
+          xmx = xx > xmx ? xx : xmx;
+        }
+        bx0 = max(bx0, (int32_t)ceilf(clamp_big(xmn - 0.515625f)));
+        bx1 = min(bx1, (int32_t)floorf(clamp_big(xmx - 0.484375f)));
+      }
+      if (bx0 > bx1 || ry0 > ry1) continue;
+      // colour of this point in this view (Eqs. 8-9)
+      const float ad = fabsf(delta);
+      const float Ar = Zc3 / (rg.fxfy * ad);
+      const float vse = Acell < Ar ? T.ruv * Ar : suv;
+      const float vs = vse < T.smin ? T.smin : (vse > T.smax ? T.smax : vse);
+      const float tau = (vs - T.smin) * T.irange;
+      int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
+      tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
+      const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
+      const uint32_t col = (((lo02 * wa + hi02 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
+                           ((((lo13 * wa + hi13 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8);
+      const float ks = rg.kshift[r];
+      const float cu = T.ux * (b - T.p0x) - T.cu0;
+      const float cw = T.wx * (b - T.p0x) - T.cw0;
+      // edge functions with the tie rule folded in as +0.5 (E integer: E+0.5 > 0 <=> E >= 0)
+      double edx[3], edy[3], bias[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int eb = e == 2 ? 0 : e + 1;
+        const int32_t dx = qx[eb] - qx[e], dy = qy[eb] - qy[e];
+        edx[e] = (double)dx;
+        edy[e] = (double)dy;
+        bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
+      }
+      uint64_t* kv = a.keys + (int64_t)r * vpx;
+      const int32_t pxq0 = 256 * bx0 + 128;
+      for (int32_t y = ry0; y <= ry1; ++y) {
+        const int32_t pyq = 256 * y + 128;
+        double E0 = edx[0] * (double)(pyq - qy[0]) - edy[0] * (double)(pxq0 - qx[0]) + bias[0];
+        double E1 = edx[1] * (double)(pyq - qy[1]) - edy[1] * (double)(pxq0 - qx[1]) + bias[1];
+        double E2 = edx[2] * (double)(pyq - qy[2]) - edy[2] * (double)(pxq0 - qx[2]) + bias[2];
+        const double st0 = edy[0] * 256.0, st1 = edy[1] * 256.0, st2 = edy[2] * 256.0;
+        const float ry = ty[y];
+        const float nyr = T.ny * ry, uyr = T.uy * ry, wyr = T.wy * ry;
+        for (int32_t x = bx0; x <= bx1; ++x) {
+          const bool in = E0 > 0.0 && E1 > 0.0 && E2 > 0.0;
+          E0 -= st0;
+          E1 -= st1;
+          E2 -= st2;
+          if (!in) continue;
+          const float rx = tx[x] - ks;
+          const float den = (T.nx * rx + nyr) + T.nz;
+          const float Z = delta / den;
+          if (!(Z > 0.0f) || isinf(Z)) continue;
+          const float ur = (T.ux * rx + uyr) + T.uz;
+          const float wr = (T.wx * rx + wyr) + T.wz;
+          const float sv = T.sx * (Z * ur + cu) + 0.5f;
+          const float tv = T.sy * (Z * wr + cw) + 0.5f;
+          const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
+          if (own)
+            atomicMin((unsigned long long*)&kv[(int64_t)y * rg.W + x],
+                      (unsigned long long)(((uint64_t)__float_as_uint(Z) << 32) | col));
+        }
+      }
+    }
   }
 }
 
@@ -574,13 +697,16 @@ void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_
   k_scan_apply<<<(unsigned)ntiles, 256, 0, s>>>(cnt, n, tile_scratch, off);
 }
 
-void launch_emit(const EmitArgs& a, hipStream_t s) {
+void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
   if (a.nt <= 0) return;
   k_emit<<<nblk(a.nt, 256), 256, 0, s>>>(a);
+  k_emit_big<<<1024, 256, 0, s>>>(a);
+  k_fetch<<<fetch_blocks, 256, 0, s>>>(a);
 }
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
-  k_splat_global<<<grid_blocks, 256, 0, s>>>(a);
+  size_t lds = sizeof(float) * (size_t)(a.rig.W + a.rig.H);
+  k_splat<<<grid_blocks, 256, lds, s>>>(a);
 }
 
 void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s) {
