@@ -510,6 +510,20 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
       const float b = rg.eye[r];
       const float delta = T.h - T.nx * b;
       if (!(delta < 0.0f)) continue;
+      // splat box columns first: empty for about a third of the (point, view) pairs
+      int32_t cbx0 = 0, cbx1 = rg.W - 1;
+      if (!full) {
+        float xmn = cA[0] - b * cC[0], xmx = xmn;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+          float xx = cA[k] - b * cC[k];
+          xmn = xx < xmn ? xx : xmn;
+          xmx = xx > xmx ? xx : xmx;
+        }
+        cbx0 = max(cbx0, (int32_t)ceilf(clamp_big(xmn - 0.515625f)));
+        cbx1 = min(cbx1, (int32_t)floorf(clamp_big(xmx - 0.484375f)));
+        if (cbx0 > cbx1) continue;
+      }
       const float x0 = T.a0 - b * T.c0, x1 = T.a1 - b * T.c1, x2 = T.a2 - b * T.c2;
       if (!(fabsf(x0) < kGuard) || !(fabsf(x1) < kGuard) || !(fabsf(x2) < kGuard)) continue;
       int32_t qx[3] = {(int32_t)rintf(x0 * 256.0f), (int32_t)rintf(x1 * 256.0f), (int32_t)rintf(x2 * 256.0f)};
@@ -523,23 +537,9 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
         u = qy[1]; qy[1] = qy[2]; qy[2] = u;
       }
       const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
-      int32_t bx0 = max(0, -((128 - xmin) >> 8));
-      int32_t bx1 = min(rg.W - 1, (xmax - 128) >> 8);
-      int32_t ry0 = by0, ry1 = by1;
-      if (full) {
-        ry0 = Y0;
-        ry1 = Y1;
-      } else {
-        float xmn = cA[0] - b * cC[0], xmx = xmn;
-#pragma unroll
-        for (int k = 1; k < 4; ++k) {
-          float xx = cA[k] - b * cC[k];
-          xmn = xx < xmn ? xx : xmn;
-          xmx = xx > xmx ? xx : xmx;
-        }
-        bx0 = max(bx0, (int32_t)ceilf(clamp_big(xmn - 0.515625f)));
-        bx1 = min(bx1, (int32_t)floorf(clamp_big(xmx - 0.484375f)));
-      }
+      const int32_t bx0 = max(cbx0, -((128 - xmin) >> 8));
+      const int32_t bx1 = min(cbx1, (xmax - 128) >> 8);
+      const int32_t ry0 = full ? Y0 : by0, ry1 = full ? Y1 : by1;
       if (bx0 > bx1 || ry0 > ry1) continue;
       // colour of this point in this view (Eqs. 8-9)
       const float ad = fabsf(delta);
