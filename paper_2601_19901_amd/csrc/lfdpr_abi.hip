@@ -150,6 +150,9 @@ void stage(lfdpr_ctx* ctx, int id, hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+hipStream_t ctx_stream_of(lfdpr_ctx* c) { return c->stream; }
+int ctx_device_of(lfdpr_ctx* c) { return c->device; }
+
 extern "C" {
 
 int lfdpr_abi_version(void) { return LFDPR_ABI_VERSION; }

@@ -80,3 +80,7 @@ void launch_interleave(const InterleaveArgs& a, hipStream_t s);
 void launch_angular_filter(const AngularArgs& a, hipStream_t s);
 
 }  // namespace lfdpr
+
+struct lfdpr_ctx;
+hipStream_t ctx_stream_of(lfdpr_ctx* c);
+int ctx_device_of(lfdpr_ctx* c);

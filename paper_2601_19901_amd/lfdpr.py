@@ -85,6 +85,20 @@ def lib():
         "lfdpr_copy_counts": ([vp, vp, i64], C.c_int),
         "lfdpr_set_debug_records": ([vp, vp, vp, i64], C.c_int),
         "lfdpr_timing": ([vp, C.c_int], C.c_int),
+        "lfdpr_net_create": ([vp, i32, i32, i32, p(vp)], C.c_int),
+        "lfdpr_net_destroy": ([vp], C.c_int),
+        "lfdpr_net_last_error": ([vp], C.c_char_p),
+        "lfdpr_net_param_count": ([vp, p(i64)], C.c_int),
+        "lfdpr_net_set_params": ([vp, vp, i64], C.c_int),
+        "lfdpr_net_get_params": ([vp, vp, i64], C.c_int),
+        "lfdpr_net_pack_input": ([vp, vp, vp, i32, i32, C.c_float, vp], C.c_int),
+        "lfdpr_net_forward": ([vp, vp, i32, i32, vp], C.c_int),
+        "lfdpr_net_backward": ([vp, vp, vp], C.c_int),
+        "lfdpr_net_adam_step": ([vp, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+        "lfdpr_net_unpack_output": ([vp, vp, i32, i32, vp], C.c_int),
+        "lfdpr_net_copy_state": ([vp, i32, vp, i64], C.c_int),
+        "lfdpr_net_save": ([vp, C.c_char_p], C.c_int),
+        "lfdpr_net_load": ([vp, C.c_char_p], C.c_int),
         "lfdpr_get_timings": ([vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -272,3 +286,99 @@ class Renderer:
             n = min(f.numel(), i.numel()) // 8
         self._check(lib().lfdpr_set_debug_records(self.h, _ptr(f) if f is not None else None,
                                                   _ptr(i) if i is not None else None, n))
+
+
+class Net:
+    """The learned angular reconstruction network of one Renderer context."""
+
+    def __init__(self, renderer: Renderer, V: int, max_h: int, max_w: int):
+        self.R = renderer
+        self._torch = renderer._torch
+        h = C.c_void_p()
+        rc = lib().lfdpr_net_create(renderer.h, V, max_h, max_w, C.byref(h))
+        if rc != LFDPR_OK:
+            raise LfdprError(rc, lib().lfdpr_strerror(rc).decode())
+        self.h = h
+        self.V = V
+        n = C.c_int64()
+        self._check(lib().lfdpr_net_param_count(self.h, C.byref(n)))
+        self.n_params = n.value
+        self.loss_buf = self._torch.zeros(1, dtype=self._torch.float32, device=f"cuda:{renderer.device}")
+
+    def _check(self, rc: int):
+        if rc != LFDPR_OK:
+            last = lib().lfdpr_net_last_error(self.h) if getattr(self, "h", None) else b""
+            raise LfdprError(rc, lib().lfdpr_strerror(rc).decode() + ": " + (last.decode() if last else ""))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lfdpr_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, np.float32)
+        self._check(lib().lfdpr_net_set_params(self.h, _ptr(a), a.size))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, np.float32)
+        self._check(lib().lfdpr_net_get_params(self.h, _ptr(a), a.size))
+        return a
+
+    def pack_input(self, views, depth, x, D: float):
+        torch = self._torch
+        V, H, W = views.shape
+        _check_dev(views, torch.int32, V * H * W, "views")
+        _check_dev(depth, torch.float32, V * H * W, "depth")
+        _check_dev(x, torch.int16, H * W * 4 * self.V, "x")
+        self._check(lib().lfdpr_net_pack_input(self.h, _ptr(views), _ptr(depth), H, W, float(D), _ptr(x)))
+
+    def forward(self, x, y, H: int, W: int):
+        torch = self._torch
+        _check_dev(x, torch.int16, H * W * 4 * self.V, "x")
+        _check_dev(y, torch.int16, H * W * 3 * self.V, "y")
+        self._check(lib().lfdpr_net_forward(self.h, _ptr(x), H, W, _ptr(y)))
+
+    def backward(self, target):
+        self._check(lib().lfdpr_net_backward(self.h, _ptr(target), _ptr(self.loss_buf)))
+        return self.loss_buf
+
+    def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+        self._check(lib().lfdpr_net_adam_step(self.h, lr, b1, b2, eps))
+
+    def unpack_output(self, y, views, H: int, W: int):
+        torch = self._torch
+        _check_dev(views, torch.int32, self.V * H * W, "views")
+        self._check(lib().lfdpr_net_unpack_output(self.h, _ptr(y), H, W, _ptr(views)))
+
+    def copy_state(self, which: int, dst):
+        self._check(lib().lfdpr_net_copy_state(self.h, which, _ptr(dst), dst.numel() * dst.element_size()))
+
+    def save(self, path: str):
+        self._check(lib().lfdpr_net_save(self.h, path.encode()))
+
+    def load(self, path: str):
+        self._check(lib().lfdpr_net_load(self.h, path.encode()))
+
+
+def params_to_flat(params) -> np.ndarray:
+    """[(W (9, co, ci), b (co)), ...] -> the library's flat FP32 parameter vector."""
+    return np.concatenate([np.concatenate([np.asarray(w, np.float32).ravel(), np.asarray(b, np.float32).ravel()])
+                           for w, b in params])
+
+
+def flat_to_params(flat: np.ndarray, V: int, hidden: int = 32):
+    shapes = [(4 * V, hidden), (hidden, hidden), (hidden, hidden), (hidden, 3 * V)]
+    out, o = [], 0
+    for ci, co in shapes:
+        w = flat[o:o + 9 * co * ci].reshape(9, co, ci)
+        o += 9 * co * ci
+        b = flat[o:o + co]
+        o += co
+        out.append((w, b))
+    return out
