@@ -78,7 +78,7 @@ typedef struct {
  * q = v + (k + 0.5 + jitter[v*S+k]) / S.  Pixels are `aspect` times wider than
  * tall (the LFD anisotropy of Sec. 3.1). */
 typedef struct {
-  int32_t V, S, W, H;          /* V*S in [1, 256]; W, H in [1, 4096] */
+  int32_t V, S, W, H;          /* V*S in [1, 1024]; W, H in [1, 4096] */
   float fovy_deg, aspect, D, cone_deg, znear;
   const float* jitter;         /* host, V*S values in [-0.5, 0.5); may be NULL when S == 1 */
   int32_t mip;                 /* multiview mipmapping (Sec. 3.3) on (1) or off (0) */
@@ -192,19 +192,23 @@ int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n_launches);
 
 /* ------------------------------------------------------------------------
  * Learned angular reconstruction (a stand-in for 4x angular supersampling,
- * Sec. 4; not part of the paper).  Per pixel the V rendered views'
- * (R, G, B, d = D/Z - 1; -1 where empty) form 4V BF16 input channels [H][W][4V];
- * four zero-padded 3x3 convolutions 4V -> 32 -> 32 -> 32 -> 3V with ReLU
- * between them, FP32 accumulation on BF16 MFMA, BF16 activations; the output
- * [H][W][3V] is the input RGB of each view plus the network.  Parameters: an
- * FP32 master vector, per layer W [9][cout][cin] (tap 3*(dy+1)+(dx+1) reads
- * pixel (y+dy, x+dx)) followed by b [cout].  All tensors are device memory
- * unless stated; calls are asynchronous on the context's stream unless stated.
+ * Sec. 4; not part of the paper).  The network is applied to every view v of
+ * a frame of V views: its input at a pixel is (R, G, B, d = D/Z - 1; d = -1
+ * where empty) of views v-2 .. v+2 (zero beyond the rig), four zero-padded
+ * 3x3 convolutions 20 -> 32 -> 32 -> 32 -> 3 with ReLU between them, FP32
+ * accumulation on BF16 MFMA, BF16 activations; the output is view v's RGB plus
+ * the network.  Tensors: compact input x [view][H][W][4] BF16 (as written by
+ * lfdpr_net_pack_input), output y [view][H][W][4] BF16 (R, G, B, 0).
+ * Parameters: an FP32 vector, per layer W [9][cout][cin] (tap 3*(dy+1)+(dx+1)
+ * reads pixel (y+dy, x+dx)) followed by b [cout].  All tensors are device
+ * memory unless stated; calls are asynchronous on the context's stream unless
+ * stated.
  * ------------------------------------------------------------------------ */
 typedef struct lfdpr_net lfdpr_net;
 
-/* V in {16, 48}; images up to max_h*max_w pixels (<= 2^22).  Parameters start
- * at zero (output = input RGB).  The network uses the context's device and stream. */
+/* V views per frame; calls process whole frames, up to V*max_h*max_w pixels
+ * in total (<= 2^26).  Parameters start at zero (output = input RGB).  The
+ * network uses the context's device and stream. */
 int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lfdpr_net** out);
 int lfdpr_net_destroy(lfdpr_net* net);
 const char* lfdpr_net_last_error(lfdpr_net* net);
@@ -213,24 +217,27 @@ int lfdpr_net_param_count(lfdpr_net* net, int64_t* n);
 /* Host FP32 parameters in / out (n must equal the count); set resets Adam.  Synchronous. */
 int lfdpr_net_set_params(lfdpr_net* net, const float* host_params, int64_t n);
 int lfdpr_net_get_params(lfdpr_net* net, float* host_params, int64_t n);
-/* Views (V, H, W) RGBA8 and depth (V, H, W) FP32 -> network input x [H][W][4V] BF16;
- * D is the rig's focal distance. */
-int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t H, int32_t W, float D,
-                         void* x);
-/* x [H][W][4V] BF16 -> y [H][W][3V] BF16; keeps the activations for lfdpr_net_backward. */
-int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t H, int32_t W, void* y);
-/* Mean-squared error of the last forward output against target [H][W][3V] BF16,
- * written to *loss (device float, may be NULL), and the gradient of every
- * parameter (kept inside the network). */
+/* n_views views (n_views, H, W) RGBA8 and depth (same shape, FP32; NULL gives
+ * d = 0, the layout of a training target) -> x [n_views][H][W][4] BF16 with
+ * (R/255, G/255, B/255, D/Z - 1). */
+int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t n_views, int32_t H,
+                         int32_t W, float D, void* x);
+/* x -> y for n_views (a multiple of V) views of H x W; keeps the activations
+ * for lfdpr_net_backward. */
+int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t n_views, int32_t H, int32_t W, void* y);
+/* Mean-squared error of the last forward output's RGB against target (same
+ * layout as y), written to *loss (device float, may be NULL), and the gradient
+ * of every parameter (kept inside the network). */
 int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss);
-/* One Adam step on the FP32 master parameters, then the BF16 copies are refreshed. */
+/* One Adam step on the FP32 parameters, then the BF16 copies are refreshed. */
 int lfdpr_net_adam_step(lfdpr_net* net, float lr, float beta1, float beta2, float eps);
-/* y [H][W][3V] BF16 -> RGBA8 views (V, H, W): clamp(floor(255 y + 0.5)), alpha 255. */
-int lfdpr_net_unpack_output(lfdpr_net* net, const void* y, int32_t H, int32_t W, uint32_t* views);
+/* y -> RGBA8 views (n_views, H, W): clamp(floor(255 y + 0.5)), alpha 255. */
+int lfdpr_net_unpack_output(lfdpr_net* net, const void* y, int32_t n_views, int32_t H, int32_t W, uint32_t* views);
 /* Copies internal state of the last forward/backward into dst (device, n_bytes
- * room): which = 1..3 activation of hidden layer k ([H][W][32] BF16), 11..13
- * gradient of hidden pre-activation k, 14 gradient of the output
- * ([H][W][pad32(3V)] BF16), 20 parameter gradients (FP32).  Synchronous. */
+ * room): which = 1..3 activation of hidden layer k ([view][H][W][32] BF16),
+ * 11..13 gradient of hidden pre-activation k, 14 gradient of the output
+ * ([view][H][W][32] BF16, channels 0..2), 20 parameter gradients (FP32).
+ * Synchronous. */
 int lfdpr_net_copy_state(lfdpr_net* net, int32_t which, void* dst, int64_t n_bytes);
 /* Checkpoint (parameters + Adam moments + step) to / from a host file.  Synchronous. */
 int lfdpr_net_save(lfdpr_net* net, const char* path);

@@ -5,16 +5,18 @@ numpy in double precision with BF16 round-to-nearest-even at exactly the
 points where the HIP kernels store BF16: after each layer's activation, the
 output, and each propagated gradient.  Shares no code with the HIP path.
 
-Network (a stand-in for 4x angular supersampling, not in the paper): per
-pixel, the V rendered views' (R, G, B, d) with d = D/Z - 1 (-1 for background)
-form 4V input channels; four 3x3 convolutions 4V -> 32 -> 32 -> 32 -> 3V with
-ReLU between them and zero padding; the output adds the input RGB of each
-view (residual).  Weights are laid out [tap][cout][cin] with tap = 3*(dy+1) +
+Network (a stand-in for 4x angular supersampling, not in the paper): it is
+applied to each view v of a frame separately.  Its input at a pixel is
+(R, G, B, d) of views v-2 .. v+2 (d = D/Z - 1, -1 for background; views
+beyond the rig are zero), 20 channels; four zero-padded 3x3 convolutions
+20 -> 32 -> 32 -> 32 -> 3 with ReLU between them; the output adds view v's own
+RGB (residual).  Weights are laid out [tap][cout][cin] with tap = 3*(dy+1) +
 (dx+1) reading input pixel (y+dy, x+dx); biases [cout].
 
 Pins (tests/test_net_oracle.py): finite differences of the double-precision
 loss; zero weights make the output equal the input RGB; a 1x1 identity
-kernel reproduces its input; convolution equals an explicit loop.
+kernel reproduces its input; convolution equals an explicit loop; the input
+assembly reads the right neighbour views.
 """
 from __future__ import annotations
 
@@ -32,15 +34,19 @@ def bf16(x) -> np.ndarray:
     return out
 
 
-def layer_shapes(V: int, hidden: int = 32):
-    return [(4 * V, hidden), (hidden, hidden), (hidden, hidden), (hidden, 3 * V)]
+NEIGH = 2                 # views v-2 .. v+2
+CIN0 = 4 * (2 * NEIGH + 1)  # 20 input channels
 
 
-def init_params(V: int, seed: int, hidden: int = 32, scale: float = 1.0):
+def layer_shapes(hidden: int = 32):
+    return [(CIN0, hidden), (hidden, hidden), (hidden, hidden), (hidden, 3)]
+
+
+def init_params(seed: int, hidden: int = 32, scale: float = 1.0):
     """He-style random weights (last layer scaled down), zero biases."""
     rng = np.random.default_rng(seed)
     ps = []
-    for k, (ci, co) in enumerate(layer_shapes(V, hidden)):
+    for k, (ci, co) in enumerate(layer_shapes(hidden)):
         std = scale * np.sqrt(2.0 / (9 * ci)) * (0.1 if k == 3 else 1.0)
         ps.append((rng.normal(0.0, std, (9, co, ci)), np.zeros(co)))
     return ps
@@ -84,42 +90,57 @@ def conv3x3_xgrad(dz: np.ndarray, w: np.ndarray) -> np.ndarray:
     return dx_[1:-1, 1:-1]
 
 
-def residual_rgb(x: np.ndarray, V: int) -> np.ndarray:
-    """Input RGB of every view, in output channel order (3v + c)."""
-    H, W, _ = x.shape
-    return x.reshape(H, W, V, 4)[..., :3].reshape(H, W, 3 * V)
+def assemble(x: np.ndarray) -> np.ndarray:
+    """Compact per-view input (V, H, W, 4) -> per-view network input (V, H, W, 20):
+    views v-2 .. v+2 in that order, zero beyond the rig."""
+    V, H, W, _ = x.shape
+    out = np.zeros((V, H, W, CIN0))
+    for v in range(V):
+        for k, off in enumerate(range(-NEIGH, NEIGH + 1)):
+            if 0 <= v + off < V:
+                out[v, :, :, 4 * k:4 * k + 4] = x[v + off]
+    return out
 
 
-def forward(x: np.ndarray, params, V: int, round_bf16: bool = True):
-    """Returns (pre-activations z1..z4, activations a0..a3, output y)."""
+def forward(x: np.ndarray, params, round_bf16: bool = True):
+    """x: compact input (V, H, W, 4).  Returns (pre-activations per layer,
+    activations a0..a3 with a0 the assembled input, output y (V, H, W, 3))."""
     r = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
-    a = [r(x)]
+    x = r(x)
+    a = [assemble(x)]
     zs = []
     for k, (w, b) in enumerate(params):
         w = r(w)
-        z = conv3x3(a[-1], w, b)
+        z = np.stack([conv3x3(a[-1][v], w, b) for v in range(x.shape[0])])
         zs.append(z)
         if k < 3:
             a.append(r(np.maximum(z, 0.0)))
-    y = r(zs[-1] + residual_rgb(a[0], V))
+    y = r(zs[-1] + x[..., :3])
     return zs, a, y
 
 
-def loss_and_grads(x: np.ndarray, target: np.ndarray, params, V: int, round_bf16: bool = True):
-    """MSE loss over all output values and gradients of every weight/bias."""
+def loss_and_grads(x: np.ndarray, target: np.ndarray, params, round_bf16: bool = True):
+    """MSE loss over all output values (V, H, W, 3) and the gradients of every
+    weight and bias."""
     r = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
-    zs, a, y = forward(x, params, V, round_bf16)
+    zs, a, y = forward(x, params, round_bf16)
     n = y.size
     diff = y - target
     loss = float((diff * diff).mean())
     dz = r(2.0 * diff / n)
     grads = [None] * 4
+    V = x.shape[0]
     for k in (3, 2, 1, 0):
         w = r(params[k][0])
-        dw, db = conv3x3_wgrad(a[k], dz)
+        dw = np.zeros_like(params[k][0], dtype=np.float64)
+        db = np.zeros_like(params[k][1], dtype=np.float64)
+        for v in range(V):
+            gw, gb = conv3x3_wgrad(a[k][v], dz[v])
+            dw += gw
+            db += gb
         grads[k] = (dw, db)
         if k > 0:
-            da = conv3x3_xgrad(dz, w)
+            da = np.stack([conv3x3_xgrad(dz[v], w) for v in range(V)])
             dz = r(da * (a[k] > 0))
     return loss, grads, y
 

@@ -28,7 +28,7 @@ struct SceneDev {
 
 template <class T>
 void dfree(T*& p) {
-  if (p) hipFree((void*)p);
+  if (p) (void)hipFree((void*)p);
   p = nullptr;
 }
 
@@ -140,7 +140,7 @@ hipEvent_t mark(lfdpr_ctx* ctx) {
     ctx->ev_pool.push_back(e);
   }
   hipEvent_t e = ctx->ev_pool[ctx->ev_used++];
-  hipEventRecord(e, ctx->stream);
+  (void)hipEventRecord(e, ctx->stream);
   return e;
 }
 
@@ -203,8 +203,8 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
 
 int lfdpr_destroy(lfdpr_ctx* ctx) {
   if (!ctx) return LFDPR_OK;
-  hipSetDevice(ctx->device);
-  hipStreamSynchronize(ctx->stream);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->scenes) free_scene(kv.second);
   dfree(ctx->d_eye);
   dfree(ctx->d_kshift);
@@ -221,7 +221,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_tiles);
   dfree(ctx->d_big);
   dfree(ctx->d_stats);
-  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return LFDPR_OK;
 }
@@ -299,7 +299,7 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
 int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   if (!ctx || !v) return fail(ctx, LFDPR_EINVAL, "null argument");
   int64_t nviews = (int64_t)v->V * v->S;
-  if (v->V < 1 || v->S < 1 || nviews > 256 || v->W < 1 || v->H < 1 || v->W > 4096 || v->H > 4096 ||
+  if (v->V < 1 || v->S < 1 || nviews > 1024 || v->W < 1 || v->H < 1 || v->W > 4096 || v->H > 4096 ||
       !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) || !(v->aspect > 0.0f) || !(v->D > 0.0f) ||
       !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f) || !(v->znear > 0.0f) || (v->S > 1 && !v->jitter) ||
       v->point_capacity < 0 || v->point_capacity > (1ll << 31))

@@ -1,12 +1,15 @@
 // Learned angular reconstruction: a small 3x3 convolutional network whose
 // inference and training run on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
-// accumulate).  It stands in for 4x angular supersampling (Sec. 4): input per
-// pixel = the V rendered views' (R, G, B, d = D/Z - 1), 4V channels; layers
-// 4V -> 32 -> 32 -> 32 -> 3V with ReLU; output = input RGB + network.
+// accumulate).  It stands in for 4x angular supersampling (Sec. 4) and is
+// applied to every view v of a frame: its input at a pixel is (R, G, B, d =
+// D/Z - 1) of views v-2 .. v+2 (20 channels, zero beyond the rig), layers
+// 20 -> 32 -> 32 -> 32 -> 3 with ReLU, output = view v's RGB + network.
 //
-// Layouts: activations NHWC (channels innermost) in BF16; weights
-// [tap][cout][cin] in BF16 with an FP32 master copy; tap = 3*(dy+1) + (dx+1)
-// reads input pixel (y+dy, x+dx), zero padding.
+// Layouts: the compact input is [view][H][W][4] BF16 and layer 1 gathers the
+// neighbour views from it directly; hidden activations are [view][H][W][32]
+// BF16; the output [view][H][W][4] (RGB, 0).  Parameters: FP32 master vector,
+// per layer W [tap][cout][cin] then b [cout] (unpadded); BF16 copies padded
+// to 32 input channels (layer 1) and 16 output channels (layer 4).
 //
 // MFMA 16x16x32 lane layout used throughout: lane l feeds row (l % 16) of A
 // and column (l % 16) of B with 8 K-values each (group l / 16); the 4 results
@@ -45,56 +48,74 @@ union Frag {
 };
 
 // ---------------------------------------------------------------- 3x3 convolution
-// One block = 4 waves = 256 output pixels of one image row segment (4 M-tiles of
-// 16 pixels per wave); NT = COUT/16 output-channel tiles per M-tile.  Per tap,
-// the block stages that tap's [COUT][CIN] weights in LDS.
-template <int NT, int MODE>
-__global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X, int CIN,
-                                                  const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
-                                                  int H, int W, uint16_t* __restrict__ Y, int COUT_STORE,
-                                                  const uint16_t* __restrict__ aux, int AUX_C) {
+constexpr int kNeigh = 2;   // views v-2 .. v+2
+constexpr int kCin0 = 20;   // real input channels of layer 1
+constexpr int kK = 32;      // padded input channels of every layer (one MFMA K step per tap)
+
+// Loads the 8 K-values of lane group g for input pixel (n, yy, xx).  GATHER:
+// from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2, n+2g-1.
+template <bool GATHER>
+__device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, int n, int yy, int xx, int H, int W, int g,
+                                        int V) {
+  if (yy < 0 || yy >= H || xx < 0 || xx >= W) return uint4{0u, 0u, 0u, 0u};
+  if (!GATHER) return *reinterpret_cast<const uint4*>(X + (((size_t)n * H + yy) * W + xx) * kK + 8 * g);
+  const int v = n % V, f0 = n - v;
+  uint2 lo = {0u, 0u}, hi = {0u, 0u};
+  const int o0 = 2 * g - kNeigh, o1 = 2 * g + 1 - kNeigh;
+  if (o0 <= kNeigh && v + o0 >= 0 && v + o0 < V)
+    lo = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o0) * H + yy) * W + xx) * 4);
+  if (o1 <= kNeigh && v + o1 >= 0 && v + o1 < V)
+    hi = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o1) * H + yy) * W + xx) * 4);
+  return uint4{lo.x, lo.y, hi.x, hi.y};
+}
+
+// One block = 4 waves; a tile is 256 consecutive output pixels of the
+// [N][H][W] grid (4 M-tiles of 16 per wave); NT = COUT/16 output-channel tiles.
+// All nine taps' [COUT][32] weights sit in LDS for the block's lifetime.
+template <int NT, int MODE, bool GATHER>
+__global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
+                                                  const float* __restrict__ bias, int N, int H, int W, int V,
+                                                  uint16_t* __restrict__ Y, int YS, const uint16_t* __restrict__ aux,
+                                                  int AUX_C) {
   constexpr int COUT = NT * 16;
-  extern __shared__ uint4 wlds[];  // [COUT][CIN] bf16 of one tap
+  __shared__ uint4 wlds[9 * COUT * kK / 8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  const int npx = H * W;
+  for (int k = threadIdx.x; k < 9 * COUT * kK / 8; k += blockDim.x) wlds[k] = reinterpret_cast<const uint4*>(Wt)[k];
+  __syncthreads();
+  const int hw = H * W;
+  const int npx = N * hw;
   const int ntile = (npx + 255) / 256;
-  const int cin_q = CIN / 8;  // uint4 per weight row
   for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
     const int pbase = tile * 256 + wv * 64;
-    int py[4], px[4];
+    int pn[4], py[4], px[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int p = pbase + m * 16 + r16;
-      py[m] = p < npx ? p / W : -100;
-      px[m] = p < npx ? p % W : -100;
+      const bool ok = p < npx;
+      const int q = ok ? p % hw : 0;
+      pn[m] = ok ? p / hw : 0;
+      py[m] = ok ? q / W : -100;
+      px[m] = ok ? q % W : -100;
     }
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      __syncthreads();
-      const uint4* wsrc = reinterpret_cast<const uint4*>(Wt + (size_t)tap * COUT * CIN);
-      for (int k = threadIdx.x; k < COUT * cin_q; k += blockDim.x) wlds[k] = wsrc[k];
-      __syncthreads();
-      for (int c0 = 0; c0 < CIN; c0 += 32) {
-        Frag b[NT];
+      Frag b[NT];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) b[n].u = wlds[(n * 16 + r16) * cin_q + (c0 >> 3) + g];
+      for (int n = 0; n < NT; ++n) b[n].u = wlds[(tap * COUT + n * 16 + r16) * (kK / 8) + g];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int yy = py[m] + dy, xx = px[m] + dx;
-          Frag a;
-          a.u = uint4{0u, 0u, 0u, 0u};
-          if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-            a.u = *reinterpret_cast<const uint4*>(X + ((size_t)yy * W + xx) * CIN + c0 + 8 * g);
+      for (int m = 0; m < 4; ++m) {
+        Frag a;
+        a.u = load_a<GATHER>(X, pn[m], py[m] + dy, px[m] + dx, H, W, g, V);
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[n].v, acc[m][n], 0, 0, 0);
-        }
+        for (int n = 0; n < NT; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[n].v, acc[m][n], 0, 0, 0);
       }
     }
     // epilogue: lane holds D[4g+e][r16] = pixel pbase + 16m + 4g + e, channel n*16 + r16
@@ -103,7 +124,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
         const int co = n * 16 + r16;
-        if (co >= COUT_STORE) continue;
+        if (co >= YS) continue;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int p = pbase + m * 16 + 4 * g + e;
@@ -112,11 +133,11 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
           if (MODE == MODE_RELU) {
             v = fmaxf(v + bias[co], 0.0f);
           } else if (MODE == MODE_OUT) {
-            v = (v + bias[co]) + from_bf16(aux[(size_t)p * AUX_C + 4 * (co / 3) + co % 3]);
+            v = co < 3 ? (v + bias[co]) + from_bf16(aux[(size_t)p * AUX_C + co]) : 0.0f;
           } else {
             v = from_bf16(aux[(size_t)p * AUX_C + co]) > 0.0f ? v : 0.0f;
           }
-          Y[(size_t)p * COUT_STORE + co] = to_bf16(v);
+          Y[(size_t)p * YS + co] = to_bf16(v);
         }
       }
   }
@@ -124,18 +145,20 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 
 // ---------------------------------------------------------------- weight gradient
 // dW[tap][co][ci] += sum_p dZ[p][co] * A[p + off(tap)][ci]: one wave per
-// (tap, 16 co, 16 ci) tile and pixel chunk; M = co, N = ci, K = pixels.
+// (tap, 16 co, 16 ci) tile and pixel chunk; M = co, N = ci, K = pixels.  Only
+// real (co < CO, ci < CI) entries are written, into the unpadded layout.
+template <bool GATHER>
 __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ dZ, int DZS, int CO,
-                                                    const uint16_t* __restrict__ A, int CI, int H, int W,
+                                                    const uint16_t* __restrict__ A, int CI, int N, int H, int W, int V,
                                                     float* __restrict__ dW, int chunk) {
   const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
-  const int nct = CO / 16, nit = CI / 16;
+  const int nct = (CO + 15) / 16, nit = 2;  // ci padded to 32
   int t = blockIdx.x;
   const int it = t % nit; t /= nit;
   const int ct = t % nct; t /= nct;
   const int tap = t;
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  const int npx = H * W;
+  const int hw = H * W, npx = N * hw;
   const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
   const int co = ct * 16 + r16, ci = it * 16 + r16;
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -146,18 +169,30 @@ __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ 
       const int p = k0 + 8 * g + e;
       uint16_t za = 0, zb = 0;
       if (p < p1) {
-        za = dZ[(size_t)p * DZS + co];
-        const int y = p / W, x = p % W;
-        const int yy = y + dy, xx = x + dx;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) zb = A[((size_t)yy * W + xx) * CI + ci];
+        za = co < DZS ? dZ[(size_t)p * DZS + co] : (uint16_t)0;
+        const int n = p / hw, q = p % hw;
+        const int yy = q / W + dy, xx = q % W + dx;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+          if (!GATHER) {
+            zb = A[(((size_t)n * H + yy) * W + xx) * kK + ci];
+          } else if (ci < kCin0) {
+            const int v = n % V, off = ci / 4 - kNeigh;
+            if (v + off >= 0 && v + off < V) zb = A[(((size_t)(n + off) * H + yy) * W + xx) * 4 + (ci & 3)];
+          }
+        }
       }
       fa.h[e] = za;
       fb.h[e] = zb;
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc, 0, 0, 0);
   }
+  if (ci < CI) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) atomicAdd(&dW[((size_t)tap * CO + ct * 16 + 4 * g + e) * CI + ci], acc[e]);
+    for (int e = 0; e < 4; ++e) {
+      const int c = ct * 16 + 4 * g + e;
+      if (c < CO) atomicAdd(&dW[((size_t)tap * CO + c) * CI + ci], acc[e]);
+    }
+  }
 }
 
 __global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, float* __restrict__ db) {
@@ -174,19 +209,19 @@ __global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, f
   if (threadIdx.x == 0) atomicAdd(&db[co], red[0]);
 }
 
-// loss = mean((y - t)^2) over npx*C values; dZ = bf16(2 (y - t) / n) into a
-// [p][CP] buffer (channels C..CP-1 zero).
-__global__ void k_mse(const uint16_t* __restrict__ Yb, const uint16_t* __restrict__ T, int C, int CP, int npx,
+// loss = mean((y - t)^2) over the 3 colour channels of npx pixels (inputs
+// [p][4]); dZ = bf16(2 (y - t) / n) into a [p][32] buffer (other channels 0).
+__global__ void k_mse(const uint16_t* __restrict__ Yb, const uint16_t* __restrict__ T, int npx,
                       uint16_t* __restrict__ dZ, float* __restrict__ loss) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)npx * C;
+  const int64_t n = (int64_t)npx * 3;
   float sq = 0.0f;
-  if (i < (int64_t)npx * CP) {
-    const int64_t p = i / CP;
-    const int c = (int)(i % CP);
+  if (i < (int64_t)npx * kK) {
+    const int64_t p = i / kK;
+    const int c = (int)(i % kK);
     uint16_t out = 0;
-    if (c < C) {
-      const float d = from_bf16(Yb[p * C + c]) - from_bf16(T[p * C + c]);
+    if (c < 3) {
+      const float d = from_bf16(Yb[p * 4 + c]) - from_bf16(T[p * 4 + c]);
       sq = d * d;
       out = to_bf16((2.0f * d) / (float)n);
     }
@@ -214,56 +249,50 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// BF16 weights for the forward pass ([tap][co][ci]) and the flipped, transposed
-// copy for the input gradient ([8 - tap][ci][co_pad], zero beyond co).
-__global__ void k_pack_w(const float* __restrict__ master, int CO, int CI, int COP, uint16_t* __restrict__ wf,
+// BF16 weights for the forward pass ([tap][cof][32], zero-padded from the
+// master [tap][co][ci]) and the flipped, transposed copy for the input
+// gradient ([8 - tap][ci][32], zero beyond co).
+__global__ void k_pack_w(const float* __restrict__ master, int CO, int CI, int COF, uint16_t* __restrict__ wf,
                          uint16_t* __restrict__ wb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = (int64_t)9 * CO * CI;
-  if (i < n) wf[i] = to_bf16(master[i]);
-  if (wb) {
-    const int64_t nb = (int64_t)9 * CI * COP;
-    if (i < nb) {
-      const int tapb = (int)(i / ((int64_t)CI * COP));
-      const int rem = (int)(i % ((int64_t)CI * COP));
-      const int ci = rem / COP, co = rem % COP;
-      const int tap = 8 - tapb;
-      wb[i] = co < CO ? to_bf16(master[((int64_t)tap * CO + co) * CI + ci]) : (uint16_t)0;
-    }
+  if (i < (int64_t)9 * COF * kK) {
+    const int tap = (int)(i / (COF * kK)), rem = (int)(i % (COF * kK));
+    const int co = rem / kK, ci = rem % kK;
+    wf[i] = (co < CO && ci < CI) ? to_bf16(master[((int64_t)tap * CO + co) * CI + ci]) : (uint16_t)0;
+  }
+  if (wb && i < (int64_t)9 * CI * kK) {
+    const int tapb = (int)(i / (CI * kK)), rem = (int)(i % (CI * kK));
+    const int ci = rem / kK, co = rem % kK;
+    wb[i] = co < CO ? to_bf16(master[((int64_t)(8 - tapb) * CO + co) * CI + ci]) : (uint16_t)0;
   }
 }
 
-// views (V, H, W) RGBA8 + depth -> x[p][4v + c] = c/255, x[p][4v+3] = D/Z - 1 (-1 when empty)
-__global__ void k_pack_input(const uint32_t* __restrict__ views, const float* __restrict__ depth, int V, int npx,
-                             float D, uint16_t* __restrict__ x) {
+// views (V, H, W) RGBA8 + depth -> x[v][p][4] = (R/255, G/255, B/255, D/Z - 1), d = -1 when empty
+__global__ void k_pack_input(const uint32_t* __restrict__ views, const float* __restrict__ depth, int64_t n, float D,
+                             uint16_t* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)V * npx) return;
-  const int64_t p = i % npx;
-  const int v = (int)(i / npx);
-  const uint32_t c = views[(int64_t)v * npx + p];
-  const float z = depth[(int64_t)v * npx + p];
+  if (i >= n) return;
+  const uint32_t c = views[i];
+  const float z = depth ? depth[i] : INFINITY;
   const float d = z < INFINITY ? D / z - 1.0f : -1.0f;
-  uint16_t* o = x + p * (4 * V) + 4 * v;
-  o[0] = to_bf16((float)(c & 255u) / 255.0f);
-  o[1] = to_bf16((float)((c >> 8) & 255u) / 255.0f);
-  o[2] = to_bf16((float)((c >> 16) & 255u) / 255.0f);
-  o[3] = to_bf16(d);
+  uint2 o;
+  o.x = (uint32_t)to_bf16((float)(c & 255u) / 255.0f) | ((uint32_t)to_bf16((float)((c >> 8) & 255u) / 255.0f) << 16);
+  o.y = (uint32_t)to_bf16((float)((c >> 16) & 255u) / 255.0f) | ((uint32_t)(depth ? to_bf16(d) : 0u) << 16);
+  reinterpret_cast<uint2*>(x)[i] = o;
 }
 
-// y[p][3v + c] -> RGBA8 views, clamp(floor(255 y + 0.5)), alpha 255
-__global__ void k_unpack_output(const uint16_t* __restrict__ y, int V, int npx, uint32_t* __restrict__ views) {
+// y[v][p][4] -> RGBA8, clamp(floor(255 y + 0.5)), alpha 255
+__global__ void k_unpack_output(const uint16_t* __restrict__ y, int64_t n, uint32_t* __restrict__ views) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)V * npx) return;
-  const int64_t p = i % npx;
-  const int v = (int)(i / npx);
+  if (i >= n) return;
   uint32_t o = 0xFF000000u;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    float f = floorf(from_bf16(y[p * (3 * V) + 3 * v + c]) * 255.0f + 0.5f);
+    float f = floorf(from_bf16(y[i * 4 + c]) * 255.0f + 0.5f);
     f = f < 0.0f ? 0.0f : (f > 255.0f ? 255.0f : f);
     o |= (uint32_t)f << (8 * c);
   }
-  views[(int64_t)v * npx + p] = o;
+  views[i] = o;
 }
 
 __global__ void k_zero_f32(float* p, int64_t n) {
@@ -281,8 +310,9 @@ struct lfdpr_net {
   lfdpr_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
-  int V = 0, maxpx = 0;
-  int ci[4], co[4], cop[4];
+  int V = 0;
+  int64_t maxpx = 0;  // views * H * W
+  int ci[4], co[4], cof[4];
   int64_t off_w[4], off_b[4], nparams = 0;
   float* master = nullptr;
   float* grad = nullptr;
@@ -291,11 +321,11 @@ struct lfdpr_net {
   int64_t step = 0;
   uint16_t* wf[4] = {nullptr, nullptr, nullptr, nullptr};
   uint16_t* wb[4] = {nullptr, nullptr, nullptr, nullptr};
-  uint16_t* act[4] = {nullptr, nullptr, nullptr, nullptr};  // act[0] unused (input is the caller's)
+  uint16_t* act[4] = {nullptr, nullptr, nullptr, nullptr};  // act[1..3]
   uint16_t* dz[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   const uint16_t* last_x = nullptr;
   const uint16_t* last_y = nullptr;
-  int last_h = 0, last_w = 0;
+  int last_n = 0, last_h = 0, last_w = 0;
   float* d_loss = nullptr;
   std::string err;
 };
@@ -313,30 +343,20 @@ int nfail(lfdpr_net* n, int code, const std::string& m) {
     if (e_ != hipSuccess) return nfail(net, LFDPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-template <int NT, int MODE>
-void launch_conv(const uint16_t* X, int CIN, const uint16_t* Wt, const float* b, int H, int W, uint16_t* Y, int CS,
+template <int NT, int MODE, bool GATHER>
+void launch_conv(const uint16_t* X, const uint16_t* Wt, const float* b, int N, int H, int W, int V, uint16_t* Y, int YS,
                  const uint16_t* aux, int AUXC, hipStream_t s) {
-  const int tiles = (H * W + 255) / 256;
-  const size_t lds = (size_t)NT * 16 * CIN * 2;
-  const int grid = tiles < 2048 ? tiles : 2048;
-  k_conv3x3<NT, MODE><<<grid, 256, lds, s>>>(X, CIN, Wt, b, H, W, Y, CS, aux, AUXC);
+  const int64_t tiles = ((int64_t)N * H * W + 255) / 256;
+  const int grid = (int)(tiles < 4096 ? tiles : 4096);
+  k_conv3x3<NT, MODE, GATHER><<<grid, 256, 0, s>>>(X, Wt, b, N, H, W, V, Y, YS, aux, AUXC);
 }
 
-// forward conv dispatch on the output tile count
-int conv_fwd(lfdpr_net* net, int layer, const uint16_t* X, int H, int W, uint16_t* Y, const uint16_t* resid) {
-  const int CIN = net->ci[layer], COUT = net->co[layer];
-  const float* b = net->master + net->off_b[layer];
-  hipStream_t s = net->stream;
-  if (layer < 3) {
-    launch_conv<2, MODE_RELU>(X, CIN, net->wf[layer], b, H, W, Y, COUT, nullptr, 0, s);
-  } else if (COUT == 48) {
-    launch_conv<3, MODE_OUT>(X, CIN, net->wf[layer], b, H, W, Y, COUT, resid, net->ci[0], s);
-  } else if (COUT == 144) {
-    launch_conv<9, MODE_OUT>(X, CIN, net->wf[layer], b, H, W, Y, COUT, resid, net->ci[0], s);
-  } else {
-    return nfail(net, LFDPR_EINVAL, "unsupported output width");
+void pack_weights(lfdpr_net* net) {
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = 9ll * kK * (net->cof[k] > net->ci[k] ? net->cof[k] : net->ci[k]);
+    k_pack_w<<<(unsigned)((n + 255) / 256), 256, 0, net->stream>>>(net->master + net->off_w[k], net->co[k], net->ci[k],
+                                                                   net->cof[k], net->wf[k], net->wb[k]);
   }
-  return LFDPR_OK;
 }
 
 }  // namespace
@@ -346,20 +366,19 @@ extern "C" {
 int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lfdpr_net** out) {
   if (!ctx || !out) return LFDPR_EINVAL;
   *out = nullptr;
-  if (!(V == 16 || V == 48) || max_h < 1 || max_w < 1 || (int64_t)max_h * max_w > (1 << 22))
-    return LFDPR_EINVAL;
+  if (V < 1 || V > 4096 || max_h < 1 || max_w < 1 || (int64_t)V * max_h * max_w > (1ll << 26)) return LFDPR_EINVAL;
   lfdpr_net* net = new lfdpr_net();
   net->ctx = ctx;
   net->stream = ctx_stream_of(ctx);
   net->device = ctx_device_of(ctx);
   net->V = V;
-  net->maxpx = max_h * max_w;
-  const int ci[4] = {4 * V, kHidden, kHidden, kHidden}, co[4] = {kHidden, kHidden, kHidden, 3 * V};
+  net->maxpx = (int64_t)V * max_h * max_w;
+  const int ci[4] = {kCin0, kHidden, kHidden, kHidden}, co[4] = {kHidden, kHidden, kHidden, 3};
   int64_t off = 0;
   for (int k = 0; k < 4; ++k) {
     net->ci[k] = ci[k];
     net->co[k] = co[k];
-    net->cop[k] = (co[k] + 31) / 32 * 32;
+    net->cof[k] = k == 3 ? 16 : kHidden;
     net->off_w[k] = off;
     off += 9ll * co[k] * ci[k];
     net->off_b[k] = off;
@@ -374,35 +393,39 @@ int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lf
   al(net->adam_v, off);
   al(net->d_loss, 1);
   for (int k = 0; k < 4; ++k) {
-    al(net->wf[k], 9ll * co[k] * ci[k]);
-    if (k > 0) al(net->wb[k], 9ll * ci[k] * net->cop[k]);
+    al(net->wf[k], 9ll * net->cof[k] * kK);
+    if (k > 0) al(net->wb[k], 9ll * ci[k] * kK);
     if (k > 0) al(net->act[k], (size_t)net->maxpx * kHidden);
   }
-  for (int k = 1; k <= 4; ++k) al(net->dz[k], (size_t)net->maxpx * (k == 4 ? net->cop[3] : kHidden));
+  for (int k = 1; k <= 4; ++k) al(net->dz[k], (size_t)net->maxpx * kK);
   if (!ok) {
     lfdpr_net_destroy(net);
     return LFDPR_ENOMEM;
   }
-  if (hipMemset(net->master, 0, off * 4) != hipSuccess || hipMemset(net->adam_m, 0, off * 4) != hipSuccess ||
-      hipMemset(net->adam_v, 0, off * 4) != hipSuccess) {
+  if (hipMemset(net->master, 0, off * 4) != hipSuccess) {
     lfdpr_net_destroy(net);
     return LFDPR_EDEVICE;
   }
   *out = net;
-  return lfdpr_net_set_params(net, nullptr, 0);
+  int rc = lfdpr_net_set_params(net, nullptr, 0);
+  if (rc) {
+    lfdpr_net_destroy(net);
+    *out = nullptr;
+  }
+  return rc;
 }
 
 int lfdpr_net_destroy(lfdpr_net* net) {
   if (!net) return LFDPR_OK;
-  hipSetDevice(net->device);
-  hipStreamSynchronize(net->stream);
-  hipFree(net->master);
-  hipFree(net->grad);
-  hipFree(net->adam_m);
-  hipFree(net->adam_v);
-  hipFree(net->d_loss);
-  for (int k = 0; k < 4; ++k) { hipFree(net->wf[k]); hipFree(net->wb[k]); hipFree(net->act[k]); }
-  for (int k = 0; k < 5; ++k) hipFree(net->dz[k]);
+  (void)hipSetDevice(net->device);
+  (void)hipStreamSynchronize(net->stream);
+  (void)hipFree(net->master);
+  (void)hipFree(net->grad);
+  (void)hipFree(net->adam_m);
+  (void)hipFree(net->adam_v);
+  (void)hipFree(net->d_loss);
+  for (int k = 0; k < 4; ++k) { (void)hipFree(net->wf[k]); (void)hipFree(net->wb[k]); (void)hipFree(net->act[k]); }
+  for (int k = 0; k < 5; ++k) (void)hipFree(net->dz[k]);
   delete net;
   return LFDPR_OK;
 }
@@ -426,13 +449,7 @@ int lfdpr_net_set_params(lfdpr_net* net, const float* host, int64_t n) {
   NHIP(hipMemset(net->adam_m, 0, net->nparams * 4));
   NHIP(hipMemset(net->adam_v, 0, net->nparams * 4));
   net->step = 0;
-  for (int k = 0; k < 4; ++k) {
-    int64_t cnt = 9ll * net->co[k] * net->ci[k];
-    int64_t cb = 9ll * net->ci[k] * net->cop[k];
-    int64_t m = cnt > cb ? cnt : cb;
-    k_pack_w<<<(unsigned)((m + 255) / 256), 256, 0, net->stream>>>(net->master + net->off_w[k], net->co[k], net->ci[k],
-                                                                   net->cop[k], net->wf[k], net->wb[k]);
-  }
+  pack_weights(net);
   NHIP(hipGetLastError());
   NHIP(hipStreamSynchronize(net->stream));
   return LFDPR_OK;
@@ -446,30 +463,32 @@ int lfdpr_net_get_params(lfdpr_net* net, float* host, int64_t n) {
   return LFDPR_OK;
 }
 
-int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t H, int32_t W, float D,
-                         void* x) {
-  if (!net || !views || !depth || !x || H < 1 || W < 1 || !(D > 0.0f)) return LFDPR_EINVAL;
+int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t n_views, int32_t H,
+                         int32_t W, float D, void* x) {
+  if (!net || !views || !x || n_views < 1 || H < 1 || W < 1 || !(D > 0.0f)) return LFDPR_EINVAL;
   NHIP(hipSetDevice(net->device));
-  const int64_t n = (int64_t)net->V * H * W;
-  k_pack_input<<<(unsigned)((n + 255) / 256), 256, 0, net->stream>>>(views, depth, net->V, H * W, D, (uint16_t*)x);
+  const int64_t n = (int64_t)n_views * H * W;
+  k_pack_input<<<(unsigned)((n + 255) / 256), 256, 0, net->stream>>>(views, depth, n, D, (uint16_t*)x);
   NHIP(hipGetLastError());
   return LFDPR_OK;
 }
 
-int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t H, int32_t W, void* y) {
+int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t n_views, int32_t H, int32_t W, void* y) {
   if (!net || !x || !y) return LFDPR_EINVAL;
-  if (H < 1 || W < 1 || (int64_t)H * W > net->maxpx)
-    return nfail(net, LFDPR_EINVAL, "image larger than the network's maximum");
+  if (n_views < 1 || n_views % net->V || H < 1 || W < 1 || (int64_t)n_views * H * W > net->maxpx)
+    return nfail(net, LFDPR_EINVAL, "views must be whole frames of V views and fit the network's maximum");
   NHIP(hipSetDevice(net->device));
   const uint16_t* in = (const uint16_t*)x;
-  int rc = conv_fwd(net, 0, in, H, W, net->act[1], nullptr);
-  if (!rc) rc = conv_fwd(net, 1, net->act[1], H, W, net->act[2], nullptr);
-  if (!rc) rc = conv_fwd(net, 2, net->act[2], H, W, net->act[3], nullptr);
-  if (!rc) rc = conv_fwd(net, 3, net->act[3], H, W, (uint16_t*)y, in);
-  if (rc) return rc;
+  hipStream_t s = net->stream;
+  const int N = n_views, V = net->V;
+  launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, net->act[1], kHidden, nullptr, 0, s);
+  launch_conv<2, MODE_RELU, false>(net->act[1], net->wf[1], net->master + net->off_b[1], N, H, W, V, net->act[2], kHidden, nullptr, 0, s);
+  launch_conv<2, MODE_RELU, false>(net->act[2], net->wf[2], net->master + net->off_b[2], N, H, W, V, net->act[3], kHidden, nullptr, 0, s);
+  launch_conv<1, MODE_OUT, false>(net->act[3], net->wf[3], net->master + net->off_b[3], N, H, W, V, (uint16_t*)y, 4, in, 4, s);
   NHIP(hipGetLastError());
   net->last_x = in;
   net->last_y = (const uint16_t*)y;
+  net->last_n = N;
   net->last_h = H;
   net->last_w = W;
   return LFDPR_OK;
@@ -480,24 +499,25 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
   if (!net->last_x) return nfail(net, LFDPR_ESTATE, "lfdpr_net_forward first");
   NHIP(hipSetDevice(net->device));
   hipStream_t s = net->stream;
-  const int H = net->last_h, W = net->last_w, npx = H * W;
+  const int N = net->last_n, H = net->last_h, W = net->last_w, V = net->V;
+  const int npx = N * H * W;
   k_zero_f32<<<(unsigned)((net->nparams + 255) / 256), 256, 0, s>>>(net->grad, net->nparams);
   k_zero_f32<<<1, 64, 0, s>>>(net->d_loss, 1);
-  const int C4 = net->co[3], C4P = net->cop[3];
-  const int64_t ne = (int64_t)npx * C4P;
-  k_mse<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(net->last_y, (const uint16_t*)target, C4, C4P, npx, net->dz[4],
-                                                     net->d_loss);
-  const int chunk = 2048;
+  const int64_t ne = (int64_t)npx * kK;
+  k_mse<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(net->last_y, (const uint16_t*)target, npx, net->dz[4], net->d_loss);
+  const int chunk = 4096;
   const unsigned nch = (unsigned)((npx + chunk - 1) / chunk);
   for (int k = 3; k >= 0; --k) {
-    const int CO = net->co[k], DZS = k == 3 ? C4P : kHidden, CI = net->ci[k];
-    const uint16_t* A = k == 0 ? net->last_x : net->act[k];
-    dim3 gw((unsigned)(9 * (CO / 16) * (CI / 16)), nch);
-    k_conv_wgrad<<<gw, 64, 0, s>>>(net->dz[k + 1], DZS, CO, A, CI, H, W, net->grad + net->off_w[k], chunk);
-    k_bias_grad<<<(unsigned)CO, 256, 0, s>>>(net->dz[k + 1], DZS, npx, net->grad + net->off_b[k]);
+    const int CO = net->co[k], CI = net->ci[k];
+    dim3 gw((unsigned)(9 * ((CO + 15) / 16) * 2), nch);
+    if (k == 0)
+      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, CI, N, H, W, V, net->grad + net->off_w[0], chunk);
+    else
+      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], CI, N, H, W, V, net->grad + net->off_w[k], chunk);
+    k_bias_grad<<<(unsigned)CO, 256, 0, s>>>(net->dz[k + 1], kK, npx, net->grad + net->off_b[k]);
     if (k > 0)  // input gradient through the flipped, transposed weights, masked by the ReLU
-      launch_conv<2, MODE_BWD>(net->dz[k + 1], DZS, net->wb[k], nullptr, H, W, net->dz[k], kHidden, net->act[k],
-                               kHidden, s);
+      launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, net->dz[k], kHidden, net->act[k],
+                                      kHidden, s);
   }
   NHIP(hipGetLastError());
   if (loss) NHIP(hipMemcpyAsync(loss, net->d_loss, 4, hipMemcpyDeviceToDevice, s));
@@ -514,34 +534,27 @@ int lfdpr_net_adam_step(lfdpr_net* net, float lr, float b1, float b2, float eps)
   k_adam<<<(unsigned)((net->nparams + 255) / 256), 256, 0, net->stream>>>(net->master, net->grad, net->adam_m,
                                                                           net->adam_v, net->nparams, lr, b1, b2, eps,
                                                                           c1, c2);
-  for (int k = 0; k < 4; ++k) {
-    int64_t cnt = 9ll * net->co[k] * net->ci[k];
-    int64_t cb = 9ll * net->ci[k] * net->cop[k];
-    int64_t m = cnt > cb ? cnt : cb;
-    k_pack_w<<<(unsigned)((m + 255) / 256), 256, 0, net->stream>>>(net->master + net->off_w[k], net->co[k], net->ci[k],
-                                                                   net->cop[k], net->wf[k], net->wb[k]);
-  }
+  pack_weights(net);
   NHIP(hipGetLastError());
   return LFDPR_OK;
 }
 
-int lfdpr_net_unpack_output(lfdpr_net* net, const void* y, int32_t H, int32_t W, uint32_t* views) {
-  if (!net || !y || !views || H < 1 || W < 1) return LFDPR_EINVAL;
+int lfdpr_net_unpack_output(lfdpr_net* net, const void* y, int32_t n_views, int32_t H, int32_t W, uint32_t* views) {
+  if (!net || !y || !views || n_views < 1 || H < 1 || W < 1) return LFDPR_EINVAL;
   NHIP(hipSetDevice(net->device));
-  const int64_t n = (int64_t)net->V * H * W;
-  k_unpack_output<<<(unsigned)((n + 255) / 256), 256, 0, net->stream>>>((const uint16_t*)y, net->V, H * W, views);
+  const int64_t n = (int64_t)n_views * H * W;
+  k_unpack_output<<<(unsigned)((n + 255) / 256), 256, 0, net->stream>>>((const uint16_t*)y, n, views);
   NHIP(hipGetLastError());
   return LFDPR_OK;
 }
 
 int lfdpr_net_copy_state(lfdpr_net* net, int32_t which, void* dst, int64_t n_bytes) {
   if (!net || !dst) return LFDPR_EINVAL;
-  const int64_t npx = (int64_t)net->last_h * net->last_w;
+  const int64_t npx = (int64_t)net->last_n * net->last_h * net->last_w;
   const void* src = nullptr;
   int64_t bytes = 0;
   if (which >= 1 && which <= 3) { src = net->act[which]; bytes = npx * kHidden * 2; }
-  else if (which >= 11 && which <= 13) { src = net->dz[which - 10]; bytes = npx * kHidden * 2; }
-  else if (which == 14) { src = net->dz[4]; bytes = npx * net->cop[3] * 2; }
+  else if (which >= 11 && which <= 14) { src = net->dz[which - 10]; bytes = npx * kK * 2; }
   else if (which == 20) { src = net->grad; bytes = net->nparams * 4; }
   else return nfail(net, LFDPR_EINVAL, "unknown state");
   if (n_bytes < bytes) return nfail(net, LFDPR_EINVAL, "destination too small");

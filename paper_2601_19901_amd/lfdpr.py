@@ -91,11 +91,11 @@ def lib():
         "lfdpr_net_param_count": ([vp, p(i64)], C.c_int),
         "lfdpr_net_set_params": ([vp, vp, i64], C.c_int),
         "lfdpr_net_get_params": ([vp, vp, i64], C.c_int),
-        "lfdpr_net_pack_input": ([vp, vp, vp, i32, i32, C.c_float, vp], C.c_int),
-        "lfdpr_net_forward": ([vp, vp, i32, i32, vp], C.c_int),
+        "lfdpr_net_pack_input": ([vp, vp, vp, i32, i32, i32, C.c_float, vp], C.c_int),
+        "lfdpr_net_forward": ([vp, vp, i32, i32, i32, vp], C.c_int),
         "lfdpr_net_backward": ([vp, vp, vp], C.c_int),
         "lfdpr_net_adam_step": ([vp, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
-        "lfdpr_net_unpack_output": ([vp, vp, i32, i32, vp], C.c_int),
+        "lfdpr_net_unpack_output": ([vp, vp, i32, i32, i32, vp], C.c_int),
         "lfdpr_net_copy_state": ([vp, i32, vp, i64], C.c_int),
         "lfdpr_net_save": ([vp, C.c_char_p], C.c_int),
         "lfdpr_net_load": ([vp, C.c_char_p], C.c_int),
@@ -330,19 +330,24 @@ class Net:
         self._check(lib().lfdpr_net_get_params(self.h, _ptr(a), a.size))
         return a
 
-    def pack_input(self, views, depth, x, D: float):
+    def pack_input(self, views, depth, x, D: float = 1.0):
+        """views (n, H, W) int32 RGBA8 (+ depth (n, H, W) float32 or None) -> x (n, H, W, 4) int16 (BF16 bits)."""
         torch = self._torch
-        V, H, W = views.shape
-        _check_dev(views, torch.int32, V * H * W, "views")
-        _check_dev(depth, torch.float32, V * H * W, "depth")
-        _check_dev(x, torch.int16, H * W * 4 * self.V, "x")
-        self._check(lib().lfdpr_net_pack_input(self.h, _ptr(views), _ptr(depth), H, W, float(D), _ptr(x)))
+        n, H, W = views.shape
+        _check_dev(views, torch.int32, n * H * W, "views")
+        if depth is not None:
+            _check_dev(depth, torch.float32, n * H * W, "depth")
+        _check_dev(x, torch.int16, n * H * W * 4, "x")
+        self._check(lib().lfdpr_net_pack_input(self.h, _ptr(views), _ptr(depth) if depth is not None else None,
+                                               n, H, W, float(D), _ptr(x)))
 
-    def forward(self, x, y, H: int, W: int):
+    def forward(self, x, y):
+        """x, y: (n, H, W, 4) int16 BF16 bits, n a multiple of V."""
         torch = self._torch
-        _check_dev(x, torch.int16, H * W * 4 * self.V, "x")
-        _check_dev(y, torch.int16, H * W * 3 * self.V, "y")
-        self._check(lib().lfdpr_net_forward(self.h, _ptr(x), H, W, _ptr(y)))
+        n, H, W, _ = x.shape
+        _check_dev(x, torch.int16, n * H * W * 4, "x")
+        _check_dev(y, torch.int16, n * H * W * 4, "y")
+        self._check(lib().lfdpr_net_forward(self.h, _ptr(x), n, H, W, _ptr(y)))
 
     def backward(self, target):
         self._check(lib().lfdpr_net_backward(self.h, _ptr(target), _ptr(self.loss_buf)))
@@ -351,10 +356,11 @@ class Net:
     def adam_step(self, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
         self._check(lib().lfdpr_net_adam_step(self.h, lr, b1, b2, eps))
 
-    def unpack_output(self, y, views, H: int, W: int):
+    def unpack_output(self, y, views):
         torch = self._torch
-        _check_dev(views, torch.int32, self.V * H * W, "views")
-        self._check(lib().lfdpr_net_unpack_output(self.h, _ptr(y), H, W, _ptr(views)))
+        n, H, W, _ = y.shape
+        _check_dev(views, torch.int32, n * H * W, "views")
+        self._check(lib().lfdpr_net_unpack_output(self.h, _ptr(y), n, H, W, _ptr(views)))
 
     def copy_state(self, which: int, dst):
         self._check(lib().lfdpr_net_copy_state(self.h, which, _ptr(dst), dst.numel() * dst.element_size()))
@@ -372,10 +378,12 @@ def params_to_flat(params) -> np.ndarray:
                            for w, b in params])
 
 
-def flat_to_params(flat: np.ndarray, V: int, hidden: int = 32):
-    shapes = [(4 * V, hidden), (hidden, hidden), (hidden, hidden), (hidden, 3 * V)]
+NET_SHAPES = [(20, 32), (32, 32), (32, 32), (32, 3)]  # (cin, cout) per layer
+
+
+def flat_to_params(flat: np.ndarray):
     out, o = [], 0
-    for ci, co in shapes:
+    for ci, co in NET_SHAPES:
         w = flat[o:o + 9 * co * ci].reshape(9, co, ci)
         o += 9 * co * ci
         b = flat[o:o + co]

@@ -31,12 +31,23 @@ def test_conv_matches_explicit_loop():
 
 
 def test_zero_weights_give_identity():
-    V = 3
     rng = np.random.default_rng(1)
-    x = N.bf16(rng.random((4, 5, 4 * V)))
-    params = [(np.zeros((9, co, ci)), np.zeros(co)) for ci, co in N.layer_shapes(V, 8)]
-    _, _, y = N.forward(x, params, V)
-    np.testing.assert_array_equal(y, N.residual_rgb(x, V))
+    x = N.bf16(rng.random((5, 4, 6, 4)))
+    params = [(np.zeros((9, co, ci)), np.zeros(co)) for ci, co in N.layer_shapes(8)]
+    _, _, y = N.forward(x, params)
+    np.testing.assert_array_equal(y, x[..., :3])
+
+
+def test_assemble_reads_neighbour_views():
+    V = 6
+    x = np.zeros((V, 2, 3, 4))
+    for v in range(V):
+        x[v] = v + 1
+    a = N.assemble(x)
+    for v in range(V):
+        for k, off in enumerate(range(-2, 3)):
+            want = v + off + 1 if 0 <= v + off < V else 0
+            assert (a[v, :, :, 4 * k:4 * k + 4] == want).all()
 
 
 def test_identity_kernel_passes_input():
@@ -48,13 +59,12 @@ def test_identity_kernel_passes_input():
 
 
 def test_gradients_match_finite_differences():
-    V = 2
     rng = np.random.default_rng(3)
-    x = rng.random((5, 6, 4 * V))
-    t = rng.random((5, 6, 3 * V))
-    params = N.init_params(V, 7, hidden=6, scale=2.0)
+    x = rng.random((4, 5, 6, 4))
+    t = rng.random((4, 5, 6, 3))
+    params = N.init_params(7, hidden=6, scale=2.0)
     params = [(w, rng.normal(0, 0.1, b.shape)) for w, b in params]
-    loss, grads, _ = N.loss_and_grads(x, t, params, V, round_bf16=False)
+    loss, grads, _ = N.loss_and_grads(x, t, params, round_bf16=False)
     h = 1e-6
     for k in range(4):
         for which in (0, 1):
@@ -63,9 +73,9 @@ def test_gradients_match_finite_differences():
                 idx = tuple(rng.integers(0, s) for s in arr.shape)
                 old = arr[idx]
                 arr[idx] = old + h
-                lp, _, _ = N.loss_and_grads(x, t, params, V, round_bf16=False)
+                lp, _, _ = N.loss_and_grads(x, t, params, round_bf16=False)
                 arr[idx] = old - h
-                lm, _, _ = N.loss_and_grads(x, t, params, V, round_bf16=False)
+                lm, _, _ = N.loss_and_grads(x, t, params, round_bf16=False)
                 arr[idx] = old
                 fd = (lp - lm) / (2 * h)
                 an = grads[k][which][idx]
