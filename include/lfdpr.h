@@ -191,11 +191,61 @@ int lfdpr_timing(lfdpr_ctx* ctx, int enable);
 int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n_launches);
 
 /* ------------------------------------------------------------------------
+ * Launch shape, autotuning and batches (not part of the paper).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t splat_blocks;  /* workgroups of the splat and fetch launches */
+  int32_t key_layout;    /* 0: 64-bit keys [view][y][x]; 1: [y][view][x] (a row of every view adjacent) */
+  float ms;              /* measured time of one frame (or one batch) */
+} lfdpr_tune_entry;
+typedef struct {
+  int32_t n, best;       /* entries tried; index of the fastest (now in use) */
+  lfdpr_tune_entry entries[16];
+} lfdpr_tune_result;
+
+/* Sets the splat launch shape and key layout of the context's single frames.
+ * Results do not depend on them (keys are exact integers; layout only moves
+ * them in memory).  Synchronises the stream. */
+int lfdpr_set_launch(lfdpr_ctx* ctx, int32_t splat_blocks, int32_t key_layout);
+
+/* Renders a scene (model: host 3x4; views: device as in lfdpr_render_frame)
+ * under every candidate launch shape and key layout, times each with HIP
+ * events on the stream and keeps the fastest.  Synchronous. */
+int lfdpr_autotune(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, lfdpr_tune_result* res);
+
+typedef struct lfdpr_batch lfdpr_batch;
+
+/* A batch renders n scene frames with one launch per pipeline stage over all
+ * of them.  views[k] is the rig of item k (host array of n): every item must
+ * have the same V*S, W, H, fovy and aspect; cones, D and jitter may differ.
+ * The batch owns its key, triangle and point buffers (point_capacity points in
+ * total; 0 = 32M) and a stream of its own.  The scenes must stay uploaded. */
+int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, const lfdpr_view_params* views,
+                       int64_t point_capacity, lfdpr_batch** out);
+int lfdpr_batch_destroy(lfdpr_batch* batch);
+const char* lfdpr_batch_last_error(lfdpr_batch* batch);
+/* 1 (default): the first lfdpr_batch_render captures the launch sequence into a
+ * hipGraph and later calls with the same output pointers replay it; 0: plain
+ * launches. */
+int lfdpr_batch_use_graph(lfdpr_batch* batch, int enable);
+/* models: host n*12 floats (row-major 3x4 per item); views: device
+ * n*(V*S)*H*W uint32 RGBA8, item-major; panels: device n*Hp*Wp*3 bytes
+ * interleaved with the context's lens (requires S == 1), or NULL.  Ordered
+ * after earlier work on the context's stream; later work on that stream sees
+ * the results. */
+int lfdpr_batch_render(lfdpr_batch* batch, const float* models, uint32_t* views, uint8_t* panels);
+/* Totals of the last batch frame.  Synchronous. */
+int lfdpr_batch_stats(lfdpr_batch* batch, lfdpr_stats* stats);
+/* The autotuner for a batch (see lfdpr_autotune).  Synchronous. */
+int lfdpr_batch_autotune(lfdpr_batch* batch, const float* models, uint32_t* views, lfdpr_tune_result* res);
+
+/* ------------------------------------------------------------------------
  * Learned angular reconstruction (a stand-in for 4x angular supersampling,
  * Sec. 4; not part of the paper).  The network is applied to every view v of
  * a frame of V views: its input at a pixel is (R, G, B, d = D/Z - 1; d = -1
  * where empty) of views v-2 .. v+2 (zero beyond the rig), four zero-padded
- * 3x3 convolutions 20 -> 32 -> 32 -> 32 -> 3 with ReLU between them, FP32
+ * 3x3 convolutions 20 -> 32 -> 32 -> 32 -> 3 with ReLU between them, dilated
+ * horizontally by 1, 3, 9, 1 (tap (dy, dx) reads pixel (y+dy, x+dil*dx)), FP32
  * accumulation on BF16 MFMA, BF16 activations; the output is view v's RGB plus
  * the network.  Tensors: compact input x [view][H][W][4] BF16 (as written by
  * lfdpr_net_pack_input), output y [view][H][W][4] BF16 (R, G, B, 0).

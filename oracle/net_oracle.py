@@ -9,8 +9,9 @@ Network (a stand-in for 4x angular supersampling, not in the paper): it is
 applied to each view v of a frame separately.  Its input at a pixel is
 (R, G, B, d) of views v-2 .. v+2 (d = D/Z - 1, -1 for background; views
 beyond the rig are zero), 20 channels; four zero-padded 3x3 convolutions
-20 -> 32 -> 32 -> 32 -> 3 with ReLU between them; the output adds view v's own
-RGB (residual).  Weights are laid out [tap][cout][cin] with tap = 3*(dy+1) +
+20 -> 32 -> 32 -> 32 -> 3 with ReLU between them, dilated horizontally by
+1, 3, 9, 1 (one view step shifts content by several pixels horizontally);
+the output adds view v's own RGB (residual).  Weights are laid out [tap][cout][cin] with tap = 3*(dy+1) +
 (dx+1) reading input pixel (y+dy, x+dx); biases [cout].
 
 Pins (tests/test_net_oracle.py): finite differences of the double-precision
@@ -36,6 +37,7 @@ def bf16(x) -> np.ndarray:
 
 NEIGH = 2                 # views v-2 .. v+2
 CIN0 = 4 * (2 * NEIGH + 1)  # 20 input channels
+DILATION = (1, 3, 9, 1)   # horizontal dilation of the four layers (receptive field +-14 px across, +-4 down)
 
 
 def layer_shapes(hidden: int = 32):
@@ -52,42 +54,43 @@ def init_params(seed: int, hidden: int = 32, scale: float = 1.0):
     return ps
 
 
-def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Zero-padded 3x3 convolution: x (H, W, Cin), w (9, Cout, Cin), b (Cout)."""
+def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray, dil: int = 1) -> np.ndarray:
+    """Zero-padded 3x3 convolution with horizontal dilation `dil`: tap (dy, dx)
+    reads pixel (y + dy, x + dil*dx).  x (H, W, Cin), w (9, Cout, Cin), b (Cout)."""
     H, W, _ = x.shape
-    xp = np.zeros((H + 2, W + 2, x.shape[2]))
-    xp[1:-1, 1:-1] = x
+    xp = np.zeros((H + 2, W + 2 * dil, x.shape[2]))
+    xp[1:-1, dil:dil + W] = x
     out = np.broadcast_to(b, (H, W, w.shape[1])).copy()
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             tap = 3 * (dy + 1) + (dx + 1)
-            out += xp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W] @ w[tap].T
+            out += xp[1 + dy:1 + dy + H, dil + dil * dx:dil + dil * dx + W] @ w[tap].T
     return out
 
 
-def conv3x3_wgrad(x: np.ndarray, dz: np.ndarray):
+def conv3x3_wgrad(x: np.ndarray, dz: np.ndarray, dil: int = 1):
     """Gradients of conv3x3 w.r.t. w (9, Cout, Cin) and b."""
     H, W, _ = x.shape
-    xp = np.zeros((H + 2, W + 2, x.shape[2]))
-    xp[1:-1, 1:-1] = x
+    xp = np.zeros((H + 2, W + 2 * dil, x.shape[2]))
+    xp[1:-1, dil:dil + W] = x
     dw = np.zeros((9, dz.shape[2], x.shape[2]))
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             tap = 3 * (dy + 1) + (dx + 1)
-            xs = xp[1 + dy:1 + dy + H, 1 + dx:1 + dx + W].reshape(-1, x.shape[2])
+            xs = xp[1 + dy:1 + dy + H, dil + dil * dx:dil + dil * dx + W].reshape(-1, x.shape[2])
             dw[tap] = dz.reshape(-1, dz.shape[2]).T @ xs
     return dw, dz.reshape(-1, dz.shape[2]).sum(axis=0)
 
 
-def conv3x3_xgrad(dz: np.ndarray, w: np.ndarray) -> np.ndarray:
+def conv3x3_xgrad(dz: np.ndarray, w: np.ndarray, dil: int = 1) -> np.ndarray:
     """Gradient of conv3x3 w.r.t. its input: the transposed convolution."""
     H, W, _ = dz.shape
-    dx_ = np.zeros((H + 2, W + 2, w.shape[2]))
+    dx_ = np.zeros((H + 2, W + 2 * dil, w.shape[2]))
     for dy in (-1, 0, 1):
         for dx in (-1, 0, 1):
             tap = 3 * (dy + 1) + (dx + 1)
-            dx_[1 + dy:1 + dy + H, 1 + dx:1 + dx + W] += dz @ w[tap]
-    return dx_[1:-1, 1:-1]
+            dx_[1 + dy:1 + dy + H, dil + dil * dx:dil + dil * dx + W] += dz @ w[tap]
+    return dx_[1:-1, dil:dil + W]
 
 
 def assemble(x: np.ndarray) -> np.ndarray:
@@ -102,7 +105,7 @@ def assemble(x: np.ndarray) -> np.ndarray:
     return out
 
 
-def forward(x: np.ndarray, params, round_bf16: bool = True):
+def forward(x: np.ndarray, params, round_bf16: bool = True, dil=DILATION):
     """x: compact input (V, H, W, 4).  Returns (pre-activations per layer,
     activations a0..a3 with a0 the assembled input, output y (V, H, W, 3))."""
     r = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
@@ -111,7 +114,7 @@ def forward(x: np.ndarray, params, round_bf16: bool = True):
     zs = []
     for k, (w, b) in enumerate(params):
         w = r(w)
-        z = np.stack([conv3x3(a[-1][v], w, b) for v in range(x.shape[0])])
+        z = np.stack([conv3x3(a[-1][v], w, b, dil[k]) for v in range(x.shape[0])])
         zs.append(z)
         if k < 3:
             a.append(r(np.maximum(z, 0.0)))
@@ -119,11 +122,11 @@ def forward(x: np.ndarray, params, round_bf16: bool = True):
     return zs, a, y
 
 
-def loss_and_grads(x: np.ndarray, target: np.ndarray, params, round_bf16: bool = True):
+def loss_and_grads(x: np.ndarray, target: np.ndarray, params, round_bf16: bool = True, dil=DILATION):
     """MSE loss over all output values (V, H, W, 3) and the gradients of every
     weight and bias."""
     r = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
-    zs, a, y = forward(x, params, round_bf16)
+    zs, a, y = forward(x, params, round_bf16, dil)
     n = y.size
     diff = y - target
     loss = float((diff * diff).mean())
@@ -135,12 +138,12 @@ def loss_and_grads(x: np.ndarray, target: np.ndarray, params, round_bf16: bool =
         dw = np.zeros_like(params[k][0], dtype=np.float64)
         db = np.zeros_like(params[k][1], dtype=np.float64)
         for v in range(V):
-            gw, gb = conv3x3_wgrad(a[k][v], dz[v])
+            gw, gb = conv3x3_wgrad(a[k][v], dz[v], dil[k])
             dw += gw
             db += gb
         grads[k] = (dw, db)
         if k > 0:
-            da = np.stack([conv3x3_xgrad(dz[v], w) for v in range(V)])
+            da = np.stack([conv3x3_xgrad(dz[v], w, dil[k]) for v in range(V)])
             dz = r(da * (a[k] > 0))
     return loss, grads, y
 

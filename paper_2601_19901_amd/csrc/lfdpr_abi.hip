@@ -74,8 +74,12 @@ struct lfdpr_ctx {
   float* dbgf = nullptr;
   int32_t* dbgi = nullptr;
   int64_t dbg_cap = 0;
-  // launch shape of the splat kernel
+  // single-frame item table (device) and its host copy
+  Item* d_item1 = nullptr;
+  Item h_item1{};
+  // launch shape of the splat kernel and key layout (autotuned)
   int splat_blocks = 4096;
+  int key_layout = 0;
   // stage timing: event pairs recorded on the stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -151,6 +155,80 @@ void stage(lfdpr_ctx* ctx, int id, hipEvent_t a, hipEvent_t b) {
 }  // namespace
 
 hipStream_t ctx_stream_of(lfdpr_ctx* c) { return c->stream; }
+
+namespace {
+
+// Rig in double, rounded once: eye offsets b_r = D tan(cone/2) (2 q_r / V - 1),
+// kshift_r = b_r / D, and the shared projection constants.
+void build_rig(const lfdpr_view_params& v, Rig& rg, std::vector<float>& eye, std::vector<float>& ks,
+               std::vector<double>& q) {
+  const int64_t nviews = (int64_t)v.V * v.S;
+  const double D = v.D;
+  const double B = D * std::tan((double)v.cone_deg * M_PI / 180.0 / 2.0);
+  const double tf = std::tan((double)v.fovy_deg * M_PI / 180.0 / 2.0);
+  eye.assign(nviews, 0.0f);
+  ks.assign(nviews, 0.0f);
+  q.assign(nviews, 0.0);
+  for (int vv = 0; vv < v.V; ++vv)
+    for (int k = 0; k < v.S; ++k) {
+      int r = vv * v.S + k;
+      q[r] = v.S == 1 ? vv + 0.5 : vv + (k + 0.5 + (double)v.jitter[r]) / v.S;
+      double b = B * (2.0 * q[r] / v.V - 1.0);
+      eye[r] = (float)b;
+      ks[r] = (float)(b / D);
+    }
+  rg = Rig{};
+  rg.n_views = (int32_t)nviews;
+  rg.W = v.W;
+  rg.H = v.H;
+  rg.mip = v.mip ? 1 : 0;
+  rg.fx = (float)((v.W / 2.0) / ((double)v.aspect * tf));
+  rg.fy = (float)((v.H / 2.0) / tf);
+  rg.cx = (float)(v.W / 2.0);
+  rg.cy = (float)(v.H / 2.0);
+  rg.rD = (float)(1.0 / D);
+  rg.znear = v.znear;
+  rg.fxfy = rg.fx * rg.fy;
+}
+
+bool view_params_ok(const lfdpr_view_params* v) {
+  const int64_t nviews = (int64_t)v->V * v->S;
+  if (v->V < 1 || v->S < 1 || nviews > 1024 || v->W < 1 || v->H < 1 || v->W > 4096 || v->H > 4096 ||
+      !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) || !(v->aspect > 0.0f) || !(v->D > 0.0f) ||
+      !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f) || !(v->znear > 0.0f) || (v->S > 1 && !v->jitter) ||
+      v->point_capacity < 0 || v->point_capacity > (1ll << 31))
+    return false;
+  if (v->S > 1)
+    for (int64_t k = 0; k < nviews; ++k)
+      if (!(v->jitter[k] >= -0.5f && v->jitter[k] < 0.5f)) return false;
+  return true;
+}
+
+InterleaveArgs interleave_args(const lfdpr_lens_params& l, const uint32_t* views, int32_t n_views, int32_t W,
+                               int32_t H, uint8_t* panel) {
+  const double two32 = 4294967296.0;
+  auto mod32 = [](long long v) { return (uint32_t)((unsigned long long)v & 0xFFFFFFFFull); };
+  InterleaveArgs a{};
+  a.views = views;
+  a.V = n_views;
+  a.Wv = W;
+  a.Hv = H;
+  a.Wp = l.Wp;
+  a.Hp = l.Hp;
+  a.mode = l.mode;
+  a.K1 = mod32(std::llround(two32 / l.pitch_subpx));
+  a.Ky = mod32(std::llround(-3.0 * l.slope * two32 / l.pitch_subpx));
+  a.K0 = mod32(std::llround(l.offset * two32));
+  for (int k = 0; k < 8; ++k) {
+    a.du[k] = (l.mode & LFDPR_RECON_ANGULAR) ? l.taps[k][0] : 0;
+    a.dx[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][1] : 0;
+    a.dy[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][2] : 0;
+  }
+  a.panel = panel;
+  return a;
+}
+
+}  // namespace
 int ctx_device_of(lfdpr_ctx* c) { return c->device; }
 
 extern "C" {
@@ -179,7 +257,8 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
   ctx = new lfdpr_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
-  if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess) {
+  if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess || dalloc(ctx->d_item1, 1) != hipSuccess) {
+    dfree(ctx->d_stats);
     delete ctx;
     return LFDPR_ENOMEM;
   }
@@ -221,6 +300,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_tiles);
   dfree(ctx->d_big);
   dfree(ctx->d_stats);
+  dfree(ctx->d_item1);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return LFDPR_OK;
@@ -298,43 +378,14 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
 
 int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   if (!ctx || !v) return fail(ctx, LFDPR_EINVAL, "null argument");
-  int64_t nviews = (int64_t)v->V * v->S;
-  if (v->V < 1 || v->S < 1 || nviews > 1024 || v->W < 1 || v->H < 1 || v->W > 4096 || v->H > 4096 ||
-      !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) || !(v->aspect > 0.0f) || !(v->D > 0.0f) ||
-      !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f) || !(v->znear > 0.0f) || (v->S > 1 && !v->jitter) ||
-      v->point_capacity < 0 || v->point_capacity > (1ll << 31))
-    return fail(ctx, LFDPR_EINVAL, "view parameters out of range");
-  if (v->S > 1)
-    for (int64_t k = 0; k < nviews; ++k)
-      if (!(v->jitter[k] >= -0.5f && v->jitter[k] < 0.5f)) return fail(ctx, LFDPR_EINVAL, "jitter out of range");
+  if (!view_params_ok(v)) return fail(ctx, LFDPR_EINVAL, "view parameters out of range");
+  const int64_t nviews = (int64_t)v->V * v->S;
   HIPOK(hipSetDevice(ctx->device));
   HIPOK(hipStreamSynchronize(ctx->stream));
-  // rig in double, rounded once
-  const double D = v->D;
-  const double B = D * std::tan((double)v->cone_deg * M_PI / 180.0 / 2.0);
-  const double tf = std::tan((double)v->fovy_deg * M_PI / 180.0 / 2.0);
-  std::vector<float> eye(nviews), ks(nviews);
-  std::vector<double> q(nviews);
-  for (int vv = 0; vv < v->V; ++vv)
-    for (int k = 0; k < v->S; ++k) {
-      int r = vv * v->S + k;
-      q[r] = v->S == 1 ? vv + 0.5 : vv + (k + 0.5 + (double)v->jitter[r]) / v->S;
-      double b = B * (2.0 * q[r] / v->V - 1.0);
-      eye[r] = (float)b;
-      ks[r] = (float)(b / D);
-    }
   Rig rg{};
-  rg.n_views = (int32_t)nviews;
-  rg.W = v->W;
-  rg.H = v->H;
-  rg.mip = v->mip ? 1 : 0;
-  rg.fx = (float)((v->W / 2.0) / ((double)v->aspect * tf));
-  rg.fy = (float)((v->H / 2.0) / tf);
-  rg.cx = (float)(v->W / 2.0);
-  rg.cy = (float)(v->H / 2.0);
-  rg.rD = (float)(1.0 / D);
-  rg.znear = v->znear;
-  rg.fxfy = rg.fx * rg.fy;
+  std::vector<float> eye, ks;
+  std::vector<double> q;
+  build_rig(*v, rg, eye, ks, q);
   // angular filter table: sub-views within one interval of each view centre
   int32_t maxe = 3 * v->S;
   std::vector<int32_t> acnt(v->V, 0), asrc((size_t)v->V * maxe, 0);
@@ -425,16 +476,30 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   int rc = ensure_tri_buffers(ctx, s.nt);
   if (rc) return rc;
   hipStream_t st = ctx->stream;
+  Item one{};
+  one.pos = s.pos;
+  one.uv = s.uv;
+  one.idx = s.idx;
+  one.tex = s.tex;
+  one.texinfo = s.texinfo;
+  one.texels = s.texels;
+  one.tri_base = 0;
+  one.nt = s.nt;
+  one.rig = ctx->rig;
+  one.keys = ctx->d_keys;
+  one.key_layout = ctx->key_layout;
+  if (std::memcmp(&one, &ctx->h_item1, sizeof it) != 0) {
+    HIPOK(hipStreamSynchronize(st));  // earlier frames may still read the table
+    HIPOK(hipMemcpy(ctx->d_item1, &one, sizeof one, hipMemcpyHostToDevice));
+    ctx->h_item1 = one;
+  }
   launch_fill_u64(ctx->d_stats, STAT_SLOTS, 0ull, st);
   SetupArgs sa{};
-  sa.pos = s.pos;
-  sa.uv = s.uv;
-  sa.idx = s.idx;
-  sa.tex = s.tex;
+  sa.items = ctx->d_item1;
+  sa.n_items = 1;
   sa.nt = s.nt;
   std::memcpy(sa.model.m, model, sizeof sa.model.m);
-  sa.rig = ctx->rig;
-  sa.texinfo = s.texinfo;
+  sa.models = nullptr;
   sa.lod_thr = ctx->d_lod_thr;
   sa.counts = ctx->d_counts;
   sa.rec = ctx->d_rec;
@@ -448,12 +513,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, st);
   hipEvent_t e2 = mark(ctx);
   EmitArgs ea{};
+  ea.items = ctx->d_item1;
   ea.nt = s.nt;
   ea.counts = ctx->d_counts;
   ea.offsets = ctx->d_offsets;
   ea.em = ctx->d_em;
-  ea.texinfo = s.texinfo;
-  ea.texels = s.texels;
   ea.points = ctx->d_points;
   ea.n_points = ctx->d_stats + STAT_TOTAL;
   ea.big = ctx->d_big;
@@ -462,15 +526,15 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   launch_emit(ea, ctx->splat_blocks, st);
   hipEvent_t e3 = mark(ctx);
   SplatArgs pa{};
-  pa.rig = ctx->rig;
+  pa.items = ctx->d_item1;
+  pa.table_rig = ctx->rig;
   pa.points = ctx->d_points;
   pa.n_points = ctx->d_stats + STAT_TOTAL;
   pa.cap = ctx->cap;
   pa.rec = ctx->d_rec;
-  pa.keys = ctx->d_keys;
   launch_splat(pa, ctx->splat_blocks, st);
   hipEvent_t e4 = mark(ctx);
-  launch_resolve(ctx->d_keys, ctx->n_keys, views, depth, st);
+  launch_resolve(ctx->d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st);
   hipEvent_t e5 = mark(ctx);
   HIPOK(hipGetLastError());
   stage(ctx, 0, e0, e1);
@@ -487,26 +551,7 @@ int lfdpr_reconstruct(lfdpr_ctx* ctx, const uint32_t* views, int32_t n_views, in
   if (!ctx->lens_set) return fail(ctx, LFDPR_ESTATE, "lfdpr_set_lens first");
   if (n_views < 1 || n_views > 4096 || W < 1 || H < 1 || W > 16384 || H > 16384)
     return fail(ctx, LFDPR_EINVAL, "view stack size out of range");
-  const lfdpr_lens_params& l = ctx->lens;
-  const double two32 = 4294967296.0;
-  auto mod32 = [](long long v) { return (uint32_t)((unsigned long long)v & 0xFFFFFFFFull); };
-  InterleaveArgs a{};
-  a.views = views;
-  a.V = n_views;
-  a.Wv = W;
-  a.Hv = H;
-  a.Wp = l.Wp;
-  a.Hp = l.Hp;
-  a.mode = l.mode;
-  a.K1 = mod32(std::llround(two32 / l.pitch_subpx));
-  a.Ky = mod32(std::llround(-3.0 * l.slope * two32 / l.pitch_subpx));
-  a.K0 = mod32(std::llround(l.offset * two32));
-  for (int k = 0; k < 8; ++k) {
-    a.du[k] = (l.mode & LFDPR_RECON_ANGULAR) ? l.taps[k][0] : 0;
-    a.dx[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][1] : 0;
-    a.dy[k] = (l.mode & LFDPR_RECON_SPATIAL) ? (int32_t)l.taps[k][2] : 0;
-  }
-  a.panel = panel;
+  InterleaveArgs a = interleave_args(ctx->lens, views, n_views, W, H, panel);
   HIPOK(hipSetDevice(ctx->device));
   hipEvent_t e0 = mark(ctx);
   launch_interleave(a, ctx->stream);
@@ -596,6 +641,377 @@ int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n) {
     ms_sum[m.first] += ms;
     n[m.first] += 1;
   }
+  return LFDPR_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batches: several scenes rendered by the same kernels over one concatenated
+// triangle index space (one launch per stage for the whole batch), optionally
+// captured once into a hipGraph and replayed with new model matrices.
+// ============================================================================
+
+struct lfdpr_batch {
+  lfdpr_ctx* ctx = nullptr;
+  int n = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_stage = nullptr;
+  std::vector<Item> items;
+  Item* d_items = nullptr;
+  std::vector<float*> eyes;
+  Model* d_models = nullptr;
+  Model* h_models = nullptr;  // pinned staging
+  uint64_t* keys = nullptr;
+  int64_t nt = 0, per_item_px = 0;
+  uint32_t* counts = nullptr;
+  uint64_t* offsets = nullptr;
+  TriRec* rec = nullptr;
+  TriEmit* em = nullptr;
+  uint64_t* tiles = nullptr;
+  uint32_t* big = nullptr;
+  uint64_t* stats = nullptr;
+  Point* points = nullptr;
+  int64_t cap = 0;
+  Rig table_rig{};
+  int splat_blocks = 4096, key_layout = 0;
+  bool use_graph = true, g_valid = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t* g_views = nullptr;
+  uint8_t* g_panels = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int bfail(lfdpr_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  return code;
+}
+
+#define BHIP(call)                                                                                  \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) return bfail(b, LFDPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_free(lfdpr_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (float* e : b->eyes) dfree(e);
+  dfree(b->d_items);
+  dfree(b->d_models);
+  if (b->h_models) (void)hipHostFree(b->h_models);
+  dfree(b->keys);
+  dfree(b->counts);
+  dfree(b->offsets);
+  dfree(b->rec);
+  dfree(b->em);
+  dfree(b->tiles);
+  dfree(b->big);
+  dfree(b->stats);
+  dfree(b->points);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->ev_stage) (void)hipEventDestroy(b->ev_stage);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+// The whole batch frame on b->stream: only kernel launches (capturable).
+void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
+  hipStream_t st = b->stream;
+  launch_fill_u64(b->stats, STAT_SLOTS, 0ull, st);
+  SetupArgs sa{};
+  sa.items = b->d_items;
+  sa.n_items = b->n;
+  sa.nt = b->nt;
+  sa.models = b->d_models;
+  sa.lod_thr = b->ctx->d_lod_thr;
+  sa.counts = b->counts;
+  sa.rec = b->rec;
+  sa.em = b->em;
+  sa.stats = b->stats;
+  launch_tri_setup(sa, st);
+  launch_scan(b->counts, b->nt, b->tiles, b->offsets, b->stats + STAT_TOTAL, st);
+  EmitArgs ea{};
+  ea.items = b->d_items;
+  ea.nt = b->nt;
+  ea.counts = b->counts;
+  ea.offsets = b->offsets;
+  ea.em = b->em;
+  ea.points = b->points;
+  ea.n_points = b->stats + STAT_TOTAL;
+  ea.big = b->big;
+  ea.n_big = b->stats + STAT_BIG;
+  ea.cap = b->cap;
+  launch_emit(ea, b->splat_blocks, st);
+  SplatArgs pa{};
+  pa.items = b->d_items;
+  pa.table_rig = b->table_rig;
+  pa.points = b->points;
+  pa.n_points = b->stats + STAT_TOTAL;
+  pa.cap = b->cap;
+  pa.rec = b->rec;
+  launch_splat(pa, b->splat_blocks, st);
+  launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st);
+  if (panels) {
+    InterleaveArgs ia = interleave_args(b->ctx->lens, views, b->table_rig.n_views, b->table_rig.W, b->table_rig.H, panels);
+    launch_interleave_batch(ia, b->n, b->per_item_px, (int64_t)b->ctx->lens.Wp * b->ctx->lens.Hp * 3, st);
+  }
+}
+
+int batch_set_shape(lfdpr_batch* b, int splat_blocks, int key_layout) {
+  if (splat_blocks == b->splat_blocks && key_layout == b->key_layout) return LFDPR_OK;
+  BHIP(hipStreamSynchronize(b->stream));
+  b->splat_blocks = splat_blocks;
+  if (key_layout != b->key_layout) {
+    b->key_layout = key_layout;
+    for (auto& it : b->items) it.key_layout = key_layout;
+    BHIP(hipMemcpy(b->d_items, b->items.data(), sizeof(Item) * b->n, hipMemcpyHostToDevice));
+  }
+  b->g_valid = false;
+  return LFDPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, const lfdpr_view_params* views,
+                       int64_t point_capacity, lfdpr_batch** out) {
+  if (!ctx || !out || !scene_ids || !views || n < 1 || n > 256 || point_capacity < 0 || point_capacity > (1ll << 31))
+    return fail(ctx, LFDPR_EINVAL, "batch arguments out of range");
+  *out = nullptr;
+  for (int k = 0; k < n; ++k) {
+    if (!view_params_ok(&views[k])) return fail(ctx, LFDPR_EINVAL, "view parameters out of range");
+    if (views[k].V * views[k].S != views[0].V * views[0].S || views[k].W != views[0].W || views[k].H != views[0].H ||
+        views[k].fovy_deg != views[0].fovy_deg || views[k].aspect != views[0].aspect)
+      return fail(ctx, LFDPR_EINVAL, "batch items must share views, size, field of view and aspect");
+    if (ctx->scenes.find(scene_ids[k]) == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  }
+  HIPOK(hipSetDevice(ctx->device));
+  lfdpr_batch* b = new lfdpr_batch();
+  b->ctx = ctx;
+  b->n = n;
+  bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&b->ev_stage, hipEventDisableTiming) == hipSuccess;
+  b->items.resize(n);
+  int64_t tri_base = 0;
+  for (int k = 0; k < n && ok; ++k) {
+    const SceneDev& s = ctx->scenes[scene_ids[k]];
+    Rig rg{};
+    std::vector<float> eye, ks;
+    std::vector<double> q;
+    build_rig(views[k], rg, eye, ks, q);
+    float* d = nullptr;
+    ok = dalloc(d, 2 * eye.size()) == hipSuccess;
+    if (!ok) break;
+    b->eyes.push_back(d);
+    ok = hipMemcpy(d, eye.data(), 4 * eye.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(d + eye.size(), ks.data(), 4 * ks.size(), hipMemcpyHostToDevice) == hipSuccess;
+    rg.eye = d;
+    rg.kshift = d + eye.size();
+    Item& it = b->items[k];
+    it = Item{};
+    it.pos = s.pos;
+    it.uv = s.uv;
+    it.idx = s.idx;
+    it.tex = s.tex;
+    it.texinfo = s.texinfo;
+    it.texels = s.texels;
+    it.tri_base = tri_base;
+    it.nt = s.nt;
+    it.rig = rg;
+    it.key_layout = 0;
+    tri_base += s.nt;
+    if (k == 0) b->table_rig = rg;
+  }
+  b->nt = tri_base;
+  b->per_item_px = (int64_t)b->table_rig.n_views * b->table_rig.W * b->table_rig.H;
+  b->cap = point_capacity ? point_capacity : (32ll << 20);
+  const int64_t ntb = b->nt > 1024 ? b->nt : 1024;
+  if (ok)
+    ok = dalloc(b->keys, (size_t)(b->per_item_px * n)) == hipSuccess && dalloc(b->counts, ntb) == hipSuccess &&
+         dalloc(b->offsets, ntb) == hipSuccess && dalloc(b->rec, ntb) == hipSuccess && dalloc(b->em, ntb) == hipSuccess &&
+         dalloc(b->tiles, (ntb + 1023) / 1024 + 1) == hipSuccess && dalloc(b->big, ntb) == hipSuccess &&
+         dalloc(b->stats, STAT_SLOTS) == hipSuccess && dalloc(b->points, (size_t)b->cap) == hipSuccess &&
+         dalloc(b->d_items, n) == hipSuccess && dalloc(b->d_models, n) == hipSuccess &&
+         hipHostMalloc((void**)&b->h_models, sizeof(Model) * n, hipHostMallocDefault) == hipSuccess;
+  if (ok) {
+    for (int k = 0; k < n; ++k) b->items[k].keys = b->keys + b->per_item_px * k;
+    ok = hipMemcpy(b->d_items, b->items.data(), sizeof(Item) * n, hipMemcpyHostToDevice) == hipSuccess;
+    launch_fill_u64(b->keys, b->per_item_px * n, ~0ull, b->stream);
+    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(b->ev_stage, b->stream) == hipSuccess &&
+         hipStreamSynchronize(b->stream) == hipSuccess;
+  }
+  if (!ok) {
+    batch_free(b);
+    delete b;
+    return fail(ctx, LFDPR_ENOMEM, "batch buffers");
+  }
+  *out = b;
+  return LFDPR_OK;
+}
+
+int lfdpr_batch_destroy(lfdpr_batch* b) {
+  if (!b) return LFDPR_OK;
+  (void)hipSetDevice(b->ctx->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
+  delete b;
+  return LFDPR_OK;
+}
+
+const char* lfdpr_batch_last_error(lfdpr_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int lfdpr_batch_use_graph(lfdpr_batch* b, int enable) {
+  if (!b) return LFDPR_EINVAL;
+  b->use_graph = enable != 0;
+  return LFDPR_OK;
+}
+
+int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uint8_t* panels) {
+  if (!b || !models || !views) return bfail(b, LFDPR_EINVAL, "null argument");
+  if (panels && (!b->ctx->lens_set || b->table_rig.n_views < 1))
+    return bfail(b, LFDPR_ESTATE, "lfdpr_set_lens on the context first");
+  for (int k = 0; k < 12 * b->n; ++k)
+    if (!std::isfinite(models[k])) return bfail(b, LFDPR_EINVAL, "non-finite model matrix");
+  BHIP(hipSetDevice(b->ctx->device));
+  // model matrices: pinned staging -> device, outside any graph
+  BHIP(hipEventSynchronize(b->ev_stage));
+  std::memcpy(b->h_models, models, sizeof(Model) * b->n);
+  BHIP(hipEventRecord(b->ev_in, b->ctx->stream));
+  BHIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  BHIP(hipMemcpyAsync(b->d_models, b->h_models, sizeof(Model) * b->n, hipMemcpyHostToDevice, b->stream));
+  BHIP(hipEventRecord(b->ev_stage, b->stream));
+  if (b->use_graph) {
+    if (!b->g_valid || b->g_views != views || b->g_panels != panels) {
+      if (b->exec) { BHIP(hipGraphExecDestroy(b->exec)); b->exec = nullptr; }
+      if (b->graph) { BHIP(hipGraphDestroy(b->graph)); b->graph = nullptr; }
+      BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      batch_enqueue(b, views, panels);
+      hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
+      if (ce != hipSuccess) return bfail(b, LFDPR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+      BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+      b->g_views = views;
+      b->g_panels = panels;
+      b->g_valid = true;
+    }
+    BHIP(hipGraphLaunch(b->exec, b->stream));
+  } else {
+    batch_enqueue(b, views, panels);
+    BHIP(hipGetLastError());
+  }
+  BHIP(hipEventRecord(b->ev_out, b->stream));
+  BHIP(hipStreamWaitEvent(b->ctx->stream, b->ev_out, 0));
+  return LFDPR_OK;
+}
+
+int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
+  if (!b || !out) return LFDPR_EINVAL;
+  uint64_t st[STAT_SLOTS];
+  BHIP(hipSetDevice(b->ctx->device));
+  BHIP(hipStreamSynchronize(b->stream));
+  BHIP(hipMemcpy(st, b->stats, sizeof st, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->points = (int64_t)st[STAT_TOTAL];
+  out->active_tris = (int64_t)st[STAT_ACTIVE];
+  out->point_views = (int64_t)st[STAT_POINT_VIEWS];
+  out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
+  out->capacity = b->cap;
+  out->point_overflow = out->points > b->cap ? 1 : 0;
+  out->n_views = b->table_rig.n_views;
+  return out->point_overflow ? LFDPR_EOVERFLOW : LFDPR_OK;
+}
+
+// Times every candidate (splat launch blocks x key layout) on the batch's own
+// workload and keeps the fastest; the results are returned per candidate.
+int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, lfdpr_tune_result* res) {
+  if (!b || !models || !views || !res) return bfail(b, LFDPR_EINVAL, "null argument");
+  static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
+  const bool graph = b->use_graph;
+  b->use_graph = false;
+  hipEvent_t t0, t1;
+  BHIP(hipEventCreate(&t0));
+  BHIP(hipEventCreate(&t1));
+  std::memset(res, 0, sizeof *res);
+  float best = INFINITY;
+  int rc = LFDPR_OK;
+  for (int layout = 0; layout < 2 && !rc; ++layout)
+    for (int bi = 0; bi < 5 && !rc; ++bi) {
+      rc = batch_set_shape(b, kBlocks[bi], layout);
+      for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
+      if (rc) break;
+      (void)hipEventRecord(t0, b->stream);
+      for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
+      (void)hipEventRecord(t1, b->stream);
+      (void)hipEventSynchronize(t1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      lfdpr_tune_entry& e = res->entries[res->n++];
+      e.splat_blocks = kBlocks[bi];
+      e.key_layout = layout;
+      e.ms = ms / 3.0f;
+      if (e.ms < best) {
+        best = e.ms;
+        res->best = res->n - 1;
+      }
+    }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  b->use_graph = graph;
+  if (rc) return rc;
+  return batch_set_shape(b, res->entries[res->best].splat_blocks, res->entries[res->best].key_layout);
+}
+
+// Same search for single frames of one scene on the context.
+int lfdpr_autotune(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, lfdpr_tune_result* res) {
+  if (!ctx || !model || !views || !res) return fail(ctx, LFDPR_EINVAL, "null argument");
+  static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
+  hipEvent_t t0, t1;
+  HIPOK(hipEventCreate(&t0));
+  HIPOK(hipEventCreate(&t1));
+  std::memset(res, 0, sizeof *res);
+  float best = INFINITY;
+  int rc = LFDPR_OK;
+  for (int layout = 0; layout < 2 && !rc; ++layout)
+    for (int bi = 0; bi < 5 && !rc; ++bi) {
+      ctx->splat_blocks = kBlocks[bi];
+      ctx->key_layout = layout;
+      for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
+      if (rc) break;
+      (void)hipEventRecord(t0, ctx->stream);
+      for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
+      (void)hipEventRecord(t1, ctx->stream);
+      (void)hipEventSynchronize(t1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      lfdpr_tune_entry& e = res->entries[res->n++];
+      e.splat_blocks = kBlocks[bi];
+      e.key_layout = layout;
+      e.ms = ms / 3.0f;
+      if (e.ms < best) {
+        best = e.ms;
+        res->best = res->n - 1;
+      }
+    }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc) return rc;
+  ctx->splat_blocks = res->entries[res->best].splat_blocks;
+  ctx->key_layout = res->entries[res->best].key_layout;
+  return LFDPR_OK;
+}
+
+int lfdpr_set_launch(lfdpr_ctx* ctx, int32_t splat_blocks, int32_t key_layout) {
+  if (!ctx || splat_blocks < 1 || splat_blocks > (1 << 20) || key_layout < 0 || key_layout > 1)
+    return fail(ctx, LFDPR_EINVAL, "launch shape out of range");
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  ctx->splat_blocks = splat_blocks;
+  ctx->key_layout = key_layout;
   return LFDPR_OK;
 }
 

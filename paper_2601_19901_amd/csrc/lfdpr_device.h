@@ -28,7 +28,8 @@ struct alignas(16) TriRec {
   float a0, c0, y0, smin;      // projected vertex 0 (x = a - b*c), Eqs. 4-5 minimum
   float a1, c1, y1, smax;      // projected vertex 1, Eqs. 4-5 maximum
   float a2, c2, y2, irange;    // projected vertex 2; 1/(smax - smin) (0 when equal)
-  float cu0, cw0, pad0, pad1;  // u.P0 and w.P0 without their x terms
+  float cu0, cw0;              // u.P0 and w.P0 without their x terms
+  int32_t item, pad1;          // batch item the triangle belongs to
 };
 
 // Per-triangle emission data (64 B).
@@ -37,7 +38,7 @@ struct alignas(16) TriEmit {
   float du2, dv2;
   int32_t s1, t1;
   int32_t s2, t2, kmin, kmax;
-  int32_t tex, pad0, pad1, pad2;
+  int32_t tex, item, pad1, pad2;
 };
 
 // One point: 16 B.  tri | flags<<28, (u16)i | (u16)j<<16, tv_min, tv_max (RGBA8).

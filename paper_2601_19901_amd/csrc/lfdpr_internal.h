@@ -9,16 +9,38 @@ namespace lfdpr {
 
 enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_BIG = 4, STAT_SLOTS = 8 };
 
-struct SetupArgs {
+// One frame of one scene inside a (possibly single-element) batch.  Items share
+// the view size and projection (W, H, fovy, aspect); eye tables may differ.
+struct Item {
   const float* pos;
   const float* uv;
   const uint32_t* idx;
   const uint16_t* tex;
-  int32_t nt;
-  Model model;
-  Rig rig;
   const TexInfo* texinfo;
-  const float* lod_thr;  // 128 mantissa thresholds
+  const uint8_t* texels;
+  int64_t tri_base;  // first batch-wide triangle index of this item
+  int32_t nt;
+  int32_t key_layout;  // 0: keys [view][y][x]; 1: keys [y][view][x] (views of a row adjacent)
+  Rig rig;
+  uint64_t* keys;    // rig.n_views * H * W keys of this item
+};
+
+__device__ __forceinline__ int find_item(const Item* items, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tri_base <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct SetupArgs {
+  const Item* items;
+  int32_t n_items;
+  int64_t nt;              // triangles over all items
+  Model model;             // used when models == nullptr (single frame)
+  const Model* models;     // per item (batch)
+  const float* lod_thr;    // 128 mantissa thresholds
   uint32_t* counts;
   TriRec* rec;
   TriEmit* em;
@@ -28,26 +50,25 @@ struct SetupArgs {
 };
 
 struct EmitArgs {
-  int32_t nt;
+  const Item* items;
+  int64_t nt;
   uint32_t* big;             // triangles emitted cooperatively (capacity nt)
   uint64_t* n_big;
   const uint32_t* counts;
   const uint64_t* offsets;
   const TriEmit* em;
-  const TexInfo* texinfo;
-  const uint8_t* texels;
   Point* points;
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
 };
 
 struct SplatArgs {
-  Rig rig;
+  const Item* items;
+  Rig table_rig;             // view size and projection shared by all items
   const Point* points;
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
   const TriRec* rec;
-  uint64_t* keys;            // n_views * H * W
 };
 
 struct InterleaveArgs {
@@ -75,7 +96,9 @@ void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_
                  hipStream_t s);
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s);
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
-void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s);
+void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,
+                    uint32_t* rgba, float* depth, hipStream_t s);
+void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_stride, int64_t panel_stride, hipStream_t s);
 void launch_interleave(const InterleaveArgs& a, hipStream_t s);
 void launch_angular_filter(const AngularArgs& a, hipStream_t s);
 

@@ -65,21 +65,24 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 // ------------------------------------------------------------------ a1/a2: triangle setup
 
 __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t act_cnt = 0, ovf_cnt = 0, pv_cnt = 0;
   if (t < a.nt) {
     uint32_t cnt = 0;
     if (a.dbgf) {
       for (int k = 0; k < 8; ++k) { a.dbgf[t * 8 + k] = 0.0f; a.dbgi[t * 8 + k] = 0; }
     }
-    const Rig& rg = a.rig;
-    const float* m = a.model.m;
+    const int item = find_item(a.items, a.n_items, t);
+    const Item& it = a.items[item];
+    const int64_t lt = t - it.tri_base;
+    const Rig& rg = it.rig;
+    const float* m = a.models ? a.models[item].m : a.model.m;
     float P[3][3];
     bool ok = true;
     uint32_t vi[3];
     for (int k = 0; k < 3; ++k) {
-      vi[k] = a.idx[(int64_t)t * 3 + k];
-      float px = a.pos[(int64_t)vi[k] * 3], py = a.pos[(int64_t)vi[k] * 3 + 1], pz = a.pos[(int64_t)vi[k] * 3 + 2];
+      vi[k] = it.idx[lt * 3 + k];
+      float px = it.pos[(int64_t)vi[k] * 3], py = it.pos[(int64_t)vi[k] * 3 + 1], pz = it.pos[(int64_t)vi[k] * 3 + 2];
       P[k][0] = ((m[0] * px + m[1] * py) + m[2] * pz) + m[3];
       P[k][1] = ((m[4] * px + m[5] * py) + m[6] * pz) + m[7];
       P[k][2] = ((m[8] * px + m[9] * py) + m[10] * pz) + m[11];
@@ -145,11 +148,11 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       float Sx = 1.0f / lxmin, Sy = 1.0f / lymin;
       float size_xy = Amin;
       // texture-based sampling, Eqs. 1-3
-      const int tex = a.tex[t];
-      const TexInfo& ti = a.texinfo[tex];
-      float uv0u = a.uv[(int64_t)vi[0] * 2], uv0v = a.uv[(int64_t)vi[0] * 2 + 1];
-      float du1 = a.uv[(int64_t)vi[1] * 2] - uv0u, dv1 = a.uv[(int64_t)vi[1] * 2 + 1] - uv0v;
-      float du2 = a.uv[(int64_t)vi[2] * 2] - uv0u, dv2 = a.uv[(int64_t)vi[2] * 2 + 1] - uv0v;
+      const int tex = it.tex[lt];
+      const TexInfo& ti = it.texinfo[tex];
+      float uv0u = it.uv[(int64_t)vi[0] * 2], uv0v = it.uv[(int64_t)vi[0] * 2 + 1];
+      float du1 = it.uv[(int64_t)vi[1] * 2] - uv0u, dv1 = it.uv[(int64_t)vi[1] * 2 + 1] - uv0v;
+      float du2 = it.uv[(int64_t)vi[2] * 2] - uv0u, dv2 = it.uv[(int64_t)vi[2] * 2 + 1] - uv0v;
       float Ats = 0.5f * fabsf(du1 * dv2 - dv1 * du2);
       float Aws = 0.5f * nl;
       float Xt = (float)ti.size;
@@ -173,7 +176,8 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       R.irange = R.smax > R.smin ? 1.0f / (R.smax - R.smin) : 0.0f;
       R.cu0 = R.uy * P0.y + R.uz * P0.z;
       R.cw0 = R.wy * P0.y + R.wz * P0.z;
-      R.pad0 = R.pad1 = 0.0f;
+      R.item = item;
+      R.pad1 = 0;
       int32_t kmin = 0, kmax = 0;
       if (rg.mip) {
         int32_t top = 256 * (ti.levels - 1);
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
         TriEmit E;
         E.uv0u = uv0u; E.uv0v = uv0v; E.du1 = du1; E.dv1 = dv1; E.du2 = du2; E.dv2 = dv2;
         E.s1 = sq[1]; E.t1 = tq[1]; E.s2 = sq[2]; E.t2 = tq[2];
-        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.pad0 = E.pad1 = E.pad2 = 0;
+        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item; E.pad1 = E.pad2 = 0;
         a.em[t] = E;
       }
     }
@@ -321,7 +325,7 @@ __device__ __forceinline__ void write_head(Point* pts, uint64_t gi, uint32_t t, 
 // One lane per triangle; triangles with more than kBigCells cells are queued
 // for k_emit_big instead.
 __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.nt) return;
   uint32_t cnt = a.counts[t];
   if (cnt == 0) return;
@@ -426,10 +430,11 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
     float b2 = (float)((double)w2 / (double)area2);
     float u = (E.uv0u + b1 * E.du1) + b2 * E.du2;
     float v = (E.uv0v + b1 * E.dv1) + b2 * E.dv2;
-    const TexInfo& ti = a.texinfo[E.tex];
+    const Item& it = a.items[E.item];
+    const TexInfo& ti = it.texinfo[E.tex];
     uint2 tv;
-    tv.x = trilinear(a.texels, ti, u, v, E.kmin);
-    tv.y = E.kmax == E.kmin ? tv.x : trilinear(a.texels, ti, u, v, E.kmax);
+    tv.x = trilinear(it.texels, ti, u, v, E.kmin);
+    tv.y = E.kmax == E.kmin ? tv.x : trilinear(it.texels, ti, u, v, E.kmax);
     *reinterpret_cast<uint2*>(&a.points[p].tvmin) = tv;
   }
 }
@@ -445,22 +450,26 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
 // (|E| < 2^50), and stepped along x.
 __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
-  const Rig& rg = a.rig;
+  const Rig& trg = a.table_rig;
   float* tx = ray_tab;
-  float* ty = ray_tab + rg.W;
-  for (int k = threadIdx.x; k < rg.W; k += blockDim.x) tx[k] = ((float)k + 0.5f - rg.cx) / rg.fx;
-  for (int k = threadIdx.x; k < rg.H; k += blockDim.x) ty[k] = ((float)k + 0.5f - rg.cy) / rg.fy;
+  float* ty = ray_tab + trg.W;
+  for (int k = threadIdx.x; k < trg.W; k += blockDim.x) tx[k] = ((float)k + 0.5f - trg.cx) / trg.fx;
+  for (int k = threadIdx.x; k < trg.H; k += blockDim.x) ty[k] = ((float)k + 0.5f - trg.cy) / trg.fy;
   __syncthreads();
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const int64_t vpx = (int64_t)rg.W * rg.H;
-  const float zlim = 0.5f * rg.znear;
-  const int32_t H8 = 256 * rg.H, W8 = 256 * rg.W;
+  const int64_t vpx = (int64_t)trg.W * trg.H;
+  const int32_t H8 = 256 * trg.H, W8 = 256 * trg.W;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
     const Point pt = a.points[p];
     const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
     const TriRec T = a.rec[tri];
+    const Rig& rg = a.items[T.item].rig;
+    uint64_t* const keys = a.items[T.item].keys;
+    const bool rowmajor = a.items[T.item].key_layout != 0;
+    const int64_t row_stride = rowmajor ? (int64_t)rg.n_views * rg.W : rg.W;
+    const float zlim = 0.5f * rg.znear;
     // view-independent vertex rows (guard band on y) and triangle row range
     if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) continue;
     const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
@@ -565,7 +574,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
         edy[e] = (double)dy;
         bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
       }
-      uint64_t* kv = a.keys + (int64_t)r * vpx;
+      uint64_t* kv = keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * vpx);
       const int32_t pxq0 = 256 * bx0 + 128;
       for (int32_t y = ry0; y <= ry1; ++y) {
         const int32_t pyq = 256 * y + 128;
@@ -591,7 +600,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
           const float tv = T.sy * (Z * wr + cw) + 0.5f;
           const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
           if (own)
-            atomicMin((unsigned long long*)&kv[(int64_t)y * rg.W + x],
+            atomicMin((unsigned long long*)&kv[(int64_t)y * row_stride + x],
                       (unsigned long long)(((uint64_t)__float_as_uint(Z) << 32) | col));
         }
       }
@@ -599,16 +608,25 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   }
 }
 
-__global__ void k_resolve(uint64_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ rgba,
-                          float* __restrict__ depth) {
+// keys -> RGBA8 (+ depth) in [item][view][y][x] order; keys re-cleared.
+__global__ void k_resolve(uint64_t* __restrict__ keys, int64_t n, int32_t nv, int32_t H, int32_t W, int32_t layout,
+                          uint32_t* __restrict__ rgba, float* __restrict__ depth) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t per_view = (int64_t)W * H, per_item = per_view * nv;
   for (; i < n; i += stride) {
-    uint64_t k = keys[i];
-    bool empty = k == ~0ull;
-    rgba[i] = empty ? 0u : (uint32_t)k;
-    if (depth) depth[i] = empty ? __uint_as_float(0x7f800000u) : __uint_as_float((uint32_t)(k >> 32));
-    keys[i] = ~0ull;
+    int64_t k = i;
+    if (layout) {
+      const int64_t b = i / per_item, rem = i % per_item;
+      const int64_t r = rem / per_view, q = rem % per_view;
+      const int64_t y = q / W, x = q % W;
+      k = b * per_item + (y * nv + r) * W + x;
+    }
+    const uint64_t key = keys[k];
+    const bool empty = key == ~0ull;
+    rgba[i] = empty ? 0u : (uint32_t)key;
+    if (depth) depth[i] = empty ? __uint_as_float(0x7f800000u) : __uint_as_float((uint32_t)(key >> 32));
+    keys[k] = ~0ull;
   }
 }
 
@@ -688,6 +706,16 @@ void launch_tri_setup(const SetupArgs& a, hipStream_t s) {
   k_tri_setup<<<nblk(a.nt, 256), 256, 0, s>>>(a);
 }
 
+void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_stride, int64_t panel_stride,
+                             hipStream_t s) {
+  for (int b = 0; b < n_items; ++b) {
+    InterleaveArgs c = a;
+    c.views = a.views + view_stride * b;
+    c.panel = a.panel + panel_stride * b;
+    launch_interleave(c, s);
+  }
+}
+
 void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
                  hipStream_t s) {
   int64_t ntiles = (n + kScanTile - 1) / kScanTile;
@@ -705,13 +733,15 @@ void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
 }
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
-  size_t lds = sizeof(float) * (size_t)(a.rig.W + a.rig.H);
+  size_t lds = sizeof(float) * (size_t)(a.table_rig.W + a.table_rig.H);
   k_splat<<<grid_blocks, 256, lds, s>>>(a);
 }
 
-void launch_resolve(uint64_t* keys, int64_t n, uint32_t* rgba, float* depth, hipStream_t s) {
+void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,
+                    uint32_t* rgba, float* depth, hipStream_t s) {
+  const int64_t n = n_items * n_views * (int64_t)H * W;
   unsigned g = (unsigned)imin(nblk(n, 256), 256 * 64);
-  k_resolve<<<g, 256, 0, s>>>(keys, n, rgba, depth);
+  k_resolve<<<g, 256, 0, s>>>(keys, n, n_views, H, W, key_layout, rgba, depth);
 }
 
 void launch_interleave(const InterleaveArgs& a, hipStream_t s) {

@@ -3,7 +3,8 @@
 // accumulate).  It stands in for 4x angular supersampling (Sec. 4) and is
 // applied to every view v of a frame: its input at a pixel is (R, G, B, d =
 // D/Z - 1) of views v-2 .. v+2 (20 channels, zero beyond the rig), layers
-// 20 -> 32 -> 32 -> 32 -> 3 with ReLU, output = view v's RGB + network.
+// 20 -> 32 -> 32 -> 32 -> 3 with ReLU, 3x3 kernels dilated horizontally by
+// 1, 3, 9, 1; output = view v's RGB + network.
 //
 // Layouts: the compact input is [view][H][W][4] BF16 and layer 1 gathers the
 // neighbour views from it directly; hidden activations are [view][H][W][32]
@@ -51,6 +52,9 @@ union Frag {
 constexpr int kNeigh = 2;   // views v-2 .. v+2
 constexpr int kCin0 = 20;   // real input channels of layer 1
 constexpr int kK = 32;      // padded input channels of every layer (one MFMA K step per tap)
+// Horizontal dilation per layer: one view step shifts content by several
+// pixels across, so the stack sees +-14 px horizontally and +-4 px vertically.
+constexpr int kDilation[4] = {1, 3, 9, 1};
 
 // Loads the 8 K-values of lane group g for input pixel (n, yy, xx).  GATHER:
 // from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2, n+2g-1.
@@ -74,7 +78,7 @@ __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, int n, i
 // All nine taps' [COUT][32] weights sit in LDS for the block's lifetime.
 template <int NT, int MODE, bool GATHER>
 __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
-                                                  const float* __restrict__ bias, int N, int H, int W, int V,
+                                                  const float* __restrict__ bias, int N, int H, int W, int V, int DIL,
                                                   uint16_t* __restrict__ Y, int YS, const uint16_t* __restrict__ aux,
                                                   int AUX_C) {
   constexpr int COUT = NT * 16;
@@ -105,7 +109,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
       for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+      const int dy = tap / 3 - 1, dx = (tap % 3 - 1) * DIL;
       Frag b[NT];
 #pragma unroll
       for (int n = 0; n < NT; ++n) b[n].u = wlds[(tap * COUT + n * 16 + r16) * (kK / 8) + g];
@@ -150,14 +154,14 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 template <bool GATHER>
 __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ dZ, int DZS, int CO,
                                                     const uint16_t* __restrict__ A, int CI, int N, int H, int W, int V,
-                                                    float* __restrict__ dW, int chunk) {
+                                                    int DIL, float* __restrict__ dW, int chunk) {
   const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
   const int nct = (CO + 15) / 16, nit = 2;  // ci padded to 32
   int t = blockIdx.x;
   const int it = t % nit; t /= nit;
   const int ct = t % nct; t /= nct;
   const int tap = t;
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  const int dy = tap / 3 - 1, dx = (tap % 3 - 1) * DIL;
   const int hw = H * W, npx = N * hw;
   const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
   const int co = ct * 16 + r16, ci = it * 16 + r16;
@@ -344,11 +348,11 @@ int nfail(lfdpr_net* n, int code, const std::string& m) {
   } while (0)
 
 template <int NT, int MODE, bool GATHER>
-void launch_conv(const uint16_t* X, const uint16_t* Wt, const float* b, int N, int H, int W, int V, uint16_t* Y, int YS,
-                 const uint16_t* aux, int AUXC, hipStream_t s) {
+void launch_conv(const uint16_t* X, const uint16_t* Wt, const float* b, int N, int H, int W, int V, int dil,
+                 uint16_t* Y, int YS, const uint16_t* aux, int AUXC, hipStream_t s) {
   const int64_t tiles = ((int64_t)N * H * W + 255) / 256;
   const int grid = (int)(tiles < 4096 ? tiles : 4096);
-  k_conv3x3<NT, MODE, GATHER><<<grid, 256, 0, s>>>(X, Wt, b, N, H, W, V, Y, YS, aux, AUXC);
+  k_conv3x3<NT, MODE, GATHER><<<grid, 256, 0, s>>>(X, Wt, b, N, H, W, V, dil, Y, YS, aux, AUXC);
 }
 
 void pack_weights(lfdpr_net* net) {
@@ -481,10 +485,11 @@ int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t n_views, int32_t H,
   const uint16_t* in = (const uint16_t*)x;
   hipStream_t s = net->stream;
   const int N = n_views, V = net->V;
-  launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, net->act[1], kHidden, nullptr, 0, s);
-  launch_conv<2, MODE_RELU, false>(net->act[1], net->wf[1], net->master + net->off_b[1], N, H, W, V, net->act[2], kHidden, nullptr, 0, s);
-  launch_conv<2, MODE_RELU, false>(net->act[2], net->wf[2], net->master + net->off_b[2], N, H, W, V, net->act[3], kHidden, nullptr, 0, s);
-  launch_conv<1, MODE_OUT, false>(net->act[3], net->wf[3], net->master + net->off_b[3], N, H, W, V, (uint16_t*)y, 4, in, 4, s);
+  const int* d = kDilation;
+  launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, d[0], net->act[1], kHidden, nullptr, 0, s);
+  launch_conv<2, MODE_RELU, false>(net->act[1], net->wf[1], net->master + net->off_b[1], N, H, W, V, d[1], net->act[2], kHidden, nullptr, 0, s);
+  launch_conv<2, MODE_RELU, false>(net->act[2], net->wf[2], net->master + net->off_b[2], N, H, W, V, d[2], net->act[3], kHidden, nullptr, 0, s);
+  launch_conv<1, MODE_OUT, false>(net->act[3], net->wf[3], net->master + net->off_b[3], N, H, W, V, d[3], (uint16_t*)y, 4, in, 4, s);
   NHIP(hipGetLastError());
   net->last_x = in;
   net->last_y = (const uint16_t*)y;
@@ -511,13 +516,15 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
     const int CO = net->co[k], CI = net->ci[k];
     dim3 gw((unsigned)(9 * ((CO + 15) / 16) * 2), nch);
     if (k == 0)
-      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, CI, N, H, W, V, net->grad + net->off_w[0], chunk);
+      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, CI, N, H, W, V, kDilation[0],
+                                           net->grad + net->off_w[0], chunk);
     else
-      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], CI, N, H, W, V, net->grad + net->off_w[k], chunk);
+      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], CI, N, H, W, V, kDilation[k],
+                                            net->grad + net->off_w[k], chunk);
     k_bias_grad<<<(unsigned)CO, 256, 0, s>>>(net->dz[k + 1], kK, npx, net->grad + net->off_b[k]);
-    if (k > 0)  // input gradient through the flipped, transposed weights, masked by the ReLU
-      launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, net->dz[k], kHidden, net->act[k],
-                                      kHidden, s);
+    if (k > 0)  // input gradient through the flipped, transposed weights (same dilation), masked by the ReLU
+      launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, kDilation[k], net->dz[k], kHidden,
+                                      net->act[k], kHidden, s);
   }
   NHIP(hipGetLastError());
   if (loss) NHIP(hipMemcpyAsync(loss, net->d_loss, 4, hipMemcpyDeviceToDevice, s));

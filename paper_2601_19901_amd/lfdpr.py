@@ -43,6 +43,14 @@ class LensParams(C.Structure):
                 ("offset", C.c_double), ("mode", C.c_int32), ("taps", (C.c_int64 * 3) * 8)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("splat_blocks", C.c_int32), ("key_layout", C.c_int32), ("ms", C.c_float)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("n", C.c_int32), ("best", C.c_int32), ("entries", TuneEntry * 16)]
+
+
 class Stats(C.Structure):
     _fields_ = [("points", C.c_int64), ("active_tris", C.c_int64), ("point_views", C.c_int64),
                 ("overflow_tris", C.c_int64), ("capacity", C.c_int64), ("point_overflow", C.c_int32),
@@ -85,6 +93,15 @@ def lib():
         "lfdpr_copy_counts": ([vp, vp, i64], C.c_int),
         "lfdpr_set_debug_records": ([vp, vp, vp, i64], C.c_int),
         "lfdpr_timing": ([vp, C.c_int], C.c_int),
+        "lfdpr_set_launch": ([vp, i32, i32], C.c_int),
+        "lfdpr_autotune": ([vp, i32, vp, vp, p(TuneResult)], C.c_int),
+        "lfdpr_batch_create": ([vp, i32, vp, vp, i64, p(vp)], C.c_int),
+        "lfdpr_batch_destroy": ([vp], C.c_int),
+        "lfdpr_batch_last_error": ([vp], C.c_char_p),
+        "lfdpr_batch_use_graph": ([vp, C.c_int], C.c_int),
+        "lfdpr_batch_render": ([vp, vp, vp, vp], C.c_int),
+        "lfdpr_batch_stats": ([vp, p(Stats)], C.c_int),
+        "lfdpr_batch_autotune": ([vp, vp, vp, vp, p(TuneResult)], C.c_int),
         "lfdpr_net_create": ([vp, i32, i32, i32, p(vp)], C.c_int),
         "lfdpr_net_destroy": ([vp], C.c_int),
         "lfdpr_net_last_error": ([vp], C.c_char_p),
@@ -117,6 +134,22 @@ def _ptr(t) -> int:
         return t.ctypes.data
     assert t.is_contiguous(), "tensor must be contiguous"
     return t.data_ptr()
+
+
+def view_params(vp, point_capacity: int = 0):
+    """ViewParams (scenes.ViewParams) -> the ABI struct; returns it with the arrays it points into."""
+    jit = None
+    if vp.S > 1:
+        jit = np.ascontiguousarray(vp.jitter, np.float32)
+    p = ViewParams(vp.V, vp.S, vp.W, vp.H, vp.fovy_deg, vp.aspect, vp.D, vp.cone_deg, vp.znear,
+                   _ptr(jit) if jit is not None else None, int(vp.mip), int(point_capacity))
+    return p, jit
+
+
+def tune_dict(res) -> dict:
+    ents = [dict(splat_blocks=res.entries[k].splat_blocks, key_layout=res.entries[k].key_layout,
+                 ms=float(res.entries[k].ms)) for k in range(res.n)]
+    return dict(best=ents[res.best], entries=ents)
 
 
 def _check_dev(t, dtype, numel, name):
@@ -182,13 +215,18 @@ class Renderer:
 
     # -- parameters ----------------------------------------------------------
     def set_views(self, vp, point_capacity: int = 0):
-        jit = None
-        if vp.S > 1:
-            jit = np.ascontiguousarray(vp.jitter, np.float32)
-        p = ViewParams(vp.V, vp.S, vp.W, vp.H, vp.fovy_deg, vp.aspect, vp.D, vp.cone_deg, vp.znear,
-                       _ptr(jit) if jit is not None else None, int(vp.mip), int(point_capacity))
+        p, keep = view_params(vp, point_capacity)
         self._check(lib().lfdpr_set_views(self.h, C.byref(p)))
         self.vp = vp
+
+    def set_launch(self, splat_blocks: int, key_layout: int):
+        self._check(lib().lfdpr_set_launch(self.h, splat_blocks, key_layout))
+
+    def autotune(self, sid: int, model: np.ndarray, views) -> dict:
+        m = np.ascontiguousarray(model, np.float32).reshape(12)
+        res = TuneResult()
+        self._check(lib().lfdpr_autotune(self.h, sid, _ptr(m), _ptr(views), C.byref(res)))
+        return tune_dict(res)
 
     def set_lens(self, lp, mode: Optional[int] = None):
         p = LensParams()
@@ -390,3 +428,66 @@ def flat_to_params(flat: np.ndarray):
         o += co
         out.append((w, b))
     return out
+
+
+class Batch:
+    """Several scene frames rendered with one launch per stage (lfdpr_batch_*)."""
+
+    def __init__(self, renderer: Renderer, scene_ids, view_params_list, point_capacity: int = 0):
+        self.R = renderer
+        self._torch = renderer._torch
+        n = len(scene_ids)
+        ids = np.ascontiguousarray(scene_ids, np.int32)
+        arr = (ViewParams * n)()
+        self._keep = []
+        for k, vp in enumerate(view_params_list):
+            p, jit = view_params(vp)
+            arr[k] = p
+            self._keep.append(jit)
+        h = C.c_void_p()
+        renderer._check(lib().lfdpr_batch_create(renderer.h, n, _ptr(ids), C.cast(arr, C.c_void_p), point_capacity,
+                                                 C.byref(h)))
+        self.h = h
+        self.n = n
+        vp0 = view_params_list[0]
+        self.shape = (n, vp0.V * vp0.S, vp0.H, vp0.W)
+
+    def _check(self, rc):
+        if rc != LFDPR_OK:
+            last = lib().lfdpr_batch_last_error(self.h)
+            raise LfdprError(rc, lib().lfdpr_strerror(rc).decode() + ": " + (last.decode() if last else ""))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lfdpr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def use_graph(self, enable: bool):
+        self._check(lib().lfdpr_batch_use_graph(self.h, int(enable)))
+
+    def alloc_views(self):
+        return self._torch.empty(self.shape, dtype=self._torch.int32, device=f"cuda:{self.R.device}")
+
+    def render(self, models, views, panels=None):
+        m = np.ascontiguousarray(np.asarray(models, np.float32).reshape(self.n, 12))
+        _check_dev(views, self._torch.int32, int(np.prod(self.shape)), "views")
+        self._check(lib().lfdpr_batch_render(self.h, _ptr(m), _ptr(views), _ptr(panels) if panels is not None else None))
+
+    def stats(self) -> dict:
+        s = Stats()
+        rc = lib().lfdpr_batch_stats(self.h, C.byref(s))
+        if rc not in (LFDPR_OK, LFDPR_EOVERFLOW):
+            self._check(rc)
+        return {k: int(getattr(s, k)) for k, _ in Stats._fields_}
+
+    def autotune(self, models, views) -> dict:
+        m = np.ascontiguousarray(np.asarray(models, np.float32).reshape(self.n, 12))
+        res = TuneResult()
+        self._check(lib().lfdpr_batch_autotune(self.h, _ptr(m), _ptr(views), C.byref(res)))
+        return tune_dict(res)

@@ -118,33 +118,35 @@ def heightfield(n: int, rng: np.random.Generator, amp: float) -> Tuple[np.ndarra
 
 
 def value_noise_texture(size: int, rng: np.random.Generator, octaves: int = 6) -> np.ndarray:
-    """Seeded fBm value noise mapped through a random two-colour ramp, RGBA8."""
-    acc = np.zeros((size, size), np.float64)
+    """Seeded fBm value noise (smooth-step interpolated lattice noise, separable)
+    mapped through a random two-colour ramp, RGBA8."""
+    acc = np.zeros((size, size), np.float32)
     amp, tot = 1.0, 0.0
-    coords = np.arange(size, dtype=np.float64) + 0.5
+    coords = np.arange(size, dtype=np.float32) + 0.5
     for o in range(octaves):
         cells = 4 * 2 ** o
         if cells > size:
             break
-        grid = rng.random((cells, cells))
-        f = coords * cells / size - 0.5
+        grid = rng.random((cells, cells)).astype(np.float32)
+        f = coords * np.float32(cells / size) - np.float32(0.5)
         i0 = np.floor(f).astype(np.int64)
         t = f - i0
         t = t * t * (3 - 2 * t)
         i0m = i0 % cells
         i1m = (i0 + 1) % cells
-        rows = grid[i0m][:, i0m] * np.outer(1 - t, 1 - t) + grid[i0m][:, i1m] * np.outer(1 - t, t) \
-            + grid[i1m][:, i0m] * np.outer(t, 1 - t) + grid[i1m][:, i1m] * np.outer(t, t)
-        acc += amp * rows
+        rows = grid[i0m] * (1 - t)[:, None] + grid[i1m] * t[:, None]          # (size, cells)
+        val = rows[:, i0m] * (1 - t)[None, :] + rows[:, i1m] * t[None, :]     # (size, size)
+        acc += np.float32(amp) * val
         tot += amp
         amp *= 0.5
-    acc /= tot
-    acc = np.clip((acc - 0.5) * 2.2 + 0.5, 0.0, 1.0)
-    c0 = rng.integers(0, 256, 3)
-    c1 = rng.integers(0, 256, 3)
-    rgb = c0[None, None, :] * (1 - acc[..., None]) + c1[None, None, :] * acc[..., None]
+    acc *= np.float32(2.2 / tot)
+    acc += np.float32(0.5 - 1.1)
+    np.clip(acc, 0.0, 1.0, out=acc)
+    c0 = rng.integers(0, 256, 3).astype(np.float32)
+    c1 = rng.integers(0, 256, 3).astype(np.float32)
     out = np.empty((size, size, 4), np.uint8)
-    out[..., :3] = np.clip(np.rint(rgb), 0, 255).astype(np.uint8)
+    for ch in range(3):
+        out[..., ch] = (c0[ch] + (c1[ch] - c0[ch]) * acc + np.float32(0.5)).astype(np.uint8)
     out[..., 3] = 255
     return out
 
@@ -418,3 +420,25 @@ def edge_length_px_stats(scene: Scene, model: np.ndarray, fx: float, fy: float) 
     q = np.stack([p[:, 0] / p[:, 2] * fx, p[:, 1] / p[:, 2] * fy], axis=1)
     e = q[scene.idx[:, 1]] - q[scene.idx[:, 0]]
     return np.hypot(e[:, 0], e[:, 1])
+
+
+def batch_workloads(seed: int = 400, n: int = 16, lo: float = 5e4, hi: float = 4e6, n_tex: int = 4) -> List[Workload]:
+    """n independent display-family scenes for one batch: triangle counts
+    log-uniform in [lo, hi] (half heightfield, half icospheres), textures of
+    512^2..2048^2, per-scene view cones 30-50 degrees, V = 48 views of 512^2."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        target = math.exp(rng.uniform(math.log(lo), math.log(hi)))
+        quads = max(8, int(round(math.sqrt(target / 4.0))))       # heightfield: 2*quads^2 ~ target/2
+        per_sphere = max(20.0, (target - 2 * quads * quads) / 200.0)
+        la = max(0, min(5, int(math.floor(math.log(per_sphere / 20.0, 4)))))
+        lb = min(la + 1, 6)
+        ta, tb = 20 * 4 ** la, 20 * 4 ** lb
+        cb = int(round(200 * min(1.0, max(0.0, (per_sphere - ta) / (tb - ta)))))
+        tex_size = int(2 ** rng.integers(9, 12))
+        w = display(seed=seed + k, hf_quads=quads, levels=(lb, la), counts=(cb, 200 - cb), tex_size=tex_size,
+                    n_tex=n_tex, cone_deg=float(rng.uniform(30.0, 50.0)))
+        w.name = f"batch-{k}"
+        out.append(w)
+    return out

@@ -1,0 +1,107 @@
+"""Batched rendering (one launch per stage for several scenes, hipGraph replay)
+and the autotuner: every result bit-identical to single-scene renders, which
+the other GPU tests tie to the oracle."""
+import numpy as np
+import pytest
+
+from paper_2601_19901_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_19901_amd import lfdpr
+    ws = [scenes.small_display(seed=s, V=12, W=96, H=96, hf_quads=hq) for s, hq in ((60, 24), (61, 48), (62, 80), (63, 16))]
+    for k, w in enumerate(ws):            # per-scene cones and distances differ
+        w.views.cone_deg = 30.0 + 6.0 * k
+        w.views.D = 10.0 + 0.5 * k
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    return torch, lfdpr, R, ws, ids
+
+
+def single(torch, R, w, sid, model):
+    R.set_views(w.views)
+    v, _ = R.alloc_views()
+    R.render_frame(sid, model, v)
+    panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    R.reconstruct(v, panel)
+    return v.cpu().numpy(), panel.cpu().numpy(), R.stats()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single_renders(setup, graph):
+    torch, lfdpr, R, ws, ids = setup
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    B.use_graph(graph)
+    views = B.alloc_views()
+    panels = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    for frame in (0, 77, 400):
+        models = [w.model(frame + 13 * k) for k, w in enumerate(ws)]
+        B.render(models, views, panels)
+        torch.cuda.synchronize()
+        bv, bp = views.cpu().numpy(), panels.cpu().numpy()
+        bst = B.stats()
+        tot_pts = 0
+        for k, w in enumerate(ws):
+            sv, sp, st = single(torch, R, w, ids[k], models[k])
+            np.testing.assert_array_equal(bv[k], sv, err_msg=f"item {k} frame {frame} views")
+            np.testing.assert_array_equal(bp[k], sp, err_msg=f"item {k} frame {frame} panel")
+            tot_pts += st["points"]
+        assert bst["points"] == tot_pts
+        print(f"frame {frame}: {bst['points']} points over {len(ws)} scenes, graph={graph}", flush=True)
+
+
+def test_graph_replays_with_interleaved_eager_work(setup):
+    """Several replays, with eager frames and synchronisations between them,
+    each equal to an eager batch render of the same models."""
+    torch, lfdpr, R, ws, ids = setup
+    G = lfdpr.Batch(R, ids, [w.views for w in ws])
+    E = lfdpr.Batch(R, ids, [w.views for w in ws])
+    E.use_graph(False)
+    vg, ve = G.alloc_views(), E.alloc_views()
+    for frame in (5, 6, 600, 5):
+        models = [w.model(frame * (k + 1)) for k, w in enumerate(ws)]
+        G.render(models, vg)
+        torch.cuda.synchronize()
+        E.render(models, ve)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(vg.cpu().numpy(), ve.cpu().numpy())
+
+
+def test_autotune_keeps_results(setup):
+    torch, lfdpr, R, ws, ids = setup
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    views = B.alloc_views()
+    models = [w.model(9) for w in ws]
+    B.use_graph(False)
+    B.render(models, views)
+    torch.cuda.synchronize()
+    ref = views.cpu().numpy().copy()
+    res = B.autotune(models, views)
+    print("batch autotune:", res["best"], flush=True)
+    assert len(res["entries"]) == 10 and res["best"] in res["entries"]
+    B.use_graph(True)
+    B.render(models, views)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(views.cpu().numpy(), ref)
+    # single-frame autotune + explicit launch shapes give identical views
+    w = ws[2]
+    R.set_views(w.views)
+    v, _ = R.alloc_views()
+    outs = []
+    for blocks, layout in ((1024, 0), (16384, 1), (3000, 1)):
+        R.set_launch(blocks, layout)
+        R.render_frame(ids[2], w.model(9), v)
+        outs.append(v.cpu().numpy().copy())
+    r1 = R.autotune(ids[2], w.model(9), v)
+    R.render_frame(ids[2], w.model(9), v)
+    outs.append(v.cpu().numpy().copy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    print("frame autotune:", r1["best"], flush=True)

@@ -96,12 +96,14 @@ def test_forward_layers_match_oracle(torch_cuda, V, F, H, W):
     inp = [a0] + acts
     for k in range(3):
         w = N.bf16(P[k][0])
-        want = N.bf16(np.maximum(np.stack([N.conv3x3(inp[k][n], w, P[k][1]) for n in range(F * V)]), 0))
-        S = np.stack([N.conv3x3(np.abs(inp[k][n]), np.abs(w), np.abs(P[k][1])) for n in range(F * V)])
+        d = N.DILATION[k]
+        want = N.bf16(np.maximum(np.stack([N.conv3x3(inp[k][n], w, P[k][1], d) for n in range(F * V)]), 0))
+        S = np.stack([N.conv3x3(np.abs(inp[k][n]), np.abs(w), np.abs(P[k][1]), d) for n in range(F * V)])
         assert_bf16_close(acts[k], want, f"V{V}x{F} layer {k + 1}", abs_sum=S)
     w = N.bf16(P[3][0])
-    want_y = N.bf16(np.stack([N.conv3x3(acts[2][n], w, P[3][1]) for n in range(F * V)]) + xf[..., :3])
-    S = np.stack([N.conv3x3(np.abs(acts[2][n]), np.abs(w), np.abs(P[3][1])) for n in range(F * V)]) + np.abs(xf[..., :3])
+    d = N.DILATION[3]
+    want_y = N.bf16(np.stack([N.conv3x3(acts[2][n], w, P[3][1], d) for n in range(F * V)]) + xf[..., :3])
+    S = np.stack([N.conv3x3(np.abs(acts[2][n]), np.abs(w), np.abs(P[3][1]), d) for n in range(F * V)]) + np.abs(xf[..., :3])
     yg = get16(y)
     assert (yg[..., 3] == 0).all()
     assert_bf16_close(yg[..., :3], want_y, f"V{V}x{F} output", abs_sum=S)
@@ -157,15 +159,16 @@ def test_backward_matches_oracle(torch_cuda):
         net.copy_state(10 + k, d)
         dzs[k] = get16(d)
         w = N.bf16(P[k][0])
-        want = N.bf16(np.stack([N.conv3x3_xgrad(dzs[k + 1][v], w) for v in range(V)]) * (acts[k] > 0))
-        S = np.stack([N.conv3x3_xgrad(np.abs(dzs[k + 1][v]), np.abs(w)) for v in range(V)])
+        d = N.DILATION[k]
+        want = N.bf16(np.stack([N.conv3x3_xgrad(dzs[k + 1][v], w, d) for v in range(V)]) * (acts[k] > 0))
+        S = np.stack([N.conv3x3_xgrad(np.abs(dzs[k + 1][v]), np.abs(w), d) for v in range(V)])
         assert_bf16_close(dzs[k], want, f"dZ{k}", abs_sum=S)
     g = torch.zeros(net.n_params, dtype=torch.float32, device="cuda")
     net.copy_state(20, g)
     G = lfdpr.flat_to_params(g.cpu().numpy().astype(np.float64))
     for k in range(4):
-        dw = sum(N.conv3x3_wgrad(acts[k][v], dzs[k + 1][v])[0] for v in range(V))
-        db = sum(N.conv3x3_wgrad(acts[k][v], dzs[k + 1][v])[1] for v in range(V))
+        dw = sum(N.conv3x3_wgrad(acts[k][v], dzs[k + 1][v], N.DILATION[k])[0] for v in range(V))
+        db = sum(N.conv3x3_wgrad(acts[k][v], dzs[k + 1][v], N.DILATION[k])[1] for v in range(V))
         err = np.abs(G[k][0] - dw).max() / (np.abs(dw).max() + 1e-30)
         _log(f"dW{k + 1}: max rel err {err:.2e}")
         assert err < 2e-3
