@@ -476,7 +476,8 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   int rc = ensure_tri_buffers(ctx, s.nt);
   if (rc) return rc;
   hipStream_t st = ctx->stream;
-  Item one{};
+  Item one;
+  std::memset(&one, 0, sizeof one);  // padding too: the table is compared bytewise
   one.pos = s.pos;
   one.uv = s.uv;
   one.idx = s.idx;
@@ -488,10 +489,10 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   one.rig = ctx->rig;
   one.keys = ctx->d_keys;
   one.key_layout = ctx->key_layout;
-  if (std::memcmp(&one, &ctx->h_item1, sizeof it) != 0) {
+  if (std::memcmp(&one, &ctx->h_item1, sizeof one) != 0) {
     HIPOK(hipStreamSynchronize(st));  // earlier frames may still read the table
     HIPOK(hipMemcpy(ctx->d_item1, &one, sizeof one, hipMemcpyHostToDevice));
-    ctx->h_item1 = one;
+    std::memcpy(&ctx->h_item1, &one, sizeof one);
   }
   launch_fill_u64(ctx->d_stats, STAT_SLOTS, 0ull, st);
   SetupArgs sa{};

@@ -67,6 +67,17 @@ def declared_symbols():
     return sorted(set(re.findall(r"\b(lfdpr_[a-z0-9_]+)\s*\(", txt)))
 
 
+def declared_arity():
+    """Number of parameters of each function include/lfdpr.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for name, args in re.findall(r"\b(lfdpr_[a-z0-9_]+)\s*\(([^)]*)\)\s*;", txt):
+        args = args.strip()
+        out[name] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
 def lib():
     global _lib
     if _lib is not None:
@@ -74,8 +85,18 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
     L = C.CDLL(LIB_PATH)
+    for name, (args, res) in signatures().items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def signatures():
+    """ctypes (argtypes, restype) of every entry point in include/lfdpr.h."""
     vp, i32, i64, p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER
-    sig = {
+    return {
         "lfdpr_abi_version": ([], C.c_int),
         "lfdpr_strerror": ([C.c_int], C.c_char_p),
         "lfdpr_create": ([C.c_int, vp, p(vp)], C.c_int),
@@ -101,7 +122,7 @@ def lib():
         "lfdpr_batch_use_graph": ([vp, C.c_int], C.c_int),
         "lfdpr_batch_render": ([vp, vp, vp, vp], C.c_int),
         "lfdpr_batch_stats": ([vp, p(Stats)], C.c_int),
-        "lfdpr_batch_autotune": ([vp, vp, vp, vp, p(TuneResult)], C.c_int),
+        "lfdpr_batch_autotune": ([vp, vp, vp, p(TuneResult)], C.c_int),
         "lfdpr_net_create": ([vp, i32, i32, i32, p(vp)], C.c_int),
         "lfdpr_net_destroy": ([vp], C.c_int),
         "lfdpr_net_last_error": ([vp], C.c_char_p),
@@ -118,12 +139,6 @@ def lib():
         "lfdpr_net_load": ([vp, C.c_char_p], C.c_int),
         "lfdpr_get_timings": ([vp, vp, vp], C.c_int),
     }
-    for name, (args, res) in sig.items():
-        f = getattr(L, name)
-        f.argtypes = args
-        f.restype = res
-    _lib = L
-    return L
 
 
 def _ptr(t) -> int:

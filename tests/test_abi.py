@@ -27,3 +27,13 @@ def test_library_exports_every_declared_symbol():
     assert lib.lfdpr_strerror(12345) == b"unknown status"
     assert lib.lfdpr_destroy(None) == 0
     assert lib.lfdpr_last_error(None) == b"null context"
+
+
+def test_binding_signatures_match_header():
+    """Every binding's argument count equals the header prototype's."""
+    arity = lfdpr.declared_arity()
+    sigs = lfdpr.signatures()
+    assert set(arity) == set(lfdpr.declared_symbols())
+    assert set(sigs) == set(arity), set(sigs) ^ set(arity)
+    bad = {n: (len(sigs[n][0]), arity[n]) for n in arity if len(sigs[n][0]) != arity[n]}
+    assert not bad, bad
