@@ -528,6 +528,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   hipEvent_t e3 = mark(ctx);
   SplatArgs pa{};
   pa.items = ctx->d_item1;
+  pa.n_items = 1;
   pa.table_rig = ctx->rig;
   pa.points = ctx->d_points;
   pa.n_points = ctx->d_stats + STAT_TOTAL;
@@ -749,6 +750,7 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
   launch_emit(ea, b->splat_blocks, st);
   SplatArgs pa{};
   pa.items = b->d_items;
+  pa.n_items = b->n;
   pa.table_rig = b->table_rig;
   pa.points = b->points;
   pa.n_points = b->stats + STAT_TOTAL;

@@ -64,6 +64,7 @@ struct EmitArgs {
 
 struct SplatArgs {
   const Item* items;
+  int32_t n_items;
   Rig table_rig;             // view size and projection shared by all items
   const Point* points;
   const uint64_t* n_points;  // device count (total emitted)

@@ -448,6 +448,178 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
 // holding exactly the values the inline expressions give.  The integer edge
 // functions are evaluated in double, which represents every value exactly
 // (|E| < 2^50), and stepped along x.
+// An item table entry read by all active lanes of a wave from one address,
+// moved to scalar registers word by word.
+__device__ __forceinline__ Item load_uniform(const Item* p) {
+  static_assert(sizeof(Item) % 4 == 0, "Item is a whole number of words");
+  Item out;
+  const int32_t* src = reinterpret_cast<const int32_t*>(p);
+  int32_t* dst = reinterpret_cast<int32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Item) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  return out;
+}
+
+// 64-bit depth-test update (relaxed, device scope); the key buffers are global
+// memory, which lets the compiler issue a global rather than a flat atomic.
+__device__ __forceinline__ void key_min(uint64_t* p, uint64_t v) {
+  typedef __attribute__((address_space(1))) unsigned long long global_u64;
+  __hip_atomic_fetch_min((global_u64*)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float uniform_f32(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// One point against every view of its item's rig; `item` is wave-uniform.
+__device__ __forceinline__ void splat_point(const Item& item, const Point& pt, const TriRec& T, uint32_t flags,
+                                            int32_t i, int32_t j, const float* tx, const float* ty) {
+  const int64_t vpx = (int64_t)item.rig.W * item.rig.H;
+  const int32_t H8 = 256 * item.rig.H, W8 = 256 * item.rig.W;
+  const Rig& rg = item.rig;
+  uint64_t* const keys = item.keys;
+  const bool rowmajor = item.key_layout != 0;
+  const int64_t row_stride = rowmajor ? (int64_t)rg.n_views * rg.W : rg.W;
+  const float zlim = 0.5f * rg.znear;
+  // view-independent vertex rows (guard band on y) and triangle row range
+  if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) return;
+  const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
+                qy2 = (int32_t)rintf(T.y2 * 256.0f);
+  if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) return;
+  const int32_t ymin = min(qy0, min(qy1, qy2)), ymax = max(qy0, max(qy1, qy2));
+  const int32_t Y0 = max(0, -((128 - ymin) >> 8));
+  const int32_t Y1 = min(rg.H - 1, (ymax - 128) >> 8);
+  if (Y0 > Y1) return;
+  // splat box corners (row-end extended cell), projected except for the eye offset
+  const int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
+  const int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
+  float cA[4], cC[4];
+  float ymn = 0.0f, ymx = 0.0f;
+  bool full = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float aa = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
+    float cc = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
+    float X = (T.p0x + aa * T.ux) + cc * T.wx;
+    float Y = (T.p0y + aa * T.uy) + cc * T.wy;
+    float Z = (T.p0z + aa * T.uz) + cc * T.wz;
+    if (!(Z >= zlim)) full = true;
+    float Yp;
+    vertex_proj(rg, X, Y, Z, cA[k], cC[k], Yp);
+    if (k == 0) { ymn = ymx = Yp; }
+    else { ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx; }
+  }
+  int32_t by0 = Y0, by1 = Y1;
+  if (!full) {
+    int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
+    by0 = max(r0, by0);
+    by1 = min(r1, by1);
+  }
+  if (by0 > by1) return;
+  // cell-centre terms of Eqs. 8-9 and the ownership bounds
+  const float cs = (float)i / T.sx, ct = (float)j / T.sy;
+  const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
+  const float Zc3 = (Zc * Zc) * Zc;
+  const float Acell = 1.0f / (T.sx * T.sy);
+  const float suv = Acell * T.ruv;
+  const float fi0 = (float)i, fi1 = (float)(i + 1), fj0 = (float)j, fj1 = (float)(j + 1);
+  const bool oilo = flags & F_ILO, oihi = flags & F_IHI, ojlo = flags & F_JLO, ojhi = flags & F_JHI;
+  const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
+  const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
+  for (int r = 0; r < rg.n_views; ++r) {
+    const float b = uniform_f32(rg.eye[r]);
+    const float delta = T.h - T.nx * b;
+    if (!(delta < 0.0f)) continue;
+    // splat box columns first: empty for about a third of the (point, view) pairs
+    int32_t cbx0 = 0, cbx1 = rg.W - 1;
+    if (!full) {
+      float xmn = cA[0] - b * cC[0], xmx = xmn;
+#pragma unroll
+      for (int k = 1; k < 4; ++k) {
+        float xx = cA[k] - b * cC[k];
+        xmn = xx < xmn ? xx : xmn;
+        xmx = xx > xmx ? xx : xmx;
+      }
+      cbx0 = max(cbx0, (int32_t)ceilf(clamp_big(xmn - 0.515625f)));
+      cbx1 = min(cbx1, (int32_t)floorf(clamp_big(xmx - 0.484375f)));
+      if (cbx0 > cbx1) continue;
+    }
+    const float x0 = T.a0 - b * T.c0, x1 = T.a1 - b * T.c1, x2 = T.a2 - b * T.c2;
+    if (!(fabsf(x0) < kGuard) || !(fabsf(x1) < kGuard) || !(fabsf(x2) < kGuard)) continue;
+    int32_t qx[3] = {(int32_t)rintf(x0 * 256.0f), (int32_t)rintf(x1 * 256.0f), (int32_t)rintf(x2 * 256.0f)};
+    int32_t qy[3] = {qy0, qy1, qy2};
+    if ((qx[0] < 0 && qx[1] < 0 && qx[2] < 0) || (qx[0] > W8 && qx[1] > W8 && qx[2] > W8)) continue;
+    const double a2 = (double)(qx[1] - qx[0]) * (double)(qy[2] - qy[0]) -
+                      (double)(qy[1] - qy[0]) * (double)(qx[2] - qx[0]);
+    if (a2 == 0.0) continue;
+    if (a2 < 0.0) {
+      int32_t u = qx[1]; qx[1] = qx[2]; qx[2] = u;
+      u = qy[1]; qy[1] = qy[2]; qy[2] = u;
+    }
+    const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
+    const int32_t bx0 = max(cbx0, -((128 - xmin) >> 8));
+    const int32_t bx1 = min(cbx1, (xmax - 128) >> 8);
+    const int32_t ry0 = full ? Y0 : by0, ry1 = full ? Y1 : by1;
+    if (bx0 > bx1 || ry0 > ry1) continue;
+    // colour of this point in this view (Eqs. 8-9)
+    const float ad = fabsf(delta);
+    const float Ar = Zc3 / (rg.fxfy * ad);
+    const float vse = Acell < Ar ? T.ruv * Ar : suv;
+    const float vs = vse < T.smin ? T.smin : (vse > T.smax ? T.smax : vse);
+    const float tau = (vs - T.smin) * T.irange;
+    int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
+    tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
+    const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
+    const uint32_t col = (((lo02 * wa + hi02 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
+                         ((((lo13 * wa + hi13 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8);
+    const float ks = uniform_f32(rg.kshift[r]);
+    const float cu = T.ux * (b - T.p0x) - T.cu0;
+    const float cw = T.wx * (b - T.p0x) - T.cw0;
+    // edge functions with the tie rule folded in as +0.5 (E integer: E+0.5 > 0 <=> E >= 0)
+    double edx[3], edy[3], bias[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int eb = e == 2 ? 0 : e + 1;
+      const int32_t dx = qx[eb] - qx[e], dy = qy[eb] - qy[e];
+      edx[e] = (double)dx;
+      edy[e] = (double)dy;
+      bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
+    }
+    uint64_t* kv = keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * vpx);
+    const int32_t pxq0 = 256 * bx0 + 128;
+    for (int32_t y = ry0; y <= ry1; ++y) {
+      const int32_t pyq = 256 * y + 128;
+      double E0 = edx[0] * (double)(pyq - qy[0]) - edy[0] * (double)(pxq0 - qx[0]) + bias[0];
+      double E1 = edx[1] * (double)(pyq - qy[1]) - edy[1] * (double)(pxq0 - qx[1]) + bias[1];
+      double E2 = edx[2] * (double)(pyq - qy[2]) - edy[2] * (double)(pxq0 - qx[2]) + bias[2];
+      const double st0 = edy[0] * 256.0, st1 = edy[1] * 256.0, st2 = edy[2] * 256.0;
+      const float ry = ty[y];
+      const float nyr = T.ny * ry, uyr = T.uy * ry, wyr = T.wy * ry;
+      for (int32_t x = bx0; x <= bx1; ++x) {
+        const bool in = E0 > 0.0 && E1 > 0.0 && E2 > 0.0;
+        E0 -= st0;
+        E1 -= st1;
+        E2 -= st2;
+        if (!in) continue;
+        const float rx = tx[x] - ks;
+        const float den = (T.nx * rx + nyr) + T.nz;
+        const float Z = delta / den;
+        if (!(Z > 0.0f) || isinf(Z)) continue;
+        const float ur = (T.ux * rx + uyr) + T.uz;
+        const float wr = (T.wx * rx + wyr) + T.wz;
+        const float sv = T.sx * (Z * ur + cu) + 0.5f;
+        const float tv = T.sy * (Z * wr + cw) + 0.5f;
+        const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
+        if (own)
+          key_min(&kv[(int64_t)y * row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
+      }
+    }
+  }
+}
+
+// kMulti: points of several items (a batch); otherwise every point belongs to
+// items[0] and the item is read once.
+template <bool kMulti>
 __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
   const Rig& trg = a.table_rig;
@@ -458,152 +630,29 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
   __syncthreads();
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const int64_t vpx = (int64_t)trg.W * trg.H;
-  const int32_t H8 = 256 * trg.H, W8 = 256 * trg.W;
+  const Item it0 = load_uniform(a.items);
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
     const Point pt = a.points[p];
     const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
     const TriRec T = a.rec[tri];
-    const Rig& rg = a.items[T.item].rig;
-    uint64_t* const keys = a.items[T.item].keys;
-    const bool rowmajor = a.items[T.item].key_layout != 0;
-    const int64_t row_stride = rowmajor ? (int64_t)rg.n_views * rg.W : rg.W;
-    const float zlim = 0.5f * rg.znear;
-    // view-independent vertex rows (guard band on y) and triangle row range
-    if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) continue;
-    const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
-                  qy2 = (int32_t)rintf(T.y2 * 256.0f);
-    if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) continue;
-    const int32_t ymin = min(qy0, min(qy1, qy2)), ymax = max(qy0, max(qy1, qy2));
-    const int32_t Y0 = max(0, -((128 - ymin) >> 8));
-    const int32_t Y1 = min(rg.H - 1, (ymax - 128) >> 8);
-    if (Y0 > Y1) continue;
-    // splat box corners (row-end extended cell), projected except for the eye offset
-    const int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
-    const int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
-    float cA[4], cC[4];
-    float ymn = 0.0f, ymx = 0.0f;
-    bool full = false;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      float aa = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
-      float cc = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
-      float X = (T.p0x + aa * T.ux) + cc * T.wx;
-      float Y = (T.p0y + aa * T.uy) + cc * T.wy;
-      float Z = (T.p0z + aa * T.uz) + cc * T.wz;
-      if (!(Z >= zlim)) full = true;
-      float Yp;
-      vertex_proj(rg, X, Y, Z, cA[k], cC[k], Yp);
-      if (k == 0) { ymn = ymx = Yp; }
-      else { ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx; }
+    if (!kMulti) {
+      splat_point(it0, pt, T, flags, i, j, tx, ty);
+      continue;
     }
-    int32_t by0 = Y0, by1 = Y1;
-    if (!full) {
-      int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
-      by0 = max(r0, by0);
-      by1 = min(r1, by1);
-    }
-    if (by0 > by1) continue;
-    // cell-centre terms of Eqs. 8-9 and the ownership bounds
-    const float cs = (float)i / T.sx, ct = (float)j / T.sy;
-    const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
-    const float Zc3 = (Zc * Zc) * Zc;
-    const float Acell = 1.0f / (T.sx * T.sy);
-    const float suv = Acell * T.ruv;
-    const float fi0 = (float)i, fi1 = (float)(i + 1), fj0 = (float)j, fj1 = (float)(j + 1);
-    const bool oilo = flags & F_ILO, oihi = flags & F_IHI, ojlo = flags & F_JLO, ojhi = flags & F_JHI;
-    const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
-    const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
-    for (int r = 0; r < rg.n_views; ++r) {
-      const float b = rg.eye[r];
-      const float delta = T.h - T.nx * b;
-      if (!(delta < 0.0f)) continue;
-      // splat box columns first: empty for about a third of the (point, view) pairs
-      int32_t cbx0 = 0, cbx1 = rg.W - 1;
-      if (!full) {
-        float xmn = cA[0] - b * cC[0], xmx = xmn;
-#pragma unroll
-        for (int k = 1; k < 4; ++k) {
-          float xx = cA[k] - b * cC[k];
-          xmn = xx < xmn ? xx : xmn;
-          xmx = xx > xmx ? xx : xmx;
-        }
-        cbx0 = max(cbx0, (int32_t)ceilf(clamp_big(xmn - 0.515625f)));
-        cbx1 = min(cbx1, (int32_t)floorf(clamp_big(xmx - 0.484375f)));
-        if (cbx0 > cbx1) continue;
+    // points of one wave nearly always belong to one item: take the items one at
+    // a time, each pass with a uniform item.  The loop runs on a ballot mask, so
+    // its trip count is the same in every lane and the body stays inside it.
+    const int32_t my = T.item;
+    uint64_t todo = __builtin_amdgcn_ballot_w64(true);
+    while (todo) {
+      const int32_t cur = __builtin_amdgcn_readlane(my, (int32_t)__builtin_ctzll(todo));
+      const bool mine = my == cur;
+      if (mine) {
+        const Item it = load_uniform(a.items + cur);
+        splat_point(it, pt, T, flags, i, j, tx, ty);
       }
-      const float x0 = T.a0 - b * T.c0, x1 = T.a1 - b * T.c1, x2 = T.a2 - b * T.c2;
-      if (!(fabsf(x0) < kGuard) || !(fabsf(x1) < kGuard) || !(fabsf(x2) < kGuard)) continue;
-      int32_t qx[3] = {(int32_t)rintf(x0 * 256.0f), (int32_t)rintf(x1 * 256.0f), (int32_t)rintf(x2 * 256.0f)};
-      int32_t qy[3] = {qy0, qy1, qy2};
-      if ((qx[0] < 0 && qx[1] < 0 && qx[2] < 0) || (qx[0] > W8 && qx[1] > W8 && qx[2] > W8)) continue;
-      const double a2 = (double)(qx[1] - qx[0]) * (double)(qy[2] - qy[0]) -
-                        (double)(qy[1] - qy[0]) * (double)(qx[2] - qx[0]);
-      if (a2 == 0.0) continue;
-      if (a2 < 0.0) {
-        int32_t u = qx[1]; qx[1] = qx[2]; qx[2] = u;
-        u = qy[1]; qy[1] = qy[2]; qy[2] = u;
-      }
-      const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
-      const int32_t bx0 = max(cbx0, -((128 - xmin) >> 8));
-      const int32_t bx1 = min(cbx1, (xmax - 128) >> 8);
-      const int32_t ry0 = full ? Y0 : by0, ry1 = full ? Y1 : by1;
-      if (bx0 > bx1 || ry0 > ry1) continue;
-      // colour of this point in this view (Eqs. 8-9)
-      const float ad = fabsf(delta);
-      const float Ar = Zc3 / (rg.fxfy * ad);
-      const float vse = Acell < Ar ? T.ruv * Ar : suv;
-      const float vs = vse < T.smin ? T.smin : (vse > T.smax ? T.smax : vse);
-      const float tau = (vs - T.smin) * T.irange;
-      int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
-      tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
-      const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
-      const uint32_t col = (((lo02 * wa + hi02 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
-                           ((((lo13 * wa + hi13 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8);
-      const float ks = rg.kshift[r];
-      const float cu = T.ux * (b - T.p0x) - T.cu0;
-      const float cw = T.wx * (b - T.p0x) - T.cw0;
-      // edge functions with the tie rule folded in as +0.5 (E integer: E+0.5 > 0 <=> E >= 0)
-      double edx[3], edy[3], bias[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const int eb = e == 2 ? 0 : e + 1;
-        const int32_t dx = qx[eb] - qx[e], dy = qy[eb] - qy[e];
-        edx[e] = (double)dx;
-        edy[e] = (double)dy;
-        bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
-      }
-      uint64_t* kv = keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * vpx);
-      const int32_t pxq0 = 256 * bx0 + 128;
-      for (int32_t y = ry0; y <= ry1; ++y) {
-        const int32_t pyq = 256 * y + 128;
-        double E0 = edx[0] * (double)(pyq - qy[0]) - edy[0] * (double)(pxq0 - qx[0]) + bias[0];
-        double E1 = edx[1] * (double)(pyq - qy[1]) - edy[1] * (double)(pxq0 - qx[1]) + bias[1];
-        double E2 = edx[2] * (double)(pyq - qy[2]) - edy[2] * (double)(pxq0 - qx[2]) + bias[2];
-        const double st0 = edy[0] * 256.0, st1 = edy[1] * 256.0, st2 = edy[2] * 256.0;
-        const float ry = ty[y];
-        const float nyr = T.ny * ry, uyr = T.uy * ry, wyr = T.wy * ry;
-        for (int32_t x = bx0; x <= bx1; ++x) {
-          const bool in = E0 > 0.0 && E1 > 0.0 && E2 > 0.0;
-          E0 -= st0;
-          E1 -= st1;
-          E2 -= st2;
-          if (!in) continue;
-          const float rx = tx[x] - ks;
-          const float den = (T.nx * rx + nyr) + T.nz;
-          const float Z = delta / den;
-          if (!(Z > 0.0f) || isinf(Z)) continue;
-          const float ur = (T.ux * rx + uyr) + T.uz;
-          const float wr = (T.wx * rx + wyr) + T.wz;
-          const float sv = T.sx * (Z * ur + cu) + 0.5f;
-          const float tv = T.sy * (Z * wr + cw) + 0.5f;
-          const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
-          if (own)
-            atomicMin((unsigned long long*)&kv[(int64_t)y * row_stride + x],
-                      (unsigned long long)(((uint64_t)__float_as_uint(Z) << 32) | col));
-        }
-      }
+      todo &= ~__builtin_amdgcn_ballot_w64(mine);
     }
   }
 }
@@ -734,7 +783,10 @@ void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
   size_t lds = sizeof(float) * (size_t)(a.table_rig.W + a.table_rig.H);
-  k_splat<<<grid_blocks, 256, lds, s>>>(a);
+  if (a.n_items > 1)
+    k_splat<true><<<grid_blocks, 256, lds, s>>>(a);
+  else
+    k_splat<false><<<grid_blocks, 256, lds, s>>>(a);
 }
 
 void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,
