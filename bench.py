@@ -1,16 +1,21 @@
 """Benchmark of the LFDPR per-frame hot path on one MI355X.
 
-One step = one whole frame of the hot path on the display-size workload
-(999,168 triangles, 16 RGBA8 2048^2 textures, 48 views of 512^2, 2560x1600
-tilted-lenticular panel): triangle set-up, scan, point emission, splat into
-all 48 views, resolve, interleave.  The scene rotates by 2*pi/1000 per frame.
-Inputs are resident in HBM before the timed region starts.
+Default workload (display-1M): one step = one whole frame of the hot path on
+999,168 triangles, 16 RGBA8 2048^2 textures, 48 views of 512^2 and a
+2560x1600 tilted-lenticular panel: triangle set-up, scan, point emission,
+splat into all 48 views, resolve, interleave.  The scene rotates by 2*pi/1000
+per frame.  Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line: value = point-view splats per second of whole-frame
+--workload display-4M-ss4: 3,996,672 triangles rendered into 192 views (4x
+angular supersampling), angular filter to 48 views, interleave.
+--workload batch16: 16 scenes of 50k-4M triangles per step, one hipGraph
+replay after the launch autotuner.
+
+Prints one JSON line: value = point-view splats per second of whole-step
 time (sum over points of the views their triangle is active in, divided by
-frame time), ms_per_step = frame ms; per-stage ms, the roofline of the
-dominant kernel (HIP events on the library's stream, inside the timed region)
-and the CPU oracle timed on a bounded sample.
+step time), ms_per_step; per-stage ms, the roofline of the dominant kernel
+(HIP events on the library's stream, inside the timed region) and, for the
+default workload, the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -46,7 +51,214 @@ BYTES = {
     "splat": lambda s: s["points"] * (16 + 112) + s["fragments"] * 8,
     "resolve": lambda s: s["pixels"] * (8 + 8 + 4),
     "interleave": lambda s: s["panel_px"] * 3 + s["panel_px"] * 3 * 4,
+    "angular_filter": lambda s: s["pixels"] * 4 + s["out_pixels"] * 4,
 }
+
+
+def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None) -> dict:
+    """Roofline object of the dominant kernel of a frame (stage ms from HIP events)."""
+    dom = max(("setup", "emit", "splat", "resolve", "interleave", "scan", "angular_filter"),
+              key=lambda k: stage_ms.get(k, 0.0))
+    dom_ms = stage_ms[dom]
+    if dom == "splat":
+        ops = SPLAT_OPS_PER_POINT_VIEW * pv_per_frame
+        achieved = ops / (dom_ms * 1e-3) / 1e12
+        return {"kernel": "k_splat", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_GOPS / 1e3, 2), "unit": "Tops/s",
+                "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": traffic,
+                "ops_per_point_view": SPLAT_OPS_PER_POINT_VIEW, "launch_ms": round(dom_ms, 4)}
+    if dom == "setup":
+        ops = SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"]
+        achieved = ops / (dom_ms * 1e-3) / 1e12
+        return {"kernel": "k_tri_setup", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_GOPS / 1e3, 2), "unit": "Tops/s",
+                "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": None, "launch_ms": round(dom_ms, 4)}
+    b = BYTES[dom](shape)
+    achieved = b / (dom_ms * 1e-3) / 1e9
+    return {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launch_ms": round(dom_ms, 4)}
+
+
+def splat_traffic():
+    """HBM bytes per k_splat launch on display-1M from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "display-1M_splat_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2601_19901_amd", "csrc", f), "rb").read())
+    m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", txt)
+    t = re.search(r"HBM bytes per launch: ([0-9.e+]+)", txt)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
+
+
+def stage_avg(R):
+    return {k: (v[0] / v[1]) for k, v in R.timings().items() if v[1]}
+
+
+def run_display(args, torch, lfdpr, scenes, four_m: bool):
+    t0 = time.time()
+    w = scenes.display_4m(seed=3) if four_m else scenes.display(seed=args.seed)
+    log(f"workload generated in {time.time() - t0:.1f}s: {w.scene.n_tris} tris")
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views, point_capacity=(48 << 20) if four_m else 0)
+    R.set_lens(w.lens)
+    views, _ = R.alloc_views()
+    filtered = torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0") if four_m else None
+    panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
+    models = [w.model(f) for f in range(args.warmup + args.steps)]
+
+    def frame(f):
+        R.render_frame(sid, models[f], views)
+        if four_m:
+            R.angular_filter(views, filtered)
+            R.reconstruct(filtered, panel)
+        else:
+            R.reconstruct(views, panel)
+
+    for f in range(args.warmup):
+        frame(f)
+    torch.cuda.synchronize()
+    R.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        frame(args.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st_avg = stage_avg(R)
+    R.timing(False)
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+
+    # the same frames again, untimed, for their statistics (deterministic)
+    pv = pts = act = 0
+    for k in range(args.steps):
+        R.render_frame(sid, models[args.warmup + k], views)
+        s = R.stats()
+        pv += s["point_views"]
+        pts += s["points"]
+        act += s["active_tris"]
+    nfr = args.steps
+    n_rendered = w.views.V * w.views.S
+    shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
+                 out_pixels=w.views.V * w.views.W * w.views.H,
+                 panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, fragments=0)
+    roof = roofline(st_avg, pv / nfr, shape, None if four_m else splat_traffic())
+    if four_m:
+        name = ("display-4M-ss4: 3,996,672 tris (1024^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
+                "192 rendered views 512x512 (4x angular supersampling over 48, jittered), angular filter to 48 views, "
+                "2560x1600 lenticular panel, rotating scene")
+    else:
+        name = ("display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
+                "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene")
+    out = {
+        "metric": METRIC,
+        "value": round((pv / nfr) / (wall_ms * 1e-3), 1),
+        "unit": "point-view splats/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "views": w.views.V, "rendered_views": n_rendered,
+                   "view_px": [w.views.W, w.views.H], "panel_px": [w.lens.Wp, w.lens.Hp],
+                   "triangles": w.scene.n_tris, "recon": "angular filter" if four_m else "none"},
+        "frame_ms": round(wall_ms, 4),
+        "frames_per_s": round(1e3 / wall_ms, 2),
+        "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
+        "active_tris_per_frame": int(act / nfr),
+        "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline and not four_m:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        o = O.render(w.scene, w.views, models[args.warmup])
+        O.interleave(o["rgba"], w.lens)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(o["stats"]["point_views"] / dt, 1), "unit": "point-view splats/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "one full display-1M frame (point generation, splat into 48 views, "
+                                         f"interleave) on one host core: {dt:.2f} s"}
+    return out
+
+
+def run_batch(args, torch, lfdpr, scenes):
+    t0 = time.time()
+    ws = scenes.batch_workloads(seed=400)
+    ntri = [w.scene.n_tris for w in ws]
+    log(f"batch generated in {time.time() - t0:.1f}s: {sum(ntri)} tris over {len(ws)} scenes")
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    B = lfdpr.Batch(R, ids, [w.views for w in ws], point_capacity=96 << 20)
+    views = B.alloc_views()
+    V, W, H = ws[0].views.V, ws[0].views.W, ws[0].views.H
+    panels = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
+    nf = args.warmup + args.steps
+    models = [[w.model(f + 37 * k) for k, w in enumerate(ws)] for f in range(nf)]
+    B.use_graph(False)
+    tune = B.autotune(models[0], views)
+    log(f"autotune: {tune['best']}")
+    # stage times of eager batch renders (same kernels as the graph)
+    for f in range(min(3, nf)):
+        B.render(models[f], views, panels)
+    torch.cuda.synchronize()
+    R.timing(True)
+    for k in range(args.steps):
+        B.render(models[args.warmup + k], views, panels)
+    torch.cuda.synchronize()
+    st_avg = stage_avg(R)
+    R.timing(False)
+    # timed: hipGraph replays
+    B.use_graph(True)
+    for f in range(args.warmup):
+        B.render(models[f], views, panels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        B.render(models[args.warmup + k], views, panels)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+    pv = pts = act = 0
+    for k in range(args.steps):
+        B.render(models[args.warmup + k], views, panels)
+        s = B.stats()
+        pv += s["point_views"]
+        pts += s["points"]
+        act += s["active_tris"]
+    nfr = args.steps
+    shape = dict(nt=sum(ntri), views=V, points=pts / nfr, pixels=len(ws) * V * W * H,
+                 panel_px=len(ws) * ws[0].lens.Wp * ws[0].lens.Hp, tris_with_points=act / nfr, fragments=0)
+    roof = roofline(st_avg, pv / nfr, shape)
+    roof["timing"] = "stage events on eager batch renders of the same frames (graph replays carry no events)"
+    return {
+        "metric": METRIC,
+        "value": round((pv / nfr) / (wall_ms * 1e-3), 1),
+        "unit": "point-view splats/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch16: 16 independent display-family scenes in one hipGraph replay, triangle counts "
+                               "log-uniform 50k-4M, textures 512^2-2048^2, cones 30-50 deg, 48 views 512x512 each, "
+                               "16 2560x1600 panels", "scenes": len(ws), "triangles": ntri,
+                   "autotuned": tune["best"]},
+        "scene_frames_per_s": round(len(ws) * 1e3 / wall_ms, 2),
+        "points_per_step": int(pts / nfr), "point_views_per_step": int(pv / nfr),
+        "stage_ms_eager": {k: round(v, 4) for k, v in st_avg.items()},
+        "roofline": roof,
+    }
+
+
+METRIC = "48-view panel frame ms & point-view splats/s; learned vs 4× angular SS at PSNR"
 
 
 def main():
@@ -54,6 +266,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "batch16"), default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -80,103 +293,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}))
         return
-    t0 = time.time()
-    w = scenes.display(seed=args.seed)
-    log(f"workload generated in {time.time() - t0:.1f}s: {w.scene.n_tris} tris")
-    R = lfdpr.Renderer(0)
-    sid = R.upload_scene(w.scene)
-    R.set_views(w.views)
-    R.set_lens(w.lens)
-    views, _ = R.alloc_views()
-    panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
-    models = [w.model(f) for f in range(args.warmup + args.steps)]
-
-    def frame(f):
-        R.render_frame(sid, models[f], views)
-        R.reconstruct(views, panel)
-
-    for f in range(args.warmup):
-        frame(f)
-    torch.cuda.synchronize()
-    R.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        frame(args.warmup + k)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stage = R.timings()
-    R.timing(False)
-    wall_ms = (t1 - t0) * 1e3 / args.steps
-
-    # the same frames again, untimed, for their statistics (deterministic)
-    pv = pts = act = 0
-    for k in range(args.steps):
-        R.render_frame(sid, models[args.warmup + k], views)
-        s = R.stats()
-        pv += s["point_views"]
-        pts += s["points"]
-        act += s["active_tris"]
-    # per-frame fragment count (pixels written before the depth test) from the last frame's views
-    nfr = args.steps
-    st_avg = {k: (v[0] / max(v[1], 1)) for k, v in stage.items() if v[1]}
-    splats_per_s = pv / (wall_ms * 1e-3 * nfr) if False else (pv / nfr) / (wall_ms * 1e-3)
-
-    # roofline of the dominant kernel
-    dom = max(("setup", "emit", "splat", "resolve", "interleave", "scan"), key=lambda k: st_avg.get(k, 0.0))
-    n_pix = w.views.V * w.views.W * w.views.H
-    shape = dict(nt=w.scene.n_tris, points=pts / nfr, pixels=n_pix, panel_px=w.lens.Wp * w.lens.Hp,
-                 tris_with_points=act / nfr, fragments=0)
-    dom_ms = st_avg[dom]
-    if dom == "splat":
-        ops = SPLAT_OPS_PER_POINT_VIEW * (pv / nfr)
-        achieved = ops / (dom_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_splat", "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 2),
-                "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": None,
-                "ops_per_point_view": SPLAT_OPS_PER_POINT_VIEW, "launch_ms": round(dom_ms, 4)}
-    elif dom == "setup":
-        ops = SETUP_OPS_PER_TRI_VIEW * w.scene.n_tris * w.views.V
-        achieved = ops / (dom_ms * 1e-3) / 1e12
-        roof = {"kernel": "k_tri_setup", "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_GOPS / 1e3, 2),
-                "unit": "Tops/s", "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": None,
-                "launch_ms": round(dom_ms, 4)}
+    if args.workload == "batch16":
+        out = run_batch(args, torch, lfdpr, scenes)
     else:
-        b = BYTES[dom](shape)
-        achieved = b / (dom_ms * 1e-3) / 1e9
-        roof = {"kernel": "k_" + dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launch_ms": round(dom_ms, 4)}
-
-    out = {
-        "metric": "48-view panel frame ms & point-view splats/s; learned vs 4× angular SS at PSNR",
-        "value": round(splats_per_s, 1),
-        "unit": "point-view splats/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall_ms, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 "
-                               "textures, 48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, "
-                               "rotating scene", "views": w.views.V, "view_px": [w.views.W, w.views.H],
-                   "panel_px": [w.lens.Wp, w.lens.Hp], "triangles": w.scene.n_tris, "recon": "none"},
-        "frame_ms": round(wall_ms, 4),
-        "frames_per_s": round(1e3 / wall_ms, 2),
-        "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
-        "active_tris_per_frame": int(act / nfr),
-        "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        tx = O.build_textures(w.scene)
-        t0 = time.perf_counter()
-        o = O.render(w.scene, w.views, models[args.warmup])
-        O.interleave(o["rgba"], w.lens)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(o["stats"]["point_views"] / dt, 1), "unit": "point-view splats/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "one full display-1M frame (point generation, splat into 48 views, "
-                                         f"interleave) on one host core: {dt:.2f} s"}
-        del tx
+        out = run_display(args, torch, lfdpr, scenes, args.workload == "display-4M-ss4")
     print(json.dumps(out), flush=True)
 
 

@@ -185,7 +185,9 @@ int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* dst_f, int32_t* dst_i, int64_
  * stage.  lfdpr_get_timings() synchronises the stream and writes, per stage,
  * the summed milliseconds and the number of recorded launches (host arrays of
  * LFDPR_N_STAGES); stages: 0 triangle set-up, 1 scan, 2 emission, 3 splat,
- * 4 resolve, 5 interleave, 6 angular filter.  lfdpr_timing(ctx, 0) stops. */
+ * 4 resolve, 5 interleave, 6 angular filter.  Batch renders on the context
+ * that are not replayed from a graph record their stages the same way (on the
+ * batch's stream).  lfdpr_timing(ctx, 0) stops. */
 #define LFDPR_N_STAGES 7
 int lfdpr_timing(lfdpr_ctx* ctx, int enable);
 int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n_launches);

@@ -135,8 +135,8 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   return LFDPR_OK;
 }
 
-// Event recorded on the stream when timing is on (nullptr otherwise).
-hipEvent_t mark(lfdpr_ctx* ctx) {
+// Event recorded on `st` when timing is on (nullptr otherwise).
+hipEvent_t mark_on(lfdpr_ctx* ctx, hipStream_t st) {
   if (!ctx->timing) return nullptr;
   if (ctx->ev_used == ctx->ev_pool.size()) {
     hipEvent_t e;
@@ -144,9 +144,11 @@ hipEvent_t mark(lfdpr_ctx* ctx) {
     ctx->ev_pool.push_back(e);
   }
   hipEvent_t e = ctx->ev_pool[ctx->ev_used++];
-  (void)hipEventRecord(e, ctx->stream);
+  (void)hipEventRecord(e, st);
   return e;
 }
+
+hipEvent_t mark(lfdpr_ctx* ctx) { return mark_on(ctx, ctx->stream); }
 
 void stage(lfdpr_ctx* ctx, int id, hipEvent_t a, hipEvent_t b) {
   if (a && b) ctx->ev_marks.push_back({id, {a, b}});
@@ -720,10 +722,14 @@ void batch_free(lfdpr_batch* b) {
   if (b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// The whole batch frame on b->stream: only kernel launches (capturable).
-void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
+// The whole batch frame on b->stream: only kernel launches (capturable), plus
+// stage events when `timed` (never while capturing).
+void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed) {
   hipStream_t st = b->stream;
+  lfdpr_ctx* ctx = b->ctx;
+  auto ev = [&]() { return timed ? mark_on(ctx, st) : nullptr; };
   launch_fill_u64(b->stats, STAT_SLOTS, 0ull, st);
+  hipEvent_t e0 = ev();
   SetupArgs sa{};
   sa.items = b->d_items;
   sa.n_items = b->n;
@@ -735,7 +741,9 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
   sa.em = b->em;
   sa.stats = b->stats;
   launch_tri_setup(sa, st);
+  hipEvent_t e1 = ev();
   launch_scan(b->counts, b->nt, b->tiles, b->offsets, b->stats + STAT_TOTAL, st);
+  hipEvent_t e2 = ev();
   EmitArgs ea{};
   ea.items = b->d_items;
   ea.nt = b->nt;
@@ -748,6 +756,7 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
   ea.n_big = b->stats + STAT_BIG;
   ea.cap = b->cap;
   launch_emit(ea, b->splat_blocks, st);
+  hipEvent_t e3 = ev();
   SplatArgs pa{};
   pa.items = b->d_items;
   pa.n_items = b->n;
@@ -757,11 +766,19 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels) {
   pa.cap = b->cap;
   pa.rec = b->rec;
   launch_splat(pa, b->splat_blocks, st);
+  hipEvent_t e4 = ev();
   launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st);
+  hipEvent_t e5 = ev();
   if (panels) {
     InterleaveArgs ia = interleave_args(b->ctx->lens, views, b->table_rig.n_views, b->table_rig.W, b->table_rig.H, panels);
     launch_interleave_batch(ia, b->n, b->per_item_px, (int64_t)b->ctx->lens.Wp * b->ctx->lens.Hp * 3, st);
+    stage(ctx, 5, e5, ev());
   }
+  stage(ctx, 0, e0, e1);
+  stage(ctx, 1, e1, e2);
+  stage(ctx, 2, e2, e3);
+  stage(ctx, 3, e3, e4);
+  stage(ctx, 4, e4, e5);
 }
 
 int batch_set_shape(lfdpr_batch* b, int splat_blocks, int key_layout) {
@@ -895,7 +912,7 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
       if (b->exec) { BHIP(hipGraphExecDestroy(b->exec)); b->exec = nullptr; }
       if (b->graph) { BHIP(hipGraphDestroy(b->graph)); b->graph = nullptr; }
       BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      batch_enqueue(b, views, panels);
+      batch_enqueue(b, views, panels, false);
       hipError_t ce = hipStreamEndCapture(b->stream, &b->graph);
       if (ce != hipSuccess) return bfail(b, LFDPR_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
       BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
@@ -905,7 +922,7 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
     }
     BHIP(hipGraphLaunch(b->exec, b->stream));
   } else {
-    batch_enqueue(b, views, panels);
+    batch_enqueue(b, views, panels, b->ctx->timing);
     BHIP(hipGetLastError());
   }
   BHIP(hipEventRecord(b->ev_out, b->stream));
