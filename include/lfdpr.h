@@ -244,15 +244,21 @@ int lfdpr_batch_autotune(lfdpr_batch* batch, const float* models, uint32_t* view
 /* ------------------------------------------------------------------------
  * Learned angular reconstruction (a stand-in for 4x angular supersampling,
  * Sec. 4; not part of the paper).  The network is applied to every view v of
- * a frame of V views: its input at a pixel is (R, G, B, d = D/Z - 1; d = -1
- * where empty) of views v-2 .. v+2 (zero beyond the rig), four zero-padded
- * 3x3 convolutions 20 -> 32 -> 32 -> 32 -> 3 with ReLU between them, dilated
- * horizontally by 1, 3, 9, 1 (tap (dy, dx) reads pixel (y+dy, x+dil*dx)), FP32
- * accumulation on BF16 MFMA, BF16 activations; the output is view v's RGB plus
- * the network.  Tensors: compact input x [view][H][W][4] BF16 (as written by
- * lfdpr_net_pack_input), output y [view][H][W][4] BF16 (R, G, B, 0).
- * Parameters: an FP32 vector, per layer W [9][cout][cin] (tap 3*(dy+1)+(dx+1)
- * reads pixel (y+dy, x+dx)) followed by b [cout].  All tensors are device
+ * a frame of V views.  Its input at a pixel is (R, G, B, d = D/Z - 1; d = -1
+ * where empty) of views v-2 .. v+2 (zero beyond the rig) and the disparity
+ * blur of view v: with s = k*d (k from lfdpr_net_set_disparity_scale; s = 0
+ * where d <= -1), the sum over t = -1, -3/4, .., 1 of w_t * view_v(x + t*s, y)
+ * (linear interpolation along the row, border pixel repeated; w_t the
+ * normalised weights round(65535 exp(-2 t^2)), the angular filter's profile),
+ * evaluated in binary32 in that order and rounded to BF16 -- 24 channels.
+ * Four zero-padded 3x3 convolutions 24 -> 32 -> 32 -> 32 -> 3 with ReLU
+ * between them, dilated horizontally by 1, 3, 9, 1 (tap (dy, dx) reads pixel
+ * (y+dy, x+dil*dx)), FP32 accumulation on BF16 MFMA, BF16 activations; the
+ * output is the blurred RGB plus the network.  Tensors: compact input x
+ * [view][H][W][4] BF16 (as written by lfdpr_net_pack_input), output y
+ * [view][H][W][4] BF16 (R, G, B, 0).  Parameters: an FP32 vector, per layer W
+ * [9][cout][cin] (tap 3*(dy+1)+(dx+1) reads pixel (y+dy, x+dx)) followed by
+ * b [cout].  All tensors are device
  * memory unless stated; calls are asynchronous on the context's stream unless
  * stated.
  * ------------------------------------------------------------------------ */
@@ -266,6 +272,10 @@ int lfdpr_net_destroy(lfdpr_net* net);
 const char* lfdpr_net_last_error(lfdpr_net* net);
 /* Number of FP32 parameters (host int64). */
 int lfdpr_net_param_count(lfdpr_net* net, int64_t* n);
+/* Pixels a surface at d = 1 moves across per view step: k = fx * 2 tan(cone/2) / V
+ * for the rig of R2 (k >= 0; 0, the default, turns the blur into the identity).
+ * Applies from the next forward. */
+int lfdpr_net_set_disparity_scale(lfdpr_net* net, float k);
 /* Host FP32 parameters in / out (n must equal the count); set resets Adam.  Synchronous. */
 int lfdpr_net_set_params(lfdpr_net* net, const float* host_params, int64_t n);
 int lfdpr_net_get_params(lfdpr_net* net, float* host_params, int64_t n);
@@ -287,6 +297,7 @@ int lfdpr_net_adam_step(lfdpr_net* net, float lr, float beta1, float beta2, floa
 int lfdpr_net_unpack_output(lfdpr_net* net, const void* y, int32_t n_views, int32_t H, int32_t W, uint32_t* views);
 /* Copies internal state of the last forward/backward into dst (device, n_bytes
  * room): which = 1..3 activation of hidden layer k ([view][H][W][32] BF16),
+ * 4 the disparity blur of the input ([view][H][W][4] BF16, (R, G, B, 0)),
  * 11..13 gradient of hidden pre-activation k, 14 gradient of the output
  * ([view][H][W][32] BF16, channels 0..2), 20 parameter gradients (FP32).
  * Synchronous. */

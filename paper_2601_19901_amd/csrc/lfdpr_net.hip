@@ -1,13 +1,19 @@
 // Learned angular reconstruction: a small 3x3 convolutional network whose
 // inference and training run on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32
 // accumulate).  It stands in for 4x angular supersampling (Sec. 4) and is
-// applied to every view v of a frame: its input at a pixel is (R, G, B, d =
-// D/Z - 1) of views v-2 .. v+2 (20 channels, zero beyond the rig), layers
-// 20 -> 32 -> 32 -> 32 -> 3 with ReLU, 3x3 kernels dilated horizontally by
-// 1, 3, 9, 1; output = view v's RGB + network.
+// applied to every view v of a frame.  Angular supersampling plus the angular
+// filter averages sub-views within about one view interval; a surface at
+// disparity d = D/Z - 1 moves k*d pixels across per view step, so away from
+// occlusions that average is a horizontal blur of width proportional to |d|.
+// The input at a pixel is (R, G, B, d) of views v-2 .. v+2 (zero beyond the
+// rig) and the disparity blur of view v (9 Gaussian taps over +-1 view step,
+// the angular filter's profile): 24 channels; layers 24 -> 32 -> 32 -> 32 -> 3
+// with ReLU, 3x3 kernels dilated horizontally by 1, 3, 9, 1; output = blurred
+// RGB + network.
 //
 // Layouts: the compact input is [view][H][W][4] BF16 and layer 1 gathers the
-// neighbour views from it directly; hidden activations are [view][H][W][32]
+// neighbour views from it directly, and the blur from its own [view][H][W][4]
+// buffer; hidden activations are [view][H][W][32]
 // BF16; the output [view][H][W][4] (RGB, 0).  Parameters: FP32 master vector,
 // per layer W [tap][cout][cin] then b [cout] (unpadded); BF16 copies padded
 // to 32 input channels (layer 1) and 16 output channels (layer 4).
@@ -50,17 +56,19 @@ union Frag {
 
 // ---------------------------------------------------------------- 3x3 convolution
 constexpr int kNeigh = 2;   // views v-2 .. v+2
-constexpr int kCin0 = 20;   // real input channels of layer 1
+constexpr int kViewCh = 4 * (2 * kNeigh + 1);  // 20 channels of the five views
+constexpr int kCin0 = kViewCh + 4;             // + blurred (R, G, B, 0) of view v
 constexpr int kK = 32;      // padded input channels of every layer (one MFMA K step per tap)
 // Horizontal dilation per layer: one view step shifts content by several
 // pixels across, so the stack sees +-14 px horizontally and +-4 px vertically.
 constexpr int kDilation[4] = {1, 3, 9, 1};
 
 // Loads the 8 K-values of lane group g for input pixel (n, yy, xx).  GATHER:
-// from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2, n+2g-1.
+// from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2,
+// n+2g-1; the slot after view n+2 (channels 20..23) takes the blur XB of view n.
 template <bool GATHER>
-__device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, int n, int yy, int xx, int H, int W, int g,
-                                        int V) {
+__device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const uint16_t* __restrict__ XB, int n, int yy,
+                                        int xx, int H, int W, int g, int V) {
   if (yy < 0 || yy >= H || xx < 0 || xx >= W) return uint4{0u, 0u, 0u, 0u};
   if (!GATHER) return *reinterpret_cast<const uint4*>(X + (((size_t)n * H + yy) * W + xx) * kK + 8 * g);
   const int v = n % V, f0 = n - v;
@@ -68,14 +76,20 @@ __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, int n, i
   const int o0 = 2 * g - kNeigh, o1 = 2 * g + 1 - kNeigh;
   if (o0 <= kNeigh && v + o0 >= 0 && v + o0 < V)
     lo = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o0) * H + yy) * W + xx) * 4);
-  if (o1 <= kNeigh && v + o1 >= 0 && v + o1 < V)
-    hi = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o1) * H + yy) * W + xx) * 4);
+  if (o1 <= kNeigh) {
+    if (v + o1 >= 0 && v + o1 < V)
+      hi = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o1) * H + yy) * W + xx) * 4);
+  } else if (o1 == kNeigh + 1) {
+    hi = *reinterpret_cast<const uint2*>(XB + (((size_t)n * H + yy) * W + xx) * 4);
+  }
   return uint4{lo.x, lo.y, hi.x, hi.y};
 }
 
 // One block = 4 waves; a tile is 256 consecutive output pixels of the
 // [N][H][W] grid (4 M-tiles of 16 per wave); NT = COUT/16 output-channel tiles.
 // All nine taps' [COUT][32] weights sit in LDS for the block's lifetime.
+// aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
+// MODE_BWD, the activation whose ReLU masks the gradient.
 template <int NT, int MODE, bool GATHER>
 __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
                                                   const float* __restrict__ bias, int N, int H, int W, int V, int DIL,
@@ -116,7 +130,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         Frag a;
-        a.u = load_a<GATHER>(X, pn[m], py[m] + dy, px[m] + dx, H, W, g, V);
+        a.u = load_a<GATHER>(X, aux, pn[m], py[m] + dy, px[m] + dx, H, W, g, V);
 #pragma unroll
         for (int n = 0; n < NT; ++n)
           acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[n].v, acc[m][n], 0, 0, 0);
@@ -153,8 +167,9 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 // real (co < CO, ci < CI) entries are written, into the unpadded layout.
 template <bool GATHER>
 __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ dZ, int DZS, int CO,
-                                                    const uint16_t* __restrict__ A, int CI, int N, int H, int W, int V,
-                                                    int DIL, float* __restrict__ dW, int chunk) {
+                                                    const uint16_t* __restrict__ A, const uint16_t* __restrict__ AB,
+                                                    int CI, int N, int H, int W, int V, int DIL,
+                                                    float* __restrict__ dW, int chunk) {
   const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
   const int nct = (CO + 15) / 16, nit = 2;  // ci padded to 32
   int t = blockIdx.x;
@@ -179,9 +194,11 @@ __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ 
         if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
           if (!GATHER) {
             zb = A[(((size_t)n * H + yy) * W + xx) * kK + ci];
-          } else if (ci < kCin0) {
+          } else if (ci < kViewCh) {
             const int v = n % V, off = ci / 4 - kNeigh;
             if (v + off >= 0 && v + off < V) zb = A[(((size_t)(n + off) * H + yy) * W + xx) * 4 + (ci & 3)];
+          } else if (ci < kCin0) {
+            zb = AB[(((size_t)n * H + yy) * W + xx) * 4 + (ci & 3)];
           }
         }
       }
@@ -285,6 +302,50 @@ __global__ void k_pack_input(const uint32_t* __restrict__ views, const float* __
   reinterpret_cast<uint2*>(x)[i] = o;
 }
 
+// Disparity blur of each view (the binary32 steps are fixed, so the result is
+// reproducible bit for bit): per pixel, s = k*d (0 where d <= -1, empty); for
+// tap t = -1, -3/4, .., 1: u = min(max(x + t*s, -1), W), x0 = floor(u),
+// f = u - x0, c = (1 - f)*C[x0] + f*C[x0 + 1] (indices clamped to the row),
+// acc += w_t*c; XB = (bf16(acc_R), bf16(acc_G), bf16(acc_B), 0).
+struct BlurTaps {
+  float w[9];
+};
+
+__global__ void __launch_bounds__(256) k_disparity_blur(const uint16_t* __restrict__ X, int64_t npx, int W, float k,
+                                                         BlurTaps bw, uint16_t* __restrict__ XB) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const int x = (int)(p % W);
+  const int64_t row = p - x;
+  const float d = from_bf16(X[p * 4 + 3]);
+  const float s = d > -1.0f ? k * d : 0.0f;
+  float acc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float t = (float)(j - 4) * 0.25f;
+    float u = (float)x + t * s;
+    u = fminf(fmaxf(u, -1.0f), (float)W);
+    const float fl = floorf(u);
+    const float f = u - fl;
+    const int i0 = (int)fl;
+    const int a = min(max(i0, 0), W - 1), b = min(max(i0 + 1, 0), W - 1);
+    const uint2 ca = *reinterpret_cast<const uint2*>(X + (row + a) * 4);
+    const uint2 cb = *reinterpret_cast<const uint2*>(X + (row + b) * 4);
+    const float g = 1.0f - f;
+    const float a0 = from_bf16((uint16_t)(ca.x & 0xFFFFu)), a1 = from_bf16((uint16_t)(ca.x >> 16)),
+                a2 = from_bf16((uint16_t)(ca.y & 0xFFFFu));
+    const float b0 = from_bf16((uint16_t)(cb.x & 0xFFFFu)), b1 = from_bf16((uint16_t)(cb.x >> 16)),
+                b2 = from_bf16((uint16_t)(cb.y & 0xFFFFu));
+    acc[0] = acc[0] + bw.w[j] * (g * a0 + f * b0);
+    acc[1] = acc[1] + bw.w[j] * (g * a1 + f * b1);
+    acc[2] = acc[2] + bw.w[j] * (g * a2 + f * b2);
+  }
+  uint2 o;
+  o.x = (uint32_t)to_bf16(acc[0]) | ((uint32_t)to_bf16(acc[1]) << 16);
+  o.y = (uint32_t)to_bf16(acc[2]);
+  reinterpret_cast<uint2*>(XB)[p] = o;
+}
+
 // y[v][p][4] -> RGBA8, clamp(floor(255 y + 0.5)), alpha 255
 __global__ void k_unpack_output(const uint16_t* __restrict__ y, int64_t n, uint32_t* __restrict__ views) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,6 +388,9 @@ struct lfdpr_net {
   uint16_t* wb[4] = {nullptr, nullptr, nullptr, nullptr};
   uint16_t* act[4] = {nullptr, nullptr, nullptr, nullptr};  // act[1..3]
   uint16_t* dz[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  uint16_t* xb = nullptr;  // disparity blur of the last forward input, [view][H][W][4]
+  float kscale = 0.0f;     // pixels per view step per unit d
+  BlurTaps taps{};
   const uint16_t* last_x = nullptr;
   const uint16_t* last_y = nullptr;
   int last_n = 0, last_h = 0, last_w = 0;
@@ -402,6 +466,16 @@ int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lf
     if (k > 0) al(net->act[k], (size_t)net->maxpx * kHidden);
   }
   for (int k = 1; k <= 4; ++k) al(net->dz[k], (size_t)net->maxpx * kK);
+  al(net->xb, (size_t)net->maxpx * 4);
+  {  // the angular filter's Gaussian profile (sigma = half a view step), normalised in binary32
+    long long wi[9], tot = 0;
+    for (int j = 0; j < 9; ++j) {
+      const double t = (j - 4) / 4.0;
+      wi[j] = std::llround(65535.0 * std::exp(-t * t / 0.5));
+      tot += wi[j];
+    }
+    for (int j = 0; j < 9; ++j) net->taps.w[j] = (float)wi[j] / (float)tot;
+  }
   if (!ok) {
     lfdpr_net_destroy(net);
     return LFDPR_ENOMEM;
@@ -430,6 +504,7 @@ int lfdpr_net_destroy(lfdpr_net* net) {
   (void)hipFree(net->d_loss);
   for (int k = 0; k < 4; ++k) { (void)hipFree(net->wf[k]); (void)hipFree(net->wb[k]); (void)hipFree(net->act[k]); }
   for (int k = 0; k < 5; ++k) (void)hipFree(net->dz[k]);
+  (void)hipFree(net->xb);
   delete net;
   return LFDPR_OK;
 }
@@ -467,6 +542,13 @@ int lfdpr_net_get_params(lfdpr_net* net, float* host, int64_t n) {
   return LFDPR_OK;
 }
 
+int lfdpr_net_set_disparity_scale(lfdpr_net* net, float k) {
+  if (!net) return LFDPR_EINVAL;
+  if (!(k >= 0.0f) || !(k < 1.0e6f)) return nfail(net, LFDPR_EINVAL, "disparity scale out of range");
+  net->kscale = k;
+  return LFDPR_OK;
+}
+
 int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t n_views, int32_t H,
                          int32_t W, float D, void* x) {
   if (!net || !views || !x || n_views < 1 || H < 1 || W < 1 || !(D > 0.0f)) return LFDPR_EINVAL;
@@ -486,10 +568,12 @@ int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t n_views, int32_t H,
   hipStream_t s = net->stream;
   const int N = n_views, V = net->V;
   const int* d = kDilation;
-  launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, d[0], net->act[1], kHidden, nullptr, 0, s);
+  const int64_t npx = (int64_t)N * H * W;
+  k_disparity_blur<<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(in, npx, W, net->kscale, net->taps, net->xb);
+  launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, d[0], net->act[1], kHidden, net->xb, 4, s);
   launch_conv<2, MODE_RELU, false>(net->act[1], net->wf[1], net->master + net->off_b[1], N, H, W, V, d[1], net->act[2], kHidden, nullptr, 0, s);
   launch_conv<2, MODE_RELU, false>(net->act[2], net->wf[2], net->master + net->off_b[2], N, H, W, V, d[2], net->act[3], kHidden, nullptr, 0, s);
-  launch_conv<1, MODE_OUT, false>(net->act[3], net->wf[3], net->master + net->off_b[3], N, H, W, V, d[3], (uint16_t*)y, 4, in, 4, s);
+  launch_conv<1, MODE_OUT, false>(net->act[3], net->wf[3], net->master + net->off_b[3], N, H, W, V, d[3], (uint16_t*)y, 4, net->xb, 4, s);
   NHIP(hipGetLastError());
   net->last_x = in;
   net->last_y = (const uint16_t*)y;
@@ -516,11 +600,11 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
     const int CO = net->co[k], CI = net->ci[k];
     dim3 gw((unsigned)(9 * ((CO + 15) / 16) * 2), nch);
     if (k == 0)
-      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, CI, N, H, W, V, kDilation[0],
+      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, net->xb, CI, N, H, W, V, kDilation[0],
                                            net->grad + net->off_w[0], chunk);
     else
-      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], CI, N, H, W, V, kDilation[k],
-                                            net->grad + net->off_w[k], chunk);
+      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], nullptr, CI, N, H, W, V,
+                                            kDilation[k], net->grad + net->off_w[k], chunk);
     k_bias_grad<<<(unsigned)CO, 256, 0, s>>>(net->dz[k + 1], kK, npx, net->grad + net->off_b[k]);
     if (k > 0)  // input gradient through the flipped, transposed weights (same dilation), masked by the ReLU
       launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, kDilation[k], net->dz[k], kHidden,
@@ -561,6 +645,7 @@ int lfdpr_net_copy_state(lfdpr_net* net, int32_t which, void* dst, int64_t n_byt
   const void* src = nullptr;
   int64_t bytes = 0;
   if (which >= 1 && which <= 3) { src = net->act[which]; bytes = npx * kHidden * 2; }
+  else if (which == 4) { src = net->xb; bytes = npx * 4 * 2; }
   else if (which >= 11 && which <= 14) { src = net->dz[which - 10]; bytes = npx * kK * 2; }
   else if (which == 20) { src = net->grad; bytes = net->nparams * 4; }
   else return nfail(net, LFDPR_EINVAL, "unknown state");

@@ -88,6 +88,7 @@ class LearnedReconstruction:
         self.torch = torch
         self.ss = ss
         self.net = lfdpr.Net(ss.rigs[1].renderer, ss.V, max_h, max_w)
+        self.net.set_disparity_scale(lfdpr.disparity_scale(ss.rigs[1].views))
         self.fallback_S = fallback_S
         self.healthy = True
         rng = np.random.default_rng(seed)

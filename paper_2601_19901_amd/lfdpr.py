@@ -7,6 +7,7 @@ Raises if the library is missing: there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import re
 from typing import Optional
@@ -128,6 +129,7 @@ def signatures():
         "lfdpr_net_last_error": ([vp], C.c_char_p),
         "lfdpr_net_param_count": ([vp, p(i64)], C.c_int),
         "lfdpr_net_set_params": ([vp, vp, i64], C.c_int),
+        "lfdpr_net_set_disparity_scale": ([vp, C.c_float], C.c_int),
         "lfdpr_net_get_params": ([vp, vp, i64], C.c_int),
         "lfdpr_net_pack_input": ([vp, vp, vp, i32, i32, i32, C.c_float, vp], C.c_int),
         "lfdpr_net_forward": ([vp, vp, i32, i32, i32, vp], C.c_int),
@@ -378,6 +380,10 @@ class Net:
         a = np.ascontiguousarray(flat, np.float32)
         self._check(lib().lfdpr_net_set_params(self.h, _ptr(a), a.size))
 
+    def set_disparity_scale(self, k: float):
+        """Pixels per view step per unit d of the input's disparity blur."""
+        self._check(lib().lfdpr_net_set_disparity_scale(self.h, float(k)))
+
     def get_params(self) -> np.ndarray:
         a = np.zeros(self.n_params, np.float32)
         self._check(lib().lfdpr_net_get_params(self.h, _ptr(a), a.size))
@@ -431,7 +437,14 @@ def params_to_flat(params) -> np.ndarray:
                            for w, b in params])
 
 
-NET_SHAPES = [(20, 32), (32, 32), (32, 32), (32, 3)]  # (cin, cout) per layer
+NET_SHAPES = [(24, 32), (32, 32), (32, 32), (32, 3)]  # (cin, cout) per layer
+
+
+def disparity_scale(vp) -> float:
+    """k = fx * 2 tan(cone/2) / V for a rig (scenes.ViewParams): the pixels a
+    surface at d = D/Z - 1 = 1 moves across per view step."""
+    fx = (vp.W / 2.0) / (vp.aspect * math.tan(math.radians(vp.fovy_deg) / 2.0))
+    return fx * 2.0 * math.tan(math.radians(vp.cone_deg) / 2.0) / vp.V
 
 
 def flat_to_params(flat: np.ndarray):

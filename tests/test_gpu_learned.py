@@ -1,6 +1,7 @@
 """The learned angular reconstruction, trained by the library's own forward and
 backward kernels on pairs the method renders, beats the plain renders against
-4x angular supersampling; poisoned parameters fall back to 4x supersampling."""
+4x angular supersampling; poisoned parameters fall back to 4x supersampling.
+Untrained (last layer zero) the network is the disparity blur alone."""
 import math
 
 import numpy as np
@@ -35,16 +36,16 @@ def trained():
 
 def test_training_reduces_loss(trained):
     _, _, _, _, _, (loss0, loss1) = trained
-    assert abs(loss0[0] - loss0[1]) < 0.02 * loss0[1]   # untrained network = plain render
-    assert loss1[0] < 0.92 * loss0[0]
+    assert loss0[0] < 0.7 * loss0[1]     # the disparity blur alone already helps
+    assert loss1[0] < 0.95 * loss0[0]    # and training improves on it
 
 
 def test_learned_beats_plain_against_supersampling(trained):
     _, _, _, before, after, _ = trained
-    # untrained (last layer zero) = the plain render
-    assert abs(before["learned_vs_ss4"] - before["plain_vs_ss4"]) < 0.05
-    assert after["learned_vs_ss4"] > after["plain_vs_ss4"] + 1.0
-    assert after["learned_vs_ref"] > after["plain_vs_ref"]
+    assert before["learned_vs_ss4"] > before["plain_vs_ss4"] + 1.0
+    assert after["learned_vs_ss4"] > before["learned_vs_ss4"]
+    assert after["learned_vs_ss4"] > after["plain_vs_ss4"] + 2.0
+    assert after["learned_vs_ref"] > after["plain_vs_ref"] + 2.0
 
 
 def test_fallback_on_poisoned_parameters(trained):

@@ -71,28 +71,42 @@ def random_params(seed, scale=1.5):
     return [(w, rng.normal(0, 0.05, b.shape)) for w, b in params]
 
 
-@pytest.mark.parametrize("V,F,H,W", [(6, 1, 24, 40), (48, 1, 8, 32), (5, 2, 7, 13)])
-def test_forward_layers_match_oracle(torch_cuda, V, F, H, W):
-    """F frames of V views each, ragged pixel counts."""
+def random_input(rng, n, H, W):
+    """Colours in [-0.5, 1.5), disparities in [-0.5, 3) with some empty (-1) pixels."""
+    x = rng.random((n, H, W, 4)) * 2 - 0.5
+    x[..., 3] = rng.uniform(-0.5, 3.0, (n, H, W))
+    x[..., 3][rng.random((n, H, W)) < 0.1] = -1.0
+    return f_to_bits(x)
+
+
+@pytest.mark.parametrize("V,F,H,W,k", [(6, 1, 24, 40, 2.75), (48, 1, 8, 32, 9.05), (5, 2, 7, 13, 0.0),
+                                       (5, 2, 7, 13, 1.3)])
+def test_forward_layers_match_oracle(torch_cuda, V, F, H, W, k):
+    """F frames of V views each, ragged pixel counts; disparity blur bit-exact."""
     torch = torch_cuda
     from paper_2601_19901_amd import lfdpr
     R, net = make_net(torch, V, H, W * F)
+    net.set_disparity_scale(k)
     params = random_params(V + H)
     flat = lfdpr.params_to_flat(params)
     net.set_params(flat)
     P = lfdpr.flat_to_params(flat.astype(np.float64))
     rng = np.random.default_rng(1)
-    xb = f_to_bits(rng.random((F * V, H, W, 4)) * 2 - 0.5)
+    xb = random_input(rng, F * V, H, W)
     x = t16(xb, torch)
     y = torch.zeros((F * V, H, W, 4), dtype=torch.int16, device="cuda")
     net.forward(x, y)
     acts = []
-    for k in (1, 2, 3):
+    for j in (1, 2, 3):
         a = torch.zeros((F * V, H, W, 32), dtype=torch.int16, device="cuda")
-        net.copy_state(k, a)
+        net.copy_state(j, a)
         acts.append(get16(a))
     xf = bits_to_f(xb)
-    a0 = np.concatenate([N.assemble(xf[f * V:(f + 1) * V]) for f in range(F)])
+    blur_g = torch.zeros((F * V, H, W, 4), dtype=torch.int16, device="cuda")
+    net.copy_state(4, blur_g)
+    blur = N.disparity_blur(xf, np.float32(k))
+    np.testing.assert_array_equal(get16(blur_g), blur)
+    a0 = np.concatenate([N.assemble(xf[f * V:(f + 1) * V], blur[f * V:(f + 1) * V]) for f in range(F)])
     inp = [a0] + acts
     for k in range(3):
         w = N.bf16(P[k][0])
@@ -102,25 +116,30 @@ def test_forward_layers_match_oracle(torch_cuda, V, F, H, W):
         assert_bf16_close(acts[k], want, f"V{V}x{F} layer {k + 1}", abs_sum=S)
     w = N.bf16(P[3][0])
     d = N.DILATION[3]
-    want_y = N.bf16(np.stack([N.conv3x3(acts[2][n], w, P[3][1], d) for n in range(F * V)]) + xf[..., :3])
-    S = np.stack([N.conv3x3(np.abs(acts[2][n]), np.abs(w), np.abs(P[3][1]), d) for n in range(F * V)]) + np.abs(xf[..., :3])
+    want_y = N.bf16(np.stack([N.conv3x3(acts[2][n], w, P[3][1], d) for n in range(F * V)]) + blur[..., :3])
+    S = np.stack([N.conv3x3(np.abs(acts[2][n]), np.abs(w), np.abs(P[3][1]), d) for n in range(F * V)]) + np.abs(blur[..., :3])
     yg = get16(y)
     assert (yg[..., 3] == 0).all()
     assert_bf16_close(yg[..., :3], want_y, f"V{V}x{F} output", abs_sum=S)
 
 
 def test_zero_parameters_are_identity(torch_cuda):
+    """Zero parameters: the output is the input RGB without a disparity scale,
+    the oracle's disparity blur with one."""
     torch = torch_cuda
     V, H, W = 8, 8, 48
     R, net = make_net(torch, V, H, W)
     rng = np.random.default_rng(0)
-    xb = f_to_bits(rng.random((V, H, W, 4)))
+    xb = random_input(rng, V, H, W)
     x = t16(xb, torch)
     y = torch.zeros((V, H, W, 4), dtype=torch.int16, device="cuda")
     net.forward(x, y)
     yb = y.cpu().numpy().view(np.uint16)
     np.testing.assert_array_equal(yb[..., :3], xb[..., :3])
     assert (yb[..., 3] == 0).all()
+    net.set_disparity_scale(5.5)
+    net.forward(x, y)
+    np.testing.assert_array_equal(get16(y)[..., :3], N.disparity_blur(bits_to_f(xb), np.float32(5.5))[..., :3])
 
 
 def test_backward_matches_oracle(torch_cuda):
@@ -128,12 +147,13 @@ def test_backward_matches_oracle(torch_cuda):
     from paper_2601_19901_amd import lfdpr
     V, H, W = 7, 20, 36
     R, net = make_net(torch, V, H, W)
+    net.set_disparity_scale(3.1)
     params = random_params(5)
     flat = lfdpr.params_to_flat(params)
     net.set_params(flat)
     P = lfdpr.flat_to_params(flat.astype(np.float64))
     rng = np.random.default_rng(5)
-    xb = f_to_bits(rng.random((V, H, W, 4)))
+    xb = random_input(rng, V, H, W)
     tb = f_to_bits(np.concatenate([rng.random((V, H, W, 3)), np.zeros((V, H, W, 1))], axis=-1))
     x, t = t16(xb, torch), t16(tb, torch)
     y = torch.zeros((V, H, W, 4), dtype=torch.int16, device="cuda")
@@ -148,7 +168,7 @@ def test_backward_matches_oracle(torch_cuda):
     dz4f = get16(dz4)
     assert (dz4f[..., 3:] == 0).all()
     assert_bf16_close(dz4f[..., :3], N.bf16(2.0 * (yf - tf) / n), "dZ4")
-    acts = [N.assemble(bits_to_f(xb))]
+    acts = [N.assemble(bits_to_f(xb), N.disparity_blur(bits_to_f(xb), np.float32(3.1)))]
     for k in (1, 2, 3):
         a = torch.zeros((V, H, W, 32), dtype=torch.int16, device="cuda")
         net.copy_state(k, a)
