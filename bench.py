@@ -40,9 +40,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic work per unit (derivation in DESIGN.md, "Roofline model").
-SPLAT_OPS_PER_POINT_VIEW = 100     # R11/R12 per (point, active view): visibility, box, colour
-SPLAT_OPS_PER_PIXEL_TEST = 62      # R11 per candidate pixel: 3 edge functions, ray, plane, cell
+# Algorithmic work per unit (derivation in DESIGN.md, "Roofline model"): per
+# (point, active view) about 100 operations of visibility, projection, splat box
+# and colour, plus about 37 per pixel the point writes (ray, depth, lattice
+# coordinates, ownership, key); the oracle counts 0.327 written pixels per
+# point-view on display-1M, so 100 + 37 * 0.327 = 112.
+SPLAT_OPS_PER_POINT_VIEW = 112
 SETUP_OPS_PER_TRI_VIEW = 75        # R4 + R6 per (triangle, view)
 BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
