@@ -85,79 +85,118 @@ __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const ui
   return uint4{lo.x, lo.y, hi.x, hi.y};
 }
 
-// One block = 4 waves; a tile is 256 consecutive output pixels of the
-// [N][H][W] grid (4 M-tiles of 16 per wave); NT = COUT/16 output-channel tiles.
-// All nine taps' [COUT][32] weights sit in LDS for the block's lifetime.
-// aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
+// One block = 4 waves, persistent over output tiles of kTY rows x kTX pixels of
+// one image (wave w computes row w: four 16-pixel M tiles); NT = COUT/16
+// output-channel tiles.  All nine taps' [COUT][32] weights stay in LDS; each
+// tile's input, rows y0-1 .. y0+kTY and columns x0-DIL .. x0+kTX-1+DIL with
+// zero padding, is staged in LDS once and read by all nine taps.  LDS rows of
+// 32 channels are four 16-byte groups stored at slot g ^ ((px >> 2) & 3), so
+// the 16 consecutive pixels a lane group reads fall into 16 distinct bank
+// groups.  aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
 // MODE_BWD, the activation whose ReLU masks the gradient.
+constexpr int kTX = 64, kTY = 4;
+constexpr int kMaxDil = 9;  // the staging registers are sized for it
+static_assert(kDilation[0] <= kMaxDil && kDilation[1] <= kMaxDil && kDilation[2] <= kMaxDil &&
+                  kDilation[3] <= kMaxDil,
+              "dilation beyond the staged halo");
+constexpr int kStagePerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * 4 + 255) / 256;
+
+__device__ __forceinline__ int swz(int row, int g) { return row * 4 + (g ^ ((row >> 2) & 3)); }
+
+template <int NT>
+constexpr size_t conv_lds_bytes(int dil) {
+  return (size_t)9 * NT * 16 * 4 * 16 + (size_t)(kTY + 2) * (kTX + 2 * dil) * 4 * 16;
+}
+
 template <int NT, int MODE, bool GATHER>
 __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Wt,
                                                   const float* __restrict__ bias, int N, int H, int W, int V, int DIL,
                                                   uint16_t* __restrict__ Y, int YS, const uint16_t* __restrict__ aux,
                                                   int AUX_C) {
   constexpr int COUT = NT * 16;
-  __shared__ uint4 wlds[9 * COUT * kK / 8];
+  extern __shared__ uint4 smem[];
+  uint4* wlds = smem;                  // [9 * COUT rows][4 groups]
+  uint4* tl = smem + 9 * COUT * 4;     // [(kTY + 2) rows][TW pixels][4 groups]
+  const int TW = kTX + 2 * DIL;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, r16 = lane & 15;
-  for (int k = threadIdx.x; k < 9 * COUT * kK / 8; k += blockDim.x) wlds[k] = reinterpret_cast<const uint4*>(Wt)[k];
-  __syncthreads();
-  const int hw = H * W;
-  const int npx = N * hw;
-  const int ntile = (npx + 255) / 256;
-  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int pbase = tile * 256 + wv * 64;
-    int pn[4], py[4], px[4];
+  for (int k = threadIdx.x; k < 9 * COUT * 4; k += blockDim.x)
+    wlds[swz(k >> 2, k & 3)] = reinterpret_cast<const uint4*>(Wt)[k];
+  const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + kTY - 1) / kTY;
+  const int ntile = N * tiles_x * tiles_y;
+  const int nstage = (kTY + 2) * TW * 4;  // <= kStagePerThread * 256 for DIL <= kMaxDil
+  // the next tile's input is fetched into registers while this one computes
+  uint4 pre[kStagePerThread];
+  auto fetch = [&](int tile) {
+    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int p = pbase + m * 16 + r16;
-      const bool ok = p < npx;
-      const int q = ok ? p % hw : 0;
-      pn[m] = ok ? p / hw : 0;
-      py[m] = ok ? q / W : -100;
-      px[m] = ok ? q % W : -100;
+    for (int j = 0; j < kStagePerThread; ++j) {
+      const int k = threadIdx.x + j * 256;
+      const int gg = k & 3, q = k >> 2;
+      const int r = q / TW, px = q % TW;
+      pre[j] = k < nstage ? load_a<GATHER>(X, aux, n, y0 - 1 + r, x0 - DIL + px, H, W, gg, V) : uint4{0u, 0u, 0u, 0u};
     }
+  };
+  if (blockIdx.x < ntile) fetch(blockIdx.x);
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
+    __syncthreads();  // weights written / previous tile's reads finished
+#pragma unroll
+    for (int j = 0; j < kStagePerThread; ++j) {
+      const int k = threadIdx.x + j * 256;
+      if (k < nstage) tl[swz(k >> 2, k & 3)] = pre[j];
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntile) fetch(tile + gridDim.x);
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
-      const int dy = tap / 3 - 1, dx = (tap % 3 - 1) * DIL;
+      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
       Frag b[NT];
 #pragma unroll
-      for (int n = 0; n < NT; ++n) b[n].u = wlds[(tap * COUT + n * 16 + r16) * (kK / 8) + g];
+      for (int t = 0; t < NT; ++t) b[t].u = wlds[swz(tap * COUT + t * 16 + r16, g)];
+      const int rowbase = (wv + 1 + dy) * TW + DIL + dx * DIL + r16;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         Frag a;
-        a.u = load_a<GATHER>(X, aux, pn[m], py[m] + dy, px[m] + dx, H, W, g, V);
+        a.u = tl[swz(rowbase + m * 16, g)];
 #pragma unroll
-        for (int n = 0; n < NT; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[n].v, acc[m][n], 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[t].v, acc[m][t], 0, 0, 0);
       }
     }
-    // epilogue: lane holds D[4g+e][r16] = pixel pbase + 16m + 4g + e, channel n*16 + r16
+    // epilogue: lane holds D[4g+e][r16] = pixel x0 + 16m + 4g + e of row y0 + wv, channel t*16 + r16
+    const int y = y0 + wv;
+    if (y < H) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int co = n * 16 + r16;
-        if (co >= YS) continue;
+        for (int t = 0; t < NT; ++t) {
+          const int co = t * 16 + r16;
+          if (co >= YS) continue;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int p = pbase + m * 16 + 4 * g + e;
-          if (p >= npx) continue;
-          float v = acc[m][n][e];
-          if (MODE == MODE_RELU) {
-            v = fmaxf(v + bias[co], 0.0f);
-          } else if (MODE == MODE_OUT) {
-            v = co < 3 ? (v + bias[co]) + from_bf16(aux[(size_t)p * AUX_C + co]) : 0.0f;
-          } else {
-            v = from_bf16(aux[(size_t)p * AUX_C + co]) > 0.0f ? v : 0.0f;
+          for (int e = 0; e < 4; ++e) {
+            const int x = x0 + m * 16 + 4 * g + e;
+            if (x >= W) continue;
+            const size_t p = ((size_t)n * H + y) * W + x;
+            float v = acc[m][t][e];
+            if (MODE == MODE_RELU) {
+              v = fmaxf(v + bias[co], 0.0f);
+            } else if (MODE == MODE_OUT) {
+              v = co < 3 ? (v + bias[co]) + from_bf16(aux[p * AUX_C + co]) : 0.0f;
+            } else {
+              v = from_bf16(aux[p * AUX_C + co]) > 0.0f ? v : 0.0f;
+            }
+            Y[p * YS + co] = to_bf16(v);
           }
-          Y[(size_t)p * YS + co] = to_bf16(v);
         }
-      }
+    }
   }
 }
 
@@ -216,10 +255,12 @@ __global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ 
   }
 }
 
-__global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, float* __restrict__ db) {
+// db[co] += sum over a chunk of pixels of dZ[p][co]; grid (CO, chunks).
+__global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, int chunk, float* __restrict__ db) {
   const int co = blockIdx.x;
+  const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
   float s = 0.0f;
-  for (int p = threadIdx.x; p < npx; p += blockDim.x) s += from_bf16(dZ[(size_t)p * DZS + co]);
+  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) s += from_bf16(dZ[(size_t)p * DZS + co]);
   __shared__ float red[256];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -232,18 +273,19 @@ __global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, f
 
 // loss = mean((y - t)^2) over the 3 colour channels of npx pixels (inputs
 // [p][4]); dZ = bf16(2 (y - t) / n) into a [p][32] buffer (other channels 0).
+// Grid-stride, one loss atomic per block.
 __global__ void k_mse(const uint16_t* __restrict__ Yb, const uint16_t* __restrict__ T, int npx,
                       uint16_t* __restrict__ dZ, float* __restrict__ loss) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)npx * 3;
+  const int64_t ne = (int64_t)npx * kK;
   float sq = 0.0f;
-  if (i < (int64_t)npx * kK) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / kK;
     const int c = (int)(i % kK);
     uint16_t out = 0;
     if (c < 3) {
       const float d = from_bf16(Yb[p * 4 + c]) - from_bf16(T[p * 4 + c]);
-      sq = d * d;
+      sq += d * d;
       out = to_bf16((2.0f * d) / (float)n);
     }
     dZ[i] = out;
@@ -414,9 +456,9 @@ int nfail(lfdpr_net* n, int code, const std::string& m) {
 template <int NT, int MODE, bool GATHER>
 void launch_conv(const uint16_t* X, const uint16_t* Wt, const float* b, int N, int H, int W, int V, int dil,
                  uint16_t* Y, int YS, const uint16_t* aux, int AUXC, hipStream_t s) {
-  const int64_t tiles = ((int64_t)N * H * W + 255) / 256;
-  const int grid = (int)(tiles < 4096 ? tiles : 4096);
-  k_conv3x3<NT, MODE, GATHER><<<grid, 256, 0, s>>>(X, Wt, b, N, H, W, V, dil, Y, YS, aux, AUXC);
+  const int64_t tiles = (int64_t)N * ((H + kTY - 1) / kTY) * ((W + kTX - 1) / kTX);
+  const int grid = (int)(tiles < 768 ? tiles : 768);  // persistent: about three blocks per CU
+  k_conv3x3<NT, MODE, GATHER><<<grid, 256, conv_lds_bytes<NT>(dil), s>>>(X, Wt, b, N, H, W, V, dil, Y, YS, aux, AUXC);
 }
 
 void pack_weights(lfdpr_net* net) {
@@ -593,7 +635,9 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
   k_zero_f32<<<(unsigned)((net->nparams + 255) / 256), 256, 0, s>>>(net->grad, net->nparams);
   k_zero_f32<<<1, 64, 0, s>>>(net->d_loss, 1);
   const int64_t ne = (int64_t)npx * kK;
-  k_mse<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(net->last_y, (const uint16_t*)target, npx, net->dz[4], net->d_loss);
+  const int64_t mse_blocks = (ne + 255) / 256;
+  k_mse<<<(unsigned)(mse_blocks < 2048 ? mse_blocks : 2048), 256, 0, s>>>(net->last_y, (const uint16_t*)target, npx,
+                                                                           net->dz[4], net->d_loss);
   const int chunk = 4096;
   const unsigned nch = (unsigned)((npx + chunk - 1) / chunk);
   for (int k = 3; k >= 0; --k) {
@@ -605,7 +649,9 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
     else
       k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], nullptr, CI, N, H, W, V,
                                             kDilation[k], net->grad + net->off_w[k], chunk);
-    k_bias_grad<<<(unsigned)CO, 256, 0, s>>>(net->dz[k + 1], kK, npx, net->grad + net->off_b[k]);
+    const int bchunk = 16384;
+    k_bias_grad<<<dim3((unsigned)CO, (unsigned)((npx + bchunk - 1) / bchunk)), 256, 0, s>>>(net->dz[k + 1], kK, npx, bchunk,
+                                                                                              net->grad + net->off_b[k]);
     if (k > 0)  // input gradient through the flipped, transposed weights (same dilation), masked by the ReLU
       launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, kDilation[k], net->dz[k], kHidden,
                                       net->act[k], kHidden, s);
