@@ -105,3 +105,42 @@ def test_autotune_keeps_results(setup):
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
     print("frame autotune:", r1["best"], flush=True)
+
+
+def test_batch16_full_size_matches_single_renders():
+    """The benchmark's 16-scene batch (10.2M triangles, 50k-4M per scene) in one
+    hipGraph replay after the autotuner: every scene's views and panel equal a
+    single-scene render of the same frame, which the parity tests tie to the
+    oracle."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_19901_amd import lfdpr
+    ws = scenes.batch_workloads(seed=400)
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    B = lfdpr.Batch(R, ids, [w.views for w in ws], point_capacity=96 << 20)
+    views = B.alloc_views()
+    panels = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    models = [w.model(7 + 37 * k) for k, w in enumerate(ws)]
+    B.use_graph(False)
+    print("batch16 autotune:", B.autotune(models, views)["best"], flush=True)
+    B.use_graph(True)
+    for _ in range(2):   # capture, then a replay
+        B.render(models, views, panels)
+    torch.cuda.synchronize()
+    bst = B.stats()
+    bv, bp = views.cpu().numpy(), panels.cpu().numpy()
+    tot = 0
+    for k, w in enumerate(ws):
+        R.set_views(w.views, point_capacity=32 << 20)
+        v, _ = R.alloc_views()
+        R.render_frame(ids[k], models[k], v)
+        panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
+        R.reconstruct(v, panel)
+        np.testing.assert_array_equal(bv[k], v.cpu().numpy(), err_msg=f"scene {k} views")
+        np.testing.assert_array_equal(bp[k], panel.cpu().numpy(), err_msg=f"scene {k} panel")
+        tot += R.stats()["point_views"]
+    assert bst["point_views"] == tot
+    print(f"batch16: {bst['points']} points, {tot} point-views, all scenes identical", flush=True)
