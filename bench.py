@@ -10,6 +10,8 @@ per frame.  Inputs are resident in HBM before the timed region starts.
 angular supersampling), angular filter to 48 views, interleave.
 --workload batch16: 16 scenes of 50k-4M triangles per step, one hipGraph
 replay after the launch autotuner.
+--workload learned-display: display-1M rendered once plus the learned
+angular reconstruction, beside the plain and 4x angular-SS frames.
 
 Prints one JSON line: value = point-view splats per second of whole-step
 time (sum over points of the views their triangle is active in, divided by
@@ -262,6 +264,64 @@ def run_batch(args, torch, lfdpr, scenes):
 
 
 METRIC = "48-view panel frame ms & point-view splats/s; learned vs 4× angular SS at PSNR"
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def run_learned(args, torch, lfdpr, scenes):
+    """The learned reconstruction's frame on display-1M: plain 1x render +
+    network (disparity blur, 4 BF16-MFMA convolutions) + panel, beside the plain
+    and 4x-angular-SS frames.  Parameters are He-initialised: the cost does not
+    depend on their values (the trained network's PSNR is measured by
+    paper_2601_19901_amd.learned)."""
+    from paper_2601_19901_amd import learned
+    t0 = time.time()
+    w = scenes.display(seed=args.seed)
+    log(f"workload generated in {time.time() - t0:.1f}s: {w.scene.n_tris} tris")
+    ss = learned.AngularSS([w], factors=(1, 4))
+    model = learned.LearnedReconstruction(ss, w.views.H, w.views.W)
+    rng = np.random.default_rng(0)
+    flat = model.net.get_params()
+    model.net.set_params((rng.normal(0.0, 0.05, flat.size)).astype(np.float32))
+    frames = list(range(args.warmup + args.steps))
+    times = learned.time_pipelines(model, w.lens, 0, frames)
+    # network forward alone, HIP events on the library's (torch's current) stream
+    R1 = ss.rigs[1].renderer
+    views, depth = ss.render_plain(0, 0)
+    model.net.pack_input(views, depth, model.x, ss.D)
+    for _ in range(args.warmup):
+        model.net.forward(model.x, model.y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        model.net.forward(model.x, model.y)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / args.steps
+    px = w.views.V * w.views.W * w.views.H
+    flops = 2 * 9 * sum(ci * co for ci, co in lfdpr.NET_SHAPES) * px
+    achieved = flops / (fwd_ms * 1e-3) / 1e12
+    R1.render_frame(ss.rigs[1].scene_ids[0], w.model(args.warmup), ss.views1)
+    pv = R1.stats()["point_views"]
+    return {
+        "metric": METRIC,
+        "value": round(pv / (times["learned_ms"] * 1e-3), 1),
+        "unit": "point-view splats/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(times["learned_ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": "learned-display: display-1M rendered once (48 views 512x512) + learned angular "
+                               "reconstruction (disparity blur + 4 BF16-MFMA 3x3 convolutions 24-32-32-32-3) + "
+                               "2560x1600 panel; compared with plain 1x and 4x angular supersampling (192 views + "
+                               "angular filter)", "views": w.views.V, "view_px": [w.views.W, w.views.H],
+                   "triangles": w.scene.n_tris},
+        "frame_ms": {k: round(v, 4) for k, v in times.items()},
+        "net_forward_ms": round(fwd_ms, 4),
+        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur", "bound": "mfma",
+                     "achieved": round(achieved, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "flops_per_frame": flops, "launch_ms": round(fwd_ms, 4)},
+    }
 
 
 def main():
@@ -269,7 +329,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "batch16"), default="display-1M")
+    ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "batch16", "learned-display"),
+                    default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -298,6 +359,8 @@ def main():
         return
     if args.workload == "batch16":
         out = run_batch(args, torch, lfdpr, scenes)
+    elif args.workload == "learned-display":
+        out = run_learned(args, torch, lfdpr, scenes)
     else:
         out = run_display(args, torch, lfdpr, scenes, args.workload == "display-4M-ss4")
     print(json.dumps(out), flush=True)
