@@ -90,9 +90,10 @@ __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const ui
 // output-channel tiles.  All nine taps' [COUT][32] weights stay in LDS; each
 // tile's input, rows y0-1 .. y0+kTY and columns x0-DIL .. x0+kTX-1+DIL with
 // zero padding, is staged in LDS once and read by all nine taps.  LDS rows of
-// 32 channels are four 16-byte groups stored at slot g ^ ((px >> 2) & 3), so
-// the 16 consecutive pixels a lane group reads fall into 16 distinct bank
-// groups.  aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
+// 32 channels are four 16-byte groups stored at slot g ^ ((px >> 1) & 3): LDS
+// serves 16-byte reads eight lanes (128 bytes) at a time, and any 8
+// consecutive pixels then fall into 8 distinct bank groups (no conflicts on
+// gfx950 by the SQ_LDS_BANK_CONFLICT counter).  aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
 // MODE_BWD, the activation whose ReLU masks the gradient.
 constexpr int kTX = 64, kTY = 4;
 constexpr int kMaxDil = 9;  // the staging registers are sized for it
@@ -101,7 +102,7 @@ static_assert(kDilation[0] <= kMaxDil && kDilation[1] <= kMaxDil && kDilation[2]
               "dilation beyond the staged halo");
 constexpr int kStagePerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * 4 + 255) / 256;
 
-__device__ __forceinline__ int swz(int row, int g) { return row * 4 + (g ^ ((row >> 2) & 3)); }
+__device__ __forceinline__ int swz(int row, int g) { return row * 4 + (g ^ ((row >> 1) & 3)); }
 
 template <int NT>
 constexpr size_t conv_lds_bytes(int dil) {
@@ -122,6 +123,14 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
   const int g = lane >> 4, r16 = lane & 15;
   for (int k = threadIdx.x; k < 9 * COUT * 4; k += blockDim.x)
     wlds[swz(k >> 2, k & 3)] = reinterpret_cast<const uint4*>(Wt)[k];
+  // the MFMA computes D = W x A (rows: output channels, columns: pixels), so
+  // lane (g, r16) ends with channels t*16 + 4g .. +3 of pixel r16 of each M tile
+  float bco[NT][4];  // their biases (3 in the output layer)
+  const int nbias = MODE == MODE_BWD ? 0 : (MODE == MODE_OUT ? 3 : YS);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bco[t][e] = t * 16 + 4 * g + e < nbias ? bias[t * 16 + 4 * g + e] : 0.0f;
   const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + kTY - 1) / kTY;
   const int ntile = N * tiles_x * tiles_y;
   const int nstage = (kTY + 2) * TW * 4;  // <= kStagePerThread * 256 for DIL <= kMaxDil
@@ -168,34 +177,46 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
         a.u = tl[swz(rowbase + m * 16, g)];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b[t].v, acc[m][t], 0, 0, 0);
+          acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[t].v, a.v, acc[m][t], 0, 0, 0);
       }
     }
-    // epilogue: lane holds D[4g+e][r16] = pixel x0 + 16m + 4g + e of row y0 + wv, channel t*16 + r16
+    // epilogue: lane holds D[4g+e][r16] = channel t*16 + 4g + e of pixel x0 + 16m + r16
+    // (row y0 + wv); four consecutive channels leave as one 8-byte store
     const int y = y0 + wv;
     if (y < H) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m) {
+        const int x = x0 + m * 16 + r16;
+        if (x >= W) continue;
+        const size_t p = ((size_t)n * H + y) * W + x;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          const int co = t * 16 + r16;
-          if (co >= YS) continue;
+          const int c0 = t * 16 + 4 * g;
+          if (c0 >= YS) continue;
+          float v[4];
+          uint2 side = {0u, 0u};
+          if (MODE != MODE_RELU) side = *reinterpret_cast<const uint2*>(aux + p * AUX_C + c0);
+          const uint16_t sh[4] = {(uint16_t)(side.x & 0xFFFFu), (uint16_t)(side.x >> 16), (uint16_t)(side.y & 0xFFFFu),
+                                  (uint16_t)(side.y >> 16)};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int x = x0 + m * 16 + 4 * g + e;
-            if (x >= W) continue;
-            const size_t p = ((size_t)n * H + y) * W + x;
-            float v = acc[m][t][e];
+            const int co = c0 + e;
+            float u = acc[m][t][e];
             if (MODE == MODE_RELU) {
-              v = fmaxf(v + bias[co], 0.0f);
+              u = fmaxf(u + bco[t][e], 0.0f);
             } else if (MODE == MODE_OUT) {
-              v = co < 3 ? (v + bias[co]) + from_bf16(aux[p * AUX_C + co]) : 0.0f;
+              u = co < 3 ? (u + bco[t][e]) + from_bf16(sh[e]) : 0.0f;
             } else {
-              v = from_bf16(aux[p * AUX_C + co]) > 0.0f ? v : 0.0f;
+              u = from_bf16(sh[e]) > 0.0f ? u : 0.0f;
             }
-            Y[p * YS + co] = to_bf16(v);
+            v[e] = u;
           }
+          uint2 o;
+          o.x = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+          o.y = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(Y + p * YS + c0) = o;
         }
+      }
     }
   }
 }
