@@ -116,7 +116,9 @@ const char* lfdpr_strerror(int code);
  * hipStream_t; NULL = the null stream).  *out receives the context. */
 int lfdpr_create(int device, void* stream, lfdpr_ctx** out);
 
-/* Frees the context and every device buffer it owns.  NULL is accepted. */
+/* Frees the context and every device buffer it owns.  NULL is accepted.
+ * LFDPR_ESTATE (nothing freed) while batches or networks created on it are
+ * alive: destroy those first. */
 int lfdpr_destroy(lfdpr_ctx* ctx);
 
 /* Message of the last failure on this context (empty when none); the string
@@ -128,7 +130,7 @@ const char* lfdpr_last_error(lfdpr_ctx* ctx);
  * Synchronises the stream before returning (host buffers are then free). */
 int lfdpr_scene_upload(lfdpr_ctx* ctx, const lfdpr_scene_desc* desc, int32_t* scene_id);
 
-/* Releases a scene's device memory. */
+/* Releases a scene's device memory; LFDPR_ESTATE while a live batch renders it. */
 int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id);
 
 /* Sets the rig and (re)allocates the per-view key buffer (8 B per pixel of
@@ -221,7 +223,9 @@ typedef struct lfdpr_batch lfdpr_batch;
  * of them.  views[k] is the rig of item k (host array of n): every item must
  * have the same V*S, W, H, fovy and aspect; cones, D and jitter may differ.
  * The batch owns its key, triangle and point buffers (point_capacity points in
- * total; 0 = 32M) and a stream of its own.  The scenes must stay uploaded. */
+ * total; 0 = 32M) and a stream of its own.  The scenes stay uploaded while the
+ * batch lives (lfdpr_scene_free refuses them); at most 2^28 - 1 triangles in
+ * all (LFDPR_EINVAL beyond). */
 int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, const lfdpr_view_params* views,
                        int64_t point_capacity, lfdpr_batch** out);
 int lfdpr_batch_destroy(lfdpr_batch* batch);

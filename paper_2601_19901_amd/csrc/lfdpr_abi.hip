@@ -24,6 +24,7 @@ struct SceneDev {
   uint16_t* tex = nullptr;
   TexInfo* texinfo = nullptr;
   uint8_t* texels = nullptr;
+  int32_t batch_refs = 0;  // live batches rendering this scene
 };
 
 template <class T>
@@ -40,6 +41,7 @@ struct lfdpr_ctx {
   std::string err;
   std::map<int32_t, SceneDev> scenes;
   int32_t next_scene = 1;
+  int32_t live_children = 0;  // batches and networks created on this context
   // rig
   bool views_set = false;
   lfdpr_view_params vp{};
@@ -232,6 +234,7 @@ InterleaveArgs interleave_args(const lfdpr_lens_params& l, const uint32_t* views
 
 }  // namespace
 int ctx_device_of(lfdpr_ctx* c) { return c->device; }
+void ctx_children_add(lfdpr_ctx* c, int delta) { c->live_children += delta; }
 
 extern "C" {
 
@@ -284,6 +287,7 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
 
 int lfdpr_destroy(lfdpr_ctx* ctx) {
   if (!ctx) return LFDPR_OK;
+  if (ctx->live_children > 0) return fail(ctx, LFDPR_ESTATE, "destroy the context's batches and networks first");
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->scenes) free_scene(kv.second);
@@ -372,6 +376,7 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
   if (!ctx) return LFDPR_EINVAL;
   auto it = ctx->scenes.find(scene_id);
   if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  if (it->second.batch_refs > 0) return fail(ctx, LFDPR_ESTATE, "the scene is rendered by a live batch");
   HIPOK(hipStreamSynchronize(ctx->stream));
   free_scene(it->second);
   ctx->scenes.erase(it);
@@ -659,6 +664,7 @@ int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n) {
 struct lfdpr_batch {
   lfdpr_ctx* ctx = nullptr;
   int n = 0;
+  std::vector<int32_t> scene_ids;
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_stage = nullptr;
   std::vector<Item> items;
@@ -850,6 +856,7 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
     if (k == 0) b->table_rig = rg;
   }
   b->nt = tri_base;
+  if (b->nt >= (1ll << 28)) ok = false;  // points carry a 28-bit triangle index
   b->per_item_px = (int64_t)b->table_rig.n_views * b->table_rig.W * b->table_rig.H;
   b->cap = point_capacity ? point_capacity : (32ll << 20);
   const int64_t ntb = b->nt > 1024 ? b->nt : 1024;
@@ -868,10 +875,17 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
          hipStreamSynchronize(b->stream) == hipSuccess;
   }
   if (!ok) {
+    const bool too_many = b->nt >= (1ll << 28);
     batch_free(b);
     delete b;
-    return fail(ctx, LFDPR_ENOMEM, "batch buffers");
+    return too_many ? fail(ctx, LFDPR_EINVAL, "more than 2^28 - 1 triangles in one batch")
+                    : fail(ctx, LFDPR_ENOMEM, "batch buffers");
   }
+  for (int k = 0; k < n; ++k) {
+    ctx->scenes[scene_ids[k]].batch_refs += 1;
+    b->scene_ids.push_back(scene_ids[k]);
+  }
+  ctx->live_children += 1;
   *out = b;
   return LFDPR_OK;
 }
@@ -880,6 +894,11 @@ int lfdpr_batch_destroy(lfdpr_batch* b) {
   if (!b) return LFDPR_OK;
   (void)hipSetDevice(b->ctx->device);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (int32_t id : b->scene_ids) {
+    auto it = b->ctx->scenes.find(id);
+    if (it != b->ctx->scenes.end()) it->second.batch_refs -= 1;
+  }
+  b->ctx->live_children -= 1;
   batch_free(b);
   delete b;
   return LFDPR_OK;

@@ -108,3 +108,5 @@ void launch_angular_filter(const AngularArgs& a, hipStream_t s);
 struct lfdpr_ctx;
 hipStream_t ctx_stream_of(lfdpr_ctx* c);
 int ctx_device_of(lfdpr_ctx* c);
+// networks count as children of their context (it is not destroyed under them)
+void ctx_children_add(lfdpr_ctx* c, int delta);

@@ -436,6 +436,7 @@ using namespace lfdpr::net;
 
 struct lfdpr_net {
   lfdpr_ctx* ctx = nullptr;
+  bool counted = false;  // registered as a child of ctx
   hipStream_t stream = nullptr;
   int device = 0;
   int V = 0;
@@ -548,6 +549,8 @@ int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lf
     return LFDPR_EDEVICE;
   }
   *out = net;
+  ctx_children_add(ctx, 1);
+  net->counted = true;
   int rc = lfdpr_net_set_params(net, nullptr, 0);
   if (rc) {
     lfdpr_net_destroy(net);
@@ -560,6 +563,7 @@ int lfdpr_net_destroy(lfdpr_net* net) {
   if (!net) return LFDPR_OK;
   (void)hipSetDevice(net->device);
   (void)hipStreamSynchronize(net->stream);
+  if (net->counted) ctx_children_add(net->ctx, -1);
   (void)hipFree(net->master);
   (void)hipFree(net->grad);
   (void)hipFree(net->adam_m);

@@ -202,8 +202,12 @@ class Renderer:
         return rc
 
     def close(self):
+        """Frees the context; refused (RuntimeError) while batches or networks
+        created on it are alive."""
         if getattr(self, "h", None):
-            lib().lfdpr_destroy(self.h)
+            rc = lib().lfdpr_destroy(self.h)
+            if rc != LFDPR_OK:
+                raise RuntimeError(f"lfdpr_destroy: {lib().lfdpr_last_error(self.h).decode()}")
             self.h = None
 
     def __del__(self):

@@ -144,3 +144,28 @@ def test_batch16_full_size_matches_single_renders():
         tot += R.stats()["point_views"]
     assert bst["point_views"] == tot
     print(f"batch16: {bst['points']} points, {tot} point-views, all scenes identical", flush=True)
+
+
+def test_lifetimes_are_enforced():
+    """A scene rendered by a live batch cannot be freed, and a context with live
+    batches or networks cannot be destroyed; both work once those are gone."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=70, V=8, W=64, H=64)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    B = lfdpr.Batch(R, [sid], [w.views])
+    assert lib_call(lfdpr, "lfdpr_scene_free", R.h, sid) == lfdpr.LFDPR_ESTATE
+    net = lfdpr.Net(R, 8, 64, 64)
+    assert lfdpr.lib().lfdpr_destroy(R.h) == lfdpr.LFDPR_ESTATE
+    B.close()
+    assert lfdpr.lib().lfdpr_destroy(R.h) == lfdpr.LFDPR_ESTATE   # the network is still alive
+    net.close()
+    assert lib_call(lfdpr, "lfdpr_scene_free", R.h, sid) == lfdpr.LFDPR_OK
+    R.close()
+
+
+def lib_call(lfdpr, name, *args):
+    return getattr(lfdpr.lib(), name)(*args)
