@@ -42,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic work per unit (derivation in DESIGN.md, "Roofline model"): per
+# Algorithmic work per unit: per
 # (point, active view) about 100 operations of visibility, projection, splat box
 # and colour, plus about 37 per pixel the point writes (ray, depth, lattice
 # coordinates, ownership, key); the oracle counts 0.327 written pixels per
@@ -337,8 +337,8 @@ def main():
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 (multi-GPU sharding "
+                                   "is not implemented)"}))
         sys.exit(2)
 
     import torch
