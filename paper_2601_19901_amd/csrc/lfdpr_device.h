@@ -38,7 +38,8 @@ struct alignas(16) TriEmit {
   float du2, dv2;
   int32_t s1, t1;
   int32_t s2, t2, kmin, kmax;
-  int32_t tex, item, pad1, pad2;
+  int32_t tex, item;
+  int32_t jlo, jhi;  // first and last lattice rows with cells
 };
 
 // One point: 16 B.  tri | flags<<28, (u16)i | (u16)j<<16, tv_min, tv_max (RGBA8).

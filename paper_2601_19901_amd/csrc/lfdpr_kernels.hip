@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
         if (!ovf) { di[0] = sq[1]; di[1] = tq[1]; di[2] = sq[2]; di[3] = tq[2]; }
         di[4] = kmin; di[5] = kmax; di[6] = 1;
       }
-      int64_t count = 0;
+      int64_t count = 0, jfirst = 0, jlast = -1;
       Lattice L;
       if (!ovf && lattice_init(L, sq[1], tq[1], sq[2], tq[2])) {
         int64_t nb = (L.iB - L.iA + 1) * (L.jB - L.jA + 1);
@@ -216,7 +216,11 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
           for (int64_t j = L.jA; j <= L.jB; ++j) {
             int64_t lo, hi;
             lattice_row(L, j, lo, hi);
-            if (hi >= lo) count += hi - lo + 1;
+            if (hi >= lo) {
+              if (count == 0) jfirst = j;
+              jlast = j;
+              count += hi - lo + 1;
+            }
           }
           if (count > kCellCap) ovf = true;
         }
@@ -233,7 +237,8 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
         TriEmit E;
         E.uv0u = uv0u; E.uv0v = uv0v; E.du1 = du1; E.dv1 = dv1; E.du2 = du2; E.dv2 = dv2;
         E.s1 = sq[1]; E.t1 = tq[1]; E.s2 = sq[2]; E.t2 = tq[2];
-        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item; E.pad1 = E.pad2 = 0;
+        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item;
+        E.jlo = (int32_t)jfirst; E.jhi = (int32_t)jlast;
         a.em[t] = E;
       }
     }
@@ -338,15 +343,7 @@ __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
   uint64_t base = a.offsets[t];
   Lattice L;
   lattice_init(L, E.s1, E.t1, E.s2, E.t2);
-  int64_t jlo = L.jB + 1, jhi = L.jA - 1;
-  for (int64_t j = L.jA; j <= L.jB; ++j) {
-    int64_t lo, hi;
-    lattice_row(L, j, lo, hi);
-    if (hi >= lo) {
-      if (jlo > L.jB) jlo = j;
-      jhi = j;
-    }
-  }
+  const int64_t jlo = E.jlo, jhi = E.jhi;  // rows with cells, found by the set-up
   uint64_t k = 0;
   for (int64_t j = jlo; j <= jhi; ++j) {
     int64_t lo, hi;
@@ -363,7 +360,6 @@ __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
 // One workgroup per queued triangle: lanes take rows, a block scan places them.
 __global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
   __shared__ uint64_t wsum[4];
-  __shared__ int64_t row_lo_hi[2];
   const uint64_t nbig = *a.n_big;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
@@ -372,18 +368,7 @@ __global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
     const uint64_t base = a.offsets[t];
     Lattice L;
     lattice_init(L, E.s1, E.t1, E.s2, E.t2);
-    if (threadIdx.x == 0) { row_lo_hi[0] = L.jB + 1; row_lo_hi[1] = L.jA - 1; }
-    __syncthreads();
-    for (int64_t j = L.jA + threadIdx.x; j <= L.jB; j += blockDim.x) {
-      int64_t lo, hi;
-      lattice_row(L, j, lo, hi);
-      if (hi >= lo) {
-        atomicMin((long long*)&row_lo_hi[0], (long long)j);
-        atomicMax((long long*)&row_lo_hi[1], (long long)j);
-      }
-    }
-    __syncthreads();
-    const int64_t jlo = row_lo_hi[0], jhi = row_lo_hi[1];
+    const int64_t jlo = E.jlo, jhi = E.jhi;  // rows with cells, found by the set-up
     uint64_t run = 0;
     for (int64_t j0 = jlo; j0 <= jhi; j0 += blockDim.x) {
       const int64_t j = j0 + threadIdx.x;
@@ -408,7 +393,7 @@ __global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
       run += total;
       __syncthreads();
     }
-    __syncthreads();  // row bounds are rewritten for the next triangle
+    __syncthreads();  // the wave sums are rewritten for the next triangle
   }
 }
 
@@ -586,13 +571,16 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
       bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
     }
     uint64_t* kv = keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * vpx);
-    const int32_t pxq0 = 256 * bx0 + 128;
-    for (int32_t y = ry0; y <= ry1; ++y) {
-      const int32_t pyq = 256 * y + 128;
-      double E0 = edx[0] * (double)(pyq - qy[0]) - edy[0] * (double)(pxq0 - qx[0]) + bias[0];
-      double E1 = edx[1] * (double)(pyq - qy[1]) - edy[1] * (double)(pxq0 - qx[1]) + bias[1];
-      double E2 = edx[2] * (double)(pyq - qy[2]) - edy[2] * (double)(pxq0 - qx[2]) + bias[2];
-      const double st0 = edy[0] * 256.0, st1 = edy[1] * 256.0, st2 = edy[2] * 256.0;
+    const int32_t pxq0 = 256 * bx0 + 128, pyq0 = 256 * ry0 + 128;
+    // edge functions at (bx0, ry0), stepped by whole pixels (all values are
+    // integers + 0.5 below 2^51, so every step is exact)
+    double R0 = edx[0] * (double)(pyq0 - qy[0]) - edy[0] * (double)(pxq0 - qx[0]) + bias[0];
+    double R1 = edx[1] * (double)(pyq0 - qy[1]) - edy[1] * (double)(pxq0 - qx[1]) + bias[1];
+    double R2 = edx[2] * (double)(pyq0 - qy[2]) - edy[2] * (double)(pxq0 - qx[2]) + bias[2];
+    const double st0 = edy[0] * 256.0, st1 = edy[1] * 256.0, st2 = edy[2] * 256.0;
+    const double sr0 = edx[0] * 256.0, sr1 = edx[1] * 256.0, sr2 = edx[2] * 256.0;
+    for (int32_t y = ry0; y <= ry1; ++y, R0 += sr0, R1 += sr1, R2 += sr2) {
+      double E0 = R0, E1 = R1, E2 = R2;
       const float ry = ty[y];
       const float nyr = T.ny * ry, uyr = T.uy * ry, wyr = T.wy * ry;
       for (int32_t x = bx0; x <= bx1; ++x) {
