@@ -7,7 +7,10 @@ splat into all 48 views, resolve, interleave.  The scene rotates by 2*pi/1000
 per frame.  Inputs are resident in HBM before the timed region starts.
 
 --workload display-4M-ss4: 3,996,672 triangles rendered into 192 views (4x
-angular supersampling), angular filter to 48 views, interleave.
+angular supersampling), angular filter to 48 views, interleave;
+display-4M-ss4-direct reconstructs the panel straight from the 192 sub-views.
+--workload display-1M-spatial2x: 48 views of 1024^2 (2x spatial
+supersampling), spatial reconstruction at the panel.
 --workload batch16: 16 scenes of 50k-4M triangles per step, one hipGraph
 replay after the launch autotuner.
 --workload learned-display: display-1M rendered once plus the learned
@@ -107,22 +110,30 @@ def stage_avg(R):
     return {k: (v[0] / v[1]) for k, v in R.timings().items() if v[1]}
 
 
-def run_display(args, torch, lfdpr, scenes, four_m: bool):
+def run_display(args, torch, lfdpr, scenes, kind: str):
+    """kind: display-1M, display-4M-ss4 (angular filter to 48 views, then the
+    panel), display-4M-ss4-direct (panel straight from the 192 sub-views) or
+    display-1M-spatial2x (1024^2 views, spatial reconstruction)."""
+    four_m = kind.startswith("display-4M")
     t0 = time.time()
     w = scenes.display_4m(seed=3) if four_m else scenes.display(seed=args.seed)
+    if kind == "display-1M-spatial2x":
+        w = scenes.spatial_ss(w)
+    lens = scenes.direct_panel_lens(w) if kind == "display-4M-ss4-direct" else w.lens
     log(f"workload generated in {time.time() - t0:.1f}s: {w.scene.n_tris} tris")
     R = lfdpr.Renderer(0)
     sid = R.upload_scene(w.scene)
-    R.set_views(w.views, point_capacity=(48 << 20) if four_m else 0)
-    R.set_lens(w.lens)
+    R.set_views(w.views, point_capacity=(48 << 20) if kind != "display-1M" else 0)
+    R.set_lens(lens)
     views, _ = R.alloc_views()
-    filtered = torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0") if four_m else None
-    panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
+    filtered = (torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0")
+                if kind == "display-4M-ss4" else None)
+    panel = torch.empty((lens.Hp, lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
     models = [w.model(f) for f in range(args.warmup + args.steps)]
 
     def frame(f):
         R.render_frame(sid, models[f], views)
-        if four_m:
+        if filtered is not None:
             R.angular_filter(views, filtered)
             R.reconstruct(filtered, panel)
         else:
@@ -155,14 +166,21 @@ def run_display(args, torch, lfdpr, scenes, four_m: bool):
     shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
                  out_pixels=w.views.V * w.views.W * w.views.H,
                  panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, fragments=0)
-    roof = roofline(st_avg, pv / nfr, shape, None if four_m else splat_traffic())
-    if four_m:
-        name = ("display-4M-ss4: 3,996,672 tris (1024^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
-                "192 rendered views 512x512 (4x angular supersampling over 48, jittered), angular filter to 48 views, "
-                "2560x1600 lenticular panel, rotating scene")
-    else:
-        name = ("display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
-                "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene")
+    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None)
+    names = {
+        "display-1M": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
+                      "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene",
+        "display-4M-ss4": "display-4M-ss4: 3,996,672 tris (1024^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 "
+                          "textures, 192 rendered views 512x512 (4x angular supersampling over 48, jittered), angular "
+                          "filter to 48 views, 2560x1600 lenticular panel, rotating scene",
+        "display-4M-ss4-direct": "display-4M-ss4-direct: the display-4M-ss4 frame with the panel reconstructed straight "
+                                 "from the 192 sub-views (angular taps over +-4 sub-view intervals), no filter pass",
+        "display-1M-spatial2x": "display-1M-spatial2x: the display-1M scene rendered into 48 views of 1024x1024 (2x "
+                                "spatial supersampling), panel through the spatial Gaussian taps",
+    }
+    name = names[kind]
+    recon = {"display-1M": "none", "display-4M-ss4": "angular filter", "display-4M-ss4-direct": "angular taps at the panel",
+             "display-1M-spatial2x": "spatial taps at the panel"}[kind]
     out = {
         "metric": METRIC,
         "value": round((pv / nfr) / (wall_ms * 1e-3), 1),
@@ -173,7 +191,7 @@ def run_display(args, torch, lfdpr, scenes, four_m: bool):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": name, "views": w.views.V, "rendered_views": n_rendered,
                    "view_px": [w.views.W, w.views.H], "panel_px": [w.lens.Wp, w.lens.Hp],
-                   "triangles": w.scene.n_tris, "recon": "angular filter" if four_m else "none"},
+                   "triangles": w.scene.n_tris, "recon": recon},
         "frame_ms": round(wall_ms, 4),
         "frames_per_s": round(1e3 / wall_ms, 2),
         "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
@@ -181,7 +199,7 @@ def run_display(args, torch, lfdpr, scenes, four_m: bool):
         "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and not four_m:
+    if not args.no_cpu_baseline and kind == "display-1M":
         from oracle import oracle as O
         t0 = time.perf_counter()
         o = O.render(w.scene, w.views, models[args.warmup])
@@ -329,7 +347,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "batch16", "learned-display"),
+    ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "display-4M-ss4-direct",
+                                           "display-1M-spatial2x", "batch16", "learned-display"),
                     default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2)
@@ -362,7 +381,7 @@ def main():
     elif args.workload == "learned-display":
         out = run_learned(args, torch, lfdpr, scenes)
     else:
-        out = run_display(args, torch, lfdpr, scenes, args.workload == "display-4M-ss4")
+        out = run_display(args, torch, lfdpr, scenes, args.workload)
     print(json.dumps(out), flush=True)
 
 

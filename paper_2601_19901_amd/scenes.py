@@ -402,6 +402,30 @@ def display_4m(seed: int = 3, S: int = 4) -> Workload:
     return w
 
 
+def spatial_ss(w: Workload, factor: int = 2, seed: int = 0) -> Workload:
+    """Spatial supersampling of a workload (Table 2 "Spatial"): views rendered
+    at `factor` times the resolution, and the panel reconstructed with the
+    spatial Gaussian taps, whose footprint stays 2.25 pixels of the original
+    views (so `factor` times as many rendered pixels)."""
+    v = w.views
+    views = dataclasses.replace(v, W=v.W * factor, H=v.H * factor)
+    taps = gaussian_taps(seed + 300, sigma_s=0.5625 * factor, trunc_s=1.125 * factor)
+    lens = dataclasses.replace(w.lens, mode=RECON_SPATIAL, taps=taps)
+    out = dataclasses.replace(w, views=views, lens=lens)
+    out.name = f"{w.name}-spatial{factor}x"
+    return out
+
+
+def direct_panel_lens(w: Workload, seed: int = 0, mode: int = RECON_ANGULAR) -> LensParams:
+    """Lens for reconstructing the panel directly from the S*V sub-views of an
+    angularly supersampled workload (Sec. 4, instead of filtering down to V
+    views first): the sub-views are taken at their nominal positions and the
+    angular taps span +-1 original view interval, i.e. +-S sub-view intervals."""
+    S = w.views.S
+    taps = gaussian_taps(seed + 400, sigma_u=0.5 * S, trunc_u=1.0 * S)
+    return dataclasses.replace(w.lens, mode=mode, taps=taps)
+
+
 def small_display(seed: int = 7, S: int = 1, V: int = 12, W: int = 96, H: int = 96,
                   hf_quads: int = 48, tex_size: int = 128) -> Workload:
     """A small member of the display family (same geometry kinds, anisotropic
