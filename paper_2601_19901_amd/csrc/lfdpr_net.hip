@@ -222,61 +222,92 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 }
 
 // ---------------------------------------------------------------- weight gradient
-// dW[tap][co][ci] += sum_p dZ[p][co] * A[p + off(tap)][ci]: one wave per
-// (tap, 16 co, 16 ci) tile and pixel chunk; M = co, N = ci, K = pixels.  Only
-// real (co < CO, ci < CI) entries are written, into the unpadded layout.
-template <bool GATHER>
-__global__ void __launch_bounds__(64) k_conv_wgrad(const uint16_t* __restrict__ dZ, int DZS, int CO,
-                                                    const uint16_t* __restrict__ A, const uint16_t* __restrict__ AB,
-                                                    int CI, int N, int H, int W, int V, int DIL,
-                                                    float* __restrict__ dW, int chunk) {
-  const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
-  const int nct = (CO + 15) / 16, nit = 2;  // ci padded to 32
-  int t = blockIdx.x;
-  const int it = t % nit; t /= nit;
-  const int ct = t % nct; t /= nct;
-  const int tap = t;
-  const int dy = tap / 3 - 1, dx = (tap % 3 - 1) * DIL;
-  const int hw = H * W, npx = N * hw;
-  const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
-  const int co = ct * 16 + r16, ci = it * 16 + r16;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int k0 = p0; k0 < p1; k0 += 32) {
-    union { uint16_t h[8]; bf16x8 v; } fa, fb;
+// dW[tap][co][ci] += sum_p dZ[p][co] * A[p + off(tap)][ci].  A block owns a
+// chunk of pixels; 256 of them at a time it stages dZ, and for each tap the
+// shifted activations, in LDS channel-major (rows of 256 pixels padded by 16
+// bytes, so the 8 lanes of a 128-byte read group hit distinct banks); wave w
+// then reduces its (co tile w/2, ci tile w%2) over the pixels with one MFMA
+// per 32 pixels (M = co, N = ci, K = pixels).  Sums leave once per chunk.
+constexpr int kWgPix = 256;
+constexpr int kWgPitch = kWgPix + 8;  // bf16 per LDS row
+
+__device__ __forceinline__ void put_cols(uint16_t* T, int col, const uint4 (&v)[4]) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int p = k0 + 8 * g + e;
-      uint16_t za = 0, zb = 0;
-      if (p < p1) {
-        za = co < DZS ? dZ[(size_t)p * DZS + co] : (uint16_t)0;
-        const int n = p / hw, q = p % hw;
-        const int yy = q / W + dy, xx = q % W + dx;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-          if (!GATHER) {
-            zb = A[(((size_t)n * H + yy) * W + xx) * kK + ci];
-          } else if (ci < kViewCh) {
-            const int v = n % V, off = ci / 4 - kNeigh;
-            if (v + off >= 0 && v + off < V) zb = A[(((size_t)(n + off) * H + yy) * W + xx) * 4 + (ci & 3)];
-          } else if (ci < kCin0) {
-            zb = AB[(((size_t)n * H + yy) * W + xx) * 4 + (ci & 3)];
-          }
-        }
-      }
-      fa.h[e] = za;
-      fb.h[e] = zb;
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc, 0, 0, 0);
-  }
-  if (ci < CI) {
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int c = ct * 16 + 4 * g + e;
-      if (c < CO) atomicAdd(&dW[((size_t)tap * CO + c) * CI + ci], acc[e]);
+    for (int h = 0; h < 4; ++h) {
+      T[(8 * q + 2 * h) * kWgPitch + col] = (uint16_t)(w[h] & 0xFFFFu);
+      T[(8 * q + 2 * h + 1) * kWgPitch + col] = (uint16_t)(w[h] >> 16);
     }
   }
 }
 
-// db[co] += sum over a chunk of pixels of dZ[p][co]; grid (CO, chunks).
+template <bool GATHER>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const uint16_t* __restrict__ dZ, int CO,
+                                                     const uint16_t* __restrict__ A, const uint16_t* __restrict__ AB,
+                                                     int CI, int N, int H, int W, int V, int DIL,
+                                                     float* __restrict__ dW, int chunk) {
+  __shared__ uint16_t dzT[kK * kWgPitch];
+  __shared__ uint16_t aT[kK * kWgPitch];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
+  const int ct = wv >> 1, it = wv & 1;
+  const bool active = ct * 16 < CO && it * 16 < CI;  // wave-uniform
+  const int hw = H * W, npx = N * hw;
+  const int c0 = blockIdx.x * chunk, c1 = min(npx, c0 + chunk);
+  f32x4 acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int base = c0; base < c1; base += kWgPix) {
+    const int p = base + (int)threadIdx.x;
+    const bool pv = p < c1;
+    const int n = pv ? p / hw : 0, q = pv ? p % hw : 0;
+    const int y = q / W, x = q % W;
+    __syncthreads();  // the previous chunk's reads are done
+    {
+      uint4 v[4] = {};
+      if (pv) {
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) v[c4] = reinterpret_cast<const uint4*>(dZ + (size_t)p * kK)[c4];
+      }
+      put_cols(dzT, threadIdx.x, v);
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {  // unrolled: acc[tap] stays in registers
+      const int yy = y + tap / 3 - 1, xx = x + (tap % 3 - 1) * DIL;
+      uint4 v[4] = {};
+      if (pv) {
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) v[c4] = load_a<GATHER>(A, AB, n, yy, xx, H, W, c4, V);
+      }
+      __syncthreads();  // the previous tap's reads of aT are done
+      put_cols(aT, threadIdx.x, v);
+      __syncthreads();
+      if (active) {
+#pragma unroll
+        for (int k = 0; k < kWgPix / 32; ++k) {
+          Frag fa, fb;
+          fa.u = *reinterpret_cast<const uint4*>(&dzT[(ct * 16 + r16) * kWgPitch + k * 32 + 8 * g]);
+          fb.u = *reinterpret_cast<const uint4*>(&aT[(it * 16 + r16) * kWgPitch + k * 32 + 8 * g]);
+          acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc[tap], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane holds D[4g+e][r16]: co = ct*16 + 4g + e, ci = it*16 + r16
+  if (active) {
+    const int ci = it * 16 + r16;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int co = ct * 16 + 4 * g + e;
+        if (co < CO && ci < CI) atomicAdd(&dW[((size_t)tap * CO + co) * CI + ci], acc[tap][e]);
+      }
+  }
+}
+
 __global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, int chunk, float* __restrict__ db) {
   const int co = blockIdx.x;
   const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
@@ -663,17 +694,16 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
   const int64_t mse_blocks = (ne + 255) / 256;
   k_mse<<<(unsigned)(mse_blocks < 2048 ? mse_blocks : 2048), 256, 0, s>>>(net->last_y, (const uint16_t*)target, npx,
                                                                            net->dz[4], net->d_loss);
-  const int chunk = 4096;
+  const int chunk = 4096;  // pixels per block of the weight gradient
   const unsigned nch = (unsigned)((npx + chunk - 1) / chunk);
   for (int k = 3; k >= 0; --k) {
     const int CO = net->co[k], CI = net->ci[k];
-    dim3 gw((unsigned)(9 * ((CO + 15) / 16) * 2), nch);
     if (k == 0)
-      k_conv_wgrad<true><<<gw, 64, 0, s>>>(net->dz[1], kK, CO, net->last_x, net->xb, CI, N, H, W, V, kDilation[0],
-                                           net->grad + net->off_w[0], chunk);
+      k_conv_wgrad<true><<<nch, 256, 0, s>>>(net->dz[1], CO, net->last_x, net->xb, CI, N, H, W, V, kDilation[0],
+                                             net->grad + net->off_w[0], chunk);
     else
-      k_conv_wgrad<false><<<gw, 64, 0, s>>>(net->dz[k + 1], kK, CO, net->act[k], nullptr, CI, N, H, W, V,
-                                            kDilation[k], net->grad + net->off_w[k], chunk);
+      k_conv_wgrad<false><<<nch, 256, 0, s>>>(net->dz[k + 1], CO, net->act[k], nullptr, CI, N, H, W, V, kDilation[k],
+                                              net->grad + net->off_w[k], chunk);
     const int bchunk = 16384;
     k_bias_grad<<<dim3((unsigned)CO, (unsigned)((npx + bchunk - 1) / bchunk)), 256, 0, s>>>(net->dz[k + 1], kK, npx, bchunk,
                                                                                               net->grad + net->off_b[k]);
