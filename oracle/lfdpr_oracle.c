@@ -19,6 +19,16 @@
  * multiview-rendering comparison, Sec. 5.1) is included as an independent
  * gold standard.
  *
+ * Shading: unlit (the splat's colour is the interpolated albedo of Eq. 9) or
+ * physically based (Sec. 3.3: shading happens while the views are rendered,
+ * with albedo, roughness, metallic and normal textures).  In the PBR mode each
+ * triangle names three more textures; the texture-based density of Eq. 1 takes
+ * the largest of the four; every texture gets its own LOD pair (Eqs. 6-7) and
+ * its own two mip fetches per point; per view all four are interpolated with
+ * the same tau (Eq. 9) and shaded with a Cook-Torrance microfacet BRDF (GGX
+ * distribution, Smith-Schlick geometry, Schlick Fresnel) under one directional
+ * light plus ambient, then tone mapped (x/(1+x), square-root gamma).
+ *
  * Numerics: IEEE binary32, round-to-nearest-even, no contraction (built with
  * -ffp-contract=off), every expression evaluated as parenthesised.  Integer
  * parts (lattice, coverage, texture filtering, interleave) are exact.
@@ -51,6 +61,7 @@ typedef struct {
     const int32_t *tex_levels;  /* ntex */
     const int64_t *tex_level_off; /* ntex*16 byte offsets into texels */
     const uint8_t *texels;
+    const uint16_t *mat;   /* nt*3 texture ids (normal, roughness, metallic) or NULL */
 } orc_scene;
 
 typedef struct {
@@ -59,6 +70,8 @@ typedef struct {
     const float *eye;      /* n_views: horizontal eye offset b_r */
     const float *kshift;   /* n_views: b_r / D */
     float model[12];       /* camera-from-scene, row-major 3x4 */
+    int shade;             /* 0 unlit albedo, 1 physically based */
+    float light[9];        /* unit direction towards the light, light RGB, ambient RGB (camera space) */
 } orc_frame;
 
 typedef struct {
@@ -78,6 +91,13 @@ typedef struct {
        [4] misses, [5] overflow tris, [6] covered fragments */
     int64_t *stats;
     const float *lod_thresholds_unused;
+    /* PBR mode only (may be NULL otherwise): per point normal-map fetches and
+       roughness/metallic bytes rmin | rmax<<8 | mmin<<16 | mmax<<24; per
+       triangle the tangent frame (T, B) and the 8 LODs (albedo, normal,
+       roughness, metallic; min, max) */
+    uint32_t *p_nmin, *p_nmax, *p_rm;
+    float *tframe;         /* nt*6 */
+    int32_t *tlod;         /* nt*8 */
 } orc_out;
 
 /* ------------------------------------------------------------------ */
@@ -251,6 +271,9 @@ typedef struct {
     int *rowstart;        /* per row */
     vproj pr[3];
     int tex;
+    int texm[4];          /* albedo, normal, roughness, metallic (PBR) */
+    int kq[8];            /* LOD min/max per texture (1/256 level) */
+    v3 tt, tb;            /* tangent frame (PBR) */
 } tri_state;
 
 static int cell_overlaps(const tri_state *ts, int64_t i, int64_t j) {
@@ -278,8 +301,9 @@ static int cell_overlaps(const tri_state *ts, int64_t i, int64_t j) {
 
 /* ------------------------------------------------------------------ */
 
-static uint32_t splat_colour(const tri_state *ts, const orc_frame *fr, float b, int i, int j,
-                             uint32_t tvmin, uint32_t tvmax) {
+/* Eqs. 8-9: interpolation weight tau of the splat of cell (i, j) in the view
+ * with eye offset b, quantised to tq/256. */
+static int splat_tq(const tri_state *ts, const orc_frame *fr, float b, int i, int j) {
     float fxfy = fr->fx * fr->fy;
     float cs = (float)i / ts->Sx, ct = (float)j / ts->Sy;
     float Zc = (ts->P[0].z + cs * ts->u.z) + ct * ts->w.z;
@@ -295,12 +319,136 @@ static uint32_t splat_colour(const tri_state *ts, const orc_frame *fr, float b, 
     int tq = (int)floorf(tau * 256.0f + 0.5f);
     if (tq < 0) tq = 0;
     if (tq > 256) tq = 256;
-    uint32_t out = 0;
-    for (int c = 0; c < 4; ++c) {
-        uint32_t a = (tvmin >> (8 * c)) & 255u, z = (tvmax >> (8 * c)) & 255u;
-        uint32_t m = (a * (uint32_t)(256 - tq) + z * (uint32_t)tq + 128u) >> 8;
-        out |= m << (8 * c);
+    return tq;
+}
+
+/* ------------------------------------------------------------------ */
+/* physically based shading (PBR mode)                                     */
+
+#define K255 0x1.010102p-8f     /* float nearest 1/255 */
+#define K2_255 0x1.010102p-7f   /* float nearest 2/255 (exactly 2*K255) */
+#define PI_F 0x1.921fb6p+1f     /* float nearest pi */
+#define INV_PI_F 0x1.45f306p-2f /* float nearest 1/pi */
+
+/* Tangent frame of the texture mapping: T = dP/du and B = dP/dv solved from
+ * the two edges and their UV differences, T made orthogonal to the unit normal
+ * and normalised, B = n x T with the sign of dP/dv.  A degenerate mapping
+ * falls back to the lattice axes u, w. */
+static void tangent_frame(v3 e1, v3 e2, float du1, float dv1, float du2, float dv2, v3 nh, v3 u, v3 w,
+                          v3 *T, v3 *B) {
+    float det = du1 * dv2 - dv1 * du2;
+    v3 t = u, bb = w;
+    if (det != 0.0f) {
+        float rd = 1.0f / det;
+        t.x = (e1.x * dv2 - e2.x * dv1) * rd;
+        t.y = (e1.y * dv2 - e2.y * dv1) * rd;
+        t.z = (e1.z * dv2 - e2.z * dv1) * rd;
+        bb.x = (e2.x * du1 - e1.x * du2) * rd;
+        bb.y = (e2.y * du1 - e1.y * du2) * rd;
+        bb.z = (e2.z * du1 - e1.z * du2) * rd;
     }
+    float tn = v3dot(nh, t);
+    v3 tp = {t.x - nh.x * tn, t.y - nh.y * tn, t.z - nh.z * tn};
+    float tl = sqrtf((tp.x * tp.x + tp.y * tp.y) + tp.z * tp.z);
+    if (tl > 0.0f && !isinf(tl)) {
+        float it = 1.0f / tl;
+        tp.x = tp.x * it; tp.y = tp.y * it; tp.z = tp.z * it;
+    } else {
+        tp = u;
+    }
+    v3 bp = v3cross(nh, tp);
+    if (v3dot(bp, bb) < 0.0f) { bp.x = -bp.x; bp.y = -bp.y; bp.z = -bp.z; }
+    *T = tp;
+    *B = bp;
+}
+
+typedef struct { float D, G, NL, NV, F[3], f[3]; } pbr_terms;
+
+/* Cook-Torrance BRDF for unit normal n, unit view v and unit light L:
+ * f = kd a / pi + F D G / (4 (n.L)(n.V) + 1e-4), GGX D with alpha = r^2,
+ * Smith-Schlick G with k = (r+1)^2/8, Schlick F with F0 = 0.04 (1-m) + a m,
+ * kd = (1 - F)(1 - m). */
+static void pbr_eval(v3 n, v3 v, v3 L, float rgh, float mtl, const float a[3], pbr_terms *o) {
+    v3 h = {L.x + v.x, L.y + v.y, L.z + v.z};
+    float hl = sqrtf((h.x * h.x + h.y * h.y) + h.z * h.z);
+    v3 H = n;
+    if (hl > 0.0f && !isinf(hl)) {
+        float ih = 1.0f / hl;
+        H.x = h.x * ih; H.y = h.y * ih; H.z = h.z * ih;
+    }
+    float NL = v3dot(n, L), NV = v3dot(n, v), NH = v3dot(n, H), VH = v3dot(v, H);
+    NL = NL > 0.0f ? NL : 0.0f;
+    NV = NV > 0.0f ? NV : 0.0f;
+    NH = NH > 0.0f ? NH : 0.0f;
+    VH = VH > 0.0f ? VH : 0.0f;
+    float al = rgh * rgh, a2 = al * al;
+    float dd = (NH * NH) * (a2 - 1.0f) + 1.0f;
+    float D = a2 / ((PI_F * dd) * dd);
+    float kk = ((rgh + 1.0f) * (rgh + 1.0f)) * 0.125f;
+    float G = (NL / (NL * (1.0f - kk) + kk)) * (NV / (NV * (1.0f - kk) + kk));
+    float fr = 1.0f - VH;
+    float f5 = ((fr * fr) * (fr * fr)) * fr;
+    float sp = (D * G) / (((4.0f * NL) * NV) + 1e-4f);
+    o->D = D; o->G = G; o->NL = NL; o->NV = NV;
+    for (int c = 0; c < 3; ++c) {
+        float F0 = 0.04f * (1.0f - mtl) + a[c] * mtl;
+        float F = F0 + (1.0f - F0) * f5;
+        float kd = (1.0f - F) * (1.0f - mtl);
+        o->F[c] = F;
+        o->f[c] = (kd * a[c]) * INV_PI_F + F * sp;
+    }
+}
+
+/* Shaded RGBA8 of a splat in the view with eye offset b: albedo, normal-map,
+ * roughness and metallic bytes already interpolated with tau (Eq. 9); the
+ * surface point is the cell centre Pc; alpha is the albedo's. */
+static uint32_t pbr_shade(const float light[9], v3 nh, v3 tt, v3 tb, v3 Pc, float b, uint32_t alb,
+                          uint32_t nrm, uint32_t rq, uint32_t mq) {
+    float a[3];
+    for (int c = 0; c < 3; ++c) a[c] = (float)((alb >> (8 * c)) & 255u) * K255;
+    float nr = (float)(nrm & 255u) * K2_255 - 1.0f;
+    float ng = (float)((nrm >> 8) & 255u) * K2_255 - 1.0f;
+    float nb = (float)((nrm >> 16) & 255u) * K2_255 - 1.0f;
+    v3 sn = {(nr * tt.x + ng * tb.x) + nb * nh.x, (nr * tt.y + ng * tb.y) + nb * nh.y,
+             (nr * tt.z + ng * tb.z) + nb * nh.z};
+    float sl = sqrtf((sn.x * sn.x + sn.y * sn.y) + sn.z * sn.z);
+    v3 n = nh;
+    if (sl > 0.0f && !isinf(sl)) {
+        float is = 1.0f / sl;
+        n.x = sn.x * is; n.y = sn.y * is; n.z = sn.z * is;
+    }
+    v3 vv = {b - Pc.x, 0.0f - Pc.y, 0.0f - Pc.z};
+    float vl = sqrtf((vv.x * vv.x + vv.y * vv.y) + vv.z * vv.z);
+    v3 v = {0.0f, 0.0f, -1.0f};
+    if (vl > 0.0f && !isinf(vl)) {
+        float iv = 1.0f / vl;
+        v.x = vv.x * iv; v.y = vv.y * iv; v.z = vv.z * iv;
+    }
+    v3 L = {light[0], light[1], light[2]};
+    float rgh = (float)rq * K255;
+    rgh = rgh > 0.03f ? rgh : 0.03f;
+    float mtl = (float)mq * K255;
+    pbr_terms T;
+    pbr_eval(n, v, L, rgh, mtl, a, &T);
+    uint32_t out = alb & 0xFF000000u;
+    for (int c = 0; c < 3; ++c) {
+        float lo = T.f[c] * (light[3 + c] * T.NL) + light[6 + c] * a[c];
+        float t = lo / (1.0f + lo);
+        float y = floorf(sqrtf(t) * 255.0f + 0.5f);
+        uint32_t q = y >= 255.0f ? 255u : (y > 0.0f ? (uint32_t)y : 0u);
+        out |= q << (8 * c);
+    }
+    return out;
+}
+
+/* Eq. 9 interpolation of one byte, and of four packed bytes, with weight tq/256. */
+static uint32_t lerp8(uint32_t a, uint32_t z, int tq) {
+    return (a * (uint32_t)(256 - tq) + z * (uint32_t)tq + 128u) >> 8;
+}
+
+static uint32_t lerp_rgba8(uint32_t lo, uint32_t hi, int tq) {
+    uint32_t out = 0;
+    for (int c = 0; c < 4; ++c) out |= lerp8((lo >> (8 * c)) & 255u, (hi >> (8 * c)) & 255u, tq) << (8 * c);
     return out;
 }
 
@@ -340,6 +488,7 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
     int64_t npts = 0;
     int nviews = fr->n_views;
     int64_t px_per_view = (int64_t)fr->W * fr->H;
+    if (fr->shade == 1 && !sc->mat) return -2;
     int *vactive = (int *)malloc(sizeof(int) * (size_t)nviews);
     for (int t = 0; t < sc->nt; ++t) {
         tri_state ts;
@@ -422,8 +571,12 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         ts.Sx = 1.0f / lxmin;
         ts.Sy = 1.0f / lymin;
         float size_xy = Amin;
-        /* Texture-based sampling, Eqs. 1-3 (one albedo texture per triangle) */
+        /* Texture-based sampling, Eqs. 1-3: one albedo texture per triangle, or
+           the four textures of the PBR mode with Eq. 1's maximum over them */
+        const int pbr = fr->shade == 1;
         ts.tex = sc->tex[t];
+        ts.texm[0] = ts.tex;
+        for (int k = 1; k < 4; ++k) ts.texm[k] = pbr ? (int)sc->mat[t * 3 + k - 1] : ts.tex;
         float uv0u, uv0v, du1, dv1, du2, dv2;
         {
             uint32_t i0 = sc->idx[t * 3], i1 = sc->idx[t * 3 + 1], i2 = sc->idx[t * 3 + 2];
@@ -435,6 +588,11 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         float Aws = 0.5f * nl;
         float Xt = (float)sc->tex_size[ts.tex];
         float ntex = (Ats * Xt) * Xt;                 /* Eq. 1 */
+        for (int k = 1; k < 4 && pbr; ++k) {
+            float Xk = (float)sc->tex_size[ts.texm[k]];
+            float nk = (Ats * Xk) * Xk;
+            ntex = nk > ntex ? nk : ntex;
+        }
         if (ntex > 0.0f) {
             float size_uv = Aws / ntex;               /* Eq. 2 */
             if (size_uv > size_xy) {                  /* Eq. 3 */
@@ -453,14 +611,30 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         }
         ts.smin = (((Zmin * Zmin) * Zmin) / (fxfy * admax)) * ts.ruv;
         ts.smax = (((Zmax * Zmax) * Zmax) / (fxfy * admin)) * ts.ruv;
-        int Lt = sc->tex_levels[ts.tex];
-        int kmin = 0, kmax = 0;
-        if (fr->mip) {
-            kmin = lod_q8((ts.smin * Xt) * Xt);       /* Eq. 6 */
-            kmax = lod_q8((ts.smax * Xt) * Xt);       /* Eq. 7 */
-            int top = 256 * (Lt - 1);
-            kmin = kmin < 0 ? 0 : (kmin > top ? top : kmin);
-            kmax = kmax < 0 ? 0 : (kmax > top ? top : kmax);
+        /* Eqs. 6-7 per texture (its own size and level count) */
+        for (int k = 0; k < 4; ++k) {
+            int tk = ts.texm[k];
+            float Xk = (float)sc->tex_size[tk];
+            int k0 = 0, k1 = 0;
+            if (fr->mip) {
+                k0 = lod_q8((ts.smin * Xk) * Xk);     /* Eq. 6 */
+                k1 = lod_q8((ts.smax * Xk) * Xk);     /* Eq. 7 */
+                int top = 256 * (sc->tex_levels[tk] - 1);
+                k0 = k0 < 0 ? 0 : (k0 > top ? top : k0);
+                k1 = k1 < 0 ? 0 : (k1 > top ? top : k1);
+            }
+            ts.kq[2 * k] = k0;
+            ts.kq[2 * k + 1] = k1;
+        }
+        int kmin = ts.kq[0], kmax = ts.kq[1];
+        if (pbr) {
+            tangent_frame(e1, e2, du1, dv1, du2, dv2, ts.nh, ts.u, ts.w, &ts.tt, &ts.tb);
+            if (out->tframe) {
+                float *tf = out->tframe + (int64_t)t * 6;
+                tf[0] = ts.tt.x; tf[1] = ts.tt.y; tf[2] = ts.tt.z; tf[3] = ts.tb.x; tf[4] = ts.tb.y; tf[5] = ts.tb.z;
+            }
+            if (out->tlod)
+                for (int k = 0; k < 8; ++k) out->tlod[(int64_t)t * 8 + k] = ts.kq[k];
         }
         /* sample lattice in the aligned, density-scaled plane; vertex 0 at cell (0,0) centre */
         int overflow = 0;
@@ -532,12 +706,17 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         }
         ts.first_point = npts;
         /* per-point attributes: UV at the cell centre, two mip fetches */
-        uint32_t *tvmin = NULL, *tvmax = NULL;
+        uint32_t *tvmin = NULL, *tvmax = NULL, *nmin = NULL, *nmax = NULL, *rm = NULL;
         unsigned *flg = NULL;
         if (ncell > 0) {
             tvmin = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
             tvmax = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
             flg = (unsigned *)malloc(sizeof(unsigned) * ncell);
+            if (pbr) {
+                nmin = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
+                nmax = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
+                rm = (uint32_t *)malloc(sizeof(uint32_t) * ncell);
+            }
         }
         for (int c = 0; c < ncell; ++c) {
             int i = cells_i[c], j = cells_j[c];
@@ -556,6 +735,15 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
             float vv = (uv0v + b1 * dv1) + b2 * dv2;
             tvmin[c] = trilinear(sc, ts.tex, uu, vv, kmin);
             tvmax[c] = trilinear(sc, ts.tex, uu, vv, kmax);
+            if (pbr) {
+                nmin[c] = trilinear(sc, ts.texm[1], uu, vv, ts.kq[2]);
+                nmax[c] = trilinear(sc, ts.texm[1], uu, vv, ts.kq[3]);
+                uint32_t r0 = trilinear(sc, ts.texm[2], uu, vv, ts.kq[4]) & 255u;
+                uint32_t r1 = trilinear(sc, ts.texm[2], uu, vv, ts.kq[5]) & 255u;
+                uint32_t m0 = trilinear(sc, ts.texm[3], uu, vv, ts.kq[6]) & 255u;
+                uint32_t m1 = trilinear(sc, ts.texm[3], uu, vv, ts.kq[7]) & 255u;
+                rm[c] = r0 | (r1 << 8) | (m0 << 16) | (m1 << 24);
+            }
             flg[c] = f;
             int64_t gi = npts + c;
             if (gi < out->point_cap) {
@@ -563,6 +751,7 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
                 out->p_i[gi] = (int16_t)i; out->p_j[gi] = (int16_t)j;
                 out->p_flags[gi] = (uint8_t)f;
                 out->p_tvmin[gi] = tvmin[c]; out->p_tvmax[gi] = tvmax[c];
+                if (pbr && out->p_nmin) { out->p_nmin[gi] = nmin[c]; out->p_nmax[gi] = nmax[c]; out->p_rm[gi] = rm[c]; }
             }
         }
         npts += ncell;
@@ -621,7 +810,18 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
                     int box[4];
                     splat_box(&ts, fr, b, ci, cj, flg[c], (int)X0, (int)X1, (int)Y0, (int)Y1, box);
                     if (x < box[0] || x > box[1] || y < box[2] || y > box[3]) { out->stats[4] += 1; continue; }
-                    uint32_t col = splat_colour(&ts, fr, b, ci, cj, tvmin[c], tvmax[c]);
+                    int tq = splat_tq(&ts, fr, b, ci, cj);
+                    uint32_t col = lerp_rgba8(tvmin[c], tvmax[c], tq);
+                    if (pbr) {
+                        /* cell centre of the owning point (vertex 0 sits at the centre of cell (0,0)) */
+                        float cs = (float)ci / ts.Sx, ct = (float)cj / ts.Sy;
+                        v3 Pc = {(ts.P[0].x + cs * ts.u.x) + ct * ts.w.x, (ts.P[0].y + cs * ts.u.y) + ct * ts.w.y,
+                                 (ts.P[0].z + cs * ts.u.z) + ct * ts.w.z};
+                        uint32_t nrm = lerp_rgba8(nmin[c], nmax[c], tq);
+                        uint32_t rq = lerp8(rm[c] & 255u, (rm[c] >> 8) & 255u, tq);
+                        uint32_t mq = lerp8((rm[c] >> 16) & 255u, rm[c] >> 24, tq);
+                        col = pbr_shade(fr->light, ts.nh, ts.tt, ts.tb, Pc, b, col, nrm, rq, mq);
+                    }
                     uint32_t zb;
                     memcpy(&zb, &Z, 4);
                     uint64_t key = ((uint64_t)zb << 32) | col;
@@ -629,7 +829,7 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
                     if (key < *dst) *dst = key;
                 }
         }
-        free(cells_i); free(cells_j); free(tvmin); free(tvmax); free(flg);
+        free(cells_i); free(cells_j); free(tvmin); free(tvmax); free(flg); free(nmin); free(nmax); free(rm);
         free(ts.ilo); free(ts.ihi); free(ts.rowstart);
     }
     out->stats[0] = npts;
@@ -886,3 +1086,28 @@ void orc_closest_point(const float p[3], const float a[3], const float b[3], con
 
 uint32_t orc_trilinear(const orc_scene *sc, int t, float u, float v, int kc) { return trilinear(sc, t, u, v, kc); }
 int orc_lod_q8(float a) { return lod_q8(a); }
+
+/* PBR pieces for the pins: tangent frame, BRDF terms, shaded RGBA8. */
+void orc_tangent_frame(const float e1[3], const float e2[3], const float uv[4], const float nh[3], const float u[3],
+                       const float w[3], float out[6]) {
+    v3 a = {e1[0], e1[1], e1[2]}, b = {e2[0], e2[1], e2[2]}, n = {nh[0], nh[1], nh[2]};
+    v3 uu = {u[0], u[1], u[2]}, ww = {w[0], w[1], w[2]}, T, B;
+    tangent_frame(a, b, uv[0], uv[1], uv[2], uv[3], n, uu, ww, &T, &B);
+    out[0] = T.x; out[1] = T.y; out[2] = T.z; out[3] = B.x; out[4] = B.y; out[5] = B.z;
+}
+
+void orc_pbr_terms(const float n[3], const float v[3], const float L[3], float rgh, float mtl, const float a[3],
+                   float out[10]) {
+    v3 nn = {n[0], n[1], n[2]}, vv = {v[0], v[1], v[2]}, LL = {L[0], L[1], L[2]};
+    pbr_terms T;
+    pbr_eval(nn, vv, LL, rgh, mtl, a, &T);
+    out[0] = T.D; out[1] = T.G; out[2] = T.NL; out[3] = T.NV;
+    for (int c = 0; c < 3; ++c) { out[4 + c] = T.F[c]; out[7 + c] = T.f[c]; }
+}
+
+uint32_t orc_pbr_shade(const float light[9], const float frame[9], const float Pc[3], float b, uint32_t alb,
+                       uint32_t nrm, uint32_t rq, uint32_t mq) {
+    v3 nh = {frame[6], frame[7], frame[8]}, tt = {frame[0], frame[1], frame[2]}, tb = {frame[3], frame[4], frame[5]};
+    v3 P = {Pc[0], Pc[1], Pc[2]};
+    return pbr_shade(light, nh, tt, tb, P, b, alb, nrm, rq, mq);
+}

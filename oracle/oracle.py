@@ -19,6 +19,12 @@ Functions and what pins them (see tests/test_oracle_pins.py):
   angular_filter    -- 4x angular SS -> V views             [pinned: focal-plane identity,
                        constant input, weight normalisation]
   rasterise         -- conventional z-buffer multiview renderer (gold standard)
+  tangent_frame, pbr_terms, pbr_shade
+                    -- physically based shading of the PBR mode [pinned: GGX
+                       normalisation integral, Helmholtz reciprocity, rotation
+                       invariance, Fresnel and geometry limits, tangent frame of
+                       axis-aligned mappings, texture-swap reductions of the
+                       point data, unlit-density reduction of Eq. 1's maximum]
 """
 from __future__ import annotations
 
@@ -66,21 +72,23 @@ class _Scene(C.Structure):
     _fields_ = [("nv", C.c_int), ("nt", C.c_int), ("pos", C.c_void_p), ("uv", C.c_void_p),
                 ("idx", C.c_void_p), ("tex", C.c_void_p), ("ntex", C.c_int),
                 ("tex_size", C.c_void_p), ("tex_levels", C.c_void_p), ("tex_level_off", C.c_void_p),
-                ("texels", C.c_void_p)]
+                ("texels", C.c_void_p), ("mat", C.c_void_p)]
 
 
 class _Frame(C.Structure):
     _fields_ = [("n_views", C.c_int), ("W", C.c_int), ("H", C.c_int), ("mip", C.c_int),
                 ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
                 ("rD", C.c_float), ("znear", C.c_float), ("eye", C.c_void_p), ("kshift", C.c_void_p),
-                ("model", C.c_float * 12)]
+                ("model", C.c_float * 12), ("shade", C.c_int), ("light", C.c_float * 9)]
 
 
 class _Out(C.Structure):
     _fields_ = [("count", C.c_void_p), ("trif", C.c_void_p), ("trii", C.c_void_p),
                 ("point_cap", C.c_int64), ("p_tri", C.c_void_p), ("p_i", C.c_void_p), ("p_j", C.c_void_p),
                 ("p_flags", C.c_void_p), ("p_tvmin", C.c_void_p), ("p_tvmax", C.c_void_p),
-                ("keys", C.c_void_p), ("stats", C.c_void_p), ("unused", C.c_void_p)]
+                ("keys", C.c_void_p), ("stats", C.c_void_p), ("unused", C.c_void_p),
+                ("p_nmin", C.c_void_p), ("p_nmax", C.c_void_p), ("p_rm", C.c_void_p),
+                ("tframe", C.c_void_p), ("tlod", C.c_void_p)]
 
 
 class _Lens(C.Structure):
@@ -188,9 +196,27 @@ def build_textures(scene) -> Textures:
 def _scene_struct(scene, tx: Textures, keep: list) -> _Scene:
     arrs = [np.ascontiguousarray(scene.pos, np.float32), np.ascontiguousarray(scene.uv, np.float32),
             np.ascontiguousarray(scene.idx, np.uint32), np.ascontiguousarray(scene.tex, np.uint16)]
+    mat = getattr(scene, "materials", None)
+    if mat is not None:
+        mat = np.ascontiguousarray(mat, np.uint16).reshape(-1, 3)
+        arrs.append(mat)
     keep += arrs
     return _Scene(scene.n_verts, scene.n_tris, _p(arrs[0]), _p(arrs[1]), _p(arrs[2]), _p(arrs[3]),
-                  tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels))
+                  tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels),
+                  _p(mat) if mat is not None else None)
+
+
+def _set_shading(f: _Frame, shading) -> None:
+    """Shading mode and light (camera space): unit direction towards the light,
+    light RGB, ambient RGB."""
+    if shading is None or int(shading.mode) == 0:
+        f.shade = 0
+        return
+    f.shade = 1
+    vals = list(np.float32(shading.light_dir)) + list(np.float32(shading.light_rgb)) + \
+        list(np.float32(shading.ambient_rgb))
+    for k in range(9):
+        f.light[k] = float(vals[k])
 
 
 def _frame_struct(vp, vt, model, keep: list) -> _Frame:
@@ -208,16 +234,24 @@ def _frame_struct(vp, vt, model, keep: list) -> _Frame:
     return f
 
 
-def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_cap: Optional[int] = None):
+def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_cap: Optional[int] = None,
+           shading=None):
     """Point generation + splatting of one frame into all V*S rendered views.
 
     Returns a dict with per-triangle counts and records, the point buffer in
-    emission order, RGBA8 views (n_views, H, W) as uint32, FP32 depth and stats."""
+    emission order, RGBA8 views (n_views, H, W) as uint32, FP32 depth and stats.
+    With a PBR `shading` the scene must carry materials; the point buffer then
+    also holds the normal-map fetches and the roughness/metallic bytes, and the
+    per-triangle tangent frames and LODs are returned."""
     tx = tx or build_textures(scene)
     vt = view_table(vp)
     keep: list = []
     sc = _scene_struct(scene, tx, keep)
     fr = _frame_struct(vp, vt, model, keep)
+    _set_shading(fr, shading)
+    pbr = fr.shade == 1
+    if pbr and getattr(scene, "materials", None) is None:
+        raise ValueError("PBR shading needs scene materials")
     nt = scene.n_tris
     nviews = vp.V * vp.S
     cap = point_cap if point_cap is not None else max(64, 24 * nt)
@@ -226,19 +260,29 @@ def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_ca
              p_flags=np.zeros(cap, np.uint8), p_tvmin=np.zeros(cap, np.uint32), p_tvmax=np.zeros(cap, np.uint32),
              keys=np.full((nviews, vp.H, vp.W), np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64),
              stats=np.zeros(8, np.int64))
+    if pbr:
+        o.update(p_nmin=np.zeros(cap, np.uint32), p_nmax=np.zeros(cap, np.uint32), p_rm=np.zeros(cap, np.uint32),
+                 tframe=np.zeros((nt, 6), np.float32), tlod=np.zeros((nt, 8), np.int32))
+    opt = [_p(o[k]) if k in o else None for k in ("p_nmin", "p_nmax", "p_rm", "tframe", "tlod")]
     out = _Out(_p(o["count"]), _p(o["trif"]), _p(o["trii"]), cap, _p(o["p_tri"]), _p(o["p_i"]), _p(o["p_j"]),
-               _p(o["p_flags"]), _p(o["p_tvmin"]), _p(o["p_tvmax"]), _p(o["keys"]), _p(o["stats"]), None)
-    lib().orc_render(C.byref(sc), C.byref(fr), C.byref(out))
+               _p(o["p_flags"]), _p(o["p_tvmin"]), _p(o["p_tvmax"]), _p(o["keys"]), _p(o["stats"]), None, *opt)
+    rc = lib().orc_render(C.byref(sc), C.byref(fr), C.byref(out))
+    if rc != 0:
+        raise ValueError(f"oracle render failed ({rc})")
     n = int(o["stats"][0])
     if n > cap:
-        return render(scene, vp, model, tx, point_cap=n)
+        return render(scene, vp, model, tx, point_cap=n, shading=shading)
     rgba = np.zeros((nviews, vp.H, vp.W), np.uint32)
     depth = np.zeros((nviews, vp.H, vp.W), np.float32)
     lib().orc_resolve(C.c_void_p(_p(o["keys"])), C.c_int64(o["keys"].size), C.c_void_p(_p(rgba)), C.c_void_p(_p(depth)))
     st = o["stats"]
-    return dict(count=o["count"], trif=o["trif"], trii=o["trii"], n_points=n,
-                points=dict(tri=o["p_tri"][:n], i=o["p_i"][:n], j=o["p_j"][:n], flags=o["p_flags"][:n],
-                            tvmin=o["p_tvmin"][:n], tvmax=o["p_tvmax"][:n]),
+    points = dict(tri=o["p_tri"][:n], i=o["p_i"][:n], j=o["p_j"][:n], flags=o["p_flags"][:n],
+                  tvmin=o["p_tvmin"][:n], tvmax=o["p_tvmax"][:n])
+    extra = {}
+    if pbr:
+        points.update(nmin=o["p_nmin"][:n], nmax=o["p_nmax"][:n], rm=o["p_rm"][:n])
+        extra = dict(tframe=o["tframe"], tlod=o["tlod"])
+    return dict(count=o["count"], trif=o["trif"], trii=o["trii"], n_points=n, points=points, **extra,
                 keys=o["keys"], rgba=rgba, depth=depth,
                 stats=dict(points=int(st[0]), active_tris=int(st[1]), point_views=int(st[2]), orphans=int(st[3]),
                            misses=int(st[4]), overflow_tris=int(st[5]), fragments=int(st[6])),
@@ -302,8 +346,7 @@ def closest_point(p, a, b, c) -> np.ndarray:
 
 
 def trilinear(tx: Textures, t: int, u: float, v: float, kc: int) -> int:
-    keep: list = []
-    sc = _Scene(0, 0, None, None, None, None, tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels))
+    sc = _Scene(0, 0, None, None, None, None, tx.ntex, _p(tx.size), _p(tx.levels), _p(tx.off), _p(tx.texels), None)
     return int(lib().orc_trilinear(C.byref(sc), C.c_int(t), C.c_float(u), C.c_float(v), C.c_int(kc)))
 
 
@@ -313,3 +356,43 @@ def lod_q8(a: float) -> int:
 
 def unpack_rgba(u32: np.ndarray) -> np.ndarray:
     return u32.view(np.uint8).reshape(*u32.shape, 4)
+
+
+# ---------------------------------------------------------------------------
+# physically based shading pieces (PBR mode)
+
+
+def _f32(x, n):
+    a = np.ascontiguousarray(np.asarray(x, np.float32).reshape(n))
+    return a
+
+
+def tangent_frame(e1, e2, duv, nh, u, w) -> np.ndarray:
+    """(T, B) of the texture mapping for edges e1, e2 with UV differences
+    duv = (du1, dv1, du2, dv2); u, w = fallback axes."""
+    arrs = [_f32(e1, 3), _f32(e2, 3), _f32(duv, 4), _f32(nh, 3), _f32(u, 3), _f32(w, 3)]
+    out = np.zeros(6, np.float32)
+    lib().orc_tangent_frame(*[C.c_void_p(_p(a)) for a in arrs], C.c_void_p(_p(out)))
+    return out
+
+
+def pbr_terms(n, v, L, rough: float, metal: float, albedo) -> Dict[str, object]:
+    """BRDF pieces for unit n, v, L: D, G, n.L, n.V, Fresnel F (RGB) and the
+    BRDF value f (RGB)."""
+    arrs = [_f32(n, 3), _f32(v, 3), _f32(L, 3)]
+    a = _f32(albedo, 3)
+    out = np.zeros(10, np.float32)
+    lib().orc_pbr_terms(*[C.c_void_p(_p(x)) for x in arrs], C.c_float(rough), C.c_float(metal),
+                        C.c_void_p(_p(a)), C.c_void_p(_p(out)))
+    return dict(D=out[0], G=out[1], NL=out[2], NV=out[3], F=out[4:7].copy(), f=out[7:10].copy())
+
+
+def pbr_shade(light, frame, Pc, b: float, albedo: int, normal: int, rough: int, metal: int) -> int:
+    """Shaded RGBA8 of one splat: light = 9 floats (direction, RGB, ambient RGB),
+    frame = 9 floats (T, B, unit normal), Pc = cell centre, b = eye offset,
+    byte inputs already interpolated with tau."""
+    lt, fr, pc = _f32(light, 9), _f32(frame, 9), _f32(Pc, 3)
+    f = lib().orc_pbr_shade
+    f.restype = C.c_uint32
+    return int(f(C.c_void_p(_p(lt)), C.c_void_p(_p(fr)), C.c_void_p(_p(pc)), C.c_float(b), C.c_uint32(albedo),
+                 C.c_uint32(normal), C.c_uint32(rough), C.c_uint32(metal)))

@@ -164,6 +164,65 @@ def checker_texture(size: int, rng: np.random.Generator) -> np.ndarray:
     return out
 
 
+def _noise_field(size: int, rng: np.random.Generator, octaves: int = 5) -> np.ndarray:
+    """Tileable fBm value noise in [0, 1] (float32, size x size)."""
+    acc = np.zeros((size, size), np.float32)
+    amp, tot = 1.0, 0.0
+    coords = np.arange(size, dtype=np.float32) + 0.5
+    for o in range(octaves):
+        cells = 4 * 2 ** o
+        if cells > size:
+            break
+        grid = rng.random((cells, cells)).astype(np.float32)
+        f = coords * np.float32(cells / size) - np.float32(0.5)
+        i0 = np.floor(f).astype(np.int64)
+        t = f - i0
+        t = t * t * (3 - 2 * t)
+        rows = grid[i0 % cells] * (1 - t)[:, None] + grid[(i0 + 1) % cells] * t[:, None]
+        acc += np.float32(amp) * (rows[:, i0 % cells] * (1 - t)[None, :] + rows[:, (i0 + 1) % cells] * t[None, :])
+        tot += amp
+        amp *= 0.5
+    return acc / np.float32(tot)
+
+
+def normal_map_texture(size: int, rng: np.random.Generator, strength: float = 6.0) -> np.ndarray:
+    """Tangent-space normal map of a tileable bump field: n = normalize(-dh/dx,
+    -dh/dy, 1) with wrap-around central differences, stored as round((n + 1)/2 * 255)."""
+    h = _noise_field(size, rng) * np.float32(strength)
+    gx = (np.roll(h, -1, axis=1) - np.roll(h, 1, axis=1)) * np.float32(0.5 * size / 64.0)
+    gy = (np.roll(h, -1, axis=0) - np.roll(h, 1, axis=0)) * np.float32(0.5 * size / 64.0)
+    n = np.stack([-gx, -gy, np.ones_like(h)], axis=-1)
+    n /= np.linalg.norm(n, axis=-1, keepdims=True)
+    out = np.empty((size, size, 4), np.uint8)
+    out[..., :3] = np.clip(np.rint((n + 1.0) * 127.5), 0, 255).astype(np.uint8)
+    out[..., 3] = 255
+    return out
+
+
+def scalar_texture(size: int, rng: np.random.Generator, lo: float, hi: float) -> np.ndarray:
+    """Grey value noise in [lo, hi] (all channels equal; the shader reads R)."""
+    v = np.float32(lo) + (np.float32(hi - lo)) * _noise_field(size, rng)
+    g = np.clip(np.rint(v * 255.0), 0, 255).astype(np.uint8)
+    out = np.empty((size, size, 4), np.uint8)
+    out[..., 0] = out[..., 1] = out[..., 2] = g
+    out[..., 3] = 255
+    return out
+
+
+def metallic_texture(size: int, rng: np.random.Generator) -> np.ndarray:
+    """Metal/dielectric mask: a seeded checker of fully metallic (255) and
+    dielectric (0) cells with soft noise on top, in R."""
+    period = max(1, min(size, int(2 ** rng.uniform(2, 6))))
+    y, x = np.mgrid[0:size, 0:size]
+    m = ((x // period + y // period) % 2).astype(np.float32)
+    v = np.clip(m * np.float32(0.9) + np.float32(0.1) * _noise_field(size, rng), 0.0, 1.0)
+    g = np.rint(v * 255.0).astype(np.uint8)
+    out = np.empty((size, size, 4), np.uint8)
+    out[..., 0] = out[..., 1] = out[..., 2] = g
+    out[..., 3] = 255
+    return out
+
+
 def constant_texture(size: int, rgba) -> np.ndarray:
     out = np.empty((size, size, 4), np.uint8)
     out[...] = np.asarray(rgba, np.uint8)
@@ -183,6 +242,7 @@ class Scene:
     tex: np.ndarray          # (nt,) uint16 texture id per triangle
     textures: List[np.ndarray]  # each (s, s, 4) uint8, s a power of two
     name: str = ""
+    materials: Optional[np.ndarray] = None  # (nt, 3) uint16: normal, roughness, metallic texture ids (PBR)
 
     @property
     def n_tris(self) -> int:
@@ -203,6 +263,10 @@ class Scene:
             assert t.dtype == np.uint8 and t.shape == (s, s, 4) and s & (s - 1) == 0
         if self.n_tris:
             assert int(self.tex.max()) < len(self.textures)
+        if self.materials is not None:
+            assert self.materials.dtype == np.uint16 and self.materials.shape == (self.n_tris, 3)
+            if self.n_tris:
+                assert int(self.materials.max()) < len(self.textures)
         return self
 
 
@@ -313,9 +377,56 @@ class Workload:
     views: ViewParams
     lens: LensParams
     tilt_deg: float = 0.0
+    shading: Optional["Shading"] = None
 
     def model(self, frame: int) -> np.ndarray:
         return model_matrix(frame, self.views.D, self.tilt_deg)
+
+
+SHADE_UNLIT, SHADE_PBR = 0, 1
+
+
+@dataclasses.dataclass
+class Shading:
+    """Splat shading: unlit albedo, or physically based with one directional
+    light plus ambient (camera space; light_dir points towards the light)."""
+    mode: int = SHADE_UNLIT
+    light_dir: Tuple[float, float, float] = (0.0, 0.0, -1.0)
+    light_rgb: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    ambient_rgb: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+
+def default_light() -> Shading:
+    d = np.array([0.35, -0.55, -0.75])
+    d = (d / np.linalg.norm(d)).astype(np.float32)
+    return Shading(SHADE_PBR, tuple(float(x) for x in d), (3.0, 2.9, 2.7), (0.12, 0.13, 0.15))
+
+
+def with_pbr(w: Workload, seed: int = 0, n_mat: int = 4, normal_scale: int = 2) -> Workload:
+    """PBR variant of a workload (Sec. 3.3 with albedo, roughness, metallic and
+    normal textures): n_mat material sets, chosen by albedo texture id mod
+    n_mat.  Set m has a normal map of normal_scale x the largest albedo size
+    for even m and 1x for odd m, roughness at half and metallic at a quarter of
+    that size, so Eq. 1's maximum and the per-texture LODs differ from the
+    unlit scene."""
+    rng = np.random.default_rng(seed + 900)
+    sc = w.scene
+    base = max(t.shape[0] for t in sc.textures)
+    textures = list(sc.textures)
+    sets = []
+    for m in range(n_mat):
+        sn = base * (normal_scale if m % 2 == 0 else 1)
+        ids = []
+        for tex in (normal_map_texture(sn, rng), scalar_texture(max(1, sn // 2), rng, 0.15, 0.95),
+                    metallic_texture(max(1, sn // 4), rng)):
+            ids.append(len(textures))
+            textures.append(tex)
+        sets.append(ids)
+    sets = np.asarray(sets, np.uint16)
+    mats = sets[sc.tex.astype(np.int64) % n_mat]
+    scene = dataclasses.replace(sc, textures=textures, materials=np.ascontiguousarray(mats, np.uint16),
+                                name=sc.name + "-pbr").check()
+    return dataclasses.replace(w, name=w.name + "-pbr", scene=scene, shading=default_light())
 
 
 def tiny(seed: int = 1, V: int = 8, size: int = 128, S: int = 1) -> Workload:
