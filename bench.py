@@ -51,6 +51,11 @@ def log(*a):
 # coordinates, ownership, key); the oracle counts 0.327 written pixels per
 # point-view on display-1M, so 100 + 37 * 0.327 = 112.
 SPLAT_OPS_PER_POINT_VIEW = 112
+# physically based shading of a splat (unpack 9, shading normal 25, view and
+# half vectors 26, four dot products 24, roughness/metallic 4, D 8, k 3, G 8,
+# Fresnel power 5, specular 5, per channel 26 x 3) ~ 205 ops, once per written
+# pixel: 0.327 written pixels per point-view (oracle, display-1M)
+SPLAT_PBR_OPS_PER_POINT_VIEW = SPLAT_OPS_PER_POINT_VIEW + round(205 * 0.327)
 SETUP_OPS_PER_TRI_VIEW = 75        # R4 + R6 per (triangle, view)
 BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
@@ -63,18 +68,19 @@ BYTES = {
 }
 
 
-def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None) -> dict:
+def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None,
+             splat_ops: int = SPLAT_OPS_PER_POINT_VIEW) -> dict:
     """Roofline object of the dominant kernel of a frame (stage ms from HIP events)."""
     dom = max(("setup", "emit", "splat", "resolve", "interleave", "scan", "angular_filter"),
               key=lambda k: stage_ms.get(k, 0.0))
     dom_ms = stage_ms[dom]
     if dom == "splat":
-        ops = SPLAT_OPS_PER_POINT_VIEW * pv_per_frame
+        ops = splat_ops * pv_per_frame
         achieved = ops / (dom_ms * 1e-3) / 1e12
         return {"kernel": "k_splat", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": round(VALU_PEAK_GOPS / 1e3, 2), "unit": "Tops/s",
                 "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": traffic,
-                "ops_per_point_view": SPLAT_OPS_PER_POINT_VIEW, "launch_ms": round(dom_ms, 4)}
+                "ops_per_point_view": splat_ops, "launch_ms": round(dom_ms, 4)}
     if dom == "setup":
         ops = SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"]
         achieved = ops / (dom_ms * 1e-3) / 1e12
@@ -112,19 +118,23 @@ def stage_avg(R):
 
 def run_display(args, torch, lfdpr, scenes, kind: str):
     """kind: display-1M, display-4M-ss4 (angular filter to 48 views, then the
-    panel), display-4M-ss4-direct (panel straight from the 192 sub-views) or
-    display-1M-spatial2x (1024^2 views, spatial reconstruction)."""
+    panel), display-4M-ss4-direct (panel straight from the 192 sub-views),
+    display-1M-spatial2x (1024^2 views, spatial reconstruction) or
+    display-1M-pbr (physically based shading with four material sets)."""
     four_m = kind.startswith("display-4M")
     t0 = time.time()
     w = scenes.display_4m(seed=3) if four_m else scenes.display(seed=args.seed)
     if kind == "display-1M-spatial2x":
         w = scenes.spatial_ss(w)
+    if kind == "display-1M-pbr":
+        w = scenes.with_pbr(w)
     lens = scenes.direct_panel_lens(w) if kind == "display-4M-ss4-direct" else w.lens
     log(f"workload generated in {time.time() - t0:.1f}s: {w.scene.n_tris} tris")
     R = lfdpr.Renderer(0)
     sid = R.upload_scene(w.scene)
     R.set_views(w.views, point_capacity=(48 << 20) if kind != "display-1M" else 0)
     R.set_lens(lens)
+    R.set_shading(w.shading)
     views, _ = R.alloc_views()
     filtered = (torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0")
                 if kind == "display-4M-ss4" else None)
@@ -166,7 +176,8 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
                  out_pixels=w.views.V * w.views.W * w.views.H,
                  panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, fragments=0)
-    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None)
+    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None,
+                    SPLAT_PBR_OPS_PER_POINT_VIEW if kind == "display-1M-pbr" else SPLAT_OPS_PER_POINT_VIEW)
     names = {
         "display-1M": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
                       "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene",
@@ -177,10 +188,13 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
                                  "from the 192 sub-views (angular taps over +-4 sub-view intervals), no filter pass",
         "display-1M-spatial2x": "display-1M-spatial2x: the display-1M scene rendered into 48 views of 1024x1024 (2x "
                                 "spatial supersampling), panel through the spatial Gaussian taps",
+        "display-1M-pbr": "display-1M-pbr: the display-1M scene with physically based shading (albedo + normal, "
+                          "roughness and metallic maps in four material sets, normal maps up to 4096^2; one "
+                          "directional light plus ambient), 48 views 512x512, 2560x1600 lenticular panel",
     }
     name = names[kind]
     recon = {"display-1M": "none", "display-4M-ss4": "angular filter", "display-4M-ss4-direct": "angular taps at the panel",
-             "display-1M-spatial2x": "spatial taps at the panel"}[kind]
+             "display-1M-spatial2x": "spatial taps at the panel", "display-1M-pbr": "none"}[kind]
     out = {
         "metric": METRIC,
         "value": round((pv / nfr) / (wall_ms * 1e-3), 1),
@@ -348,7 +362,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", choices=("display-1M", "display-4M-ss4", "display-4M-ss4-direct",
-                                           "display-1M-spatial2x", "batch16", "learned-display"),
+                                           "display-1M-spatial2x", "display-1M-pbr", "batch16", "learned-display"),
                     default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=2)

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LFDPR_ABI_VERSION 1
+#define LFDPR_ABI_VERSION 2
 
 enum {
   LFDPR_OK = 0,
@@ -53,6 +53,7 @@ enum {
 };
 
 enum { LFDPR_RECON_NONE = 0, LFDPR_RECON_SPATIAL = 1, LFDPR_RECON_ANGULAR = 2, LFDPR_RECON_BOTH = 3 };
+enum { LFDPR_SHADE_UNLIT = 0, LFDPR_SHADE_PBR = 1 };
 
 typedef struct lfdpr_ctx lfdpr_ctx;
 
@@ -133,6 +134,37 @@ int lfdpr_scene_upload(lfdpr_ctx* ctx, const lfdpr_scene_desc* desc, int32_t* sc
 /* Releases a scene's device memory; LFDPR_ESTATE while a live batch renders it. */
 int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id);
 
+/* Materials of the physically based mode (Sec. 3.3: the shader reads albedo,
+ * roughness, metallic and normal textures, each with its own LOD pair).  Three
+ * host arrays of n_tris texture ids into the scene's texture list: a
+ * tangent-space normal map (RGB = (n + 1)/2 * 255), a roughness map and a
+ * metallic map (both read from R).  The triangle's albedo stays tex_id.  All
+ * three NULL removes the materials.  Copied; synchronises the stream.
+ * LFDPR_EINVAL for an unknown scene, an id >= n_tex or only some arrays. */
+int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* normal_id,
+                              const uint16_t* roughness_id, const uint16_t* metallic_id);
+
+/* Splat shading (Sec. 3.3: shading while the views are rendered).
+ * LFDPR_SHADE_UNLIT (the default): the colour is the interpolated albedo of
+ * Eq. 9.  LFDPR_SHADE_PBR: Eq. 1 takes the largest of a triangle's four
+ * textures; each texture gets its LOD pair (Eqs. 6-7) and two mip fetches per
+ * point; per view the four are interpolated with the same tau (Eq. 9) and
+ * shaded at the cell centre with a Cook-Torrance BRDF (GGX distribution with
+ * alpha = roughness^2 (roughness at least 0.03), Smith-Schlick geometry with
+ * k = (roughness+1)^2/8, Schlick Fresnel with F0 = 0.04 (1-m) + albedo m,
+ * diffuse (1-F)(1-m) albedo/pi) under one directional light plus ambient, then
+ * tone mapped as sqrt(x/(1+x)) and rounded to 8 bits; alpha is the albedo's.
+ * light_dir is the camera-space unit vector towards the light (length within
+ * 1e-3 of 1); light_rgb and ambient_rgb lie in [0, 1e4].  Only single-frame
+ * rendering shades: batches return LFDPR_ESTATE while the mode is PBR. */
+typedef struct {
+  int32_t mode;                /* LFDPR_SHADE_* */
+  float light_dir[3];
+  float light_rgb[3];
+  float ambient_rgb[3];
+} lfdpr_shading;
+int lfdpr_set_shading(lfdpr_ctx* ctx, const lfdpr_shading* shading);
+
 /* Sets the rig and (re)allocates the per-view key buffer (8 B per pixel of
  * every rendered view, the 64-bit view buffer of Sec. 5.1) and the point
  * buffer (16 B per point).  Synchronous. */
@@ -146,7 +178,9 @@ int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* lens);
  *   views_rgba device, V*S*H*W uint32 (RGBA8);
  *   depth      device, V*S*H*W float, or NULL.
  * Asynchronous.  A point-capacity overflow is reported by lfdpr_get_stats
- * (the frame's views are then incomplete). */
+ * (the frame's views are then incomplete).  With LFDPR_SHADE_PBR the scene
+ * needs materials (LFDPR_ESTATE otherwise); the first such frame allocates
+ * 64 B per triangle and 16 B per point of material buffers (synchronous). */
 int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views_rgba, float* depth);
 
 /* Interleaves n_views views of W x H (device, [view][row][col] RGBA8) into the
@@ -168,6 +202,13 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* stats);
  * tri | flags<<28, (u16)i | (u16)j<<16, tv_min, tv_max) into dst (device,
  * room for cap points) and its length into *n_points (host).  Synchronises. */
 int lfdpr_copy_points(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points);
+
+/* Copies the last frame's per-point material words (device, 16 B per point in
+ * point order: normal-map fetch at LOD_min and at LOD_max (RGBA8), then
+ * rough_min | rough_max<<8 | metal_min<<16 | metal_max<<24, then 0) into dst
+ * (device, room for cap points) and the point count into *n_points (host).
+ * LFDPR_ESTATE when the last frame was not shaded physically.  Synchronises. */
+int lfdpr_copy_point_materials(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points);
 
 /* Copies the last frame's per-triangle point counts (device, uint32 per
  * triangle of the scene last rendered) into dst.  Synchronises. */

@@ -24,7 +24,8 @@ struct SceneDev {
   uint16_t* tex = nullptr;
   TexInfo* texinfo = nullptr;
   uint8_t* texels = nullptr;
-  int32_t batch_refs = 0;  // live batches rendering this scene
+  uint16_t* mat = nullptr;  // nt x (normal, roughness, metallic) texture ids, or null
+  int32_t batch_refs = 0;   // live batches rendering this scene
 };
 
 template <class T>
@@ -79,6 +80,14 @@ struct lfdpr_ctx {
   // single-frame item table (device) and its host copy
   Item* d_item1 = nullptr;
   Item h_item1{};
+  // shading: unlit albedo or physically based (material records and per-point
+  // material words allocated on first use)
+  lfdpr_shading shading{};
+  TriMat* d_tm = nullptr;
+  int64_t tm_cap = 0;
+  uint4* d_pmat = nullptr;
+  int64_t pmat_cap = 0;
+  bool last_pbr = false;
   // launch shape of the splat kernel and key layout (autotuned)
   int splat_blocks = 4096;
   int key_layout = 0;
@@ -116,6 +125,7 @@ void free_scene(SceneDev& s) {
   dfree(s.tex);
   dfree(s.texinfo);
   dfree(s.texels);
+  dfree(s.mat);
 }
 
 int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
@@ -307,6 +317,8 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_big);
   dfree(ctx->d_stats);
   dfree(ctx->d_item1);
+  dfree(ctx->d_tm);
+  dfree(ctx->d_pmat);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return LFDPR_OK;
@@ -380,6 +392,55 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
   HIPOK(hipStreamSynchronize(ctx->stream));
   free_scene(it->second);
   ctx->scenes.erase(it);
+  return LFDPR_OK;
+}
+
+int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* normal_id,
+                              const uint16_t* roughness_id, const uint16_t* metallic_id) {
+  if (!ctx) return LFDPR_EINVAL;
+  auto it = ctx->scenes.find(scene_id);
+  if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  SceneDev& s = it->second;
+  const int given = (normal_id != nullptr) + (roughness_id != nullptr) + (metallic_id != nullptr);
+  if (given != 0 && given != 3) return fail(ctx, LFDPR_EINVAL, "all three material arrays or none");
+  std::vector<uint16_t> m;
+  if (given == 3) {
+    m.resize((size_t)s.nt * 3);
+    for (int64_t t = 0; t < s.nt; ++t) {
+      const uint16_t ids[3] = {normal_id[t], roughness_id[t], metallic_id[t]};
+      for (int k = 0; k < 3; ++k) {
+        if (ids[k] >= s.ntex) return fail(ctx, LFDPR_EINVAL, "material texture id out of range");
+        m[(size_t)t * 3 + k] = ids[k];
+      }
+    }
+  }
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));  // earlier frames may still read the old table
+  dfree(s.mat);
+  if (given == 3) {
+    if (dalloc(s.mat, m.size()) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "material table");
+    HIPOK(hipMemcpy(s.mat, m.data(), m.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
+  return LFDPR_OK;
+}
+
+int lfdpr_set_shading(lfdpr_ctx* ctx, const lfdpr_shading* sh) {
+  if (!ctx || !sh) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (sh->mode != LFDPR_SHADE_UNLIT && sh->mode != LFDPR_SHADE_PBR) return fail(ctx, LFDPR_EINVAL, "shading mode");
+  if (sh->mode == LFDPR_SHADE_PBR) {
+    double len2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const float c[3] = {sh->light_dir[k], sh->light_rgb[k], sh->ambient_rgb[k]};
+      for (float x : c)
+        if (!std::isfinite(x)) return fail(ctx, LFDPR_EINVAL, "non-finite light");
+      if (!(sh->light_rgb[k] >= 0.0f && sh->light_rgb[k] <= 1e4f && sh->ambient_rgb[k] >= 0.0f &&
+            sh->ambient_rgb[k] <= 1e4f))
+        return fail(ctx, LFDPR_EINVAL, "light and ambient RGB must lie in [0, 1e4]");
+      len2 += (double)sh->light_dir[k] * sh->light_dir[k];
+    }
+    if (std::fabs(std::sqrt(len2) - 1.0) > 1e-3) return fail(ctx, LFDPR_EINVAL, "light direction is not a unit vector");
+  }
+  ctx->shading = *sh;
   return LFDPR_OK;
 }
 
@@ -479,9 +540,21 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
     if (!std::isfinite(model[k])) return fail(ctx, LFDPR_EINVAL, "non-finite model matrix");
   const SceneDev& s = it->second;
   if (ctx->dbgf && s.nt > ctx->dbg_cap) return fail(ctx, LFDPR_EINVAL, "debug record buffers smaller than the scene");
+  const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
+  if (pbr && s.nt > 0 && !s.mat) return fail(ctx, LFDPR_ESTATE, "physically based shading needs lfdpr_scene_set_materials");
   HIPOK(hipSetDevice(ctx->device));
   int rc = ensure_tri_buffers(ctx, s.nt);
   if (rc) return rc;
+  if (pbr && (ctx->tm_cap < ctx->tri_cap || ctx->pmat_cap != ctx->cap)) {
+    HIPOK(hipStreamSynchronize(ctx->stream));  // earlier frames may still read them
+    dfree(ctx->d_tm);
+    dfree(ctx->d_pmat);
+    ctx->tm_cap = ctx->pmat_cap = 0;
+    if (dalloc(ctx->d_tm, (size_t)ctx->tri_cap) != hipSuccess || dalloc(ctx->d_pmat, (size_t)ctx->cap) != hipSuccess)
+      return fail(ctx, LFDPR_ENOMEM, "material buffers");
+    ctx->tm_cap = ctx->tri_cap;
+    ctx->pmat_cap = ctx->cap;
+  }
   hipStream_t st = ctx->stream;
   Item one;
   std::memset(&one, 0, sizeof one);  // padding too: the table is compared bytewise
@@ -496,6 +569,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   one.rig = ctx->rig;
   one.keys = ctx->d_keys;
   one.key_layout = ctx->key_layout;
+  one.mat = pbr ? s.mat : nullptr;
   if (std::memcmp(&one, &ctx->h_item1, sizeof one) != 0) {
     HIPOK(hipStreamSynchronize(st));  // earlier frames may still read the table
     HIPOK(hipMemcpy(ctx->d_item1, &one, sizeof one, hipMemcpyHostToDevice));
@@ -515,6 +589,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   sa.dbgf = ctx->dbgf;
   sa.dbgi = ctx->dbgi;
   sa.stats = ctx->d_stats;
+  sa.tm = pbr ? ctx->d_tm : nullptr;
   hipEvent_t e0 = mark(ctx);
   launch_tri_setup(sa, st);
   hipEvent_t e1 = mark(ctx);
@@ -531,6 +606,8 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   ea.big = ctx->d_big;
   ea.n_big = ctx->d_stats + STAT_BIG;
   ea.cap = ctx->cap;
+  ea.tm = pbr ? ctx->d_tm : nullptr;
+  ea.pmat = pbr ? ctx->d_pmat : nullptr;
   launch_emit(ea, ctx->splat_blocks, st);
   hipEvent_t e3 = mark(ctx);
   SplatArgs pa{};
@@ -541,6 +618,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   pa.n_points = ctx->d_stats + STAT_TOTAL;
   pa.cap = ctx->cap;
   pa.rec = ctx->d_rec;
+  pa.tm = pbr ? ctx->d_tm : nullptr;
+  pa.pmat = pbr ? ctx->d_pmat : nullptr;
+  const lfdpr_shading& sh = ctx->shading;
+  pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
+                  sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
   launch_splat(pa, ctx->splat_blocks, st);
   hipEvent_t e4 = mark(ctx);
   launch_resolve(ctx->d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st);
@@ -552,6 +634,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   stage(ctx, 3, e3, e4);
   stage(ctx, 4, e4, e5);
   ctx->last_nt = s.nt;
+  ctx->last_pbr = pbr;
   return LFDPR_OK;
 }
 
@@ -619,6 +702,20 @@ int lfdpr_copy_points(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points)
   *n_points = (int64_t)total;
   if (n > cap) n = cap;
   if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_points, (size_t)n * sizeof(Point), hipMemcpyDeviceToDevice));
+  return LFDPR_OK;
+}
+
+int lfdpr_copy_point_materials(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points) {
+  if (!ctx || !dst || !n_points || cap < 0) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (!ctx->last_pbr) return fail(ctx, LFDPR_ESTATE, "the last frame was not rendered with physically based shading");
+  uint64_t total = 0;
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(hipMemcpy(&total, ctx->d_stats + STAT_TOTAL, 8, hipMemcpyDeviceToHost));
+  int64_t n = (int64_t)total < ctx->cap ? (int64_t)total : ctx->cap;
+  *n_points = (int64_t)total;
+  if (n > cap) n = cap;
+  if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_pmat, (size_t)n * sizeof(uint4), hipMemcpyDeviceToDevice));
   return LFDPR_OK;
 }
 
@@ -914,6 +1011,8 @@ int lfdpr_batch_use_graph(lfdpr_batch* b, int enable) {
 
 int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uint8_t* panels) {
   if (!b || !models || !views) return bfail(b, LFDPR_EINVAL, "null argument");
+  if (b->ctx->shading.mode != LFDPR_SHADE_UNLIT)
+    return bfail(b, LFDPR_ESTATE, "batches render unlit albedo: set LFDPR_SHADE_UNLIT on the context");
   if (panels && (!b->ctx->lens_set || b->table_rig.n_views < 1))
     return bfail(b, LFDPR_ESTATE, "lfdpr_set_lens on the context first");
   for (int k = 0; k < 12 * b->n; ++k)
@@ -970,6 +1069,8 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
 // workload and keeps the fastest; the results are returned per candidate.
 int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, lfdpr_tune_result* res) {
   if (!b || !models || !views || !res) return bfail(b, LFDPR_EINVAL, "null argument");
+  if (b->ctx->shading.mode != LFDPR_SHADE_UNLIT)
+    return bfail(b, LFDPR_ESTATE, "batches render unlit albedo: set LFDPR_SHADE_UNLIT on the context");
   static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
   const bool graph = b->use_graph;
   b->use_graph = false;

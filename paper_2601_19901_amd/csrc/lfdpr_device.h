@@ -52,6 +52,23 @@ struct TexInfo {
   int64_t off[16];  // byte offset of each level in the texel pool
 };
 
+// Per-triangle material record of the physically based mode (64 B): normal,
+// roughness and metallic textures with their LOD pairs (Eqs. 6-7, 1/256
+// level) and the tangent frame (T, B) of the texture mapping, camera space.
+struct alignas(16) TriMat {
+  int32_t texn, texr, texm, pad0;
+  int32_t kn0, kn1, kr0, kr1;
+  int32_t km0, km1;
+  float tx, ty;
+  float tz, bx, by, bz;
+};
+
+// One directional light (unit direction towards it, camera space), its RGB
+// radiance and the ambient RGB.
+struct Shading {
+  float lx, ly, lz, lr, lg, lb, ar, ag, ab;
+};
+
 struct Rig {
   int32_t n_views, W, H, mip;
   float fx, fy, cx, cy, rD, znear, fxfy;
@@ -251,6 +268,98 @@ LF_HD uint32_t trilinear(const uint8_t* pool, const TexInfo& ti, float u, float 
     r |= ((acc + (1u << 23)) >> 24) << (8 * c);
   }
   return r;
+}
+
+// ---------------------------------------------------------------- shading
+constexpr float kInv255 = 0x1.010102p-8f;     // binary32 nearest 1/255
+constexpr float kTwoInv255 = 0x1.010102p-7f;  // binary32 nearest 2/255 (= 2 kInv255 exactly)
+constexpr float kPiF = 0x1.921fb6p+1f;        // binary32 nearest pi
+constexpr float kInvPiF = 0x1.45f306p-2f;     // binary32 nearest 1/pi
+
+LF_HD F3 scale3(F3 a, float s) { return F3{a.x * s, a.y * s, a.z * s}; }
+
+// Tangent frame of a triangle's texture mapping: dP/du and dP/dv from the two
+// edges and their UV differences; T = dP/du without its normal component,
+// normalised; B = n x T, turned to the side of dP/dv.  Degenerate mappings
+// take the lattice axes (u, w).
+LF_HD void texture_frame(F3 e1, F3 e2, float du1, float dv1, float du2, float dv2, F3 n, F3 u, F3 w, F3& T,
+                         F3& B) {
+  const float det = du1 * dv2 - dv1 * du2;
+  F3 dpu = u, dpv = w;
+  if (det != 0.0f) {
+    const float rd = 1.0f / det;
+    dpu = F3{(e1.x * dv2 - e2.x * dv1) * rd, (e1.y * dv2 - e2.y * dv1) * rd, (e1.z * dv2 - e2.z * dv1) * rd};
+    dpv = F3{(e2.x * du1 - e1.x * du2) * rd, (e2.y * du1 - e1.y * du2) * rd, (e2.z * du1 - e1.z * du2) * rd};
+  }
+  const float along = dot3(n, dpu);
+  F3 t{dpu.x - n.x * along, dpu.y - n.y * along, dpu.z - n.z * along};
+  const float len = sqrtf(dot3(t, t));
+  if (len > 0.0f && !__builtin_isinf(len)) t = scale3(t, 1.0f / len);
+  else t = u;
+  F3 b{n.y * t.z - n.z * t.y, n.z * t.x - n.x * t.z, n.x * t.y - n.y * t.x};
+  if (dot3(b, dpv) < 0.0f) b = F3{-b.x, -b.y, -b.z};
+  T = t;
+  B = b;
+}
+
+// Unit vector along v, or `fallback` when v has no finite non-zero length.
+LF_HD F3 unit_or(F3 v, F3 fallback) {
+  const float len = sqrtf(dot3(v, v));
+  if (len > 0.0f && !__builtin_isinf(len)) return scale3(v, 1.0f / len);
+  return fallback;
+}
+
+// Physically based colour of a splat in the view whose eye sits at (b, 0, 0):
+// Cook-Torrance with a GGX distribution (alpha = roughness^2), Smith-Schlick
+// geometry (k = (r+1)^2/8), Schlick Fresnel (F0 = 0.04 (1-m) + albedo m), a
+// diffuse share (1-F)(1-m) albedo/pi, one directional light plus ambient,
+// tone mapped as sqrt(x/(1+x)).  Inputs: albedo, tangent-space normal (RGB =
+// (n+1)/2), roughness and metallic bytes, interpolated with tau (Eq. 9); the
+// surface point is the cell centre pc; alpha is the albedo's.
+LF_HD uint32_t shade_splat(const Shading& L, F3 ng, F3 T, F3 B, F3 pc, float b, uint32_t alb, uint32_t nrm,
+                           uint32_t rq, uint32_t mq) {
+  const float ar = (float)(alb & 255u) * kInv255;
+  const float ag = (float)((alb >> 8) & 255u) * kInv255;
+  const float ab = (float)((alb >> 16) & 255u) * kInv255;
+  const float tr = (float)(nrm & 255u) * kTwoInv255 - 1.0f;
+  const float tg = (float)((nrm >> 8) & 255u) * kTwoInv255 - 1.0f;
+  const float tb = (float)((nrm >> 16) & 255u) * kTwoInv255 - 1.0f;
+  const F3 n = unit_or(F3{(tr * T.x + tg * B.x) + tb * ng.x, (tr * T.y + tg * B.y) + tb * ng.y,
+                          (tr * T.z + tg * B.z) + tb * ng.z}, ng);
+  const F3 v = unit_or(F3{b - pc.x, 0.0f - pc.y, 0.0f - pc.z}, F3{0.0f, 0.0f, -1.0f});
+  const F3 l{L.lx, L.ly, L.lz};
+  const F3 h = unit_or(F3{l.x + v.x, l.y + v.y, l.z + v.z}, n);
+  float nl = dot3(n, l), nv = dot3(n, v), nh = dot3(n, h), vh = dot3(v, h);
+  nl = nl > 0.0f ? nl : 0.0f;
+  nv = nv > 0.0f ? nv : 0.0f;
+  nh = nh > 0.0f ? nh : 0.0f;
+  vh = vh > 0.0f ? vh : 0.0f;
+  float r = (float)rq * kInv255;
+  r = r > 0.03f ? r : 0.03f;
+  const float m = (float)mq * kInv255;
+  const float alpha = r * r, a2 = alpha * alpha;
+  const float dd = (nh * nh) * (a2 - 1.0f) + 1.0f;
+  const float D = a2 / ((kPiF * dd) * dd);
+  const float k = ((r + 1.0f) * (r + 1.0f)) * 0.125f;
+  const float G = (nl / (nl * (1.0f - k) + k)) * (nv / (nv * (1.0f - k) + k));
+  const float c1 = 1.0f - vh;
+  const float c5 = ((c1 * c1) * (c1 * c1)) * c1;
+  const float spec = (D * G) / (((4.0f * nl) * nv) + 1e-4f);
+  const float alb3[3] = {ar, ag, ab}, rad[3] = {L.lr, L.lg, L.lb}, amb[3] = {L.ar, L.ag, L.ab};
+  uint32_t out = alb & 0xFF000000u;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float F0 = 0.04f * (1.0f - m) + alb3[c] * m;
+    const float F = F0 + (1.0f - F0) * c5;
+    const float kd = (1.0f - F) * (1.0f - m);
+    const float f = (kd * alb3[c]) * kInvPiF + F * spec;
+    const float lo = f * (rad[c] * nl) + amb[c] * alb3[c];
+    const float t = lo / (1.0f + lo);
+    const float y = floorf(sqrtf(t) * 255.0f + 0.5f);
+    const uint32_t q = y >= 255.0f ? 255u : (y > 0.0f ? (uint32_t)y : 0u);
+    out |= q << (8 * c);
+  }
+  return out;
 }
 
 }  // namespace lfdpr

@@ -23,6 +23,7 @@ struct Item {
   int32_t key_layout;  // 0: keys [view][y][x]; 1: keys [y][view][x] (views of a row adjacent)
   Rig rig;
   uint64_t* keys;    // rig.n_views * H * W keys of this item
+  const uint16_t* mat;  // physically based mode: nt x (normal, roughness, metallic) texture ids; else null
 };
 
 __device__ __forceinline__ int find_item(const Item* items, int n, int64_t t) {
@@ -47,6 +48,7 @@ struct SetupArgs {
   float* dbgf;     // optional nt*8
   int32_t* dbgi;   // optional nt*8
   uint64_t* stats;
+  TriMat* tm;      // physically based mode: per-triangle material records; else null
 };
 
 struct EmitArgs {
@@ -60,6 +62,8 @@ struct EmitArgs {
   Point* points;
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
+  const TriMat* tm;          // physically based mode: material records, and
+  uint4* pmat;               // per point normal min/max and roughness/metallic bytes; else null
 };
 
 struct SplatArgs {
@@ -70,6 +74,9 @@ struct SplatArgs {
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
   const TriRec* rec;
+  const TriMat* tm;          // physically based mode (single item only); else null
+  const uint4* pmat;
+  Shading sh;
 };
 
 struct InterleaveArgs {

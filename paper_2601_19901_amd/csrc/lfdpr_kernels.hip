@@ -150,6 +150,14 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       // texture-based sampling, Eqs. 1-3
       const int tex = it.tex[lt];
       const TexInfo& ti = it.texinfo[tex];
+      // physically based mode: three more textures; Eq. 1 takes the largest
+      const bool pbr = a.tm != nullptr;
+      int32_t texk[4] = {tex, tex, tex, tex};
+      if (pbr) {
+        texk[1] = it.mat[lt * 3];
+        texk[2] = it.mat[lt * 3 + 1];
+        texk[3] = it.mat[lt * 3 + 2];
+      }
       float uv0u = it.uv[(int64_t)vi[0] * 2], uv0v = it.uv[(int64_t)vi[0] * 2 + 1];
       float du1 = it.uv[(int64_t)vi[1] * 2] - uv0u, dv1 = it.uv[(int64_t)vi[1] * 2 + 1] - uv0v;
       float du2 = it.uv[(int64_t)vi[2] * 2] - uv0u, dv2 = it.uv[(int64_t)vi[2] * 2 + 1] - uv0v;
@@ -157,6 +165,13 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       float Aws = 0.5f * nl;
       float Xt = (float)ti.size;
       float ntex = (Ats * Xt) * Xt;
+      if (pbr) {
+        for (int k = 1; k < 4; ++k) {
+          const float Xk = (float)it.texinfo[texk[k]].size;
+          const float nk = (Ats * Xk) * Xk;
+          ntex = nk > ntex ? nk : ntex;
+        }
+      }
       if (ntex > 0.0f) {
         float size_uv = Aws / ntex;
         if (size_uv > size_xy) {
@@ -185,6 +200,28 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
         kmax = lod_q8(a.lod_thr, (R.smax * Xt) * Xt);
         kmin = kmin < 0 ? 0 : (kmin > top ? top : kmin);
         kmax = kmax < 0 ? 0 : (kmax > top ? top : kmax);
+      }
+      TriMat M{};
+      if (pbr) {
+        // Eqs. 6-7 for each material texture at its own size and level count
+        int32_t kq[6] = {0, 0, 0, 0, 0, 0};
+        if (rg.mip) {
+          for (int k = 1; k < 4; ++k) {
+            const TexInfo& tk = it.texinfo[texk[k]];
+            const float Xk = (float)tk.size;
+            const int32_t top = 256 * (tk.levels - 1);
+            int32_t k0 = lod_q8(a.lod_thr, (R.smin * Xk) * Xk);
+            int32_t k1 = lod_q8(a.lod_thr, (R.smax * Xk) * Xk);
+            kq[2 * k - 2] = k0 < 0 ? 0 : (k0 > top ? top : k0);
+            kq[2 * k - 1] = k1 < 0 ? 0 : (k1 > top ? top : k1);
+          }
+        }
+        F3 Tf, Bf;
+        texture_frame(e1, e2, du1, dv1, du2, dv2, F3{R.nx, R.ny, R.nz}, F3{R.ux, R.uy, R.uz},
+                      F3{R.wx, R.wy, R.wz}, Tf, Bf);
+        M.texn = texk[1]; M.texr = texk[2]; M.texm = texk[3];
+        M.kn0 = kq[0]; M.kn1 = kq[1]; M.kr0 = kq[2]; M.kr1 = kq[3]; M.km0 = kq[4]; M.km1 = kq[5];
+        M.tx = Tf.x; M.ty = Tf.y; M.tz = Tf.z; M.bx = Bf.x; M.by = Bf.y; M.bz = Bf.z;
       }
       // sample lattice, vertex 0 at the centre of cell (0,0)
       bool ovf = false;
@@ -240,6 +277,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
         E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item;
         E.jlo = (int32_t)jfirst; E.jhi = (int32_t)jlast;
         a.em[t] = E;
+        if (pbr) a.tm[t] = M;
       }
     }
     a.counts[t] = cnt;
@@ -421,6 +459,24 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
     tv.x = trilinear(it.texels, ti, u, v, E.kmin);
     tv.y = E.kmax == E.kmin ? tv.x : trilinear(it.texels, ti, u, v, E.kmax);
     *reinterpret_cast<uint2*>(&a.points[p].tvmin) = tv;
+    if (a.tm) {
+      // physically based mode: normal map (RGBA8) and the R bytes of the
+      // roughness and metallic maps, each at its own LOD pair
+      const TriMat& M = a.tm[t];
+      const TexInfo& tn = it.texinfo[M.texn];
+      const TexInfo& tr = it.texinfo[M.texr];
+      const TexInfo& tm = it.texinfo[M.texm];
+      uint4 pm;
+      pm.x = trilinear(it.texels, tn, u, v, M.kn0);
+      pm.y = M.kn1 == M.kn0 ? pm.x : trilinear(it.texels, tn, u, v, M.kn1);
+      const uint32_t r0 = trilinear(it.texels, tr, u, v, M.kr0) & 255u;
+      const uint32_t r1 = M.kr1 == M.kr0 ? r0 : trilinear(it.texels, tr, u, v, M.kr1) & 255u;
+      const uint32_t m0 = trilinear(it.texels, tm, u, v, M.km0) & 255u;
+      const uint32_t m1 = M.km1 == M.km0 ? m0 : trilinear(it.texels, tm, u, v, M.km1) & 255u;
+      pm.z = r0 | (r1 << 8) | (m0 << 16) | (m1 << 24);
+      pm.w = 0u;
+      a.pmat[p] = pm;
+    }
   }
 }
 
@@ -457,8 +513,11 @@ __device__ __forceinline__ float uniform_f32(float x) {
 }
 
 // One point against every view of its item's rig; `item` is wave-uniform.
+// kPBR: the colour is shaded (material record tm[tri], point words pm).
+template <bool kPBR>
 __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, const TriRec& T, uint32_t flags,
-                                            int32_t i, int32_t j, const float* tx, const float* ty) {
+                                            int32_t i, int32_t j, const float* tx, const float* ty,
+                                            const SplatArgs& a, uint64_t p) {
   const int64_t vpx = (int64_t)item.rig.W * item.rig.H;
   const int32_t H8 = 256 * item.rig.H, W8 = 256 * item.rig.W;
   const Rig& rg = item.rig;
@@ -505,6 +564,17 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   const float cs = (float)i / T.sx, ct = (float)j / T.sy;
   const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
   const float Zc3 = (Zc * Zc) * Zc;
+  F3 pc{0.0f, 0.0f, Zc}, Tf{0.0f, 0.0f, 0.0f}, Bf{0.0f, 0.0f, 0.0f};
+  uint4 pm{0u, 0u, 0u, 0u};
+  if constexpr (kPBR) {
+    // cell centre in camera space, tangent frame, material bytes of the point
+    pc.x = (T.p0x + cs * T.ux) + ct * T.wx;
+    pc.y = (T.p0y + cs * T.uy) + ct * T.wy;
+    const TriMat& M = a.tm[pt.tri_flags & 0x0FFFFFFFu];
+    Tf = F3{M.tx, M.ty, M.tz};
+    Bf = F3{M.bx, M.by, M.bz};
+    pm = a.pmat[p];
+  }
   const float Acell = 1.0f / (T.sx * T.sy);
   const float suv = Acell * T.ruv;
   const float fi0 = (float)i, fi1 = (float)(i + 1), fj0 = (float)j, fj1 = (float)(j + 1);
@@ -555,8 +625,18 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
     int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
     tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
     const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
-    const uint32_t col = (((lo02 * wa + hi02 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
-                         ((((lo13 * wa + hi13 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8);
+    uint32_t col = (((lo02 * wa + hi02 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
+                   ((((lo13 * wa + hi13 * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8);
+    if constexpr (kPBR) {
+      // the normal map and the roughness / metallic bytes take the same tau
+      auto lerp_even = [&](uint32_t lo, uint32_t hi) {  // bytes 0 and 2 of each word
+        return (((lo & 0x00FF00FFu) * wa + (hi & 0x00FF00FFu) * wz + 0x00800080u) >> 8) & 0x00FF00FFu;
+      };
+      const uint32_t nrm = lerp_even(pm.x, pm.y) | (lerp_even(pm.x >> 8, pm.y >> 8) << 8);
+      const uint32_t rq = ((pm.z & 255u) * wa + ((pm.z >> 8) & 255u) * wz + 128u) >> 8;
+      const uint32_t mq = (((pm.z >> 16) & 255u) * wa + (pm.z >> 24) * wz + 128u) >> 8;
+      col = shade_splat(a.sh, F3{T.nx, T.ny, T.nz}, Tf, Bf, pc, b, col, nrm, rq, mq);
+    }
     const float ks = uniform_f32(rg.kshift[r]);
     const float cu = T.ux * (b - T.p0x) - T.cu0;
     const float cw = T.wx * (b - T.p0x) - T.cw0;
@@ -606,9 +686,10 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
 }
 
 // kMulti: points of several items (a batch); otherwise every point belongs to
-// items[0] and the item is read once.
-template <bool kMulti>
+// items[0] and the item is read once.  kPBR (single item): shaded colours.
+template <bool kMulti, bool kPBR>
 __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
+  static_assert(!(kMulti && kPBR), "physically based shading renders single frames");
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
   const Rig& trg = a.table_rig;
   float* tx = ray_tab;
@@ -625,7 +706,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
     const TriRec T = a.rec[tri];
     if (!kMulti) {
-      splat_point(it0, pt, T, flags, i, j, tx, ty);
+      splat_point<kPBR>(it0, pt, T, flags, i, j, tx, ty, a, p);
       continue;
     }
     // points of one wave nearly always belong to one item: take the items one at
@@ -638,7 +719,7 @@ __global__ void __launch_bounds__(256) k_splat(SplatArgs a) {
       const bool mine = my == cur;
       if (mine) {
         const Item it = load_uniform(a.items + cur);
-        splat_point(it, pt, T, flags, i, j, tx, ty);
+        splat_point<false>(it, pt, T, flags, i, j, tx, ty, a, p);
       }
       todo &= ~__builtin_amdgcn_ballot_w64(mine);
     }
@@ -772,9 +853,11 @@ void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
   size_t lds = sizeof(float) * (size_t)(a.table_rig.W + a.table_rig.H);
   if (a.n_items > 1)
-    k_splat<true><<<grid_blocks, 256, lds, s>>>(a);
+    k_splat<true, false><<<grid_blocks, 256, lds, s>>>(a);
+  else if (a.tm)
+    k_splat<false, true><<<grid_blocks, 256, lds, s>>>(a);
   else
-    k_splat<false><<<grid_blocks, 256, lds, s>>>(a);
+    k_splat<false, false><<<grid_blocks, 256, lds, s>>>(a);
 }
 
 void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,

@@ -44,6 +44,11 @@ class LensParams(C.Structure):
                 ("offset", C.c_double), ("mode", C.c_int32), ("taps", (C.c_int64 * 3) * 8)]
 
 
+class ShadingParams(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3),
+                ("ambient_rgb", C.c_float * 3)]
+
+
 class TuneEntry(C.Structure):
     _fields_ = [("splat_blocks", C.c_int32), ("key_layout", C.c_int32), ("ms", C.c_float)]
 
@@ -105,6 +110,9 @@ def signatures():
         "lfdpr_last_error": ([vp], C.c_char_p),
         "lfdpr_scene_upload": ([vp, p(SceneDesc), p(i32)], C.c_int),
         "lfdpr_scene_free": ([vp, i32], C.c_int),
+        "lfdpr_scene_set_materials": ([vp, i32, vp, vp, vp], C.c_int),
+        "lfdpr_set_shading": ([vp, p(ShadingParams)], C.c_int),
+        "lfdpr_copy_point_materials": ([vp, vp, i64, p(i64)], C.c_int),
         "lfdpr_set_views": ([vp, p(ViewParams)], C.c_int),
         "lfdpr_set_lens": ([vp, p(LensParams)], C.c_int),
         "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
@@ -229,7 +237,23 @@ class Renderer:
                       _ptr(tex) if tex.size else None, len(texs), _ptr(sizes), C.cast(ptrs, C.c_void_p))
         sid = C.c_int32()
         self._check(lib().lfdpr_scene_upload(self.h, C.byref(d), C.byref(sid)))
+        mats = getattr(scene, "materials", None)
+        if mats is not None:
+            m = np.ascontiguousarray(mats, np.uint16).reshape(-1, 3)
+            cols = [np.ascontiguousarray(m[:, k]) for k in range(3)]
+            self._check(lib().lfdpr_scene_set_materials(self.h, sid.value, *[_ptr(c) for c in cols]))
         return sid.value
+
+    def set_shading(self, shading):
+        """Splat shading (scenes.Shading, or None for unlit albedo)."""
+        sp = ShadingParams()
+        if shading is not None and int(shading.mode) != 0:
+            sp.mode = int(shading.mode)
+            for k in range(3):
+                sp.light_dir[k] = float(np.float32(shading.light_dir[k]))
+                sp.light_rgb[k] = float(np.float32(shading.light_rgb[k]))
+                sp.ambient_rgb[k] = float(np.float32(shading.ambient_rgb[k]))
+        self._check(lib().lfdpr_set_shading(self.h, C.byref(sp)))
 
     def free_scene(self, sid: int):
         self._check(lib().lfdpr_scene_free(self.h, sid))
@@ -320,6 +344,17 @@ class Renderer:
         return dict(tri=tri, flags=(a[:, 0] >> 28).astype(np.uint8), i=(a[:, 1] & 0xFFFF).astype(np.uint16).view(np.int16),
                     j=(a[:, 1] >> 16).astype(np.uint16).view(np.int16), tvmin=a[:, 2].copy(), tvmax=a[:, 3].copy(),
                     n=int(got.value))
+
+    def point_materials(self) -> dict:
+        """Per-point material words of the last physically shaded frame."""
+        torch = self._torch
+        s = self.stats(allow_overflow=True)
+        n = min(s["points"], s["capacity"])
+        buf = torch.empty((max(n, 1), 4), dtype=torch.int32, device=f"cuda:{self.device}")
+        got = C.c_int64()
+        self._check(lib().lfdpr_copy_point_materials(self.h, _ptr(buf), n, C.byref(got)))
+        a = buf[:n].cpu().numpy().view(np.uint32)
+        return dict(nmin=a[:, 0].copy(), nmax=a[:, 1].copy(), rm=a[:, 2].copy(), n=int(got.value))
 
     def counts(self, nt: int) -> np.ndarray:
         torch = self._torch

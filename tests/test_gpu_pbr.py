@@ -1,0 +1,122 @@
+"""Physically based splat shading on the GPU (through the C ABI) against the
+CPU oracle.
+
+Bar: everything bit-exact -- point counts, set-up records, the point buffer
+with the albedo fetches, the per-point normal / roughness / metallic words,
+shaded views and depth -- on the tiny and small display scenes and on the
+full display-size scene with PBR materials in the launch configuration the
+benchmark times.  Also: shading state changes and the refusals the ABI
+documents (no materials, batches, bad light)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_19901_amd import scenes
+from test_gpu_parity import _log, assert_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pbr_parity(w, frame, label):
+    from paper_2601_19901_amd import lfdpr
+    _log(f"[{label}] {w.scene.n_tris} tris, {len(w.scene.textures)} textures, {w.views.V * w.views.S} views "
+         f"{w.views.W}x{w.views.H}, frame {frame}")
+    o = O.render(w.scene, w.views, w.model(frame), shading=w.shading)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_shading(w.shading)
+    g = run_gpu(R, sid, w, w.model(frame), w.scene.n_tris)
+    pm = R.point_materials()
+    assert pm["n"] == o["n_points"]
+    for k in ("nmin", "nmax", "rm"):
+        np.testing.assert_array_equal(pm[k], o["points"][k], err_msg=f"{label}: points.{k}")
+    assert_parity(g, o, w.scene.n_tris, label)
+    return R, sid, g, o
+
+
+@pytest.mark.parametrize("frame", [0, 137])
+def test_pbr_tiny_parity(torch_cuda, frame):
+    _pbr_parity(scenes.with_pbr(scenes.tiny()), frame, f"tiny-pbr f{frame}")
+
+
+@pytest.mark.parametrize("seed,frame,mip", [(7, 0, True), (8, 40, False)])
+def test_pbr_small_display_parity(torch_cuda, seed, frame, mip):
+    w = scenes.with_pbr(scenes.small_display(seed=seed), seed=seed)
+    w.views.mip = mip
+    _pbr_parity(w, frame, f"small-pbr s{seed} f{frame} mip{int(mip)}")
+
+
+def test_pbr_display_size_parity(torch_cuda):
+    """Display-size scene (999,168 triangles, 48 views of 512^2) with four
+    material sets (normal maps up to 4096^2): everything bit-exact, and the
+    panel interleaved from the shaded views."""
+    torch = torch_cuda
+    _log("generating display-size PBR scene")
+    w = scenes.with_pbr(scenes.display())
+    R, sid, g, o = _pbr_parity(w, 17, "display-pbr")
+    R.set_lens(w.lens)
+    panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    R.reconstruct(g["views_t"], panel)
+    np.testing.assert_array_equal(panel.cpu().numpy(), O.interleave(o["rgba"], w.lens))
+
+
+def test_pbr_state_and_refusals(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    base = scenes.tiny(V=4, size=64)
+    w = scenes.with_pbr(base)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    plain = R.upload_scene(base.scene)
+    R.set_views(w.views)
+    views = torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda")
+    # a PBR frame, then unlit again: the unlit frame equals the unlit oracle
+    R.set_shading(w.shading)
+    R.render_frame(sid, w.model(1), views)
+    o = O.render(w.scene, w.views, w.model(1), shading=w.shading)
+    np.testing.assert_array_equal(views.cpu().numpy().view(np.uint32), o["rgba"])
+    R.set_shading(None)
+    R.render_frame(sid, w.model(1), views)
+    u = O.render(w.scene, w.views, w.model(1))
+    np.testing.assert_array_equal(views.cpu().numpy().view(np.uint32), u["rgba"])
+    with pytest.raises(lfdpr.LfdprError) as e:      # last frame was unlit
+        R.point_materials()
+    assert e.value.code == lfdpr.LFDPR_ESTATE
+    # PBR on a scene without materials
+    R.set_shading(w.shading)
+    with pytest.raises(lfdpr.LfdprError) as e:
+        R.render_frame(plain, w.model(1), views)
+    assert e.value.code == lfdpr.LFDPR_ESTATE
+    # a light direction that is not a unit vector, a negative light
+    bad = scenes.Shading(scenes.SHADE_PBR, (0.0, 0.0, -2.0), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    with pytest.raises(lfdpr.LfdprError) as e:
+        R.set_shading(bad)
+    assert e.value.code == lfdpr.LFDPR_EINVAL
+    neg = scenes.Shading(scenes.SHADE_PBR, (0.0, 0.0, -1.0), (-1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    with pytest.raises(lfdpr.LfdprError) as e:
+        R.set_shading(neg)
+    assert e.value.code == lfdpr.LFDPR_EINVAL
+    # batches render unlit only
+    b = lfdpr.Batch(R, [sid], [w.views])
+    bv = b.alloc_views()
+    with pytest.raises(lfdpr.LfdprError) as e:
+        b.render(w.model(1)[None], bv)
+    assert e.value.code == lfdpr.LFDPR_ESTATE
+    R.set_shading(None)
+    b.render(w.model(1)[None], bv)
+    np.testing.assert_array_equal(bv[0].cpu().numpy().view(np.uint32), u["rgba"])
+    b.close()
+    # the failed calls left the context usable: a PBR frame is still bit-exact
+    R.set_shading(w.shading)
+    R.render_frame(sid, w.model(1), views)
+    np.testing.assert_array_equal(views.cpu().numpy().view(np.uint32), o["rgba"])
+    R.close()
