@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
     const int item = find_item(a.items, a.n_items, t);
     const Item& it = a.items[item];
     const int64_t lt = t - it.tri_base;
-    const Rig& rg = it.rig;
+    const Rig rg = it.rig;  // in registers: the view loop reads it every iteration
     const float* m = a.models ? a.models[item].m : a.model.m;
     float P[3][3];
     bool ok = true;
@@ -106,8 +106,11 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
     int nact = 0;
     float lxmin = INFINITY, lymin = INFINITY, Amin = INFINITY, admin = INFINITY, admax = 0.0f;
     if (ok) {
+      // the next view's eye offset is fetched one iteration ahead
+      float b_next = rg.eye[0];
       for (int r = 0; r < rg.n_views; ++r) {
-        float b = rg.eye[r];
+        const float b = b_next;
+        if (r + 1 < rg.n_views) b_next = rg.eye[r + 1];
         int32_t qx[3], qy[3];
         if (!view_active(rg, R, b, qx, qy)) continue;
         ++nact;
@@ -508,6 +511,13 @@ __device__ __forceinline__ void key_min(uint64_t* p, uint64_t v) {
   __hip_atomic_fetch_min((global_u64*)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Element i (wave-uniform) of a table that no kernel of the launch writes, as a
+// scalar-cache read straight into a scalar register.
+__device__ __forceinline__ float table_f32(const float* p, int i) {
+  typedef const __attribute__((address_space(4))) float const_f32;
+  return ((const_f32*)p)[i];
+}
+
 __device__ __forceinline__ float uniform_f32(float x) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
@@ -581,8 +591,10 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   const bool oilo = flags & F_ILO, oihi = flags & F_IHI, ojlo = flags & F_JLO, ojhi = flags & F_JHI;
   const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
   const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
+  float b_next = table_f32(rg.eye, 0);  // the next view's eye offset, one iteration ahead
   for (int r = 0; r < rg.n_views; ++r) {
-    const float b = uniform_f32(rg.eye[r]);
+    const float b = b_next;
+    if (r + 1 < rg.n_views) b_next = table_f32(rg.eye, r + 1);
     const float delta = T.h - T.nx * b;
     if (!(delta < 0.0f)) continue;
     // splat box columns first: empty for about a third of the (point, view) pairs
@@ -637,7 +649,7 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
       const uint32_t mq = (((pm.z >> 16) & 255u) * wa + (pm.z >> 24) * wz + 128u) >> 8;
       col = shade_splat(a.sh, F3{T.nx, T.ny, T.nz}, Tf, Bf, pc, b, col, nrm, rq, mq);
     }
-    const float ks = uniform_f32(rg.kshift[r]);
+    const float ks = table_f32(rg.kshift, r);
     const float cu = T.ux * (b - T.p0x) - T.cu0;
     const float cw = T.wx * (b - T.p0x) - T.cw0;
     // edge functions with the tie rule folded in as +0.5 (E integer: E+0.5 > 0 <=> E >= 0)
