@@ -135,6 +135,7 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     R.set_views(w.views, point_capacity=(48 << 20) if kind != "display-1M" else 0)
     R.set_lens(lens)
     R.set_shading(w.shading)
+    R.set_frames_in_flight(args.frames_in_flight)
     views, _ = R.alloc_views()
     filtered = (torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0")
                 if kind == "display-4M-ss4" else None)
@@ -162,6 +163,16 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     st_avg = stage_avg(R)
     R.timing(False)
     wall_ms = (t1 - t0) * 1e3 / args.steps
+    serial_ms = None
+    if args.frames_in_flight > 1:
+        # the same frames with one frame in flight, for comparison
+        R.set_frames_in_flight(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            frame(args.warmup + k)
+        torch.cuda.synchronize()
+        serial_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # the same frames again, untimed, for their statistics (deterministic)
     pv = pts = act = 0
@@ -208,6 +219,8 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
                    "triangles": w.scene.n_tris, "recon": recon},
         "frame_ms": round(wall_ms, 4),
         "frames_per_s": round(1e3 / wall_ms, 2),
+        "frames_in_flight": args.frames_in_flight,
+        "frame_ms_one_in_flight": round(serial_ms if serial_ms is not None else wall_ms, 4),
         "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
         "active_tris_per_frame": int(act / nfr),
         "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
@@ -365,6 +378,8 @@ def main():
                                            "display-1M-spatial2x", "display-1M-pbr", "batch16", "learned-display"),
                     default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--frames-in-flight", type=int, choices=(1, 2), default=2,
+                    help="display workloads: frames whose point generation overlaps the previous splat")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")

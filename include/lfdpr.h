@@ -222,6 +222,22 @@ int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n);
  * i = {lattice s1, t1, s2, t2 (Q8), LOD_min, LOD_max (1/256), active, overflow}. */
 int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* dst_f, int32_t* dst_i, int64_t n_tris);
 
+/* Frames in flight: 1 (the default) or 2.  With 2, render_frame runs the
+ * frame's point generation (set-up, scan, emission, mip fetches) on a stream
+ * of the context's own, into a second set of per-frame buffers, while the
+ * previous frame's splat runs on the context's stream; the splat and the
+ * resolve of each frame stay on the context's stream, ordered after that
+ * frame's point generation, so the views are complete when the context's
+ * stream reaches them (as with 1).  Point generation reads only the scene,
+ * the model matrix (passed by value) and the rig, and does not wait for work
+ * the caller enqueued on the context's stream; it waits for the splat that
+ * last read its buffers.  Statistics, copies and debug records refer to the
+ * last frame as before.  A render_frame enqueued while a stream is being
+ * captured into a hipGraph needs 1.  The second set of buffers is allocated
+ * on first use (per-triangle records, point buffer, statistics).
+ * Synchronises both streams. */
+int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n);
+
 /* Stage timing with HIP events recorded on the context's stream.
  * lfdpr_timing(ctx, 1) clears and starts recording; every following
  * render_frame / reconstruct / angular_filter records one event pair per

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,30 @@ struct lfdpr_ctx {
   uint4* d_pmat = nullptr;
   int64_t pmat_cap = 0;
   bool last_pbr = false;
+  int64_t points_alloc = 0;  // points the current d_points holds
+  // Frames in flight (lfdpr_set_frames_in_flight).  With 2, a frame's point
+  // generation runs on `side` into the second set of per-frame buffers while
+  // the previous frame splats on `stream`; the sets are swapped with the
+  // fields above at every frame, so the fields always hold the last frame's.
+  int frames_in_flight = 1;
+  hipStream_t side = nullptr;
+  int slot = 0;  // which set the fields hold
+  hipEvent_t ev_emitted[2] = {nullptr, nullptr}, ev_splatted[2] = {nullptr, nullptr};
+  bool splatted_pending[2] = {false, false};
+  struct FrameBufs {
+    int64_t points_alloc = 0, tri_cap = 0, tm_cap = 0, pmat_cap = 0, last_nt = 0;
+    Point* d_points = nullptr;
+    uint32_t* d_counts = nullptr;
+    uint64_t* d_offsets = nullptr;
+    TriRec* d_rec = nullptr;
+    TriEmit* d_em = nullptr;
+    uint64_t* d_tiles = nullptr;
+    uint32_t* d_big = nullptr;
+    uint64_t* d_stats = nullptr;
+    TriMat* d_tm = nullptr;
+    uint4* d_pmat = nullptr;
+    bool last_pbr = false;
+  } other;
   // launch shape of the splat kernel and key layout (autotuned)
   int splat_blocks = 4096;
   int key_layout = 0;
@@ -128,8 +153,70 @@ void free_scene(SceneDev& s) {
   dfree(s.mat);
 }
 
+// Waits for everything the context enqueued, on its stream and its side stream.
+hipError_t sync_all(lfdpr_ctx* ctx) {
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess && ctx->side) e = hipStreamSynchronize(ctx->side);
+  return e;
+}
+
+// Exchanges the per-frame buffers held in the context's fields with the other set.
+void swap_frame_buffers(lfdpr_ctx* ctx) {
+  auto& o = ctx->other;
+  std::swap(ctx->points_alloc, o.points_alloc);
+  std::swap(ctx->tri_cap, o.tri_cap);
+  std::swap(ctx->tm_cap, o.tm_cap);
+  std::swap(ctx->pmat_cap, o.pmat_cap);
+  std::swap(ctx->last_nt, o.last_nt);
+  std::swap(ctx->d_points, o.d_points);
+  std::swap(ctx->d_counts, o.d_counts);
+  std::swap(ctx->d_offsets, o.d_offsets);
+  std::swap(ctx->d_rec, o.d_rec);
+  std::swap(ctx->d_em, o.d_em);
+  std::swap(ctx->d_tiles, o.d_tiles);
+  std::swap(ctx->d_big, o.d_big);
+  std::swap(ctx->d_stats, o.d_stats);
+  std::swap(ctx->d_tm, o.d_tm);
+  std::swap(ctx->d_pmat, o.d_pmat);
+  std::swap(ctx->last_pbr, o.last_pbr);
+  ctx->slot ^= 1;
+}
+
+int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt);
+
+// Per-frame buffers of the set in the context's fields, sized for a frame of
+// nt triangles (material buffers only for physically based shading).
+int prepare_frame_buffers(lfdpr_ctx* ctx, int64_t nt, bool pbr) {
+  int rc = ensure_tri_buffers(ctx, nt);
+  if (rc) return rc;
+  if (!ctx->d_points || ctx->points_alloc != ctx->cap) {
+    if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
+    dfree(ctx->d_points);
+    ctx->points_alloc = 0;
+    if (dalloc(ctx->d_points, (size_t)ctx->cap) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "point buffer");
+    ctx->points_alloc = ctx->cap;
+  }
+  if (!ctx->d_stats) {
+    if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "statistics");
+    if (hipMemset(ctx->d_stats, 0, STAT_SLOTS * sizeof(uint64_t)) != hipSuccess)
+      return fail(ctx, LFDPR_EDEVICE, "clearing statistics");
+  }
+  if (pbr && (ctx->tm_cap < ctx->tri_cap || ctx->pmat_cap != ctx->cap)) {
+    if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
+    dfree(ctx->d_tm);
+    dfree(ctx->d_pmat);
+    ctx->tm_cap = ctx->pmat_cap = 0;
+    if (dalloc(ctx->d_tm, (size_t)ctx->tri_cap) != hipSuccess || dalloc(ctx->d_pmat, (size_t)ctx->cap) != hipSuccess)
+      return fail(ctx, LFDPR_ENOMEM, "material buffers");
+    ctx->tm_cap = ctx->tri_cap;
+    ctx->pmat_cap = ctx->cap;
+  }
+  return LFDPR_OK;
+}
+
 int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   if (nt <= ctx->tri_cap && ctx->d_counts) return LFDPR_OK;
+  if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
   int64_t n = nt > 1024 ? nt : 1024;
   dfree(ctx->d_counts);
   dfree(ctx->d_offsets);
@@ -299,8 +386,26 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   if (!ctx) return LFDPR_OK;
   if (ctx->live_children > 0) return fail(ctx, LFDPR_ESTATE, "destroy the context's batches and networks first");
   (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->stream);
+  (void)sync_all(ctx);
   for (auto& kv : ctx->scenes) free_scene(kv.second);
+  {
+    auto& o = ctx->other;
+    dfree(o.d_points);
+    dfree(o.d_counts);
+    dfree(o.d_offsets);
+    dfree(o.d_rec);
+    dfree(o.d_em);
+    dfree(o.d_tiles);
+    dfree(o.d_big);
+    dfree(o.d_stats);
+    dfree(o.d_tm);
+    dfree(o.d_pmat);
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (ctx->ev_emitted[k]) (void)hipEventDestroy(ctx->ev_emitted[k]);
+    if (ctx->ev_splatted[k]) (void)hipEventDestroy(ctx->ev_splatted[k]);
+  }
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   dfree(ctx->d_eye);
   dfree(ctx->d_kshift);
   dfree(ctx->d_lod_thr);
@@ -389,7 +494,7 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id) {
   auto it = ctx->scenes.find(scene_id);
   if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
   if (it->second.batch_refs > 0) return fail(ctx, LFDPR_ESTATE, "the scene is rendered by a live batch");
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   free_scene(it->second);
   ctx->scenes.erase(it);
   return LFDPR_OK;
@@ -415,7 +520,7 @@ int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* 
     }
   }
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));  // earlier frames may still read the old table
+  HIPOK(sync_all(ctx));  // earlier frames may still read the old table
   dfree(s.mat);
   if (given == 3) {
     if (dalloc(s.mat, m.size()) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "material table");
@@ -449,7 +554,7 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   if (!view_params_ok(v)) return fail(ctx, LFDPR_EINVAL, "view parameters out of range");
   const int64_t nviews = (int64_t)v->V * v->S;
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   Rig rg{};
   std::vector<float> eye, ks;
   std::vector<double> q;
@@ -480,9 +585,13 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
     return fail(ctx, LFDPR_ENOMEM, "rig tables");
   if (cap != ctx->cap || !ctx->d_points) {
     dfree(ctx->d_points);
-    ctx->cap = 0;
+    ctx->cap = ctx->points_alloc = 0;
     if (dalloc(ctx->d_points, (size_t)cap) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "point buffer");
-    ctx->cap = cap;
+    ctx->cap = ctx->points_alloc = cap;
+  }
+  if (ctx->other.points_alloc != cap) {  // the second set (two frames in flight) follows on first use
+    dfree(ctx->other.d_points);
+    ctx->other.points_alloc = 0;
   }
   if (nkeys != ctx->n_keys || !ctx->d_keys) {
     dfree(ctx->d_keys);
@@ -497,7 +606,7 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   HIPOK(hipMemcpy(ctx->d_awt, awt.data(), 4 * awt.size(), hipMemcpyHostToDevice));
   launch_fill_u64(ctx->d_keys, nkeys, ~0ull, ctx->stream);
   HIPOK(hipGetLastError());
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   rg.eye = ctx->d_eye;
   rg.kshift = ctx->d_kshift;
   ctx->rig = rg;
@@ -543,19 +652,20 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
   if (pbr && s.nt > 0 && !s.mat) return fail(ctx, LFDPR_ESTATE, "physically based shading needs lfdpr_scene_set_materials");
   HIPOK(hipSetDevice(ctx->device));
-  int rc = ensure_tri_buffers(ctx, s.nt);
-  if (rc) return rc;
-  if (pbr && (ctx->tm_cap < ctx->tri_cap || ctx->pmat_cap != ctx->cap)) {
-    HIPOK(hipStreamSynchronize(ctx->stream));  // earlier frames may still read them
-    dfree(ctx->d_tm);
-    dfree(ctx->d_pmat);
-    ctx->tm_cap = ctx->pmat_cap = 0;
-    if (dalloc(ctx->d_tm, (size_t)ctx->tri_cap) != hipSuccess || dalloc(ctx->d_pmat, (size_t)ctx->cap) != hipSuccess)
-      return fail(ctx, LFDPR_ENOMEM, "material buffers");
-    ctx->tm_cap = ctx->tri_cap;
-    ctx->pmat_cap = ctx->cap;
+  // two frames in flight: this frame takes the other set of per-frame buffers
+  const bool piped = ctx->frames_in_flight == 2;
+  if (piped) swap_frame_buffers(ctx);
+  int rc = prepare_frame_buffers(ctx, s.nt, pbr);
+  if (rc) {
+    if (piped) swap_frame_buffers(ctx);
+    return rc;
   }
   hipStream_t st = ctx->stream;
+  // point generation runs on the side stream when two frames are in flight;
+  // it first waits for the splat that last read this set of buffers
+  hipStream_t gen = piped ? ctx->side : st;
+  const int sl = ctx->slot;
+  if (piped && ctx->splatted_pending[sl]) HIPOK(hipStreamWaitEvent(gen, ctx->ev_splatted[sl], 0));
   Item one;
   std::memset(&one, 0, sizeof one);  // padding too: the table is compared bytewise
   one.pos = s.pos;
@@ -571,11 +681,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   one.key_layout = ctx->key_layout;
   one.mat = pbr ? s.mat : nullptr;
   if (std::memcmp(&one, &ctx->h_item1, sizeof one) != 0) {
-    HIPOK(hipStreamSynchronize(st));  // earlier frames may still read the table
+    HIPOK(sync_all(ctx));  // earlier frames may still read the table
     HIPOK(hipMemcpy(ctx->d_item1, &one, sizeof one, hipMemcpyHostToDevice));
     std::memcpy(&ctx->h_item1, &one, sizeof one);
   }
-  launch_fill_u64(ctx->d_stats, STAT_SLOTS, 0ull, st);
+  launch_fill_u64(ctx->d_stats, STAT_SLOTS, 0ull, gen);
   SetupArgs sa{};
   sa.items = ctx->d_item1;
   sa.n_items = 1;
@@ -590,11 +700,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   sa.dbgi = ctx->dbgi;
   sa.stats = ctx->d_stats;
   sa.tm = pbr ? ctx->d_tm : nullptr;
-  hipEvent_t e0 = mark(ctx);
-  launch_tri_setup(sa, st);
-  hipEvent_t e1 = mark(ctx);
-  launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, st);
-  hipEvent_t e2 = mark(ctx);
+  hipEvent_t e0 = mark_on(ctx, gen);
+  launch_tri_setup(sa, gen);
+  hipEvent_t e1 = mark_on(ctx, gen);
+  launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, gen);
+  hipEvent_t e2 = mark_on(ctx, gen);
   EmitArgs ea{};
   ea.items = ctx->d_item1;
   ea.nt = s.nt;
@@ -608,8 +718,13 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   ea.cap = ctx->cap;
   ea.tm = pbr ? ctx->d_tm : nullptr;
   ea.pmat = pbr ? ctx->d_pmat : nullptr;
-  launch_emit(ea, ctx->splat_blocks, st);
-  hipEvent_t e3 = mark(ctx);
+  launch_emit(ea, ctx->splat_blocks, gen);
+  hipEvent_t e3 = mark_on(ctx, gen);
+  if (piped) {
+    HIPOK(hipEventRecord(ctx->ev_emitted[sl], gen));
+    HIPOK(hipStreamWaitEvent(st, ctx->ev_emitted[sl], 0));
+  }
+  hipEvent_t e3s = piped ? mark(ctx) : e3;
   SplatArgs pa{};
   pa.items = ctx->d_item1;
   pa.n_items = 1;
@@ -624,6 +739,10 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
                   sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
   launch_splat(pa, ctx->splat_blocks, st);
+  if (piped) {
+    HIPOK(hipEventRecord(ctx->ev_splatted[sl], st));
+    ctx->splatted_pending[sl] = true;
+  }
   hipEvent_t e4 = mark(ctx);
   launch_resolve(ctx->d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st);
   hipEvent_t e5 = mark(ctx);
@@ -631,7 +750,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   stage(ctx, 0, e0, e1);
   stage(ctx, 1, e1, e2);
   stage(ctx, 2, e2, e3);
-  stage(ctx, 3, e3, e4);
+  stage(ctx, 3, e3s, e4);
   stage(ctx, 4, e4, e5);
   ctx->last_nt = s.nt;
   ctx->last_pbr = pbr;
@@ -679,7 +798,7 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   if (!ctx || !out) return fail(ctx, LFDPR_EINVAL, "null argument");
   uint64_t st[STAT_SLOTS];
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   HIPOK(hipMemcpy(st, ctx->d_stats, sizeof st, hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof *out);
   out->points = (int64_t)st[STAT_TOTAL];
@@ -696,7 +815,7 @@ int lfdpr_copy_points(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* n_points)
   if (!ctx || !dst || !n_points || cap < 0) return fail(ctx, LFDPR_EINVAL, "null argument");
   uint64_t total = 0;
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   HIPOK(hipMemcpy(&total, ctx->d_stats + STAT_TOTAL, 8, hipMemcpyDeviceToHost));
   int64_t n = (int64_t)total < ctx->cap ? (int64_t)total : ctx->cap;
   *n_points = (int64_t)total;
@@ -710,7 +829,7 @@ int lfdpr_copy_point_materials(lfdpr_ctx* ctx, void* dst, int64_t cap, int64_t* 
   if (!ctx->last_pbr) return fail(ctx, LFDPR_ESTATE, "the last frame was not rendered with physically based shading");
   uint64_t total = 0;
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   HIPOK(hipMemcpy(&total, ctx->d_stats + STAT_TOTAL, 8, hipMemcpyDeviceToHost));
   int64_t n = (int64_t)total < ctx->cap ? (int64_t)total : ctx->cap;
   *n_points = (int64_t)total;
@@ -723,14 +842,14 @@ int lfdpr_copy_counts(lfdpr_ctx* ctx, uint32_t* dst, int64_t n) {
   if (!ctx || !dst || n < 0) return fail(ctx, LFDPR_EINVAL, "null argument");
   if (n > ctx->last_nt) return fail(ctx, LFDPR_EINVAL, "more counts than triangles");
   HIPOK(hipSetDevice(ctx->device));
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   if (n > 0) HIPOK(hipMemcpy(dst, ctx->d_counts, (size_t)n * 4, hipMemcpyDeviceToDevice));
   return LFDPR_OK;
 }
 
 int lfdpr_timing(lfdpr_ctx* ctx, int enable) {
   if (!ctx) return LFDPR_EINVAL;
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   ctx->timing = enable != 0;
   ctx->ev_used = 0;
   ctx->ev_marks.clear();
@@ -739,7 +858,7 @@ int lfdpr_timing(lfdpr_ctx* ctx, int enable) {
 
 int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n) {
   if (!ctx || !ms_sum || !n) return fail(ctx, LFDPR_EINVAL, "null argument");
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   for (int k = 0; k < LFDPR_N_STAGES; ++k) { ms_sum[k] = 0.0; n[k] = 0; }
   for (auto& m : ctx->ev_marks) {
     float ms = 0.0f;
@@ -1146,10 +1265,26 @@ int lfdpr_autotune(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_
   return LFDPR_OK;
 }
 
+int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n) {
+  if (!ctx || n < 1 || n > 2) return fail(ctx, LFDPR_EINVAL, "frames in flight must be 1 or 2");
+  HIPOK(hipSetDevice(ctx->device));
+  HIPOK(sync_all(ctx));
+  if (n == 2 && !ctx->side) {
+    HIPOK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    for (int k = 0; k < 2; ++k) {
+      HIPOK(hipEventCreateWithFlags(&ctx->ev_emitted[k], hipEventDisableTiming));
+      HIPOK(hipEventCreateWithFlags(&ctx->ev_splatted[k], hipEventDisableTiming));
+    }
+  }
+  ctx->frames_in_flight = n;
+  ctx->splatted_pending[0] = ctx->splatted_pending[1] = false;
+  return LFDPR_OK;
+}
+
 int lfdpr_set_launch(lfdpr_ctx* ctx, int32_t splat_blocks, int32_t key_layout) {
   if (!ctx || splat_blocks < 1 || splat_blocks > (1 << 20) || key_layout < 0 || key_layout > 1)
     return fail(ctx, LFDPR_EINVAL, "launch shape out of range");
-  HIPOK(hipStreamSynchronize(ctx->stream));
+  HIPOK(sync_all(ctx));
   ctx->splat_blocks = splat_blocks;
   ctx->key_layout = key_layout;
   return LFDPR_OK;

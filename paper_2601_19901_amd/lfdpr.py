@@ -124,6 +124,7 @@ def signatures():
         "lfdpr_set_debug_records": ([vp, vp, vp, i64], C.c_int),
         "lfdpr_timing": ([vp, C.c_int], C.c_int),
         "lfdpr_set_launch": ([vp, i32, i32], C.c_int),
+        "lfdpr_set_frames_in_flight": ([vp, i32], C.c_int),
         "lfdpr_autotune": ([vp, i32, vp, vp, p(TuneResult)], C.c_int),
         "lfdpr_batch_create": ([vp, i32, vp, vp, i64, p(vp)], C.c_int),
         "lfdpr_batch_destroy": ([vp], C.c_int),
@@ -266,6 +267,9 @@ class Renderer:
 
     def set_launch(self, splat_blocks: int, key_layout: int):
         self._check(lib().lfdpr_set_launch(self.h, splat_blocks, key_layout))
+
+    def set_frames_in_flight(self, n: int):
+        self._check(lib().lfdpr_set_frames_in_flight(self.h, n))
 
     def autotune(self, sid: int, model: np.ndarray, views) -> dict:
         m = np.ascontiguousarray(model, np.float32).reshape(12)
