@@ -327,6 +327,8 @@ def run_learned(args, torch, lfdpr, scenes):
     rng = np.random.default_rng(0)
     flat = model.net.get_params()
     model.net.set_params((rng.normal(0.0, 0.05, flat.size)).astype(np.float32))
+    for f in (1, 4):
+        ss.rigs[f].renderer.set_frames_in_flight(args.frames_in_flight)
     frames = list(range(args.warmup + args.steps))
     times = learned.time_pipelines(model, w.lens, 0, frames)
     # network forward alone, HIP events on the library's (torch's current) stream
@@ -361,6 +363,7 @@ def run_learned(args, torch, lfdpr, scenes):
                                "angular filter)", "views": w.views.V, "view_px": [w.views.W, w.views.H],
                    "triangles": w.scene.n_tris},
         "frame_ms": {k: round(v, 4) for k, v in times.items()},
+        "frames_in_flight": args.frames_in_flight,
         "net_forward_ms": round(fwd_ms, 4),
         "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur", "bound": "mfma",
                      "achieved": round(achieved, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -379,7 +382,7 @@ def main():
                     default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--frames-in-flight", type=int, choices=(1, 2), default=2,
-                    help="display workloads: frames whose point generation overlaps the previous splat")
+                    help="frames whose point generation overlaps the previous frame (display and learned workloads)")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
