@@ -98,6 +98,7 @@ struct lfdpr_ctx {
   hipStream_t side = nullptr;
   int slot = 0;  // which set the fields hold
   hipEvent_t ev_emitted[2] = {nullptr, nullptr}, ev_splatted[2] = {nullptr, nullptr};
+  hipEvent_t ev_caller = nullptr;  // the caller's stream, for debug records written on `side`
   bool splatted_pending[2] = {false, false};
   struct FrameBufs {
     int64_t points_alloc = 0, tri_cap = 0, tm_cap = 0, pmat_cap = 0, last_nt = 0;
@@ -405,6 +406,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
     if (ctx->ev_emitted[k]) (void)hipEventDestroy(ctx->ev_emitted[k]);
     if (ctx->ev_splatted[k]) (void)hipEventDestroy(ctx->ev_splatted[k]);
   }
+  if (ctx->ev_caller) (void)hipEventDestroy(ctx->ev_caller);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   dfree(ctx->d_eye);
   dfree(ctx->d_kshift);
@@ -666,6 +668,11 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   hipStream_t gen = piped ? ctx->side : st;
   const int sl = ctx->slot;
   if (piped && ctx->splatted_pending[sl]) HIPOK(hipStreamWaitEvent(gen, ctx->ev_splatted[sl], 0));
+  if (piped && ctx->dbgf) {
+    // the set-up writes the caller's debug record buffers: after the caller's earlier work
+    HIPOK(hipEventRecord(ctx->ev_caller, st));
+    HIPOK(hipStreamWaitEvent(gen, ctx->ev_caller, 0));
+  }
   Item one;
   std::memset(&one, 0, sizeof one);  // padding too: the table is compared bytewise
   one.pos = s.pos;
@@ -1275,6 +1282,7 @@ int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n) {
       HIPOK(hipEventCreateWithFlags(&ctx->ev_emitted[k], hipEventDisableTiming));
       HIPOK(hipEventCreateWithFlags(&ctx->ev_splatted[k], hipEventDisableTiming));
     }
+    HIPOK(hipEventCreateWithFlags(&ctx->ev_caller, hipEventDisableTiming));
   }
   ctx->frames_in_flight = n;
   ctx->splatted_pending[0] = ctx->splatted_pending[1] = false;
