@@ -93,6 +93,24 @@ def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None,
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launch_ms": round(dom_ms, 4)}
 
 
+def frame_roofline(stage_ms: dict, pv_per_frame: float, shape: dict, frame_ms: float,
+                   splat_ops: int = SPLAT_OPS_PER_POINT_VIEW) -> dict:
+    """The frame's achievable time: for every stage the larger of its
+    algorithmic bytes at the HBM peak and its algorithmic lane-ops at the ALU
+    peak, summed over the stages; frac = that sum / the measured frame time."""
+    peak_ops = VALU_PEAK_GOPS * 1e9
+    peak_bytes = HBM_PEAK_GBS * 1e9
+    ops = {"setup": SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"], "splat": splat_ops * pv_per_frame}
+    bounds = {}
+    for k in stage_ms:
+        t_mem = BYTES[k](shape) / peak_bytes if k in BYTES else 0.0
+        t_alu = ops.get(k, 0.0) / peak_ops
+        bounds[k] = round(max(t_mem, t_alu) * 1e3, 4)
+    total = sum(bounds.values())
+    return {"achievable_ms": round(total, 4), "measured_ms": round(frame_ms, 4), "frac": round(total / frame_ms, 4),
+            "bound_ms": bounds}
+
+
 def splat_traffic():
     """HBM bytes per k_splat launch on display-1M from the committed rocprofv3
     counter summary, if it was taken on the current kernel sources (else None)."""
@@ -225,6 +243,9 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         "active_tris_per_frame": int(act / nfr),
         "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
         "roofline": roof,
+        "frame_roofline": frame_roofline(st_avg, pv / nfr, shape, wall_ms,
+                                         SPLAT_PBR_OPS_PER_POINT_VIEW if kind == "display-1M-pbr"
+                                         else SPLAT_OPS_PER_POINT_VIEW),
     }
     if not args.no_cpu_baseline and kind == "display-1M":
         from oracle import oracle as O
