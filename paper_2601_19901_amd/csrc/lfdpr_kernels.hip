@@ -719,21 +719,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR ?
     const Point pt = a.points[p];
     const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
-    const TriRec T = a.rec[tri];
     if (!kMulti) {
+      const TriRec T = a.rec[tri];
       splat_point<kPBR>(it0, pt, T, flags, i, j, tx, ty, a, p);
       continue;
     }
     // points of one wave nearly always belong to one item: take the items one at
     // a time, each pass with a uniform item.  The loop runs on a ballot mask, so
     // its trip count is the same in every lane and the body stays inside it.
-    const int32_t my = T.item;
+    // Only the record's item is read before the loop (the whole record inside).
+    const int32_t my = a.rec[tri].item;
     uint64_t todo = __builtin_amdgcn_ballot_w64(true);
     while (todo) {
       const int32_t cur = __builtin_amdgcn_readlane(my, (int32_t)__builtin_ctzll(todo));
       const bool mine = my == cur;
       if (mine) {
         const Item it = load_uniform(a.items + cur);
+        const TriRec T = a.rec[tri];
         splat_point<false>(it, pt, T, flags, i, j, tx, ty, a, p);
       }
       todo &= ~__builtin_amdgcn_ballot_w64(mine);
