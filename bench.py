@@ -57,6 +57,7 @@ SPLAT_OPS_PER_POINT_VIEW = 112
 # pixel: 0.327 written pixels per point-view (oracle, display-1M)
 SPLAT_PBR_OPS_PER_POINT_VIEW = SPLAT_OPS_PER_POINT_VIEW + round(205 * 0.327)
 SETUP_OPS_PER_TRI_VIEW = 75        # R4 + R6 per (triangle, view)
+NET_FWD_BYTES_PER_PX = 16 + 80 + 128 + 128 + 80   # blur + four convolution layers, BF16
 BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
     "scan": lambda s: s["nt"] * (4 + 4 + 8),
@@ -368,6 +369,14 @@ def run_learned(args, torch, lfdpr, scenes):
     px = w.views.V * w.views.W * w.views.H
     flops = 2 * 9 * sum(ci * co for ci, co in lfdpr.NET_SHAPES) * px
     achieved = flops / (fwd_ms * 1e-3) / 1e12
+    # algorithmic HBM bytes per pixel of the forward pass (BF16 activations):
+    # blur reads the 4-channel input and writes 4 channels (16); layer 1 reads
+    # the input and the blur and writes 32 channels (80); layers 2-3 read and
+    # write 32 channels (128 each); the output layer reads 32 channels and the
+    # blurred RGB and writes 4 channels (80).  121 flop/B, below the 312 flop/B
+    # ridge of MI355X: the forward pass is HBM bound.
+    net_bytes = NET_FWD_BYTES_PER_PX * px
+    gbs = net_bytes / (fwd_ms * 1e-3) / 1e9
     R1.render_frame(ss.rigs[1].scene_ids[0], w.model(args.warmup), ss.views1)
     pv = R1.stats()["point_views"]
     return {
@@ -386,10 +395,12 @@ def run_learned(args, torch, lfdpr, scenes):
         "frame_ms": {k: round(v, 4) for k, v in times.items()},
         "frames_in_flight": args.frames_in_flight,
         "net_forward_ms": round(fwd_ms, 4),
-        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur", "bound": "mfma",
-                     "achieved": round(achieved, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                     "flops_per_frame": flops, "launch_ms": round(fwd_ms, 4)},
+        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur", "bound": "hbm",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_frame": net_bytes, "flops_per_frame": flops,
+                     "mfma_achieved_tflops": round(achieved, 1),
+                     "mfma_frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "launch_ms": round(fwd_ms, 4)},
     }
 
 
