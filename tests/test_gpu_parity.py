@@ -174,11 +174,13 @@ def test_determinism_and_launch_shape_independence(torch_cuda):
         np.testing.assert_array_equal(b.view(np.uint32), imgs[0][1].view(np.uint32))
 
 
-def test_edge_cases(torch_cuda):
+@pytest.mark.parametrize("in_flight", [1, 2])
+def test_edge_cases(torch_cuda, in_flight):
     torch = torch_cuda
     from paper_2601_19901_amd import lfdpr
     w = scenes.tiny()
     R = _renderer(torch_cuda)
+    R.set_frames_in_flight(in_flight)
     sid = R.upload_scene(w.scene)
     # render before set_views -> state error
     v = torch.empty((8, 128, 128), dtype=torch.int32, device="cuda")
@@ -219,7 +221,7 @@ def test_edge_cases(torch_cuda):
     R.set_views(w.views)
     o = O.render(w.scene, w.views, w.model(2))
     g = run_gpu(R, sid, w, w.model(2), w.scene.n_tris)
-    assert_parity(g, o, w.scene.n_tris, "after-errors")
+    assert_parity(g, o, w.scene.n_tris, f"after-errors, {in_flight} in flight")
 
 
 @pytest.fixture(scope="module")
