@@ -55,6 +55,17 @@ def test_pbr_small_display_parity(torch_cuda, seed, frame, mip):
     _pbr_parity(w, frame, f"small-pbr s{seed} f{frame} mip{int(mip)}")
 
 
+def test_pbr_with_angular_supersampling(torch_cuda):
+    """PBR shading of 4x angularly supersampled sub-views (each sub-view shades
+    with its own jittered eye offset), then the angular filter: bit-exact."""
+    torch = torch_cuda
+    w = scenes.with_pbr(scenes.small_display(seed=12, S=4, V=8), seed=12)
+    R, sid, g, o = _pbr_parity(w, 3, "pbr ss4")
+    out = torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda")
+    R.angular_filter(g["views_t"], out)
+    np.testing.assert_array_equal(out.cpu().numpy().view(np.uint32), O.angular_filter(o["rgba"], w.views))
+
+
 def test_pbr_display_size_parity(torch_cuda):
     """Display-size scene (999,168 triangles, 48 views of 512^2) with four
     material sets (normal maps up to 4096^2): everything bit-exact, and the
