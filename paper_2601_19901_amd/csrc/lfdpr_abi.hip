@@ -1277,12 +1277,23 @@ int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n) {
   HIPOK(hipSetDevice(ctx->device));
   HIPOK(sync_all(ctx));
   if (n == 2 && !ctx->side) {
-    HIPOK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-    for (int k = 0; k < 2; ++k) {
-      HIPOK(hipEventCreateWithFlags(&ctx->ev_emitted[k], hipEventDisableTiming));
-      HIPOK(hipEventCreateWithFlags(&ctx->ev_splatted[k], hipEventDisableTiming));
+    // created together or not at all: the context keeps them only on success
+    hipStream_t side = nullptr;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; k < 5 && ok; ++k) ok = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (side) (void)hipStreamDestroy(side);
+      return fail(ctx, LFDPR_EDEVICE, "creating the second stream and its events");
     }
-    HIPOK(hipEventCreateWithFlags(&ctx->ev_caller, hipEventDisableTiming));
+    ctx->side = side;
+    ctx->ev_emitted[0] = ev[0];
+    ctx->ev_emitted[1] = ev[1];
+    ctx->ev_splatted[0] = ev[2];
+    ctx->ev_splatted[1] = ev[3];
+    ctx->ev_caller = ev[4];
   }
   ctx->frames_in_flight = n;
   ctx->splatted_pending[0] = ctx->splatted_pending[1] = false;
