@@ -140,7 +140,8 @@ int lfdpr_scene_free(lfdpr_ctx* ctx, int32_t scene_id);
  * tangent-space normal map (RGB = (n + 1)/2 * 255), a roughness map and a
  * metallic map (both read from R).  The triangle's albedo stays tex_id.  All
  * three NULL removes the materials.  Copied; synchronises the stream.
- * LFDPR_EINVAL for an unknown scene, an id >= n_tex or only some arrays. */
+ * LFDPR_EINVAL for an unknown scene, an id >= n_tex or only some arrays;
+ * LFDPR_ESTATE while a live batch renders the scene. */
 int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* normal_id,
                               const uint16_t* roughness_id, const uint16_t* metallic_id);
 
@@ -155,8 +156,10 @@ int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* 
  * diffuse (1-F)(1-m) albedo/pi) under one directional light plus ambient, then
  * tone mapped as sqrt(x/(1+x)) and rounded to 8 bits; alpha is the albedo's.
  * light_dir is the camera-space unit vector towards the light (length within
- * 1e-3 of 1); light_rgb and ambient_rgb lie in [0, 1e4].  Only single-frame
- * rendering shades: batches return LFDPR_ESTATE while the mode is PBR. */
+ * 1e-3 of 1); light_rgb and ambient_rgb lie in [0, 1e4].  Batches shade with
+ * the context's mode too: every scene of the batch then needs materials
+ * (LFDPR_ESTATE otherwise), and a batch graph is captured again when the mode
+ * or the light changes. */
 typedef struct {
   int32_t mode;                /* LFDPR_SHADE_* */
   float light_dir[3];

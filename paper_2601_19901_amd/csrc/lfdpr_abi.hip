@@ -508,6 +508,7 @@ int lfdpr_scene_set_materials(lfdpr_ctx* ctx, int32_t scene_id, const uint16_t* 
   auto it = ctx->scenes.find(scene_id);
   if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
   SceneDev& s = it->second;
+  if (s.batch_refs > 0) return fail(ctx, LFDPR_ESTATE, "the scene is rendered by a live batch");
   const int given = (normal_id != nullptr) + (roughness_id != nullptr) + (metallic_id != nullptr);
   if (given != 0 && given != 3) return fail(ctx, LFDPR_EINVAL, "all three material arrays or none");
   std::vector<uint16_t> m;
@@ -906,9 +907,13 @@ struct lfdpr_batch {
   uint64_t* stats = nullptr;
   Point* points = nullptr;
   int64_t cap = 0;
+  TriMat* tm = nullptr;  // physically based shading: material records and
+  uint4* pmat = nullptr; // per-point material words (allocated on first use)
   Rig table_rig{};
   int splat_blocks = 4096, key_layout = 0;
   bool use_graph = true, g_valid = false;
+  bool g_pbr = false;    // shading the graph was captured with
+  lfdpr_shading g_sh{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   uint32_t* g_views = nullptr;
@@ -945,6 +950,8 @@ void batch_free(lfdpr_batch* b) {
   dfree(b->big);
   dfree(b->stats);
   dfree(b->points);
+  dfree(b->tm);
+  dfree(b->pmat);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->ev_stage) (void)hipEventDestroy(b->ev_stage);
@@ -956,6 +963,7 @@ void batch_free(lfdpr_batch* b) {
 void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed) {
   hipStream_t st = b->stream;
   lfdpr_ctx* ctx = b->ctx;
+  const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
   auto ev = [&]() { return timed ? mark_on(ctx, st) : nullptr; };
   launch_fill_u64(b->stats, STAT_SLOTS, 0ull, st);
   hipEvent_t e0 = ev();
@@ -969,6 +977,7 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed)
   sa.rec = b->rec;
   sa.em = b->em;
   sa.stats = b->stats;
+  sa.tm = pbr ? b->tm : nullptr;
   launch_tri_setup(sa, st);
   hipEvent_t e1 = ev();
   launch_scan(b->counts, b->nt, b->tiles, b->offsets, b->stats + STAT_TOTAL, st);
@@ -984,6 +993,8 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed)
   ea.big = b->big;
   ea.n_big = b->stats + STAT_BIG;
   ea.cap = b->cap;
+  ea.tm = pbr ? b->tm : nullptr;
+  ea.pmat = pbr ? b->pmat : nullptr;
   launch_emit(ea, b->splat_blocks, st);
   hipEvent_t e3 = ev();
   SplatArgs pa{};
@@ -994,6 +1005,11 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed)
   pa.n_points = b->stats + STAT_TOTAL;
   pa.cap = b->cap;
   pa.rec = b->rec;
+  pa.tm = pbr ? b->tm : nullptr;
+  pa.pmat = pbr ? b->pmat : nullptr;
+  const lfdpr_shading& sh = ctx->shading;
+  pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
+                  sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
   launch_splat(pa, b->splat_blocks, st);
   hipEvent_t e4 = ev();
   launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st);
@@ -1137,13 +1153,44 @@ int lfdpr_batch_use_graph(lfdpr_batch* b, int enable) {
 
 int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uint8_t* panels) {
   if (!b || !models || !views) return bfail(b, LFDPR_EINVAL, "null argument");
-  if (b->ctx->shading.mode != LFDPR_SHADE_UNLIT)
-    return bfail(b, LFDPR_ESTATE, "batches render unlit albedo: set LFDPR_SHADE_UNLIT on the context");
+  const bool pbr = b->ctx->shading.mode == LFDPR_SHADE_PBR;
+  if (pbr)
+    for (int k = 0; k < b->n; ++k) {
+      const SceneDev& s = b->ctx->scenes[b->scene_ids[k]];
+      if (s.nt > 0 && !s.mat)
+        return bfail(b, LFDPR_ESTATE, "physically based shading needs lfdpr_scene_set_materials on every scene");
+    }
   if (panels && (!b->ctx->lens_set || b->table_rig.n_views < 1))
     return bfail(b, LFDPR_ESTATE, "lfdpr_set_lens on the context first");
   for (int k = 0; k < 12 * b->n; ++k)
     if (!std::isfinite(models[k])) return bfail(b, LFDPR_EINVAL, "non-finite model matrix");
   BHIP(hipSetDevice(b->ctx->device));
+  // shading: material buffers on first use, the items' material tables, and a
+  // new graph when the captured shading differs
+  if (pbr && !b->tm) {
+    BHIP(hipStreamSynchronize(b->stream));
+    const int64_t ntb = b->nt > 1024 ? b->nt : 1024;
+    if (dalloc(b->tm, (size_t)ntb) != hipSuccess || dalloc(b->pmat, (size_t)b->cap) != hipSuccess) {
+      dfree(b->tm);
+      dfree(b->pmat);
+      return bfail(b, LFDPR_ENOMEM, "material buffers");
+    }
+  }
+  bool items_changed = false;
+  for (int k = 0; k < b->n; ++k) {
+    const uint16_t* m = pbr ? b->ctx->scenes[b->scene_ids[k]].mat : nullptr;
+    if (b->items[k].mat != m) {
+      b->items[k].mat = m;
+      items_changed = true;
+    }
+  }
+  if (items_changed) {
+    BHIP(hipStreamSynchronize(b->stream));  // earlier replays may still read the table
+    BHIP(hipMemcpy(b->d_items, b->items.data(), sizeof(Item) * b->n, hipMemcpyHostToDevice));
+  }
+  if (items_changed || b->g_pbr != pbr ||
+      (pbr && std::memcmp(&b->g_sh, &b->ctx->shading, sizeof b->g_sh) != 0))
+    b->g_valid = false;
   // model matrices: pinned staging -> device, outside any graph
   BHIP(hipEventSynchronize(b->ev_stage));
   std::memcpy(b->h_models, models, sizeof(Model) * b->n);
@@ -1162,6 +1209,8 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
       BHIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
       b->g_views = views;
       b->g_panels = panels;
+      b->g_pbr = pbr;
+      b->g_sh = b->ctx->shading;
       b->g_valid = true;
     }
     BHIP(hipGraphLaunch(b->exec, b->stream));
@@ -1195,8 +1244,6 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
 // workload and keeps the fastest; the results are returned per candidate.
 int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, lfdpr_tune_result* res) {
   if (!b || !models || !views || !res) return bfail(b, LFDPR_EINVAL, "null argument");
-  if (b->ctx->shading.mode != LFDPR_SHADE_UNLIT)
-    return bfail(b, LFDPR_ESTATE, "batches render unlit albedo: set LFDPR_SHADE_UNLIT on the context");
   static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
   const bool graph = b->use_graph;
   b->use_graph = false;

@@ -74,7 +74,7 @@ struct SplatArgs {
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
   const TriRec* rec;
-  const TriMat* tm;          // physically based mode (single item only); else null
+  const TriMat* tm;          // physically based mode; else null
   const uint4* pmat;
   Shading sh;
 };

@@ -698,13 +698,12 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
 }
 
 // kMulti: points of several items (a batch); otherwise every point belongs to
-// items[0] and the item is read once.  kPBR (single item): shaded colours;
+// items[0] and the item is read once.  kPBR: shaded colours;
 // held to 128 VGPRs (4 waves per SIMD instead of 3 at its natural 138), which
 // measured faster despite an 8-byte spill.  The batch instantiation keeps 139:
 // capped, it spills 40 bytes and slows down.
 template <bool kMulti, bool kPBR>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR ? 4 : 1))) k_splat(SplatArgs a) {
-  static_assert(!(kMulti && kPBR), "physically based shading renders single frames");
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR && !kMulti ? 4 : 1))) k_splat(SplatArgs a) {
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
   const Rig& trg = a.table_rig;
   float* tx = ray_tab;
@@ -736,7 +735,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR ?
       if (mine) {
         const Item it = load_uniform(a.items + cur);
         const TriRec T = a.rec[tri];
-        splat_point<false>(it, pt, T, flags, i, j, tx, ty, a, p);
+        splat_point<kPBR>(it, pt, T, flags, i, j, tx, ty, a, p);
       }
       todo &= ~__builtin_amdgcn_ballot_w64(mine);
     }
@@ -869,7 +868,9 @@ void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
   size_t lds = sizeof(float) * (size_t)(a.table_rig.W + a.table_rig.H);
-  if (a.n_items > 1)
+  if (a.n_items > 1 && a.tm)
+    k_splat<true, true><<<grid_blocks, 256, lds, s>>>(a);
+  else if (a.n_items > 1)
     k_splat<true, false><<<grid_blocks, 256, lds, s>>>(a);
   else if (a.tm)
     k_splat<false, true><<<grid_blocks, 256, lds, s>>>(a);

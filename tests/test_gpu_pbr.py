@@ -6,7 +6,9 @@ with the albedo fetches, the per-point normal / roughness / metallic words,
 shaded views and depth -- on the tiny and small display scenes and on the
 full display-size scene with PBR materials in the launch configuration the
 benchmark times.  Also: shading state changes and the refusals the ABI
-documents (no materials, batches, bad light)."""
+documents (no materials, bad light, material changes under a live batch),
+and batches of PBR scenes against the oracle, eager and replayed as a graph,
+across a light change and a switch back to unlit albedo."""
 import numpy as np
 import pytest
 
@@ -116,12 +118,20 @@ def test_pbr_state_and_refusals(torch_cuda):
     with pytest.raises(lfdpr.LfdprError) as e:
         R.set_shading(neg)
     assert e.value.code == lfdpr.LFDPR_EINVAL
-    # batches render unlit only
+    # a batch shades too, but every scene of it needs materials
+    R.set_shading(w.shading)
+    bp = lfdpr.Batch(R, [sid, plain], [w.views, w.views])
+    bpv = bp.alloc_views()
+    with pytest.raises(lfdpr.LfdprError) as e:
+        bp.render(np.stack([w.model(1), w.model(1)]), bpv)
+    assert e.value.code == lfdpr.LFDPR_ESTATE
+    bp.close()
     b = lfdpr.Batch(R, [sid], [w.views])
     bv = b.alloc_views()
-    with pytest.raises(lfdpr.LfdprError) as e:
-        b.render(w.model(1)[None], bv)
-    assert e.value.code == lfdpr.LFDPR_ESTATE
+    b.render(w.model(1)[None], bv)
+    np.testing.assert_array_equal(bv[0].cpu().numpy().view(np.uint32), o["rgba"])
+    # materials of a scene that a live batch renders stay fixed
+    assert lfdpr.lib().lfdpr_scene_set_materials(R.h, sid, None, None, None) == lfdpr.LFDPR_ESTATE
     R.set_shading(None)
     b.render(w.model(1)[None], bv)
     np.testing.assert_array_equal(bv[0].cpu().numpy().view(np.uint32), u["rgba"])
@@ -130,4 +140,40 @@ def test_pbr_state_and_refusals(torch_cuda):
     R.set_shading(w.shading)
     R.render_frame(sid, w.model(1), views)
     np.testing.assert_array_equal(views.cpu().numpy().view(np.uint32), o["rgba"])
+    R.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_pbr_batch_matches_the_oracle(torch_cuda, graph):
+    """Three PBR scenes with different cones and distances in one batch: every
+    item bit-exact against the oracle's shaded render; a new light (the graph
+    is captured again) and unlit albedo afterwards stay exact."""
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    ws = []
+    for k, (seed, hq) in enumerate(((80, 24), (81, 48), (82, 16))):
+        w = scenes.with_pbr(scenes.small_display(seed=seed, V=12, W=96, H=96, hf_quads=hq), seed=seed)
+        w.views.cone_deg = 30.0 + 6.0 * k
+        w.views.D = 10.0 + 0.5 * k
+        ws.append(w)
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    B.use_graph(graph)
+    views = B.alloc_views()
+    warm = scenes.Shading(scenes.SHADE_PBR, (0.6, 0.0, -0.8), (2.0, 1.5, 1.0), (0.05, 0.04, 0.03))
+    for frame, sh in ((0, ws[0].shading), (77, ws[0].shading), (77, warm), (400, None)):
+        R.set_shading(sh)
+        models = [w.model(frame + 13 * k) for k, w in enumerate(ws)]
+        B.render(np.stack(models), views)
+        torch.cuda.synchronize()
+        bv = views.cpu().numpy().view(np.uint32)
+        tot = 0
+        for k, w in enumerate(ws):
+            o = O.render(w.scene, w.views, models[k], shading=sh)
+            np.testing.assert_array_equal(bv[k], o["rgba"], err_msg=f"item {k} frame {frame} shading {sh}")
+            tot += o["stats"]["point_views"]
+        assert B.stats()["point_views"] == tot
+        _log(f"PBR batch frame {frame}, graph={graph}, shading {'unlit' if sh is None else sh.light_dir}: exact")
+    B.close()
     R.close()
