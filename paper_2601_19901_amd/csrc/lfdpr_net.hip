@@ -125,12 +125,23 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     wlds[swz(k >> 2, k & 3)] = reinterpret_cast<const uint4*>(Wt)[k];
   // the MFMA computes D = W x A (rows: output channels, columns: pixels), so
   // lane (g, r16) ends with channels t*16 + 4g .. +3 of pixel r16 of each M tile
+  // Loads whose results the epilogue uses are unconditional (clamped indices):
+  // a load issued under a branch leaves the compiler unsure that a later wait
+  // covered it, and it would then wait for all memory traffic in the epilogue.
   float bco[NT][4];  // their biases (3 in the output layer)
   const int nbias = MODE == MODE_BWD ? 0 : (MODE == MODE_OUT ? 3 : YS);
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bco[t][e] = t * 16 + 4 * g + e < nbias ? bias[t * 16 + 4 * g + e] : 0.0f;
+    for (int e = 0; e < 4; ++e) {
+      const int c = t * 16 + 4 * g + e;
+      if (MODE == MODE_BWD) {
+        bco[t][e] = 0.0f;
+      } else {
+        const float bv = bias[c < nbias ? c : 0];
+        bco[t][e] = c < nbias ? bv : 0.0f;
+      }
+    }
   const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + kTY - 1) / kTY;
   const int ntile = N * tiles_x * tiles_y;
   const int nstage = (kTY + 2) * TW * 4;  // <= kStagePerThread * 256 for DIL <= kMaxDil
@@ -147,18 +158,48 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
       pre[j] = k < nstage ? load_a<GATHER>(X, aux, n, y0 - 1 + r, x0 - DIL + px, H, W, gg, V) : uint4{0u, 0u, 0u, 0u};
     }
   };
-  if (blockIdx.x < ntile) fetch(blockIdx.x);
-  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
-    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
-    __syncthreads();  // weights written / previous tile's reads finished
+  auto stage = [&]() {
 #pragma unroll
     for (int j = 0; j < kStagePerThread; ++j) {
       const int k = threadIdx.x + j * 256;
       if (k < nstage) tl[swz(k >> 2, k & 3)] = pre[j];
     }
-    __syncthreads();
-    if (tile + (int)gridDim.x < ntile) fetch(tile + gridDim.x);
+  };
+  // Software pipeline per tile: MFMAs on the staged tile; then the next tile
+  // (already in registers) goes to LDS, the one after it is requested, and only
+  // then do this tile's results leave.  Vector-memory waits count stores as well
+  // as loads, so each wait (before staging) covers requests that have had a
+  // whole tile of MFMAs to complete, never the stores just issued.
+  if (blockIdx.x < ntile) {
+    fetch(blockIdx.x);
+    stage();
+    __syncthreads();  // weights and the first tile in LDS
+    if (blockIdx.x + (int)gridDim.x < ntile) fetch(blockIdx.x + gridDim.x);
+  }
+  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
+    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
+    const int y = y0 + wv;
+    // the epilogue's side input (residual or ReLU mask), clamped into the image
+    // and used only where in range: the residual is requested before the MFMAs;
+    // the mask (two 32-channel tiles) after them, which keeps the backward
+    // instantiation at three waves per SIMD
+    uint2 side[4][NT];
+    auto load_side = [&]() {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int x = min(x0 + m * 16 + r16, W - 1), yc = min(y, H - 1), c0 = t * 16 + 4 * g;
+          side[m][t] = *reinterpret_cast<const uint2*>(aux + (((size_t)n * H + yc) * W + x) * AUX_C +
+                                                       (c0 < YS ? c0 : 0));
+        }
+    };
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) side[m][t] = uint2{0u, 0u};
+    if (MODE == MODE_OUT) load_side();
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
@@ -180,9 +221,15 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
           acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[t].v, a.v, acc[m][t], 0, 0, 0);
       }
     }
+    if (MODE == MODE_BWD) load_side();
+    const int next = tile + (int)gridDim.x;
+    __syncthreads();  // every wave has finished reading this tile
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) on every path: all requests so far have landed
+    if (next < ntile) stage();
+    __syncthreads();
+    if (next + (int)gridDim.x < ntile) fetch(next + gridDim.x);
     // epilogue: lane holds D[4g+e][r16] = channel t*16 + 4g + e of pixel x0 + 16m + r16
     // (row y0 + wv); four consecutive channels leave as one 8-byte store
-    const int y = y0 + wv;
     if (y < H) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -194,10 +241,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
           const int c0 = t * 16 + 4 * g;
           if (c0 >= YS) continue;
           float v[4];
-          uint2 side = {0u, 0u};
-          if (MODE != MODE_RELU) side = *reinterpret_cast<const uint2*>(aux + p * AUX_C + c0);
-          const uint16_t sh[4] = {(uint16_t)(side.x & 0xFFFFu), (uint16_t)(side.x >> 16), (uint16_t)(side.y & 0xFFFFu),
-                                  (uint16_t)(side.y >> 16)};
+          const uint16_t sh[4] = {(uint16_t)(side[m][t].x & 0xFFFFu), (uint16_t)(side[m][t].x >> 16),
+                                  (uint16_t)(side[m][t].y & 0xFFFFu), (uint16_t)(side[m][t].y >> 16)};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int co = c0 + e;
@@ -405,13 +450,10 @@ struct BlurTaps {
   float w[9];
 };
 
-__global__ void __launch_bounds__(256) k_disparity_blur(const uint16_t* __restrict__ X, int64_t npx, int W, float k,
-                                                         BlurTaps bw, uint16_t* __restrict__ XB) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npx) return;
-  const int x = (int)(p % W);
-  const int64_t row = p - x;
-  const float d = from_bf16(X[p * 4 + 3]);
+// One output pixel of the blur; px(i) returns input pixel i of the row.
+template <typename RowPx>
+__device__ __forceinline__ uint2 blur_pixel(RowPx px, int x, int W, float k, const BlurTaps& bw) {
+  const float d = from_bf16((uint16_t)(px(x).y >> 16));
   const float s = d > -1.0f ? k * d : 0.0f;
   float acc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -423,8 +465,8 @@ __global__ void __launch_bounds__(256) k_disparity_blur(const uint16_t* __restri
     const float f = u - fl;
     const int i0 = (int)fl;
     const int a = min(max(i0, 0), W - 1), b = min(max(i0 + 1, 0), W - 1);
-    const uint2 ca = *reinterpret_cast<const uint2*>(X + (row + a) * 4);
-    const uint2 cb = *reinterpret_cast<const uint2*>(X + (row + b) * 4);
+    const uint2 ca = px(a);
+    const uint2 cb = px(b);
     const float g = 1.0f - f;
     const float a0 = from_bf16((uint16_t)(ca.x & 0xFFFFu)), a1 = from_bf16((uint16_t)(ca.x >> 16)),
                 a2 = from_bf16((uint16_t)(ca.y & 0xFFFFu));
@@ -437,7 +479,35 @@ __global__ void __launch_bounds__(256) k_disparity_blur(const uint16_t* __restri
   uint2 o;
   o.x = (uint32_t)to_bf16(acc[0]) | ((uint32_t)to_bf16(acc[1]) << 16);
   o.y = (uint32_t)to_bf16(acc[2]);
-  reinterpret_cast<uint2*>(XB)[p] = o;
+  return o;
+}
+
+// Rows of up to kBlurRowMax pixels: a block stages a whole row (8 bytes per
+// pixel) in LDS with coalesced loads, and every tap is gathered from there.
+constexpr int kBlurRowMax = 4096;
+
+__global__ void __launch_bounds__(256) k_disparity_blur_rows(const uint16_t* __restrict__ X, int64_t nrows, int W,
+                                                              float k, BlurTaps bw, uint16_t* __restrict__ XB) {
+  extern __shared__ uint2 lrow[];  // W pixels
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const uint2* src = reinterpret_cast<const uint2*>(X) + r * W;
+    __syncthreads();  // the previous row's gathers are finished
+    for (int i = threadIdx.x; i < W; i += blockDim.x) lrow[i] = src[i];
+    __syncthreads();
+    uint2* dst = reinterpret_cast<uint2*>(XB) + r * W;
+    for (int x = threadIdx.x; x < W; x += blockDim.x)
+      dst[x] = blur_pixel([&](int i) { return lrow[i]; }, x, W, k, bw);
+  }
+}
+
+// Wider rows: one thread per pixel, taps gathered from global memory.
+__global__ void __launch_bounds__(256) k_disparity_blur(const uint16_t* __restrict__ X, int64_t npx, int W, float k,
+                                                         BlurTaps bw, uint16_t* __restrict__ XB) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npx) return;
+  const int x = (int)(p % W);
+  const uint2* row = reinterpret_cast<const uint2*>(X) + (p - x);
+  reinterpret_cast<uint2*>(XB)[p] = blur_pixel([&](int i) { return row[i]; }, x, W, k, bw);
 }
 
 // y[v][p][4] -> RGBA8, clamp(floor(255 y + 0.5)), alpha 255
@@ -667,7 +737,13 @@ int lfdpr_net_forward(lfdpr_net* net, const void* x, int32_t n_views, int32_t H,
   const int N = n_views, V = net->V;
   const int* d = kDilation;
   const int64_t npx = (int64_t)N * H * W;
-  k_disparity_blur<<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(in, npx, W, net->kscale, net->taps, net->xb);
+  if (W <= kBlurRowMax) {
+    const int64_t rows = (int64_t)N * H;
+    k_disparity_blur_rows<<<(unsigned)(rows < 4096 ? rows : 4096), 256, (size_t)W * sizeof(uint2), s>>>(
+        in, rows, W, net->kscale, net->taps, net->xb);
+  } else {
+    k_disparity_blur<<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(in, npx, W, net->kscale, net->taps, net->xb);
+  }
   launch_conv<2, MODE_RELU, true>(in, net->wf[0], net->master + net->off_b[0], N, H, W, V, d[0], net->act[1], kHidden, net->xb, 4, s);
   launch_conv<2, MODE_RELU, false>(net->act[1], net->wf[1], net->master + net->off_b[1], N, H, W, V, d[1], net->act[2], kHidden, nullptr, 0, s);
   launch_conv<2, MODE_RELU, false>(net->act[2], net->wf[2], net->master + net->off_b[2], N, H, W, V, d[2], net->act[3], kHidden, nullptr, 0, s);

@@ -80,9 +80,11 @@ def random_input(rng, n, H, W):
 
 
 @pytest.mark.parametrize("V,F,H,W,k", [(6, 1, 24, 40, 2.75), (48, 1, 8, 32, 9.05), (5, 2, 7, 13, 0.0),
-                                       (5, 2, 7, 13, 1.3)])
+                                       (5, 2, 7, 13, 1.3), (2, 1, 3, 4100, 40.0)])
 def test_forward_layers_match_oracle(torch_cuda, V, F, H, W, k):
-    """F frames of V views each, ragged pixel counts; disparity blur bit-exact."""
+    """F frames of V views each, ragged pixel counts; disparity blur bit-exact
+    (rows of up to 4096 pixels are blurred from LDS, wider ones by global
+    gathers: the last case)."""
     torch = torch_cuda
     from paper_2601_19901_amd import lfdpr
     R, net = make_net(torch, V, H, W * F)
