@@ -145,11 +145,35 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
   const int tiles_x = (W + kTX - 1) / kTX, tiles_y = (H + kTY - 1) / kTY;
   const int ntile = N * tiles_x * tiles_y;
   const int nstage = (kTY + 2) * TW * 4;  // <= kStagePerThread * 256 for DIL <= kMaxDil
+  // Tile order.  Image-major ([n][row band][column]), except for the gathering
+  // first layer: position-major with the view fastest, so the five output views
+  // that read one input view's tile follow each other.  Workgroups are handed to
+  // the 8 XCDs round robin and each XCD has its own L2, so the blocks of XCD c
+  // (blockIdx % 8 == c) take the c-th eighth of that order, in order: tiles that
+  // share halo rows and columns (or input views) then run at about the same time
+  // on the XCD that caches them.  Any other grid takes tiles blockIdx + k*grid.
+  const bool by_xcd = gridDim.x % 8 == 0 && ntile >= (int)gridDim.x;
+  const int xc = blockIdx.x % 8;
+  const int t_end = by_xcd ? (int)((int64_t)ntile * (xc + 1) / 8) : ntile;
+  const int t_first = by_xcd ? (int)((int64_t)ntile * xc / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int t_step = by_xcd ? (int)(gridDim.x / 8) : (int)gridDim.x;
+  auto decode = [&](int tile, int& n, int& y0, int& x0) {
+    int pos;
+    if (GATHER) {
+      n = tile % N;
+      pos = tile / N;
+    } else {
+      n = tile / (tiles_x * tiles_y);
+      pos = tile % (tiles_x * tiles_y);
+    }
+    y0 = (pos / tiles_x) * kTY;
+    x0 = (pos % tiles_x) * kTX;
+  };
   // the next tile's input is fetched into registers while this one computes
   uint4 pre[kStagePerThread];
   auto fetch = [&](int tile) {
-    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
-    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
+    int n, y0, x0;
+    decode(tile, n, y0, x0);
 #pragma unroll
     for (int j = 0; j < kStagePerThread; ++j) {
       const int k = threadIdx.x + j * 256;
@@ -170,15 +194,15 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
   // then do this tile's results leave.  Vector-memory waits count stores as well
   // as loads, so each wait (before staging) covers requests that have had a
   // whole tile of MFMAs to complete, never the stores just issued.
-  if (blockIdx.x < ntile) {
-    fetch(blockIdx.x);
+  if (t_first < t_end) {
+    fetch(t_first);
     stage();
     __syncthreads();  // weights and the first tile in LDS
-    if (blockIdx.x + (int)gridDim.x < ntile) fetch(blockIdx.x + gridDim.x);
+    if (t_first + t_step < t_end) fetch(t_first + t_step);
   }
-  for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int n = tile / (tiles_x * tiles_y), rem = tile % (tiles_x * tiles_y);
-    const int y0 = (rem / tiles_x) * kTY, x0 = (rem % tiles_x) * kTX;
+  for (int tile = t_first; tile < t_end; tile += t_step) {
+    int n, y0, x0;
+    decode(tile, n, y0, x0);
     const int y = y0 + wv;
     // the epilogue's side input (residual or ReLU mask), clamped into the image
     // and used only where in range: the residual is requested before the MFMAs;
@@ -205,7 +229,9 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+    // all nine taps unrolled: in a rolled loop the compiler moves the
+    // accumulators between AGPRs on every iteration (about 40 moves per 8 MFMAs)
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3 - 1, dx = tap % 3 - 1;
       Frag b[NT];
@@ -222,12 +248,12 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
       }
     }
     if (MODE == MODE_BWD) load_side();
-    const int next = tile + (int)gridDim.x;
+    const int next = tile + t_step;
     __syncthreads();  // every wave has finished reading this tile
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) on every path: all requests so far have landed
-    if (next < ntile) stage();
+    if (next < t_end) stage();
     __syncthreads();
-    if (next + (int)gridDim.x < ntile) fetch(next + gridDim.x);
+    if (next + t_step < t_end) fetch(next + t_step);
     // epilogue: lane holds D[4g+e][r16] = channel t*16 + 4g + e of pixel x0 + 16m + r16
     // (row y0 + wv); four consecutive channels leave as one 8-byte store
     if (y < H) {
