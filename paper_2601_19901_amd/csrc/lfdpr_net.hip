@@ -74,21 +74,22 @@ constexpr int kDilation[4] = {1, 3, 9, 1};
 // Loads the 8 K-values of lane group g for input pixel (n, yy, xx).  GATHER:
 // from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2,
 // n+2g-1; the slot after view n+2 (channels 20..23) takes the blur XB of view n.
+// Pixel indices fit in 32 bits: a network holds at most 2^26 pixels.
 template <bool GATHER>
 __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const uint16_t* __restrict__ XB, int n, int yy,
                                         int xx, int H, int W, int g, int V) {
   if (yy < 0 || yy >= H || xx < 0 || xx >= W) return uint4{0u, 0u, 0u, 0u};
-  if (!GATHER) return *reinterpret_cast<const uint4*>(X + (((size_t)n * H + yy) * W + xx) * kK + 8 * g);
+  if (!GATHER) return *reinterpret_cast<const uint4*>(X + (size_t)((n * H + yy) * W + xx) * kK + 8 * g);
   const int v = n % V, f0 = n - v;
   uint2 lo = {0u, 0u}, hi = {0u, 0u};
   const int o0 = 2 * g - kNeigh, o1 = 2 * g + 1 - kNeigh;
   if (o0 <= kNeigh && v + o0 >= 0 && v + o0 < V)
-    lo = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o0) * H + yy) * W + xx) * 4);
+    lo = *reinterpret_cast<const uint2*>(X + (size_t)(((f0 + v + o0) * H + yy) * W + xx) * 4);
   if (o1 <= kNeigh) {
     if (v + o1 >= 0 && v + o1 < V)
-      hi = *reinterpret_cast<const uint2*>(X + (((size_t)(f0 + v + o1) * H + yy) * W + xx) * 4);
+      hi = *reinterpret_cast<const uint2*>(X + (size_t)(((f0 + v + o1) * H + yy) * W + xx) * 4);
   } else if (o1 == kNeigh + 1) {
-    hi = *reinterpret_cast<const uint2*>(XB + (((size_t)n * H + yy) * W + xx) * 4);
+    hi = *reinterpret_cast<const uint2*>(XB + (size_t)((n * H + yy) * W + xx) * 4);
   }
   return uint4{lo.x, lo.y, hi.x, hi.y};
 }
@@ -177,6 +178,16 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     y0 = (pos / tiles_x) * kTY;
     x0 = (pos % tiles_x) * kTX;
   };
+  // Staging slots of this thread, the same for every tile: slot j is 16-byte
+  // group threadIdx % 4 of LDS pixel q = threadIdx / 4 + 64 j, at tile row
+  // q / TW and column q % TW (rows from kTY + 2 on lie past the staged tile).
+  int slot_rc[kStagePerThread];
+#pragma unroll
+  for (int j = 0; j < kStagePerThread; ++j) {
+    const int q = (int)(threadIdx.x >> 2) + 64 * j;
+    slot_rc[j] = ((q / TW) << 16) | (q % TW);
+  }
+  const int sg = threadIdx.x & 3;
   // the next tile's input is fetched into registers while this one computes
   uint4 pre[kStagePerThread];
   auto fetch = [&](int tile) {
@@ -184,10 +195,8 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     decode(tile, n, y0, x0);
 #pragma unroll
     for (int j = 0; j < kStagePerThread; ++j) {
-      const int k = threadIdx.x + j * 256;
-      const int gg = k & 3, q = k >> 2;
-      const int r = q / TW, px = q % TW;
-      pre[j] = k < nstage ? load_a<GATHER>(X, aux, n, y0 - 1 + r, x0 - DIL + px, H, W, gg, V) : uint4{0u, 0u, 0u, 0u};
+      const int r = slot_rc[j] >> 16, c = slot_rc[j] & 0xFFFF;
+      pre[j] = r < kTY + 2 ? load_a<GATHER>(X, aux, n, y0 - 1 + r, x0 - DIL + c, H, W, sg, V) : uint4{0u, 0u, 0u, 0u};
     }
   };
   auto stage = [&]() {
