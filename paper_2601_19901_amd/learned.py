@@ -169,6 +169,74 @@ class LearnedReconstruction:
         return self.out
 
 
+class LearnedPipeline:
+    """Learned frames to the panel with the network of frame i overlapping the
+    rendering of frame i+1.  Rendering stays on the renderer's stream; input
+    packing, the network, unpacking and the interleave run on a second stream
+    (default priority) through a context and a copy of the network of their
+    own.  Two view / depth buffer pairs alternate between the streams, fenced
+    by events: a buffer is rendered into again only after the network side has
+    packed it.  Every panel equals the serial path (reconstruct, then the
+    interleave) bit for bit; with poisoned parameters frames take the 4x
+    supersampling fallback serially."""
+
+    def __init__(self, lr_: LearnedReconstruction, lens: scenes.LensParams):
+        import torch
+        self.torch = torch
+        self.lr = lr_
+        self.ss = lr_.ss
+        V, H, W = self.ss.V, self.ss.H, self.ss.W
+        dev = "cuda:0"
+        self.stream = torch.cuda.Stream(device=0)
+        self.R = lfdpr.Renderer(0, stream=self.stream)
+        self.R.set_lens(lens)
+        self.net = lfdpr.Net(self.R, V, H, W)
+        self.net.set_disparity_scale(lfdpr.disparity_scale(self.ss.rigs[1].views))
+        self.views = [torch.empty((V, H, W), dtype=torch.int32, device=dev) for _ in range(2)]
+        self.depth = [torch.empty((V, H, W), dtype=torch.float32, device=dev) for _ in range(2)]
+        self.x = torch.empty((V, H, W, 4), dtype=torch.int16, device=dev)
+        self.y = torch.empty_like(self.x)
+        self.out = torch.empty((V, H, W), dtype=torch.int32, device=dev)
+        self.rendered = [torch.cuda.Event(), torch.cuda.Event()]
+        self.packed = [None, None]
+        self.n = 0
+        self.sync_params()
+
+    def sync_params(self):
+        """Copies the model's current parameters to the pipeline's network."""
+        self.torch.cuda.synchronize()
+        if self.lr.healthy:
+            self.net.set_params(self.lr.net.get_params())
+
+    def frame(self, k: int, frame: int, panel):
+        rig = self.ss.rigs[1]
+        rs = rig.renderer.stream
+        if not self.lr.healthy:
+            rs.wait_stream(self.stream)
+            self.ss.rigs[1].renderer.reconstruct(self.lr.reconstruct(k, frame), panel)
+            self.stream.wait_stream(rs)
+            return
+        s = self.n % 2
+        self.n += 1
+        if self.packed[s] is not None:
+            rs.wait_event(self.packed[s])
+        rig.renderer.render_frame(rig.scene_ids[k], self.ss.workloads[k].model(frame), self.views[s], self.depth[s])
+        self.rendered[s].record(rs)
+        self.stream.wait_event(self.rendered[s])
+        self.net.pack_input(self.views[s], self.depth[s], self.x, self.ss.D)
+        ev = self.torch.cuda.Event()
+        ev.record(self.stream)
+        self.packed[s] = ev
+        self.net.forward(self.x, self.y)
+        self.net.unpack_output(self.y, self.out)
+        self.R.reconstruct(self.out, panel)
+
+    def close(self):
+        self.torch.cuda.synchronize()
+        self.net.close()
+        self.R.close()
+
+
 def evaluate(lr_: LearnedReconstruction, frames: Sequence, ref_S: int, fallback_S: int = 4) -> dict:
     """PSNR of plain 1x, learned and 4x-supersampled views against a high-factor
     angular supersampling reference, and against the 4x result."""
@@ -191,7 +259,9 @@ def evaluate(lr_: LearnedReconstruction, frames: Sequence, ref_S: int, fallback_
 
 def time_pipelines(lr_: LearnedReconstruction, lens: scenes.LensParams, k: int, frames: Sequence[int],
                    fallback_S: int = 4) -> dict:
-    """Frame time (ms) to the panel: 1x plain, learned, and 4x supersampled + filter."""
+    """Frame time (ms) to the panel: 1x plain, learned (network of a frame
+    overlapping the next frame's rendering; learned_serial_ms without that
+    overlap), and 4x supersampled + filter."""
     torch = lr_.torch
     ss = lr_.ss
     R1 = ss.rigs[1].renderer
@@ -216,12 +286,19 @@ def time_pipelines(lr_: LearnedReconstruction, lens: scenes.LensParams, k: int, 
     def learned(f):
         R1.reconstruct(lr_.reconstruct(k, f), panel)
 
+    pipe = LearnedPipeline(lr_, lens)
+
+    def learned_overlapped(f):
+        pipe.frame(k, f, panel)
+
     def ss4(f):
         R1.reconstruct(ss.render_ss(k, f, fallback_S), panel)
 
     run("plain_1x_ms", plain)
-    run("learned_ms", learned)
+    run("learned_ms", learned_overlapped)
+    run("learned_serial_ms", learned)
     run("ss4_ms", ss4)
+    pipe.close()
     return out
 
 

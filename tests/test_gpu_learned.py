@@ -58,3 +58,54 @@ def test_fallback_on_poisoned_parameters(trained):
     ref = ss.render_ss(3, 5, 4)
     assert learned.psnr_views(out, ref) == math.inf
     assert model.set_params(good) and model.healthy
+
+
+def test_overlapped_frames_equal_serial_frames(trained):
+    """LearnedPipeline (network of frame i on its own stream while frame i+1
+    renders, two alternating buffers) gives every panel bit for bit as the
+    serial path; a poisoned-parameter frame in the middle takes the fallback."""
+    learned, ss, model, _, _, _ = trained
+    import torch
+    lens = ss.workloads[3].lens
+    R1 = ss.rigs[1].renderer
+    R1.set_lens(lens)
+    frames = [5, 6, 7, 300, 301, 999, 0]
+
+    def new_panel():
+        return torch.empty((lens.Hp, lens.Wp, 3), dtype=torch.uint8, device="cuda")
+
+    serial = []
+    for f in frames:
+        p = new_panel()
+        R1.reconstruct(model.reconstruct(3, f), p)
+        serial.append(p.cpu().numpy())
+    pipe = learned.LearnedPipeline(model, lens)
+    panels = []
+    for f in frames:
+        p = new_panel()
+        pipe.frame(3, f, p)
+        panels.append(p)
+    torch.cuda.synchronize()
+    for f, a, b in zip(frames, serial, panels):
+        np.testing.assert_array_equal(b.cpu().numpy(), a, err_msg=f"frame {f}")
+    # fallback in the middle of overlapped frames
+    good = model.net.get_params()
+    bad = good.copy()
+    bad[3] = np.nan
+    out = []
+    for f, ok in ((10, True), (11, False), (12, True)):
+        assert model.set_params(good if ok else bad) == ok
+        p = new_panel()
+        pipe.frame(3, f, p)
+        out.append(p)
+    torch.cuda.synchronize()
+    want = []
+    for f, ok in ((10, True), (11, False), (12, True)):
+        model.set_params(good if ok else bad)
+        p = new_panel()
+        R1.reconstruct(model.reconstruct(3, f), p)
+        want.append(p.cpu().numpy())
+    model.set_params(good)
+    for (f, _), a, b in zip(((10, 0), (11, 0), (12, 0)), want, out):
+        np.testing.assert_array_equal(b.cpu().numpy(), a, err_msg=f"frame {f} around the fallback")
+    pipe.close()
