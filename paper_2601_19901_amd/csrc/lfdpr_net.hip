@@ -28,6 +28,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lfdpr.h"
@@ -71,10 +72,11 @@ constexpr int kK = 32;      // padded input channels of every layer (one MFMA K 
 // pixels across, so the stack sees +-14 px horizontally and +-4 px vertically.
 constexpr int kDilation[4] = {1, 3, 9, 1};
 
-// Loads the 8 K-values of lane group g for input pixel (n, yy, xx).  GATHER:
-// from the compact [n][H][W][4] input, channels 8g..8g+7 = views n+2g-2,
-// n+2g-1; the slot after view n+2 (channels 20..23) takes the blur XB of view n.
-// Pixel indices fit in 32 bits: a network holds at most 2^26 pixels.
+// Loads the 8 K-values of lane group g for input pixel (n, yy, xx), zero
+// outside the image.  GATHER: from the compact [n][H][W][4] input, channels
+// 8g..8g+7 = views n+2g-2, n+2g-1; the slot after view n+2 (channels 20..23)
+// takes the blur XB of view n.  Pixel indices fit in 32 bits: a network holds
+// at most 2^26 pixels.
 template <bool GATHER>
 __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const uint16_t* __restrict__ XB, int n, int yy,
                                         int xx, int H, int W, int g, int V) {
@@ -110,6 +112,8 @@ static_assert(kDilation[0] <= kMaxDil && kDilation[1] <= kMaxDil && kDilation[2]
                   kDilation[3] <= kMaxDil,
               "dilation beyond the staged halo");
 constexpr int kStagePerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * 4 + 255) / 256;
+constexpr int kPlanes = 2 * kNeigh + 2;  // layer 1's sources: five views and the blur
+constexpr int kGatherPerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * kPlanes + 255) / 256;
 
 __device__ __forceinline__ int swz(int row, int g) { return row * 4 + (g ^ ((row >> 1) & 3)); }
 
@@ -178,32 +182,73 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     y0 = (pos / tiles_x) * kTY;
     x0 = (pos % tiles_x) * kTX;
   };
-  // Staging slots of this thread, the same for every tile: slot j is 16-byte
-  // group threadIdx % 4 of LDS pixel q = threadIdx / 4 + 64 j, at tile row
-  // q / TW and column q % TW (rows from kTY + 2 on lie past the staged tile).
-  int slot_rc[kStagePerThread];
+  // Staging items of this thread, the same for every tile.  Layers 2-4: item j
+  // is 16-byte group threadIdx % 4 of LDS pixel q = threadIdx / 4 + 64 j, at
+  // tile row q / TW and column q % TW (rows from kTY + 2 on lie past the staged
+  // tile).  Layer 1 (GATHER) stages plane by plane -- views v-2 .. v+2 of the
+  // compact input, then the blur, 8 bytes per pixel -- so each wave load reads
+  // 64 consecutive pixels of one plane: item j = threadIdx + 256 j is plane
+  // j' / ((kTY + 2) TW), then row and column; plane p fills half p % 2 of
+  // group p / 2, and group 3 (channels 24-31) stays zero.
+  constexpr int kSlots = GATHER ? kGatherPerThread : kStagePerThread;
+  int geo[kSlots];
 #pragma unroll
-  for (int j = 0; j < kStagePerThread; ++j) {
-    const int q = (int)(threadIdx.x >> 2) + 64 * j;
-    slot_rc[j] = ((q / TW) << 16) | (q % TW);
+  for (int j = 0; j < kSlots; ++j) {
+    if (GATHER) {
+      const int i = (int)threadIdx.x + 256 * j, m = (kTY + 2) * TW;
+      const int pl = i / m, rem = i % m;
+      geo[j] = (pl << 24) | ((rem / TW) << 16) | (rem % TW);
+    } else {
+      const int q = (int)(threadIdx.x >> 2) + 64 * j;
+      geo[j] = ((q / TW) << 16) | (q % TW);
+    }
   }
   const int sg = threadIdx.x & 3;
+  if (GATHER) {  // the zero group: the whole tile once, before any staging
+    for (int k = threadIdx.x; k < nstage; k += blockDim.x) tl[k] = uint4{0u, 0u, 0u, 0u};
+    __syncthreads();
+  }
   // the next tile's input is fetched into registers while this one computes
-  uint4 pre[kStagePerThread];
+  typename std::conditional<GATHER, uint2, uint4>::type pre[kSlots];
   auto fetch = [&](int tile) {
     int n, y0, x0;
     decode(tile, n, y0, x0);
+    if constexpr (GATHER) {
+      const int vv = n % V, f0 = n - vv;
 #pragma unroll
-    for (int j = 0; j < kStagePerThread; ++j) {
-      const int r = slot_rc[j] >> 16, c = slot_rc[j] & 0xFFFF;
-      pre[j] = r < kTY + 2 ? load_a<GATHER>(X, aux, n, y0 - 1 + r, x0 - DIL + c, H, W, sg, V) : uint4{0u, 0u, 0u, 0u};
+      for (int j = 0; j < kSlots; ++j) {
+        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, c = geo[j] & 0xFFFF;
+        const int yy = y0 - 1 + r, xx = x0 - DIL + c;
+        uint2 val = {0u, 0u};
+        if (pl < kPlanes && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+          if (pl < kPlanes - 1) {
+            const int vo = vv + pl - kNeigh;
+            if (vo >= 0 && vo < V)
+              val = *reinterpret_cast<const uint2*>(X + (size_t)(((f0 + vo) * H + yy) * W + xx) * 4);
+          } else {
+            val = *reinterpret_cast<const uint2*>(aux + (size_t)((n * H + yy) * W + xx) * 4);
+          }
+        }
+        pre[j] = val;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kSlots; ++j) {
+        const int r = geo[j] >> 16, c = geo[j] & 0xFFFF;
+        pre[j] = r < kTY + 2 ? load_a<false>(X, nullptr, n, y0 - 1 + r, x0 - DIL + c, H, W, sg, V) : uint4{0u, 0u, 0u, 0u};
+      }
     }
   };
   auto stage = [&]() {
 #pragma unroll
-    for (int j = 0; j < kStagePerThread; ++j) {
-      const int k = threadIdx.x + j * 256;
-      if (k < nstage) tl[swz(k >> 2, k & 3)] = pre[j];
+    for (int j = 0; j < kSlots; ++j) {
+      if constexpr (GATHER) {
+        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, c = geo[j] & 0xFFFF;
+        if (pl < kPlanes) reinterpret_cast<uint2*>(&tl[swz(r * TW + c, pl >> 1)])[pl & 1] = pre[j];
+      } else {
+        const int k = threadIdx.x + j * 256;
+        if (k < nstage) tl[swz(k >> 2, k & 3)] = pre[j];
+      }
     }
   };
   // Software pipeline per tile: MFMAs on the staged tile; then the next tile
