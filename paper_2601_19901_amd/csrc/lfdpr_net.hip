@@ -355,13 +355,15 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 }
 
 // ---------------------------------------------------------------- weight gradient
-// dW[tap][co][ci] += sum_p dZ[p][co] * A[p + off(tap)][ci].  A block owns a
+// dW[tap][co][ci] = sum_p dZ[p][co] * A[p + off(tap)][ci].  A block owns a
 // chunk of pixels; 256 of them at a time it stages dZ, and for each tap the
 // shifted activations, in LDS channel-major (rows of 256 pixels padded by 16
 // bytes, so the 8 lanes of a 128-byte read group hit distinct banks); wave w
 // then reduces its (co tile w/2, ci tile w%2) over the pixels with one MFMA
-// per 32 pixels (M = co, N = ci, K = pixels).  Sums leave once per chunk.
+// per 32 pixels (M = co, N = ci, K = pixels).  Each block writes its sums to
+// its own row of a partials buffer, which k_sum_partials adds in block order.
 constexpr int kWgPix = 256;
+constexpr int kMaxGradBlocks = 1024;  // blocks of one gradient sum (partials buffer rows)
 constexpr int kWgPitch = kWgPix + 8;  // bf16 per LDS row
 
 __device__ __forceinline__ void put_cols(uint16_t* T, int col, const uint4 (&v)[4]) {
@@ -436,44 +438,87 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const uint16_t* __restrict__
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int co = ct * 16 + 4 * g + e;
-        if (co < CO && ci < CI) atomicAdd(&dW[((size_t)tap * CO + co) * CI + ci], acc[tap][e]);
+        if (co < CO && ci < CI) dW[(size_t)blockIdx.x * 9 * CO * CI + ((size_t)tap * CO + co) * CI + ci] = acc[tap][e];
       }
   }
 }
 
-__global__ void k_bias_grad(const uint16_t* __restrict__ dZ, int DZS, int npx, int chunk, float* __restrict__ db) {
-  const int co = blockIdx.x;
-  const int p0 = blockIdx.y * chunk, p1 = min(npx, p0 + chunk);
-  float s = 0.0f;
-  for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) s += from_bf16(dZ[(size_t)p * DZS + co]);
-  __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
+__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* __restrict__ dZ, int CO, int npx, int chunk,
+                                                    float* __restrict__ db) {
+  // db[block][c] = sum over the block's pixels of dZ[p][c] (dZ [p][32] BF16):
+  // thread t adds channels 8(t % 4) .. +7 of pixels t / 4, t / 4 + 64, .. from
+  // 16-byte loads; the 64 partial sums of each channel meet in LDS
+  __shared__ float red[8][256];
+  const int g = threadIdx.x & 3, q = threadIdx.x >> 2;
+  const int p0 = blockIdx.x * chunk, p1 = min(npx, p0 + chunk);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int p = p0 + q; p < p1; p += 64) {
+    const uint4 v = *reinterpret_cast<const uint4*>(dZ + (size_t)p * kK + 8 * g);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      acc[2 * h] += from_bf16((uint16_t)(w[h] & 0xFFFFu));
+      acc[2 * h + 1] += from_bf16((uint16_t)(w[h] >> 16));
+    }
   }
-  if (threadIdx.x == 0) atomicAdd(&db[co], red[0]);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) red[e][threadIdx.x] = acc[e];
+  __syncthreads();
+  if ((int)threadIdx.x < CO) {
+    const int c = threadIdx.x, gg = c >> 3, e = c & 7;
+    float sum = 0.0f;
+    for (int k = 0; k < 64; ++k) sum += red[e][gg + 4 * k];
+    db[(size_t)blockIdx.x * CO + c] = sum;
+  }
+}
+
+// out[i] = sum over the nblk rows of part[b][i] in a fixed order, so gradients
+// come out the same on every run (no atomics in their sums): in a block of 256,
+// lane (phase f = t / 16, column j = t % 16) adds rows f, f + 16, .. in
+// ascending order, then the 16 phase sums of each column are added in phase
+// order.  Grid: ceil(n / 16) blocks.
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nblk, int n,
+                                                       float* __restrict__ out) {
+  __shared__ float red[16][17];
+  const int j = threadIdx.x & 15, f = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + j;
+  float sum = 0.0f;
+  if (i < n) {
+#pragma unroll 8
+    for (int b = f; b < nblk; b += 16) sum += part[(size_t)b * n + i];
+  }
+  red[f][j] = sum;
+  __syncthreads();
+  if (f == 0 && i < n) {
+    float total = 0.0f;
+    for (int k = 0; k < 16; ++k) total += red[k][j];
+    out[i] = total;
+  }
 }
 
 // loss = mean((y - t)^2) over the 3 colour channels of npx pixels (inputs
-// [p][4]); dZ = bf16(2 (y - t) / n) into a [p][32] buffer (other channels 0).
-// Grid-stride, one loss atomic per block.
-__global__ void k_mse(const uint16_t* __restrict__ Yb, const uint16_t* __restrict__ T, int npx,
-                      uint16_t* __restrict__ dZ, float* __restrict__ loss) {
+// [p][4]); dZ = bf16(2 (y - t) / n) into a [p][32] buffer (other channels 0),
+// one pixel (four 16-byte stores) per thread.  Grid-stride, one loss atomic per
+// block.
+__global__ void __launch_bounds__(256) k_mse(const uint16_t* __restrict__ Yb, const uint16_t* __restrict__ T, int npx,
+                                              uint16_t* __restrict__ dZ, float* __restrict__ loss) {
   const int64_t n = (int64_t)npx * 3;
-  const int64_t ne = (int64_t)npx * kK;
   float sq = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = i / kK;
-    const int c = (int)(i % kK);
-    uint16_t out = 0;
-    if (c < 3) {
-      const float d = from_bf16(Yb[p * 4 + c]) - from_bf16(T[p * 4 + c]);
-      sq += d * d;
-      out = to_bf16((2.0f * d) / (float)n);
-    }
-    dZ[i] = out;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npx; p += (int64_t)gridDim.x * blockDim.x) {
+    const uint2 yv = *reinterpret_cast<const uint2*>(Yb + p * 4);
+    const uint2 tv = *reinterpret_cast<const uint2*>(T + p * 4);
+    const float d0 = from_bf16((uint16_t)(yv.x & 0xFFFFu)) - from_bf16((uint16_t)(tv.x & 0xFFFFu));
+    const float d1 = from_bf16((uint16_t)(yv.x >> 16)) - from_bf16((uint16_t)(tv.x >> 16));
+    const float d2 = from_bf16((uint16_t)(yv.y & 0xFFFFu)) - from_bf16((uint16_t)(tv.y & 0xFFFFu));
+    sq += d0 * d0;
+    sq += d1 * d1;
+    sq += d2 * d2;
+    uint4* out = reinterpret_cast<uint4*>(dZ + p * kK);
+    out[0] = uint4{(uint32_t)to_bf16((2.0f * d0) / (float)n) | ((uint32_t)to_bf16((2.0f * d1) / (float)n) << 16),
+                   (uint32_t)to_bf16((2.0f * d2) / (float)n), 0u, 0u};
+    out[1] = uint4{0u, 0u, 0u, 0u};
+    out[2] = uint4{0u, 0u, 0u, 0u};
+    out[3] = uint4{0u, 0u, 0u, 0u};
   }
   __shared__ float red[256];
   red[threadIdx.x] = sq;
@@ -648,6 +693,7 @@ struct lfdpr_net {
   const uint16_t* last_y = nullptr;
   int last_n = 0, last_h = 0, last_w = 0;
   float* d_loss = nullptr;
+  float* part = nullptr;   // per-block partial gradients: kMaxGradBlocks x (9*32*32 + 32)
   std::string err;
 };
 
@@ -713,6 +759,7 @@ int lfdpr_net_create(lfdpr_ctx* ctx, int32_t V, int32_t max_h, int32_t max_w, lf
   al(net->adam_m, off);
   al(net->adam_v, off);
   al(net->d_loss, 1);
+  al(net->part, (size_t)kMaxGradBlocks * (9 * kHidden * kHidden + kHidden));
   for (int k = 0; k < 4; ++k) {
     al(net->wf[k], 9ll * net->cof[k] * kK);
     if (k > 0) al(net->wb[k], 9ll * ci[k] * kK);
@@ -758,6 +805,7 @@ int lfdpr_net_destroy(lfdpr_net* net) {
   (void)hipFree(net->adam_m);
   (void)hipFree(net->adam_v);
   (void)hipFree(net->d_loss);
+  (void)hipFree(net->part);
   for (int k = 0; k < 4; ++k) { (void)hipFree(net->wf[k]); (void)hipFree(net->wb[k]); (void)hipFree(net->act[k]); }
   for (int k = 0; k < 5; ++k) (void)hipFree(net->dz[k]);
   (void)hipFree(net->xb);
@@ -854,23 +902,29 @@ int lfdpr_net_backward(lfdpr_net* net, const void* target, float* loss) {
   const int npx = N * H * W;
   k_zero_f32<<<(unsigned)((net->nparams + 255) / 256), 256, 0, s>>>(net->grad, net->nparams);
   k_zero_f32<<<1, 64, 0, s>>>(net->d_loss, 1);
-  const int64_t ne = (int64_t)npx * kK;
-  const int64_t mse_blocks = (ne + 255) / 256;
+  const int64_t mse_blocks = ((int64_t)npx + 255) / 256;
   k_mse<<<(unsigned)(mse_blocks < 2048 ? mse_blocks : 2048), 256, 0, s>>>(net->last_y, (const uint16_t*)target, npx,
                                                                            net->dz[4], net->d_loss);
-  const int chunk = 4096;  // pixels per block of the weight gradient
+  // Gradient sums: at most kMaxGradBlocks blocks each (multiples of 256 pixels
+  // for the weights, of 64 for the biases), then k_sum_partials in block order.
+  const int chunk = (int)((((int64_t)npx + kMaxGradBlocks - 1) / kMaxGradBlocks + 255) / 256 * 256);
   const unsigned nch = (unsigned)((npx + chunk - 1) / chunk);
+  const int bchunk = (int)((((int64_t)npx + kMaxGradBlocks - 1) / kMaxGradBlocks + 63) / 64 * 64);
+  const unsigned nbch = (unsigned)((npx + bchunk - 1) / bchunk);
+  float* const part_w = net->part;
+  float* const part_b = net->part + (size_t)kMaxGradBlocks * 9 * kHidden * kHidden;
   for (int k = 3; k >= 0; --k) {
     const int CO = net->co[k], CI = net->ci[k];
     if (k == 0)
       k_conv_wgrad<true><<<nch, 256, 0, s>>>(net->dz[1], CO, net->last_x, net->xb, CI, N, H, W, V, kDilation[0],
-                                             net->grad + net->off_w[0], chunk);
+                                             part_w, chunk);
     else
       k_conv_wgrad<false><<<nch, 256, 0, s>>>(net->dz[k + 1], CO, net->act[k], nullptr, CI, N, H, W, V, kDilation[k],
-                                              net->grad + net->off_w[k], chunk);
-    const int bchunk = 16384;
-    k_bias_grad<<<dim3((unsigned)CO, (unsigned)((npx + bchunk - 1) / bchunk)), 256, 0, s>>>(net->dz[k + 1], kK, npx, bchunk,
-                                                                                              net->grad + net->off_b[k]);
+                                              part_w, chunk);
+    const int nw = 9 * CO * CI;
+    k_sum_partials<<<(unsigned)((nw + 15) / 16), 256, 0, s>>>(part_w, (int)nch, nw, net->grad + net->off_w[k]);
+    k_bias_grad<<<nbch, 256, 0, s>>>(net->dz[k + 1], CO, npx, bchunk, part_b);
+    k_sum_partials<<<(unsigned)((CO + 15) / 16), 256, 0, s>>>(part_b, (int)nbch, CO, net->grad + net->off_b[k]);
     if (k > 0)  // input gradient through the flipped, transposed weights (same dilation), masked by the ReLU
       launch_conv<2, MODE_BWD, false>(net->dz[k + 1], net->wb[k], nullptr, N, H, W, V, kDilation[k], net->dz[k], kHidden,
                                       net->act[k], kHidden, s);
