@@ -104,8 +104,9 @@ __device__ __forceinline__ uint4 load_a(const uint16_t* __restrict__ X, const ui
 // 32 channels are four 16-byte groups stored at slot g ^ ((px >> 1) & 3): LDS
 // serves 16-byte reads eight lanes (128 bytes) at a time, and any 8
 // consecutive pixels then fall into 8 distinct bank groups (no conflicts on
-// gfx950 by the SQ_LDS_BANK_CONFLICT counter).  aux: GATHER, the blur buffer; MODE_OUT, the residual (stride AUX_C);
-// MODE_BWD, the activation whose ReLU masks the gradient.
+// gfx950 by the SQ_LDS_BANK_CONFLICT counter).  aux: GATHER, the blur buffer;
+// MODE_OUT, the residual (stride AUX_C); MODE_BWD, the activation whose ReLU
+// masks the gradient.
 constexpr int kTX = 64, kTY = 4;
 constexpr int kMaxDil = 9;  // the staging registers are sized for it
 static_assert(kDilation[0] <= kMaxDil && kDilation[1] <= kMaxDil && kDilation[2] <= kMaxDil &&
@@ -136,11 +137,11 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
   const int g = lane >> 4, r16 = lane & 15;
   for (int k = threadIdx.x; k < 9 * COUT * 4; k += blockDim.x)
     wlds[swz(k >> 2, k & 3)] = reinterpret_cast<const uint4*>(Wt)[k];
-  // the MFMA computes D = W x A (rows: output channels, columns: pixels), so
-  // lane (g, r16) ends with channels t*16 + 4g .. +3 of pixel r16 of each M tile
   // Loads whose results the epilogue uses are unconditional (clamped indices):
   // a load issued under a branch leaves the compiler unsure that a later wait
   // covered it, and it would then wait for all memory traffic in the epilogue.
+  // The MFMA computes D = W x A (rows: output channels, columns: pixels), so
+  // lane (g, r16) ends with channels t*16 + 4g .. +3 of pixel r16 of each M tile.
   float bco[NT][4];  // their biases (3 in the output layer)
   const int nbias = MODE == MODE_BWD ? 0 : (MODE == MODE_OUT ? 3 : YS);
 #pragma unroll
