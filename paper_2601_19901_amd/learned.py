@@ -308,7 +308,7 @@ def main(argv=None):
     ap.add_argument("--train-frames", type=int, default=2000)
     ap.add_argument("--test-scenes", type=int, default=2)
     ap.add_argument("--test-frames", type=int, default=200)
-    ap.add_argument("--steps-per-frame", type=int, default=24)
+    ap.add_argument("--steps-per-frame", type=int, default=48)
     ap.add_argument("--crop", type=int, default=128)
     ap.add_argument("--ref-S", type=int, default=16)
     ap.add_argument("--small", action="store_true", help="small-display family (CPU-oracle size) for a quick run")
