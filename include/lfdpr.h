@@ -295,6 +295,16 @@ const char* lfdpr_batch_last_error(lfdpr_batch* batch);
  * hipGraph and later calls with the same output pointers replay it; 0: plain
  * launches. */
 int lfdpr_batch_use_graph(lfdpr_batch* batch, int enable);
+/* 2: the point generation of a batch call (set-up, scan, emission; Sec. 3.1)
+ * runs on a stream of the batch's own while the previous call's splat runs,
+ * into a second set of generation buffers (allocated here: points, triangle
+ * records, counts; as much device memory again); the splat still follows
+ * earlier work on the context's stream, so results are identical.  Pipelined
+ * calls launch their kernels directly (no graph).  1 (default): one set, the
+ * graph replay of lfdpr_batch_use_graph.  Synchronises the batch; statistics
+ * describe the last call either way.  LFDPR_EINVAL for other values,
+ * LFDPR_ENOMEM (nothing changed) if the second set cannot be allocated. */
+int lfdpr_batch_set_frames_in_flight(lfdpr_batch* batch, int32_t n);
 /* models: host n*12 floats (row-major 3x4 per item); views: device
  * n*(V*S)*H*W uint32 RGBA8, item-major; panels: device n*Hp*Wp*3 bytes
  * interleaved with the context's lens (requires S == 1), or NULL.  Ordered

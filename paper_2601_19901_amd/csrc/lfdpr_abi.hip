@@ -918,6 +918,28 @@ struct lfdpr_batch {
   hipGraphExec_t exec = nullptr;
   uint32_t* g_views = nullptr;
   uint8_t* g_panels = nullptr;
+  // Two batch frames in flight: a second set of generation buffers, swapped
+  // with the fields above at every call, point generation on `gen` while the
+  // previous call splats on `stream`.
+  struct GenSet {
+    Model* d_models = nullptr;
+    Model* h_models = nullptr;
+    hipEvent_t ev_stage = nullptr;
+    uint32_t* counts = nullptr;
+    uint64_t* offsets = nullptr;
+    TriRec* rec = nullptr;
+    TriEmit* em = nullptr;
+    uint64_t* tiles = nullptr;
+    uint32_t* big = nullptr;
+    uint64_t* stats = nullptr;
+    Point* points = nullptr;
+    TriMat* tm = nullptr;
+    uint4* pmat = nullptr;
+  } alt;
+  int in_flight = 1, slot = 0;
+  hipStream_t gen = nullptr;
+  hipEvent_t ev_gen[2] = {nullptr, nullptr}, ev_spl[2] = {nullptr, nullptr};
+  bool spl_pending[2] = {false, false};
   std::string err;
 };
 
@@ -933,6 +955,58 @@ int bfail(lfdpr_batch* b, int code, const std::string& m) {
     hipError_t e_ = (call);                                                                         \
     if (e_ != hipSuccess) return bfail(b, LFDPR_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// The second buffer set, the generation stream and its events.
+void batch_free_alt(lfdpr_batch* b) {
+  lfdpr_batch::GenSet& a = b->alt;
+  dfree(a.d_models);
+  if (a.h_models) (void)hipHostFree(a.h_models);
+  a.h_models = nullptr;
+  if (a.ev_stage) (void)hipEventDestroy(a.ev_stage);
+  a.ev_stage = nullptr;
+  dfree(a.counts);
+  dfree(a.offsets);
+  dfree(a.rec);
+  dfree(a.em);
+  dfree(a.tiles);
+  dfree(a.big);
+  dfree(a.stats);
+  dfree(a.points);
+  dfree(a.tm);
+  dfree(a.pmat);
+  for (int k = 0; k < 2; ++k) {
+    if (b->ev_gen[k]) (void)hipEventDestroy(b->ev_gen[k]);
+    if (b->ev_spl[k]) (void)hipEventDestroy(b->ev_spl[k]);
+    b->ev_gen[k] = b->ev_spl[k] = nullptr;
+    b->spl_pending[k] = false;
+  }
+  if (b->gen) (void)hipStreamDestroy(b->gen);
+  b->gen = nullptr;
+}
+
+void batch_swap_sets(lfdpr_batch* b) {
+  lfdpr_batch::GenSet& a = b->alt;
+  std::swap(b->d_models, a.d_models);
+  std::swap(b->h_models, a.h_models);
+  std::swap(b->ev_stage, a.ev_stage);
+  std::swap(b->counts, a.counts);
+  std::swap(b->offsets, a.offsets);
+  std::swap(b->rec, a.rec);
+  std::swap(b->em, a.em);
+  std::swap(b->tiles, a.tiles);
+  std::swap(b->big, a.big);
+  std::swap(b->stats, a.stats);
+  std::swap(b->points, a.points);
+  std::swap(b->tm, a.tm);
+  std::swap(b->pmat, a.pmat);
+}
+
+// Every stream of the batch idle.
+hipError_t batch_sync(lfdpr_batch* b) {
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess && b->gen) e = hipStreamSynchronize(b->gen);
+  return e;
+}
 
 void batch_free(lfdpr_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -952,16 +1026,17 @@ void batch_free(lfdpr_batch* b) {
   dfree(b->points);
   dfree(b->tm);
   dfree(b->pmat);
+  batch_free_alt(b);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
   if (b->ev_stage) (void)hipEventDestroy(b->ev_stage);
   if (b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// The whole batch frame on b->stream: only kernel launches (capturable), plus
-// stage events when `timed` (never while capturing).
-void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed) {
-  hipStream_t st = b->stream;
+// Point generation of a batch frame (statistics reset, set-up, scan, emission)
+// on stream st: only kernel launches (capturable), plus stage events when
+// `timed` (never while capturing).  Returns the mark at its end (timed).
+hipEvent_t batch_gen(lfdpr_batch* b, hipStream_t st, bool timed) {
   lfdpr_ctx* ctx = b->ctx;
   const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
   auto ev = [&]() { return timed ? mark_on(ctx, st) : nullptr; };
@@ -997,6 +1072,18 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed)
   ea.pmat = pbr ? b->pmat : nullptr;
   launch_emit(ea, b->splat_blocks, st);
   hipEvent_t e3 = ev();
+  stage(ctx, 0, e0, e1);
+  stage(ctx, 1, e1, e2);
+  stage(ctx, 2, e2, e3);
+  return e3;
+}
+
+// Splat, resolve and interleave of a batch frame on stream st; e3 marks the
+// start of the splat stage when `timed`.
+void batch_splat(lfdpr_batch* b, uint32_t* views, uint8_t* panels, hipStream_t st, bool timed, hipEvent_t e3) {
+  lfdpr_ctx* ctx = b->ctx;
+  const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
+  auto ev = [&]() { return timed ? mark_on(ctx, st) : nullptr; };
   SplatArgs pa{};
   pa.items = b->d_items;
   pa.n_items = b->n;
@@ -1019,16 +1106,19 @@ void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed)
     launch_interleave_batch(ia, b->n, b->per_item_px, (int64_t)b->ctx->lens.Wp * b->ctx->lens.Hp * 3, st);
     stage(ctx, 5, e5, ev());
   }
-  stage(ctx, 0, e0, e1);
-  stage(ctx, 1, e1, e2);
-  stage(ctx, 2, e2, e3);
   stage(ctx, 3, e3, e4);
   stage(ctx, 4, e4, e5);
 }
 
+// The whole batch frame on b->stream.
+void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed) {
+  const hipEvent_t e3 = batch_gen(b, b->stream, timed);
+  batch_splat(b, views, panels, b->stream, timed, e3);
+}
+
 int batch_set_shape(lfdpr_batch* b, int splat_blocks, int key_layout) {
   if (splat_blocks == b->splat_blocks && key_layout == b->key_layout) return LFDPR_OK;
-  BHIP(hipStreamSynchronize(b->stream));
+  BHIP(batch_sync(b));
   b->splat_blocks = splat_blocks;
   if (key_layout != b->key_layout) {
     b->key_layout = key_layout;
@@ -1132,7 +1222,7 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
 int lfdpr_batch_destroy(lfdpr_batch* b) {
   if (!b) return LFDPR_OK;
   (void)hipSetDevice(b->ctx->device);
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  (void)batch_sync(b);
   for (int32_t id : b->scene_ids) {
     auto it = b->ctx->scenes.find(id);
     if (it != b->ctx->scenes.end()) it->second.batch_refs -= 1;
@@ -1148,6 +1238,43 @@ const char* lfdpr_batch_last_error(lfdpr_batch* b) { return b ? b->err.c_str() :
 int lfdpr_batch_use_graph(lfdpr_batch* b, int enable) {
   if (!b) return LFDPR_EINVAL;
   b->use_graph = enable != 0;
+  return LFDPR_OK;
+}
+
+int lfdpr_batch_set_frames_in_flight(lfdpr_batch* b, int32_t n) {
+  if (!b) return LFDPR_EINVAL;
+  if (n != 1 && n != 2) return bfail(b, LFDPR_EINVAL, "frames in flight must be 1 or 2");
+  if (n == b->in_flight) return LFDPR_OK;
+  BHIP(hipSetDevice(b->ctx->device));
+  BHIP(batch_sync(b));
+  b->g_valid = false;  // a captured graph names the buffers of one set
+  if (n == 1) {
+    batch_free_alt(b);
+    b->in_flight = 1;
+    return LFDPR_OK;
+  }
+  const int64_t ntb = b->nt > 1024 ? b->nt : 1024;
+  lfdpr_batch::GenSet& a = b->alt;
+  bool ok = hipStreamCreateWithFlags(&b->gen, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&a.ev_stage, hipEventDisableTiming) == hipSuccess &&
+            hipEventRecord(a.ev_stage, b->gen) == hipSuccess;
+  for (int k = 0; k < 2 && ok; ++k)
+    ok = hipEventCreateWithFlags(&b->ev_gen[k], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&b->ev_spl[k], hipEventDisableTiming) == hipSuccess;
+  if (ok)
+    ok = dalloc(a.counts, ntb) == hipSuccess && dalloc(a.offsets, ntb) == hipSuccess && dalloc(a.rec, ntb) == hipSuccess &&
+         dalloc(a.em, ntb) == hipSuccess && dalloc(a.tiles, (ntb + 1023) / 1024 + 1) == hipSuccess &&
+         dalloc(a.big, ntb) == hipSuccess && dalloc(a.stats, STAT_SLOTS) == hipSuccess &&
+         dalloc(a.points, (size_t)b->cap) == hipSuccess && dalloc(a.d_models, b->n) == hipSuccess &&
+         hipHostMalloc((void**)&a.h_models, sizeof(Model) * b->n, hipHostMallocDefault) == hipSuccess;
+  if (ok && b->tm) ok = dalloc(a.tm, (size_t)ntb) == hipSuccess && dalloc(a.pmat, (size_t)b->cap) == hipSuccess;
+  if (ok) ok = hipStreamSynchronize(b->gen) == hipSuccess;
+  if (!ok) {
+    batch_free_alt(b);
+    return bfail(b, LFDPR_ENOMEM, "second batch buffer set");
+  }
+  b->slot = 0;
+  b->in_flight = 2;
   return LFDPR_OK;
 }
 
@@ -1167,12 +1294,18 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
   BHIP(hipSetDevice(b->ctx->device));
   // shading: material buffers on first use, the items' material tables, and a
   // new graph when the captured shading differs
-  if (pbr && !b->tm) {
-    BHIP(hipStreamSynchronize(b->stream));
+  if (pbr && (!b->tm || (b->in_flight == 2 && !b->alt.tm))) {
+    BHIP(batch_sync(b));
     const int64_t ntb = b->nt > 1024 ? b->nt : 1024;
-    if (dalloc(b->tm, (size_t)ntb) != hipSuccess || dalloc(b->pmat, (size_t)b->cap) != hipSuccess) {
+    bool ok = true;
+    if (!b->tm) ok = dalloc(b->tm, (size_t)ntb) == hipSuccess && dalloc(b->pmat, (size_t)b->cap) == hipSuccess;
+    if (ok && b->in_flight == 2 && !b->alt.tm)
+      ok = dalloc(b->alt.tm, (size_t)ntb) == hipSuccess && dalloc(b->alt.pmat, (size_t)b->cap) == hipSuccess;
+    if (!ok) {
       dfree(b->tm);
       dfree(b->pmat);
+      dfree(b->alt.tm);
+      dfree(b->alt.pmat);
       return bfail(b, LFDPR_ENOMEM, "material buffers");
     }
   }
@@ -1185,12 +1318,38 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
     }
   }
   if (items_changed) {
-    BHIP(hipStreamSynchronize(b->stream));  // earlier replays may still read the table
+    BHIP(batch_sync(b));  // earlier replays may still read the table
     BHIP(hipMemcpy(b->d_items, b->items.data(), sizeof(Item) * b->n, hipMemcpyHostToDevice));
   }
   if (items_changed || b->g_pbr != pbr ||
       (pbr && std::memcmp(&b->g_sh, &b->ctx->shading, sizeof b->g_sh) != 0))
     b->g_valid = false;
+  if (b->in_flight == 2) {
+    // this call's generation buffers; generation waits only for the splat
+    // that last read them, the splat for earlier work on the context's stream
+    batch_swap_sets(b);
+    b->slot ^= 1;
+    const int sl = b->slot;
+    const bool timed = b->ctx->timing;
+    BHIP(hipEventSynchronize(b->ev_stage));
+    std::memcpy(b->h_models, models, sizeof(Model) * b->n);
+    if (b->spl_pending[sl]) BHIP(hipStreamWaitEvent(b->gen, b->ev_spl[sl], 0));
+    BHIP(hipMemcpyAsync(b->d_models, b->h_models, sizeof(Model) * b->n, hipMemcpyHostToDevice, b->gen));
+    BHIP(hipEventRecord(b->ev_stage, b->gen));
+    (void)batch_gen(b, b->gen, timed);
+    BHIP(hipGetLastError());
+    BHIP(hipEventRecord(b->ev_gen[sl], b->gen));
+    BHIP(hipEventRecord(b->ev_in, b->ctx->stream));
+    BHIP(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    BHIP(hipStreamWaitEvent(b->stream, b->ev_gen[sl], 0));
+    batch_splat(b, views, panels, b->stream, timed, timed ? mark_on(b->ctx, b->stream) : nullptr);
+    BHIP(hipGetLastError());
+    BHIP(hipEventRecord(b->ev_spl[sl], b->stream));
+    b->spl_pending[sl] = true;
+    BHIP(hipEventRecord(b->ev_out, b->stream));
+    BHIP(hipStreamWaitEvent(b->ctx->stream, b->ev_out, 0));
+    return LFDPR_OK;
+  }
   // model matrices: pinned staging -> device, outside any graph
   BHIP(hipEventSynchronize(b->ev_stage));
   std::memcpy(b->h_models, models, sizeof(Model) * b->n);

@@ -130,6 +130,7 @@ def signatures():
         "lfdpr_batch_destroy": ([vp], C.c_int),
         "lfdpr_batch_last_error": ([vp], C.c_char_p),
         "lfdpr_batch_use_graph": ([vp, C.c_int], C.c_int),
+        "lfdpr_batch_set_frames_in_flight": ([vp, C.c_int32], C.c_int),
         "lfdpr_batch_render": ([vp, vp, vp, vp], C.c_int),
         "lfdpr_batch_stats": ([vp, p(Stats)], C.c_int),
         "lfdpr_batch_autotune": ([vp, vp, vp, p(TuneResult)], C.c_int),
@@ -541,6 +542,10 @@ class Batch:
 
     def use_graph(self, enable: bool):
         self._check(lib().lfdpr_batch_use_graph(self.h, int(enable)))
+
+    def set_frames_in_flight(self, n: int):
+        """2: a call's point generation overlaps the previous call's splat."""
+        self._check(lib().lfdpr_batch_set_frames_in_flight(self.h, int(n)))
 
     def alloc_views(self):
         return self._torch.empty(self.shape, dtype=self._torch.int32, device=f"cuda:{self.R.device}")

@@ -74,6 +74,59 @@ def test_graph_replays_with_interleaved_eager_work(setup):
         np.testing.assert_array_equal(vg.cpu().numpy(), ve.cpu().numpy())
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_pipelined_batches_equal_serial_batches(setup, graph):
+    """Two batch calls in flight (a call's point generation on the batch's
+    second stream while the previous call splats): every call's views and
+    panels equal a serial batch's bit for bit, statistics describe the last
+    call, and switching back to one in flight (graph replay) keeps results."""
+    torch, lfdpr, R, ws, ids = setup
+    S = lfdpr.Batch(R, ids, [w.views for w in ws])
+    S.use_graph(False)
+    P = lfdpr.Batch(R, ids, [w.views for w in ws])
+    P.use_graph(graph)
+    P.set_frames_in_flight(2)
+
+    def panels():
+        return torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+
+    frames = [0, 77, 400, 5, 6, 6]
+    want = []
+    for f in frames:
+        models = [w.model(f + 13 * k) for k, w in enumerate(ws)]
+        v, p = S.alloc_views(), panels()
+        S.render(models, v, p)
+        torch.cuda.synchronize()
+        want.append((v.cpu().numpy(), p.cpu().numpy()))
+    last = S.stats()
+    got = []
+    for f in frames:
+        models = [w.model(f + 13 * k) for k, w in enumerate(ws)]
+        v, p = P.alloc_views(), panels()
+        P.render(models, v, p)
+        got.append((v, p))
+    torch.cuda.synchronize()
+    assert P.stats() == last
+    for f, (wv, wp), (v, p) in zip(frames, want, got):
+        np.testing.assert_array_equal(v.cpu().numpy(), wv, err_msg=f"frame {f} views")
+        np.testing.assert_array_equal(p.cpu().numpy(), wp, err_msg=f"frame {f} panels")
+    P.set_frames_in_flight(1)
+    P.use_graph(True)
+    models = [w.model(31 + 13 * k) for k, w in enumerate(ws)]
+    for B in (S, P):
+        v, p = B.alloc_views(), panels()
+        for _ in range(2):
+            B.render(models, v, p)
+        torch.cuda.synchronize()
+        got.append((v.cpu().numpy(), p.cpu().numpy()))
+    np.testing.assert_array_equal(got[-1][0], got[-2][0])
+    np.testing.assert_array_equal(got[-1][1], got[-2][1])
+    with pytest.raises(lfdpr.LfdprError):
+        P.set_frames_in_flight(3)
+    S.close()
+    P.close()
+
+
 def test_autotune_keeps_results(setup):
     torch, lfdpr, R, ws, ids = setup
     B = lfdpr.Batch(R, ids, [w.views for w in ws])
@@ -144,6 +197,18 @@ def test_batch16_full_size_matches_single_renders():
         tot += R.stats()["point_views"]
     assert bst["point_views"] == tot
     print(f"batch16: {bst['points']} points, {tot} point-views, all scenes identical", flush=True)
+    # two batch calls in flight: another frame, then this one, equal to the replay
+    B.set_frames_in_flight(2)
+    other = B.alloc_views()
+    B.render([w.model(900 + k) for k, w in enumerate(ws)], other)
+    v2 = B.alloc_views()
+    p2 = torch.empty_like(panels)
+    B.render(models, v2, p2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(v2.cpu().numpy(), bv)
+    np.testing.assert_array_equal(p2.cpu().numpy(), bp)
+    assert B.stats() == bst
+    B.close()
 
 
 def test_lifetimes_are_enforced():

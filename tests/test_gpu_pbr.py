@@ -143,8 +143,8 @@ def test_pbr_state_and_refusals(torch_cuda):
     R.close()
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_pbr_batch_matches_the_oracle(torch_cuda, graph):
+@pytest.mark.parametrize("graph,in_flight", [(False, 1), (True, 1), (False, 2)])
+def test_pbr_batch_matches_the_oracle(torch_cuda, graph, in_flight):
     """Three PBR scenes with different cones and distances in one batch: every
     item bit-exact against the oracle's shaded render; a new light (the graph
     is captured again) and unlit albedo afterwards stay exact."""
@@ -160,11 +160,12 @@ def test_pbr_batch_matches_the_oracle(torch_cuda, graph):
     ids = [R.upload_scene(w.scene) for w in ws]
     B = lfdpr.Batch(R, ids, [w.views for w in ws])
     B.use_graph(graph)
-    views = B.alloc_views()
+    B.set_frames_in_flight(in_flight)
     warm = scenes.Shading(scenes.SHADE_PBR, (0.6, 0.0, -0.8), (2.0, 1.5, 1.0), (0.05, 0.04, 0.03))
     for frame, sh in ((0, ws[0].shading), (77, ws[0].shading), (77, warm), (400, None)):
         R.set_shading(sh)
         models = [w.model(frame + 13 * k) for k, w in enumerate(ws)]
+        views = B.alloc_views()
         B.render(np.stack(models), views)
         torch.cuda.synchronize()
         bv = views.cpu().numpy().view(np.uint32)
@@ -174,6 +175,6 @@ def test_pbr_batch_matches_the_oracle(torch_cuda, graph):
             np.testing.assert_array_equal(bv[k], o["rgba"], err_msg=f"item {k} frame {frame} shading {sh}")
             tot += o["stats"]["point_views"]
         assert B.stats()["point_views"] == tot
-        _log(f"PBR batch frame {frame}, graph={graph}, shading {'unlit' if sh is None else sh.light_dir}: exact")
+        _log(f"PBR batch frame {frame}, graph={graph}, {in_flight} in flight, shading {'unlit' if sh is None else sh.light_dir}: exact")
     B.close()
     R.close()
