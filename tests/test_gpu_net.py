@@ -273,3 +273,30 @@ def test_pack_and_unpack(torch_cuda):
     want = np.clip(np.floor(yf.astype(np.float32) * np.float32(255.0) + np.float32(0.5)), 0, 255)
     np.testing.assert_array_equal(got[..., :3], want.astype(np.uint8))
     assert (got[..., 3] == 255).all()
+
+
+def test_gradients_are_identical_run_to_run(torch_cuda):
+    """Parameter gradients are summed per block and then over blocks in a fixed
+    order (no atomics): two backward passes over the same 48 x 128 x 128 crop
+    (hundreds of blocks per sum) give the same bits.  (The reported loss is a
+    sum of per-block atomics and may differ in its last bits.)"""
+    torch = torch_cuda
+    from paper_2601_19901_amd import lfdpr
+    V, H, W = 48, 128, 128
+    R, net = make_net(torch, V, H, W)
+    net.set_params(lfdpr.params_to_flat(random_params(11, scale=1.0)))
+    net.set_disparity_scale(3.3)
+    rng = np.random.default_rng(12)
+    x = t16(random_input(rng, V, H, W), torch)
+    t = t16(f_to_bits(np.concatenate([rng.random((V, H, W, 3)), np.zeros((V, H, W, 1))], -1)), torch)
+    y = torch.zeros((V, H, W, 4), dtype=torch.int16, device="cuda")
+    grads, losses = [], []
+    for _ in range(2):
+        net.forward(x, y)
+        losses.append(float(net.backward(t).cpu().numpy()[0]))
+        g = torch.zeros(net.n_params, dtype=torch.float32, device="cuda")
+        net.copy_state(20, g)
+        grads.append(g.cpu().numpy())
+    np.testing.assert_array_equal(grads[0].view(np.uint32), grads[1].view(np.uint32))
+    assert np.any(grads[0] != 0.0)
+    _log(f"loss {losses[0]:.6f} / {losses[1]:.6f}, {net.n_params} gradients bit-identical")
