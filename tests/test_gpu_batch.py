@@ -110,6 +110,15 @@ def test_pipelined_batches_equal_serial_batches(setup, graph):
     for f, (wv, wp), (v, p) in zip(frames, want, got):
         np.testing.assert_array_equal(v.cpu().numpy(), wv, err_msg=f"frame {f} views")
         np.testing.assert_array_equal(p.cpu().numpy(), wp, err_msg=f"frame {f} panels")
+    # the autotuner with two calls in flight, then a pipelined call in its shape
+    models = [w.model(77 + 13 * k) for k, w in enumerate(ws)]
+    v = P.alloc_views()
+    P.autotune(models, v)
+    v, p = P.alloc_views(), panels()
+    P.render(models, v, p)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(v.cpu().numpy(), want[1][0])
+    np.testing.assert_array_equal(p.cpu().numpy(), want[1][1])
     P.set_frames_in_flight(1)
     P.use_graph(True)
     models = [w.model(31 + 13 * k) for k, w in enumerate(ws)]
