@@ -176,9 +176,12 @@ class LearnedPipeline:
     (default priority) through a context and a copy of the network of their
     own.  Two view / depth buffer pairs alternate between the streams, fenced
     by events: a buffer is rendered into again only after the network side has
-    packed it.  Every panel equals the serial path (reconstruct, then the
-    interleave) bit for bit; with poisoned parameters frames take the 4x
-    supersampling fallback serially."""
+    packed it.  The renderer keeps one frame in flight while the pipeline runs
+    (its own next-frame point generation would be a third stream competing for
+    the same gaps; measured slower) and gets its setting back on close().
+    Every panel equals the serial path (reconstruct, then the interleave) bit
+    for bit; with poisoned parameters frames take the 4x supersampling fallback
+    serially."""
 
     def __init__(self, lr_: LearnedReconstruction, lens: scenes.LensParams):
         import torch
@@ -200,6 +203,9 @@ class LearnedPipeline:
         self.rendered = [torch.cuda.Event(), torch.cuda.Event()]
         self.packed = [None, None]
         self.n = 0
+        R1 = self.ss.rigs[1].renderer
+        self.render_in_flight = R1.frames_in_flight
+        R1.set_frames_in_flight(1)
         self.sync_params()
 
     def sync_params(self):
@@ -233,6 +239,7 @@ class LearnedPipeline:
 
     def close(self):
         self.torch.cuda.synchronize()
+        self.ss.rigs[1].renderer.set_frames_in_flight(self.render_in_flight)
         self.net.close()
         self.R.close()
 
@@ -286,20 +293,20 @@ def time_pipelines(lr_: LearnedReconstruction, lens: scenes.LensParams, k: int, 
     def learned(f):
         R1.reconstruct(lr_.reconstruct(k, f), panel)
 
+    def ss4(f):
+        R1.reconstruct(ss.render_ss(k, f, fallback_S), panel)
+
+    run("plain_1x_ms", plain)
+    run("learned_serial_ms", learned)
+    run("ss4_ms", ss4)
     pipe = LearnedPipeline(lr_, lens)
 
     def learned_overlapped(f):
         pipe.frame(k, f, panel)
 
-    def ss4(f):
-        R1.reconstruct(ss.render_ss(k, f, fallback_S), panel)
-
-    run("plain_1x_ms", plain)
     run("learned_ms", learned_overlapped)
-    run("learned_serial_ms", learned)
-    run("ss4_ms", ss4)
     pipe.close()
-    return out
+    return {k2: out[k2] for k2 in ("plain_1x_ms", "learned_ms", "learned_serial_ms", "ss4_ms")}
 
 
 def main(argv=None):

@@ -200,6 +200,7 @@ class Renderer:
         self.h = h
         self.vp = None
         self.lens = None
+        self.frames_in_flight = 1
         self._keep = {}
 
     def _check(self, rc: int, ctx="self"):
@@ -271,6 +272,7 @@ class Renderer:
 
     def set_frames_in_flight(self, n: int):
         self._check(lib().lfdpr_set_frames_in_flight(self.h, n))
+        self.frames_in_flight = int(n)
 
     def autotune(self, sid: int, model: np.ndarray, views) -> dict:
         m = np.ascontiguousarray(model, np.float32).reshape(12)
