@@ -112,23 +112,30 @@ def frame_roofline(stage_ms: dict, pv_per_frame: float, shape: dict, frame_ms: f
             "bound_ms": bounds}
 
 
-def splat_traffic():
-    """HBM bytes per k_splat launch on display-1M from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources (else None)."""
+def profile_traffic(name: str, sources, label: str):
+    """HBM bytes (`label: <value>` in profiles/<name>) from a committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources
+    (the summary's sha256 over `sources` in csrc/ matches; else None)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "display-1M_splat_traffic.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     h = hashlib.sha256()
-    for f in ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"):
+    for f in sources:
         h.update(open(os.path.join(ROOT, "paper_2601_19901_amd", "csrc", f), "rb").read())
     m = re.search(r"kernel sources sha256: ([0-9a-f]{64})", txt)
-    t = re.search(r"HBM bytes per launch: ([0-9.e+]+)", txt)
+    t = re.search(re.escape(label) + r": ([0-9.e+]+)", txt)
     if not m or not t or m.group(1) != h.hexdigest():
         return None
     return float(t.group(1))
+
+
+def splat_traffic():
+    """HBM bytes per k_splat launch on display-1M (see profile_traffic)."""
+    return profile_traffic("display-1M_splat_traffic.md", ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"),
+                           "HBM bytes per launch")
 
 
 def stage_avg(R):
@@ -413,9 +420,11 @@ def run_learned(args, torch, lfdpr, scenes):
         "frame_ms": {k: round(v, 4) for k, v in times.items()},
         "frames_in_flight": args.frames_in_flight,
         "net_forward_ms": round(fwd_ms, 4),
-        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur", "bound": "hbm",
+        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur_rows", "bound": "hbm",
                      "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": profile_traffic("learned-display_forward_traffic.md", ("lfdpr_net.hip",),
+                                                "HBM bytes per forward"),
                      "bytes_per_frame": net_bytes, "flops_per_frame": flops,
                      "mfma_achieved_tflops": round(achieved, 1),
                      "mfma_frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "launch_ms": round(fwd_ms, 4)},
