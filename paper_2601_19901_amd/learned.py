@@ -5,7 +5,7 @@ The network (lfdpr_net_* in include/lfdpr.h) maps the V views rendered once
 filter gives (Sec. 4: angular supersampling projects splats into more views at
 random angles inside view intervals).  Training pairs are rendered on the fly
 by the method itself; the plain 4x supersampled reconstruction stays available
-as the fallback and as the reference the network is judged against.
+as the fallback and as the reference the network is measured against.
 
 Everything here is orchestration: rendering, packing, convolutions, loss,
 gradients and Adam run in the library's HIP kernels; torch only holds device
