@@ -1,0 +1,95 @@
+"""Host logic of bench.py (no GPU): the roofline arithmetic, the frame
+roofline, the counter-profile lookup with its source hash, and the refusal
+of more than one GPU."""
+import hashlib
+import importlib.util
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def shape(**kw):
+    s = dict(nt=1000, views=48, points=5000, pixels=48 * 64 * 64, panel_px=320 * 200, tris_with_points=600,
+             fragments=0, out_pixels=0)
+    s.update(kw)
+    return s
+
+
+def test_alu_peak_is_the_chip_lane_rate(bench):
+    # 256 CUs x 64 lanes x 2.4 GHz
+    assert bench.VALU_PEAK_GOPS == pytest.approx(39321.6)
+    assert bench.HBM_PEAK_GBS == 8000.0
+
+
+def test_splat_dominant_roofline(bench):
+    st = {"setup": 0.2, "emit": 0.1, "splat": 2.0, "resolve": 0.05}
+    pv = 1.0e8
+    r = bench.roofline(st, pv, shape(), traffic=123.0)
+    assert r["kernel"] == "k_splat" and r["bound"] == "alu" and r["traffic"] == 123.0
+    want = bench.SPLAT_OPS_PER_POINT_VIEW * pv / 2.0e-3 / 1e12
+    assert r["achieved"] == pytest.approx(want, abs=1e-3)
+    assert r["frac"] == pytest.approx(want / 39.3216, abs=1e-4)
+
+
+def test_memory_dominant_roofline(bench):
+    s = shape()
+    st = {"splat": 0.01, "resolve": 0.5}
+    r = bench.roofline(st, 10.0, s)
+    assert r["kernel"] == "k_resolve" and r["bound"] == "hbm"
+    want = s["pixels"] * 20 / 0.5e-3 / 1e9       # key read + clear (8 + 8) and RGBA8 (4) per pixel
+    assert r["achieved"] == pytest.approx(want, abs=0.05)   # reported to 0.1 GB/s
+    assert r["frac"] == pytest.approx(want / 8000.0, abs=1e-4)
+
+
+def test_frame_roofline_sums_the_larger_bound_per_stage(bench):
+    s = shape()
+    st = {"setup": 0.3, "splat": 1.5, "resolve": 0.05, "interleave": 0.04}
+    pv = 2.0e7
+    r = bench.frame_roofline(st, pv, s, frame_ms=2.0)
+    peak_ops, peak_b = bench.VALU_PEAK_GOPS * 1e9, bench.HBM_PEAK_GBS * 1e9
+    want = {
+        "setup": max(bench.BYTES["setup"](s) / peak_b, bench.SETUP_OPS_PER_TRI_VIEW * s["nt"] * s["views"] / peak_ops),
+        "splat": max(bench.BYTES["splat"](s) / peak_b, bench.SPLAT_OPS_PER_POINT_VIEW * pv / peak_ops),
+        "resolve": bench.BYTES["resolve"](s) / peak_b,
+        "interleave": bench.BYTES["interleave"](s) / peak_b,
+    }
+    for k, v in want.items():
+        assert r["bound_ms"][k] == pytest.approx(v * 1e3, abs=1e-4)
+    assert r["achievable_ms"] == pytest.approx(sum(want.values()) * 1e3, abs=4e-4)
+    assert r["frac"] == pytest.approx(r["achievable_ms"] / 2.0, abs=1e-4)
+
+
+def test_profile_traffic_requires_matching_sources(bench, tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2601_19901_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (csrc / "a.hip").write_bytes(b"kernel source v1\n")
+    sha = hashlib.sha256(b"kernel source v1\n").hexdigest()
+    (tmp_path / "profiles" / "p.md").write_text(f"HBM bytes per launch: 1.5e+09\n\nkernel sources sha256: {sha}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per launch") == 1.5e9
+    assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per forward") is None   # label absent
+    assert bench.profile_traffic("missing.md", ("a.hip",), "HBM bytes per launch") is None
+    (csrc / "a.hip").write_bytes(b"kernel source v2\n")                                  # sources changed
+    assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per launch") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
