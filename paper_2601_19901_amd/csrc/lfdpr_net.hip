@@ -28,7 +28,6 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
-#include <type_traits>
 #include <vector>
 
 #include "../../include/lfdpr.h"
@@ -114,7 +113,7 @@ static_assert(kDilation[0] <= kMaxDil && kDilation[1] <= kMaxDil && kDilation[2]
               "dilation beyond the staged halo");
 constexpr int kStagePerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * 4 + 255) / 256;
 constexpr int kPlanes = 2 * kNeigh + 2;  // layer 1's sources: five views and the blur
-constexpr int kGatherPerThread = ((kTY + 2) * (kTX + 2 * kMaxDil) * kPlanes + 255) / 256;
+constexpr int kGatherPerThread = ((kTY + 2) * (kTX / 2 + kMaxDil + 1) * kPlanes + 255) / 256;  // pixel pairs
 
 __device__ __forceinline__ int swz(int row, int g) { return row * 4 + (g ^ ((row >> 1) & 3)); }
 
@@ -187,18 +186,22 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
   // is 16-byte group threadIdx % 4 of LDS pixel q = threadIdx / 4 + 64 j, at
   // tile row q / TW and column q % TW (rows from kTY + 2 on lie past the staged
   // tile).  Layer 1 (GATHER) stages plane by plane -- views v-2 .. v+2 of the
-  // compact input, then the blur, 8 bytes per pixel -- so each wave load reads
-  // 64 consecutive pixels of one plane: item j = threadIdx + 256 j is plane
-  // j' / ((kTY + 2) TW), then row and column; plane p fills half p % 2 of
-  // group p / 2, and group 3 (channels 24-31) stays zero.
+  // compact input, then the blur, 8 bytes per pixel -- in pairs of pixels from
+  // an even column xs = x0 - DIL - (DIL & 1), so each wave load reads 128
+  // consecutive pixels of one plane (16 bytes a lane where the pair is inside
+  // the image and 16-byte aligned, else two 8-byte loads): item j' = threadIdx
+  // + 256 j is plane j' / ((kTY + 2) NP), then row and pair (NP pairs a row);
+  // plane p fills half p % 2 of group p / 2, pixels outside the tile's columns
+  // are dropped, and group 3 (channels 24-31) stays zero.
   constexpr int kSlots = GATHER ? kGatherPerThread : kStagePerThread;
+  const int NP = kTX / 2 + DIL + (DIL & 1);  // pixel pairs per staged row (layer 1)
   int geo[kSlots];
 #pragma unroll
   for (int j = 0; j < kSlots; ++j) {
     if (GATHER) {
-      const int i = (int)threadIdx.x + 256 * j, m = (kTY + 2) * TW;
+      const int i = (int)threadIdx.x + 256 * j, m = (kTY + 2) * NP;
       const int pl = i / m, rem = i % m;
-      geo[j] = (pl << 24) | ((rem / TW) << 16) | (rem % TW);
+      geo[j] = (pl << 24) | ((rem / NP) << 16) | (rem % NP);
     } else {
       const int q = (int)(threadIdx.x >> 2) + 64 * j;
       geo[j] = ((q / TW) << 16) | (q % TW);
@@ -210,24 +213,39 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
     __syncthreads();
   }
   // the next tile's input is fetched into registers while this one computes
-  typename std::conditional<GATHER, uint2, uint4>::type pre[kSlots];
+  uint4 pre[kSlots];
   auto fetch = [&](int tile) {
     int n, y0, x0;
     decode(tile, n, y0, x0);
     if constexpr (GATHER) {
       const int vv = n % V, f0 = n - vv;
+      const int xs = x0 - DIL - (DIL & 1);
 #pragma unroll
       for (int j = 0; j < kSlots; ++j) {
-        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, c = geo[j] & 0xFFFF;
-        const int yy = y0 - 1 + r, xx = x0 - DIL + c;
-        uint2 val = {0u, 0u};
-        if (pl < kPlanes && yy >= 0 && yy < H && xx >= 0 && xx < W) {
-          if (pl < kPlanes - 1) {
-            const int vo = vv + pl - kNeigh;
-            if (vo >= 0 && vo < V)
-              val = *reinterpret_cast<const uint2*>(X + (size_t)(((f0 + vo) * H + yy) * W + xx) * 4);
+        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, q = geo[j] & 0xFFFF;
+        const int yy = y0 - 1 + r, xx = xs + 2 * q;
+        uint4 val = {0u, 0u, 0u, 0u};
+        const int vo = vv + pl - kNeigh;
+        const bool plane_ok = pl < kPlanes - 1 ? (vo >= 0 && vo < V) : pl == kPlanes - 1;
+        if (plane_ok && yy >= 0 && yy < H) {
+          const uint16_t* src = pl < kPlanes - 1 ? X : aux;
+          const int img = pl < kPlanes - 1 ? f0 + vo : n;
+          const bool ok0 = xx >= 0 && xx < W, ok1 = xx + 1 >= 0 && xx + 1 < W;
+          const int p0 = (img * H + yy) * W + xx;  // dereferenced only where in the image
+          const uint16_t* a0 = src + (size_t)p0 * 4;
+          if (ok0 && ok1 && ((uintptr_t)a0 & 15) == 0) {
+            val = *reinterpret_cast<const uint4*>(a0);
           } else {
-            val = *reinterpret_cast<const uint2*>(aux + (size_t)((n * H + yy) * W + xx) * 4);
+            if (ok0) {
+              const uint2 a = *reinterpret_cast<const uint2*>(src + (size_t)p0 * 4);
+              val.x = a.x;
+              val.y = a.y;
+            }
+            if (ok1) {
+              const uint2 b = *reinterpret_cast<const uint2*>(src + (size_t)(p0 + 1) * 4);
+              val.z = b.x;
+              val.w = b.y;
+            }
           }
         }
         pre[j] = val;
@@ -244,8 +262,13 @@ __global__ void __launch_bounds__(256) k_conv3x3(const uint16_t* __restrict__ X,
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) {
       if constexpr (GATHER) {
-        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, c = geo[j] & 0xFFFF;
-        if (pl < kPlanes) reinterpret_cast<uint2*>(&tl[swz(r * TW + c, pl >> 1)])[pl & 1] = pre[j];
+        const int pl = geo[j] >> 24, r = (geo[j] >> 16) & 0xFF, q = geo[j] & 0xFFFF;
+        const int c0 = 2 * q - (DIL & 1);  // tile column of the pair's first pixel
+        if (pl < kPlanes) {
+          if (c0 >= 0) reinterpret_cast<uint2*>(&tl[swz(r * TW + c0, pl >> 1)])[pl & 1] = uint2{pre[j].x, pre[j].y};
+          if (c0 + 1 < TW)
+            reinterpret_cast<uint2*>(&tl[swz(r * TW + c0 + 1, pl >> 1)])[pl & 1] = uint2{pre[j].z, pre[j].w};
+        }
       } else {
         const int k = threadIdx.x + j * 256;
         if (k < nstage) tl[swz(k >> 2, k & 3)] = pre[j];
