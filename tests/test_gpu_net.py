@@ -300,3 +300,34 @@ def test_gradients_are_identical_run_to_run(torch_cuda):
     np.testing.assert_array_equal(grads[0].view(np.uint32), grads[1].view(np.uint32))
     assert np.any(grads[0] != 0.0)
     _log(f"loss {losses[0]:.6f} / {losses[1]:.6f}, {net.n_params} gradients bit-identical")
+
+
+def test_forward_from_an_input_only_8_byte_aligned(torch_cuda):
+    """Layer 1 reads pixel pairs with 16-byte loads only where the address is
+    16-byte aligned: an input that starts 8 bytes into its buffer (and an odd
+    image width) gives the same activations and output as an aligned copy."""
+    torch = torch_cuda
+    from paper_2601_19901_amd import lfdpr
+    V, H, W = 6, 9, 77
+    R, net = make_net(torch, V, H, W)
+    net.set_params(lfdpr.params_to_flat(random_params(21)))
+    net.set_disparity_scale(4.5)
+    xb = random_input(np.random.default_rng(22), V, H, W)
+    x = t16(xb, torch)
+    n = x.numel()
+    buf = torch.zeros(n + 8, dtype=torch.int16, device="cuda")
+    buf[4:4 + n] = x.reshape(-1)
+    xm = buf[4:4 + n].view(V, H, W, 4)
+    assert xm.data_ptr() % 16 == 8 and x.data_ptr() % 16 == 0
+    outs = []
+    for inp in (x, xm):
+        y = torch.zeros((V, H, W, 4), dtype=torch.int16, device="cuda")
+        net.forward(inp, y)
+        states = [y.cpu().numpy()]
+        for k in (1, 2, 3):
+            a = torch.zeros((V, H, W, 32), dtype=torch.int16, device="cuda")
+            net.copy_state(k, a)
+            states.append(a.cpu().numpy())
+        outs.append(states)
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
