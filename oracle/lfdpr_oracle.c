@@ -98,6 +98,11 @@ typedef struct {
     uint32_t *p_nmin, *p_nmax, *p_rm;
     float *tframe;         /* nt*6 */
     int32_t *tlod;         /* nt*8 */
+    /* optional observation of Eqs. 8-9 (may be NULL): for every (point, view)
+       that writes a pixel, the quantised interpolation weight tq (else -1) and
+       the splat's RGBA8 colour in that view; point_cap x n_views each */
+    int16_t *pv_tq;
+    uint32_t *pv_col;
 } orc_out;
 
 /* ------------------------------------------------------------------ */
@@ -256,6 +261,20 @@ static int q8_xy(vproj p, float b, int64_t *qx, int64_t *qy) {
     return 1;
 }
 
+/* Sec. 3 (the vertex stage checks visibility per LFD view): the triangle faces
+ * the eye at (b, 0, 0) by more than a grazing margin.  delta = n.(P0 - e) is
+ * the signed distance of the eye from the triangle's plane; the view is kept
+ * when delta < 0 (front facing) and |delta| >= |P0 - e| / 256, i.e. the eye
+ * direction to vertex 0 is at least asin(1/256) (0.22 degrees) off the plane.
+ * Views closer to edge-on project the triangle to (almost) nothing, and the
+ * pixel rays that the 1/256-px vertex snap still lets into it meet the plane
+ * far outside it (the ray-plane map magnifies by 1/cos). */
+static int faces_eye(v3 P0, float delta, float b) {
+    float dx = P0.x - b;
+    float d2 = (dx * dx + P0.y * P0.y) + P0.z * P0.z;
+    return delta < 0.0f && delta * delta >= d2 * 0x1p-16f;
+}
+
 /* ------------------------------------------------------------------ */
 /* per-triangle state                                                     */
 
@@ -284,6 +303,9 @@ static int cell_overlaps(const tri_state *ts, int64_t i, int64_t j) {
     int64_t mint = imin64(ts->T[0], imin64(ts->T[1], ts->T[2]));
     int64_t maxt = imax64(ts->T[0], imax64(ts->T[1], ts->T[2]));
     if (!(bx1 > mins && bx0 < maxs && by1 > mint && by0 < maxt)) return 0;
+    /* a snapped lattice of zero area (a point or a segment) keeps every cell
+       whose dilated box meets the bounding box of its vertices */
+    if (ts->area2 == 0) return 1;
     int64_t sg = ts->area2 > 0 ? 1 : -1;
     for (int e = 0; e < 3; ++e) {
         int a = e, b = (e + 1) % 3;
@@ -518,7 +540,7 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         for (int r = 0; r < nviews; ++r) {
             float b = fr->eye[r];
             float delta = ts.h - ts.nh.x * b;
-            int act = delta < 0.0f;
+            int act = faces_eye(ts.P[0], delta, b);
             int64_t qx[3], qy[3];
             for (int k = 0; k < 3 && act; ++k) act = q8_xy(ts.pr[k], b, &qx[k], &qy[k]);
             if (act) {
@@ -661,7 +683,7 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
         /* emission by exhaustive cell test over the lattice bounding box */
         int *cells_i = NULL, *cells_j = NULL;
         int ncell = 0;
-        if (ts.area2 != 0) {
+        if (!overflow) {
             int64_t mins = imin64(ts.S[0], imin64(ts.S[1], ts.S[2])), maxs = imax64(ts.S[0], imax64(ts.S[1], ts.S[2]));
             int64_t mint = imin64(ts.T[0], imin64(ts.T[1], ts.T[2])), maxt = imax64(ts.T[0], imax64(ts.T[1], ts.T[2]));
             /* cells whose dilated box overlaps the lattice bounding box with positive length */
@@ -729,8 +751,9 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
             int64_t cxq = 256 * (int64_t)i + 128, cyq = 256 * (int64_t)j + 128;
             int64_t w1 = (cxq - ts.S[0]) * (ts.T[2] - ts.T[0]) - (cyq - ts.T[0]) * (ts.S[2] - ts.S[0]);
             int64_t w2 = (ts.S[1] - ts.S[0]) * (cyq - ts.T[0]) - (ts.T[1] - ts.T[0]) * (cxq - ts.S[0]);
-            float b1 = (float)((double)w1 / (double)ts.area2);
-            float b2 = (float)((double)w2 / (double)ts.area2);
+            /* a zero-area lattice has no barycentrics: its points take vertex 0's UV */
+            float b1 = ts.area2 != 0 ? (float)((double)w1 / (double)ts.area2) : 0.0f;
+            float b2 = ts.area2 != 0 ? (float)((double)w2 / (double)ts.area2) : 0.0f;
             float uu = (uv0u + b1 * du1) + b2 * du2;
             float vv = (uv0v + b1 * dv1) + b2 * dv2;
             tvmin[c] = trilinear(sc, ts.tex, uu, vv, kmin);
@@ -821,6 +844,11 @@ int orc_render(const orc_scene *sc, const orc_frame *fr, orc_out *out) {
                         uint32_t rq = lerp8(rm[c] & 255u, (rm[c] >> 8) & 255u, tq);
                         uint32_t mq = lerp8((rm[c] >> 16) & 255u, rm[c] >> 24, tq);
                         col = pbr_shade(fr->light, ts.nh, ts.tt, ts.tb, Pc, b, col, nrm, rq, mq);
+                    }
+                    if (out->pv_tq && ts.first_point + c < out->point_cap) {
+                        int64_t o = (ts.first_point + c) * nviews + r;
+                        out->pv_tq[o] = (int16_t)tq;
+                        out->pv_col[o] = col;
                     }
                     uint32_t zb;
                     memcpy(&zb, &Z, 4);
@@ -984,7 +1012,7 @@ int orc_rasterise(const orc_scene *sc, const orc_frame *fr, uint32_t *rgba, floa
         for (int r = 0; r < fr->n_views; ++r) {
             float b = fr->eye[r];
             float delta = h - nh.x * b;
-            if (!(delta < 0.0f)) continue;
+            if (!faces_eye(P[0], delta, b)) continue;
             int64_t qx[3], qy[3];
             int ok = 1;
             for (int k = 0; k < 3 && ok; ++k) ok = q8_xy(pr[k], b, &qx[k], &qy[k]);
@@ -1065,7 +1093,6 @@ int orc_lattice_cells(const int64_t S[3], const int64_t T[3], int cap, int32_t *
     memset(&ts, 0, sizeof ts);
     for (int k = 0; k < 3; ++k) { ts.S[k] = S[k]; ts.T[k] = T[k]; }
     ts.area2 = (S[1] - S[0]) * (T[2] - T[0]) - (T[1] - T[0]) * (S[2] - S[0]);
-    if (ts.area2 == 0) return 0;
     int64_t mins = imin64(S[0], imin64(S[1], S[2])), maxs = imax64(S[0], imax64(S[1], S[2]));
     int64_t mint = imin64(T[0], imin64(T[1], T[2])), maxt = imax64(T[0], imax64(T[1], T[2]));
     int n = 0;

@@ -8,12 +8,16 @@ HIP library computes its own copies independently.
 
 Functions and what pins them (see tests/test_oracle_pins.py):
   view_table        -- camera rig (parallel off-axis eyes, shared focal plane)
+                                                            [pinned: eye offsets recovered
+                       from rendered depth, focal-plane invariance]
   lens_constants    -- tilted-lens phase constants (prototype geometry, Sec. 5.1)
   angular_table     -- Gaussian weights for the angular supersampling filter
   build_textures    -- box mip chains                      [pinned: numpy box mean]
   render            -- point generation + splatting         [pinned: brute-force lattice
                        counts, closest-point brute force, reverse-projection geometry,
-                       rasteriser coverage identity, constant-texture identity]
+                       rasteriser coverage identity, constant-texture identity,
+                       Eqs. 8-9 in double from ray-cast footprints, no orphans or
+                       misses at display size]
   interleave        -- panel interleave + reconstruction    [pinned: index-map readout,
                        lens-independence, slope-0 closed form]
   angular_filter    -- 4x angular SS -> V views             [pinned: focal-plane identity,
@@ -88,7 +92,7 @@ class _Out(C.Structure):
                 ("p_flags", C.c_void_p), ("p_tvmin", C.c_void_p), ("p_tvmax", C.c_void_p),
                 ("keys", C.c_void_p), ("stats", C.c_void_p), ("unused", C.c_void_p),
                 ("p_nmin", C.c_void_p), ("p_nmax", C.c_void_p), ("p_rm", C.c_void_p),
-                ("tframe", C.c_void_p), ("tlod", C.c_void_p)]
+                ("tframe", C.c_void_p), ("tlod", C.c_void_p), ("pv_tq", C.c_void_p), ("pv_col", C.c_void_p)]
 
 
 class _Lens(C.Structure):
@@ -235,14 +239,16 @@ def _frame_struct(vp, vt, model, keep: list) -> _Frame:
 
 
 def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_cap: Optional[int] = None,
-           shading=None):
+           shading=None, observe: bool = False):
     """Point generation + splatting of one frame into all V*S rendered views.
 
     Returns a dict with per-triangle counts and records, the point buffer in
     emission order, RGBA8 views (n_views, H, W) as uint32, FP32 depth and stats.
     With a PBR `shading` the scene must carry materials; the point buffer then
     also holds the normal-map fetches and the roughness/metallic bytes, and the
-    per-triangle tangent frames and LODs are returned."""
+    per-triangle tangent frames and LODs are returned.  With `observe`, the
+    Eq. 9 weight tq and the colour of every (point, view) that writes a pixel
+    are returned as `pv_tq` (-1 elsewhere) and `pv_col`, (n_points, n_views)."""
     tx = tx or build_textures(scene)
     vt = view_table(vp)
     keep: list = []
@@ -263,7 +269,9 @@ def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_ca
     if pbr:
         o.update(p_nmin=np.zeros(cap, np.uint32), p_nmax=np.zeros(cap, np.uint32), p_rm=np.zeros(cap, np.uint32),
                  tframe=np.zeros((nt, 6), np.float32), tlod=np.zeros((nt, 8), np.int32))
-    opt = [_p(o[k]) if k in o else None for k in ("p_nmin", "p_nmax", "p_rm", "tframe", "tlod")]
+    if observe:
+        o.update(pv_tq=np.full((cap, nviews), -1, np.int16), pv_col=np.zeros((cap, nviews), np.uint32))
+    opt = [_p(o[k]) if k in o else None for k in ("p_nmin", "p_nmax", "p_rm", "tframe", "tlod", "pv_tq", "pv_col")]
     out = _Out(_p(o["count"]), _p(o["trif"]), _p(o["trii"]), cap, _p(o["p_tri"]), _p(o["p_i"]), _p(o["p_j"]),
                _p(o["p_flags"]), _p(o["p_tvmin"]), _p(o["p_tvmax"]), _p(o["keys"]), _p(o["stats"]), None, *opt)
     rc = lib().orc_render(C.byref(sc), C.byref(fr), C.byref(out))
@@ -271,7 +279,7 @@ def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_ca
         raise ValueError(f"oracle render failed ({rc})")
     n = int(o["stats"][0])
     if n > cap:
-        return render(scene, vp, model, tx, point_cap=n, shading=shading)
+        return render(scene, vp, model, tx, point_cap=n, shading=shading, observe=observe)
     rgba = np.zeros((nviews, vp.H, vp.W), np.uint32)
     depth = np.zeros((nviews, vp.H, vp.W), np.float32)
     lib().orc_resolve(C.c_void_p(_p(o["keys"])), C.c_int64(o["keys"].size), C.c_void_p(_p(rgba)), C.c_void_p(_p(depth)))
@@ -282,6 +290,8 @@ def render(scene, vp, model: np.ndarray, tx: Optional[Textures] = None, point_ca
     if pbr:
         points.update(nmin=o["p_nmin"][:n], nmax=o["p_nmax"][:n], rm=o["p_rm"][:n])
         extra = dict(tframe=o["tframe"], tlod=o["tlod"])
+    if observe:
+        extra.update(pv_tq=o["pv_tq"][:n], pv_col=o["pv_col"][:n])
     return dict(count=o["count"], trif=o["trif"], trii=o["trii"], n_points=n, points=points, **extra,
                 keys=o["keys"], rgba=rgba, depth=depth,
                 stats=dict(points=int(st[0]), active_tris=int(st[1]), point_views=int(st[2]), orphans=int(st[3]),

@@ -111,11 +111,22 @@ LF_HD bool q8_xy(float A, float C, float Yp, float b, int32_t& qx, int32_t& qy) 
   return true;
 }
 
-// View r is active for the triangle: front facing, inside the guard band, and
-// not entirely beyond one screen edge.  Fills the Q8 vertices on success.
+// The eye at (b, 0, 0) sees the triangle's front more than edge-on: delta =
+// n.(P0 - e) < 0 and |delta| >= |P0 - e|/256 (the eye direction at least
+// asin(1/256) off the plane; nearer edge-on the ray-plane map magnifies the
+// 1/256-px vertex snap without bound).  p0y2 = P0y*P0y, p0z2 = P0z*P0z.
+LF_HD bool faces_eye(float p0x, float p0y2, float p0z2, float delta, float b) {
+  const float dx = p0x - b;
+  const float d2 = (dx * dx + p0y2) + p0z2;
+  return delta < 0.0f && delta * delta >= d2 * 0x1p-16f;
+}
+
+// View r is active for the triangle: facing the eye (above), inside the guard
+// band, and not entirely beyond one screen edge.  Fills the Q8 vertices on
+// success.
 LF_HD bool view_active(const Rig& rg, const TriRec& t, float b, int32_t qx[3], int32_t qy[3]) {
   float delta = t.h - t.nx * b;
-  if (!(delta < 0.0f)) return false;
+  if (!faces_eye(t.p0x, t.p0y * t.p0y, t.p0z * t.p0z, delta, b)) return false;
   if (!q8_xy(t.a0, t.c0, t.y0, b, qx[0], qy[0])) return false;
   if (!q8_xy(t.a1, t.c1, t.y1, b, qx[1], qy[1])) return false;
   if (!q8_xy(t.a2, t.c2, t.y2, b, qx[2], qy[2])) return false;
@@ -162,33 +173,34 @@ LF_HD F3 nearest_on_triangle(F3 p, F3 a, F3 b, F3 c) {
 // ---------------------------------------------------------------- lattice
 // Conservative cell rule: cell (i,j)'s box [256i-4, 256i+260] x [256j-4, 256j+260]
 // (Q8) overlaps the snapped triangle with positive area.  The two box axes give
-// the bounding ranges below; each of the three edges bounds i within a row.
+// the bounding ranges below; each of the three edges bounds i within a row.  A
+// snapped triangle of zero area (a point or a segment) keeps every cell that
+// passes the box-axis test.
 struct Lattice {
   int64_t S[3], T[3];
-  int64_t sg;                 // sign of the doubled area
+  int64_t sg;                 // sign of the doubled area (0: degenerate)
   int64_t iA, iB, jA, jB;     // cells passing the box-axis test
 };
 
-LF_HD bool lattice_init(Lattice& L, int32_t s1, int32_t t1, int32_t s2, int32_t t2) {
+LF_HD void lattice_init(Lattice& L, int32_t s1, int32_t t1, int32_t s2, int32_t t2) {
   L.S[0] = 128; L.T[0] = 128;
   L.S[1] = s1; L.T[1] = t1;
   L.S[2] = s2; L.T[2] = t2;
   int64_t a2 = (L.S[1] - L.S[0]) * (L.T[2] - L.T[0]) - (L.T[1] - L.T[0]) * (L.S[2] - L.S[0]);
-  if (a2 == 0) return false;
-  L.sg = a2 > 0 ? 1 : -1;
+  L.sg = a2 > 0 ? 1 : (a2 < 0 ? -1 : 0);
   int64_t mins = imin(L.S[0], imin(L.S[1], L.S[2])), maxs = imax(L.S[0], imax(L.S[1], L.S[2]));
   int64_t mint = imin(L.T[0], imin(L.T[1], L.T[2])), maxt = imax(L.T[0], imax(L.T[1], L.T[2]));
   L.iA = floor_div(mins - kEpsQ8, 256);
   L.iB = floor_div(maxs + kEpsQ8 - 1, 256);
   L.jA = floor_div(mint - kEpsQ8, 256);
   L.jB = floor_div(maxt + kEpsQ8 - 1, 256);
-  return true;
 }
 
 // Emitted i-range [lo, hi] of row j (empty when lo > hi).
 LF_HD void lattice_row(const Lattice& L, int64_t j, int64_t& lo, int64_t& hi) {
   lo = L.iA;
   hi = L.iB;
+  if (L.sg == 0) return;
   int64_t y0 = 256 * j - kEpsQ8, y1 = 256 * j + 256 + kEpsQ8;
   for (int e = 0; e < 3; ++e) {
     int a = e, b = e == 2 ? 0 : e + 1;

@@ -248,7 +248,8 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       }
       int64_t count = 0, jfirst = 0, jlast = -1;
       Lattice L;
-      if (!ovf && lattice_init(L, sq[1], tq[1], sq[2], tq[2])) {
+      if (!ovf) {
+        lattice_init(L, sq[1], tq[1], sq[2], tq[2]);
         int64_t nb = (L.iB - L.iA + 1) * (L.jB - L.jA + 1);
         if (nb > kBoxCap) {
           ovf = true;
@@ -452,8 +453,9 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
     int64_t cxq = 256 * i + 128, cyq = 256 * j + 128;
     int64_t w1 = (cxq - 128) * (T2 - 128) - (cyq - 128) * (S2 - 128);
     int64_t w2 = (S1 - 128) * (cyq - 128) - (T1 - 128) * (cxq - 128);
-    float b1 = (float)((double)w1 / (double)area2);
-    float b2 = (float)((double)w2 / (double)area2);
+    // a zero-area lattice has no barycentrics: its points take vertex 0's UV
+    float b1 = area2 != 0 ? (float)((double)w1 / (double)area2) : 0.0f;
+    float b2 = area2 != 0 ? (float)((double)w2 / (double)area2) : 0.0f;
     float u = (E.uv0u + b1 * E.du1) + b2 * E.du2;
     float v = (E.uv0v + b1 * E.dv1) + b2 * E.dv2;
     const Item& it = a.items[E.item];
@@ -591,12 +593,13 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   const bool oilo = flags & F_ILO, oihi = flags & F_IHI, ojlo = flags & F_JLO, ojhi = flags & F_JHI;
   const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
   const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
+  const float p0y2 = T.p0y * T.p0y, p0z2 = T.p0z * T.p0z;
   float b_next = table_f32(rg.eye, 0);  // the next view's eye offset, one iteration ahead
   for (int r = 0; r < rg.n_views; ++r) {
     const float b = b_next;
     if (r + 1 < rg.n_views) b_next = table_f32(rg.eye, r + 1);
     const float delta = T.h - T.nx * b;
-    if (!(delta < 0.0f)) continue;
+    if (!faces_eye(T.p0x, p0y2, p0z2, delta, b)) continue;
     // splat box columns first: empty for about a third of the (point, view) pairs
     int32_t cbx0 = 0, cbx1 = rg.W - 1;
     if (!full) {

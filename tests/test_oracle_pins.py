@@ -152,6 +152,21 @@ def _exact_cells(S, T):
     return out
 
 
+def _exact_cells_degenerate(S, T):
+    """A snapped lattice triangle of zero area (a point or a segment) keeps the
+    cells whose eps-dilated open box meets the closed bounding box of its
+    vertices (exact rationals)."""
+    eps = Fraction(4, 256)
+    s0, s1 = Fraction(min(S), 256), Fraction(max(S), 256)
+    t0, t1 = Fraction(min(T), 256), Fraction(max(T), 256)
+    out = []
+    for j in range(math.floor(t0) - 2, math.floor(t1) + 3):
+        for i in range(math.floor(s0) - 2, math.floor(s1) + 3):
+            if i - eps < s1 and i + 1 + eps > s0 and j - eps < t1 and j + 1 + eps > t0:
+                out.append((i, j))
+    return out
+
+
 def test_lattice_cells_equal_exact_rational_clipping():
     rng = np.random.default_rng(3)
     n_checked = 0
@@ -173,10 +188,35 @@ def test_lattice_cells_equal_exact_rational_clipping():
         area2 = (S[1] - S[0]) * (T[2] - T[0]) - (T[1] - T[0]) * (S[2] - S[0])
         ci, cj = O.lattice_cells(S, T)
         got = list(zip(ci.tolist(), cj.tolist()))
-        want = _exact_cells(S, T) if area2 != 0 else []
+        want = _exact_cells(S, T) if area2 != 0 else _exact_cells_degenerate(S, T)
         assert got == want, (S, T)
         n_checked += 1
     assert n_checked == 220
+
+
+def test_degenerate_lattice_keeps_the_cells_along_it():
+    """Zero-area snapped lattices (Sec. 3.2: splats must leave no holes, so a
+    visible triangle never emits nothing): a point keeps exactly the cell that
+    holds it, a segment the cells along its bounding box, each cell once and
+    covering the segment."""
+    cases = [([128, 128, 128], [128, 128, 128], [(0, 0)]),
+             ([128, 128, 128], [128, 127, 129], [(0, 0)]),
+             ([128, 151, 141], [128, 128, 128], [(0, 0)]),
+             ([128, 600, 1000], [128, 128, 128], [(0, 0), (1, 0), (2, 0), (3, 0)]),
+             ([128, 128, 128], [128, -300, -700], [(0, -3), (0, -2), (0, -1), (0, 0)])]
+    for S, T, want in cases:
+        ci, cj = O.lattice_cells(S, T)
+        got = list(zip(ci.tolist(), cj.tolist()))
+        assert got == want, (S, T)
+    # a diagonal segment: every point on it lies in an emitted cell
+    S, T = [128, 1280, 2432], [128, 704, 1280]
+    ci, cj = O.lattice_cells(S, T)
+    cells = set(zip(ci.tolist(), cj.tolist()))
+    assert len(cells) == len(ci)
+    for k in range(0, 1001):
+        s = Fraction(128, 256) + Fraction(k, 1000) * Fraction(2432 - 128, 256)
+        t = Fraction(128, 256) + Fraction(k, 1000) * Fraction(1280 - 128, 256)
+        assert any(i <= s <= i + 1 and j <= t <= j + 1 for i, j in cells)
 
 
 def test_lattice_right_triangle_golden():
@@ -199,9 +239,11 @@ def _active_views_double(P, vt, vp):
     P = np.asarray(P, np.float64)
     n = np.cross(P[1] - P[0], P[2] - P[0])
     act = []
+    nh = n / np.linalg.norm(n)
     for r, b in enumerate(vt["eye"].astype(np.float64)):
         e = np.array([b, 0, 0])
-        if np.dot(n, e - P[0]) <= 0:
+        # front facing, and the eye direction at least asin(1/256) off the plane
+        if np.dot(nh, e - P[0]) < np.linalg.norm(e - P[0]) / 256.0:
             act.append(False)
             continue
         x = vt["cx"] + vt["fx"] * ((P[:, 0] - b) / P[:, 2] + b / vp.D)
@@ -293,6 +335,205 @@ def test_texture_based_density_matches_texel_count():
     assert Sx * Sy * Aws == pytest.approx(n_tex, rel=1e-4)
     # the emitted count is the texel count plus the conservative boundary ring
     assert n_tex <= res["count"][0] <= 4 * n_tex + 12
+
+
+def _footprint(X, b, vt, vp, nh, h=1e-2):
+    """Area on the plane (unit normal nh through X) of the pixel around X's
+    projection in the view with eye offset b, by casting rays through the
+    pixel's neighbourhood (central differences), double precision."""
+    x = float(vt["cx"]) + float(vt["fx"]) * ((X[0] - b) / X[2] + b / vp.D)
+    y = float(vt["cy"]) + float(vt["fy"]) * X[1] / X[2]
+    ax = (_ray_hit(x + h, y, b, vt, vp, X, nh) - _ray_hit(x - h, y, b, vt, vp, X, nh)) / (2 * h)
+    ay = (_ray_hit(x, y + h, b, vt, vp, X, nh) - _ray_hit(x, y - h, b, vt, vp, X, nh)) / (2 * h)
+    return float(np.linalg.norm(np.cross(ax, ay)))
+
+
+def _random_texture(size, seed=0):
+    t = np.random.default_rng(seed).integers(0, 256, (size, size, 4), dtype=np.uint8)
+    t[..., 3] = 255
+    return t
+
+
+TILTED = np.array([[-0.8, -0.6, 3.0], [-0.3, 0.8, 4.2], [0.9, -0.5, 5.5]])
+
+
+def _check_eq8_eq9(tex_size):
+    """Per (point, view): Eqs. 8-9 evaluated in double from ray-cast geometry
+    against the oracle's quantised weight tq and splat colour.  Returns the
+    number of pairs checked and how many took each branch of Eq. 8."""
+    P = TILTED
+    n = np.cross(P[1] - P[0], P[2] - P[0])
+    assert n[2] < 0
+    uv = np.array([[0.0, 0.0], [0.0, 1.0], [1.0, 0.0]])
+    sc = one_tri_scene(P, uv, tex=_random_texture(tex_size))
+    vp = rig(V=8, W=64, H=64, aspect=1.6, D=4.0)
+    vt = O.view_table(vp)
+    r = O.render(sc, vp, IDENT, observe=True)
+    Sx, Sy, smin_o, smax_o = (float(v) for v in r["trif"][0, :4])
+    nh = n / np.linalg.norm(n)
+    Ats = 0.5 * abs((uv[1, 0] - uv[0, 0]) * (uv[2, 1] - uv[0, 1]) - (uv[1, 1] - uv[0, 1]) * (uv[2, 0] - uv[0, 0]))
+    ruv = Ats / (0.5 * np.linalg.norm(n))
+    eyes = vt["eye"].astype(np.float64)
+    act = _active_views_double(P, vt, vp)
+    # Eqs. 4-5: extremes of the pixel footprint over the vertices and active views
+    foot = [_footprint(P[k], eyes[v], vt, vp, nh) for k in range(3) for v in range(len(eyes)) if act[v]]
+    smin, smax = min(foot) * ruv, max(foot) * ruv
+    assert smin_o == pytest.approx(smin, rel=1e-4) and smax_o == pytest.approx(smax, rel=1e-4)
+    # lattice axes: camera X projected into the plane, and n x u
+    u = np.array([1.0, 0.0, 0.0]) - nh * nh[0]
+    u /= np.linalg.norm(u)
+    w = np.cross(nh, u)
+    Acell = 1.0 / (Sx * Sy)
+    suv = Acell * ruv
+    pts = r["points"]
+    tq_o, col_o = r["pv_tq"], r["pv_col"]
+    checked, branch = 0, [0, 0]
+    for p, v in zip(*np.nonzero(tq_o >= 0)):
+        Xc = P[0] + (int(pts["i"][p]) / Sx) * u + (int(pts["j"][p]) / Sy) * w   # cell centre
+        av = Acell / _footprint(Xc, eyes[v], vt, vp, nh)    # splat size in view pixels
+        vse = suv / min(1.0, av)                             # Eq. 8
+        vs = min(max(vse, smin), smax)
+        tau = (vs - smin) / (smax - smin)                    # Eq. 9
+        tq = min(max(math.floor(256 * tau + 0.5), 0), 256)
+        assert abs(int(tq_o[p, v]) - tq) <= 1, (p, v, int(tq_o[p, v]), tq)
+        lo = np.frombuffer(np.uint32(pts["tvmin"][p]).tobytes(), np.uint8).astype(float)
+        hi = np.frombuffer(np.uint32(pts["tvmax"][p]).tobytes(), np.uint8).astype(float)
+        got = np.frombuffer(np.uint32(col_o[p, v]).tobytes(), np.uint8).astype(float)
+        assert np.abs(got - np.floor(lo + (hi - lo) * tau + 0.5)).max() <= 1, (p, v, got, lo, hi, tau)
+        branch[int(av >= 1.0)] += 1
+        checked += 1
+    # every written pixel carries the colour of one of the point-views of its view
+    for v in range(len(eyes)):
+        cols = set(col_o[tq_o[:, v] >= 0, v].tolist())
+        drawn = r["rgba"][v][np.isfinite(r["depth"][v])]
+        assert set(drawn.tolist()) <= cols
+    return checked, branch, tq_o[tq_o >= 0]
+
+
+def test_eq8_eq9_interpolation_weight_on_a_tilted_triangle():
+    """Eqs. 8-9 (multiview mipmapping: per view, the splat's texture footprint
+    picks a blend between the triangle's finest and coarsest mip colours).  A
+    tilted triangle has smin < smax; with a fine texture the splat is smaller
+    than a pixel (Eq. 8 divides by the splat's pixel size), with a coarse one
+    (Eq. 3 coarsens the lattice) larger (Eq. 8 keeps the splat's UV area)."""
+    n1, b1, tq1 = _check_eq8_eq9(1024)
+    assert n1 > 1000 and b1[0] > 0.9 * n1
+    assert len(np.unique(tq1)) > 100 and tq1.min() < 16 and tq1.max() > 200
+    n2, b2, _ = _check_eq8_eq9(16)
+    assert n2 > 500 and b2[1] > 0.5 * n2
+
+
+def _compile_variant(tmp_path, old, new):
+    """The oracle with one planted mistake, compiled into a separate library."""
+    import ctypes as C
+    import subprocess
+    src = open(os.path.join(os.path.dirname(O.__file__), "lfdpr_oracle.c")).read()
+    assert old in src
+    path = tmp_path / "variant.c"
+    path.write_text(src.replace(old, new, 1))
+    so = tmp_path / "libvariant.so"
+    subprocess.check_call(["gcc", *O.CFLAGS, "-o", str(so), str(path), "-lm"])
+    lib = C.CDLL(str(so))
+    lib.orc_lattice_cells.restype = C.c_int
+    lib.orc_trilinear.restype = C.c_uint32
+    lib.orc_lod_q8.restype = C.c_int
+    lib.orc_lod_q8.argtypes = [C.c_float]
+    return lib
+
+
+@pytest.mark.parametrize("old,new", [
+    ("lerp_rgba8(tvmin[c], tvmax[c], tq)", "lerp_rgba8(tvmax[c], tvmin[c], tq)"),          # tau swapped
+    ("float vse = Acell < Ar ?", "float vse = Acell > Ar ?"),                               # Eq. 8 branch
+    ("float vs = vse < ts->smin ? ts->smin : (vse > ts->smax ? ts->smax : vse);",
+     "float vs = vse < ts->smax ? ts->smax : (vse > ts->smin ? ts->smin : vse);"),         # clamp
+    ("float Ar = ((Zc * Zc) * Zc) / (fxfy * ad);", "float Ar = (Zc * Zc) / (fxfy * ad);"),  # footprint
+])
+def test_eq8_eq9_pin_catches_planted_mistakes(tmp_path, monkeypatch, old, new):
+    monkeypatch.setattr(O, "_lib", _compile_variant(tmp_path, old, new))
+    with pytest.raises(AssertionError):
+        _check_eq8_eq9(1024)
+        _check_eq8_eq9(16)
+
+
+def _rendered_eye_offsets(vp, Z=2.0):
+    """Eye offset of every view recovered from the rendered depth of a tilted
+    plane at depth ~Z: the pixel ray from eye (b, 0, 0) through pixel x meets
+    the plane n.X = h at depth Zp, which fixes b (double precision)."""
+    n = np.array([0.35, 0.2, -1.0])
+    n /= np.linalg.norm(n)
+    c = np.array([0.0, 0.0, Z])
+    h = float(np.dot(n, c))
+    a = np.cross(n, [0.0, 1.0, 0.0])
+    a /= np.linalg.norm(a)
+    bb = np.cross(n, a)
+    L = 0.6 * Z
+    quad = [c - L * a - L * bb, c + L * a - L * bb, c - L * a + L * bb, c + L * a + L * bb]
+    P = np.array(quad, np.float32)
+    idx = np.array([[0, 1, 2], [1, 3, 2]], np.uint32)
+    if np.cross(P[1] - P[0], P[2] - P[0]) @ n < 0:
+        idx = idx[:, [0, 2, 1]]
+    sc = scenes.Scene(P, np.zeros((4, 2), np.float32), idx, np.zeros(2, np.uint16),
+                      [scenes.constant_texture(4, (200, 10, 10, 255))]).check()
+    r = O.render(sc, vp, IDENT)
+    t = math.tan(math.radians(vp.fovy_deg) / 2.0)
+    fx, fy = (vp.W / 2.0) / (vp.aspect * t), (vp.H / 2.0) / t
+    out = []
+    for v in range(vp.V * vp.S):
+        ys, xs = np.nonzero(np.isfinite(r["depth"][v]))
+        k = len(xs) // 2
+        x, y, Zp = xs[k] + 0.5, ys[k] + 0.5, float(r["depth"][v][ys[k], xs[k]])
+        # Zp (n.d) = h - n_x b with d = ((x - W/2)/fx - b/D, (y - H/2)/fy, 1)
+        px, py = (x - vp.W / 2.0) / fx, (y - vp.H / 2.0) / fy
+        b = (h - Zp * (n[0] * px + n[1] * py + n[2])) / (n[0] * (1.0 - Zp / vp.D))
+        out.append(b)
+    return np.array(out)
+
+
+def _check_rig(V=8, D=4.0, cone=40.0):
+    vp = rig(V=V, W=96, H=64, aspect=1.6, D=D, cone=cone)
+    b = _rendered_eye_offsets(vp)
+    half = D * math.tan(math.radians(cone) / 2.0)
+    assert np.allclose(np.diff(b), 2.0 * half / V, rtol=2e-4), np.diff(b)     # eye spacing
+    assert b[0] == pytest.approx(-half * (1 - 1.0 / V), rel=2e-4)             # outer eyes
+    assert b[-1] == pytest.approx(half * (1 - 1.0 / V), rel=2e-4)
+
+
+def test_rig_eye_offsets_from_rendered_depth():
+    """Sec. 3.1/5.1: V parallel eyes spread evenly over the horizontal viewing
+    cone, one per view interval at its centre: spacing 2 D tan(cone/2) / V,
+    outer eyes at +-D tan(cone/2) (1 - 1/V); recovered from rendered depth."""
+    _check_rig(V=8, D=4.0, cone=40.0)
+    _check_rig(V=5, D=3.0, cone=30.0)
+
+
+def test_focal_plane_point_is_in_the_same_pixel_in_every_view():
+    """The views share the zero-disparity plane Z = D: a surface on it covers
+    the same pixels, at the same depth, in every view."""
+    D = 4.0
+    P = np.array([[-0.3, -0.25, D], [0.35, -0.2, D], [-0.1, 0.3, D]], np.float32)
+    if np.cross(P[1] - P[0], P[2] - P[0])[2] > 0:
+        P = P[[0, 2, 1]]
+    sc = one_tri_scene(P, [[0, 0], [1, 0], [0, 1]], tex=scenes.constant_texture(4, (1, 2, 3, 255)))
+    r = O.render(sc, rig(V=8, W=64, H=48, aspect=1.6, D=D), IDENT)
+    cover = np.isfinite(r["depth"])
+    assert cover[0].sum() > 30
+    assert all(np.array_equal(cover[v], cover[0]) for v in range(8))
+    assert np.allclose(r["depth"][cover[0][None].repeat(8, 0)], D, rtol=1e-6)
+
+
+def test_rig_pin_catches_a_planted_cone_error(monkeypatch):
+    real = O.view_table
+
+    def wrong(vp):   # tan(cone) where the rig needs tan(cone/2)
+        t = real(vp)
+        B, Bw = vp.D * math.tan(math.radians(vp.cone_deg) / 2.0), vp.D * math.tan(math.radians(vp.cone_deg))
+        t["eye"] = (t["eye"].astype(np.float64) * (Bw / B)).astype(np.float32)
+        t["kshift"] = (t["eye"].astype(np.float64) / vp.D).astype(np.float32)
+        return t
+
+    monkeypatch.setattr(O, "view_table", wrong)
+    with pytest.raises(AssertionError):
+        _check_rig(V=8, D=4.0, cone=40.0)
 
 
 def test_multiview_mip_setup_closed_form():
@@ -519,3 +760,25 @@ def test_taps_are_gaussian_and_truncated():
     assert np.abs(du).max() < 1.0 and np.hypot(t[:, 1], t[:, 2]).max() / 256 < 1.125 + 1 / 256
     assert abs(du.mean()) < 0.03 and abs(dx.mean()) < 0.03
     assert 0.35 < du.std() < 0.5
+
+
+# ---------------------------------------------------------------------------
+# no holes at display size (Sec. 3.2: splats are sized to avoid holes)
+
+
+@pytest.fixture(scope="module")
+def display_1m():
+    w = scenes.display()
+    return w, O.build_textures(w.scene)
+
+
+@pytest.mark.parametrize("frame", [0, 17, 111])
+def test_display_frames_have_no_orphans_or_misses(display_1m, frame):
+    """On the 1M-triangle, 48-view display workload every pixel covered by a
+    visible triangle is owned by one of its points and lies in that point's
+    splat (frames that had an orphaned zero-area lattice or an edge-on miss
+    before the rules for those cases)."""
+    w, tx = display_1m
+    st = O.render(w.scene, w.views, w.model(frame), tx)["stats"]
+    assert st["orphans"] == 0 and st["misses"] == 0 and st["overflow_tris"] == 0, st
+    assert st["fragments"] > 40_000_000
