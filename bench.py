@@ -45,43 +45,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic work per unit: per
-# (point, active view) about 100 operations of visibility, projection, splat box
-# and colour, plus about 37 per pixel the point writes (ray, depth, lattice
-# coordinates, ownership, key); the oracle counts 0.327 written pixels per
-# point-view on display-1M, so 100 + 37 * 0.327 = 112.
-SPLAT_OPS_PER_POINT_VIEW = 112
+# Algorithmic work of the splat, as the method's own operation count: about 25
+# operations per (point, active view) (the splat's projected box and its colour,
+# Eqs. 8-9) plus about 40 per written pixel (pixel ray, plane depth, lattice
+# coordinates, ownership, 64-bit key and depth test).  Written pixels come from
+# the GPU's own count of depth-test updates (lfdpr_stats.written_px).
+SPLAT_OPS_PER_POINT_VIEW_ALG = 25
+SPLAT_OPS_PER_WRITTEN_PX_ALG = 40
+# A finer census of the definition as evaluated (visibility 2, vertex
+# projection + Q8 + guard 12, area 7, triangle box 8, splat box 20, Eqs. 8-9
+# colour 26, lattice offsets 6, edge set-up 12 per point-view; ray 1, plane 4,
+# divide 1, checks 2, ur/wr 8, s/t 8, ownership 4, key 2, atomic 1 per
+# written pixel), reported beside the algorithmic fraction.
+SPLAT_OPS_PER_POINT_VIEW = 100
+SPLAT_OPS_PER_WRITTEN_PX = 37
 # physically based shading of a splat (unpack 9, shading normal 25, view and
 # half vectors 26, four dot products 24, roughness/metallic 4, D 8, k 3, G 8,
-# Fresnel power 5, specular 5, per channel 26 x 3) ~ 205 ops, once per written
-# pixel: 0.327 written pixels per point-view (oracle, display-1M)
-SPLAT_PBR_OPS_PER_POINT_VIEW = SPLAT_OPS_PER_POINT_VIEW + round(205 * 0.327)
-SETUP_OPS_PER_TRI_VIEW = 75        # R4 + R6 per (triangle, view)
+# Fresnel power 5, specular 5, per channel 26 x 3) ~ 205 ops per written pixel
+SPLAT_PBR_OPS_PER_WRITTEN_PX = 205
+SETUP_OPS_PER_TRI_VIEW = 40        # visibility and the density terms per (triangle, view)
 NET_FWD_BYTES_PER_PX = 16 + 80 + 128 + 128 + 80   # blur + four convolution layers, BF16
 BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
     "scan": lambda s: s["nt"] * (4 + 4 + 8),
     "emit": lambda s: s["tris_with_points"] * 76 + s["points"] * (16 + 2 * 16),
-    "splat": lambda s: s["points"] * (16 + 112) + s["fragments"] * 8,
+    "splat": lambda s: s["points"] * (16 + 112) + s["written_px"] * 8,
     "resolve": lambda s: s["pixels"] * (8 + 8 + 4),
     "interleave": lambda s: s["panel_px"] * 3 + s["panel_px"] * 3 * 4,
     "angular_filter": lambda s: s["pixels"] * 4 + s["out_pixels"] * 4,
 }
 
 
-def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None,
-             splat_ops: int = SPLAT_OPS_PER_POINT_VIEW) -> dict:
+def splat_ops(pv: float, written: float, pbr: bool = False) -> float:
+    """Algorithmic lane-operations of one splat launch (see above)."""
+    per_px = SPLAT_OPS_PER_WRITTEN_PX_ALG + (SPLAT_PBR_OPS_PER_WRITTEN_PX if pbr else 0)
+    return SPLAT_OPS_PER_POINT_VIEW_ALG * pv + per_px * written
+
+
+def splat_ops_census(pv: float, written: float, pbr: bool = False) -> float:
+    per_px = SPLAT_OPS_PER_WRITTEN_PX + (SPLAT_PBR_OPS_PER_WRITTEN_PX if pbr else 0)
+    return SPLAT_OPS_PER_POINT_VIEW * pv + per_px * written
+
+
+def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None, pbr: bool = False) -> dict:
     """Roofline object of the dominant kernel of a frame (stage ms from HIP events)."""
     dom = max(("setup", "emit", "splat", "resolve", "interleave", "scan", "angular_filter"),
               key=lambda k: stage_ms.get(k, 0.0))
     dom_ms = stage_ms[dom]
+    peak_t = VALU_PEAK_GOPS / 1e3
     if dom == "splat":
-        ops = splat_ops * pv_per_frame
+        wpx = shape["written_px"]
+        ops = splat_ops(pv_per_frame, wpx, pbr)
         achieved = ops / (dom_ms * 1e-3) / 1e12
+        census = splat_ops_census(pv_per_frame, wpx, pbr) / (dom_ms * 1e-3) / 1e12
         return {"kernel": "k_splat", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": round(VALU_PEAK_GOPS / 1e3, 2), "unit": "Tops/s",
-                "frac": round(achieved / (VALU_PEAK_GOPS / 1e3), 4), "traffic": traffic,
-                "ops_per_point_view": splat_ops, "launch_ms": round(dom_ms, 4)}
+                "peak": round(peak_t, 2), "unit": "Tops/s",
+                "frac": round(achieved / peak_t, 4), "traffic": traffic,
+                "ops": f"{SPLAT_OPS_PER_POINT_VIEW_ALG} per point-view + "
+                       f"{SPLAT_OPS_PER_WRITTEN_PX_ALG + (SPLAT_PBR_OPS_PER_WRITTEN_PX if pbr else 0)} per written pixel",
+                "point_views": int(pv_per_frame), "written_px": int(wpx),
+                "frac_census": round(census / peak_t, 4), "launch_ms": round(dom_ms, 4)}
     if dom == "setup":
         ops = SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"]
         achieved = ops / (dom_ms * 1e-3) / 1e12
@@ -94,14 +117,14 @@ def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None,
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launch_ms": round(dom_ms, 4)}
 
 
-def frame_roofline(stage_ms: dict, pv_per_frame: float, shape: dict, frame_ms: float,
-                   splat_ops: int = SPLAT_OPS_PER_POINT_VIEW) -> dict:
+def frame_roofline(stage_ms: dict, pv_per_frame: float, shape: dict, frame_ms: float, pbr: bool = False) -> dict:
     """The frame's achievable time: for every stage the larger of its
     algorithmic bytes at the HBM peak and its algorithmic lane-ops at the ALU
     peak, summed over the stages; frac = that sum / the measured frame time."""
     peak_ops = VALU_PEAK_GOPS * 1e9
     peak_bytes = HBM_PEAK_GBS * 1e9
-    ops = {"setup": SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"], "splat": splat_ops * pv_per_frame}
+    ops = {"setup": SETUP_OPS_PER_TRI_VIEW * shape["nt"] * shape["views"],
+           "splat": splat_ops(pv_per_frame, shape["written_px"], pbr)}
     bounds = {}
     for k in stage_ms:
         t_mem = BYTES[k](shape) / peak_bytes if k in BYTES else 0.0
@@ -136,6 +159,24 @@ def splat_traffic():
     """HBM bytes per k_splat launch on display-1M (see profile_traffic)."""
     return profile_traffic("display-1M_splat_traffic.md", ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"),
                            "HBM bytes per launch")
+
+
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: logical CPUs visible to this process,
+    all logical CPUs, and the CPU model."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"nproc": usable, "logical_cpus": os.cpu_count(), "cpu_model": model, "oracle_threads": 1}
 
 
 def stage_avg(R):
@@ -180,15 +221,21 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         frame(f)
     torch.cuda.synchronize()
     R.timing(True)
+    # one event per frame on the library's stream after the frame's panel:
+    # frame-to-frame intervals give the p50 / p99 frame times
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ends[0].record(R.stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         frame(args.warmup + k)
+        ends[k + 1].record(R.stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st_avg = stage_avg(R)
     R.timing(False)
     wall_ms = (t1 - t0) * 1e3 / args.steps
+    intervals = np.array([ends[k].elapsed_time(ends[k + 1]) for k in range(args.steps)])
     serial_ms = None
     if args.frames_in_flight > 1:
         # the same frames with one frame in flight, for comparison
@@ -201,20 +248,21 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         serial_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     # the same frames again, untimed, for their statistics (deterministic)
-    pv = pts = act = 0
+    pv = pts = act = wpx = 0
     for k in range(args.steps):
         R.render_frame(sid, models[args.warmup + k], views)
         s = R.stats()
         pv += s["point_views"]
         pts += s["points"]
         act += s["active_tris"]
+        wpx += s["written_px"]
     nfr = args.steps
     n_rendered = w.views.V * w.views.S
+    pbr = kind == "display-1M-pbr"
     shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
                  out_pixels=w.views.V * w.views.W * w.views.H,
-                 panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, fragments=0)
-    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None,
-                    SPLAT_PBR_OPS_PER_POINT_VIEW if kind == "display-1M-pbr" else SPLAT_OPS_PER_POINT_VIEW)
+                 panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, written_px=wpx / nfr)
+    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None, pbr)
     names = {
         "display-1M": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
                       "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene",
@@ -244,17 +292,20 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
                    "view_px": [w.views.W, w.views.H], "panel_px": [w.lens.Wp, w.lens.Hp],
                    "triangles": w.scene.n_tris, "recon": recon},
         "frame_ms": round(wall_ms, 4),
+        "frame_ms_p50": round(float(np.percentile(intervals, 50)), 4),
+        "frame_ms_p99": round(float(np.percentile(intervals, 99)), 4),
         "frames_per_s": round(1e3 / wall_ms, 2),
         "frames_in_flight": args.frames_in_flight,
         "frame_ms_one_in_flight": round(serial_ms if serial_ms is not None else wall_ms, 4),
         "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
-        "active_tris_per_frame": int(act / nfr),
+        "written_px_per_frame": int(wpx / nfr), "active_tris_per_frame": int(act / nfr),
         "stage_ms": {k: round(v, 4) for k, v in st_avg.items()},
         "roofline": roof,
-        "frame_roofline": frame_roofline(st_avg, pv / nfr, shape, wall_ms,
-                                         SPLAT_PBR_OPS_PER_POINT_VIEW if kind == "display-1M-pbr"
-                                         else SPLAT_OPS_PER_POINT_VIEW),
+        "frame_roofline": frame_roofline(st_avg, pv / nfr, shape, wall_ms, pbr),
     }
+    if not args.no_learned and kind == "display-1M":
+        log("learned reconstruction: checkpoint, PSNR against 16x angular supersampling, frame times")
+        out["learned"] = learned_summary(args, torch, lfdpr, scenes, w)
     if not args.no_cpu_baseline and kind == "display-1M":
         from oracle import oracle as O
         nf = 3
@@ -268,7 +319,45 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         out["cpu_baseline"] = {"value": round(pv_cpu / dt, 1), "unit": "point-view splats/s",
                                "cores": 1, "kind": "oracle",
                                "sample": f"{nf} consecutive full display-1M frames (point generation, splat into 48 "
-                                         f"views, interleave) on one host core: {dt:.2f} s"}
+                                         f"views, interleave) on one host core: {dt:.2f} s",
+                               "host": host_cpu()}
+    return out
+
+
+LEARNED_CHECKPOINT = os.path.join(ROOT, "paper_2601_19901_amd", "weights", "learned_display-1M.lfnet")
+
+
+def learned_summary(args, torch, lfdpr, scenes, w) -> dict:
+    """The learned angular reconstruction on the benchmark's own scene (never
+    trained on: training used scenes of seeds 5000-5003), with the committed
+    checkpoint: frame time to the panel of plain 1x, learned and 4x angular
+    supersampling in the same run, and PSNR of each against 16x angular
+    supersampling + filter on frames spread over the rotation."""
+    from paper_2601_19901_amd import learned
+    if not os.path.exists(LEARNED_CHECKPOINT):
+        return {"error": f"checkpoint {os.path.relpath(LEARNED_CHECKPOINT, ROOT)} missing"}
+    t0 = time.time()
+    ss = learned.AngularSS([w], factors=(1, 4, 16))
+    model = learned.LearnedReconstruction(ss, w.views.H, w.views.W)
+    model.net.load(LEARNED_CHECKPOINT)
+    check = model.validate([(0, 250), (0, 750)])
+    frames = [(0, f) for f in range(0, 1000, 125)]
+    psnr = learned.evaluate(model, frames, ref_S=16)
+    for S in (1, 4):
+        ss.rigs[S].renderer.set_frames_in_flight(args.frames_in_flight)
+    times = learned.time_pipelines(model, w.lens, 0, list(range(30)))
+    out = {
+        "checkpoint": os.path.relpath(LEARNED_CHECKPOINT, ROOT),
+        "validated_against_4x": check,
+        "frame_ms": {k: round(v, 4) for k, v in times.items()},
+        "psnr_db_vs_16x": {k: round(v, 3) for k, v in psnr.items() if k.endswith("vs_ref")},
+        "psnr_frames": f"{len(frames)} frames of the benchmark scene (seed {args.seed}), every 125th of the rotation",
+        "learned_minus_ss4_db": round(psnr["learned_vs_ref"] - psnr["ss4_vs_ref"], 3),
+        "learned_speedup_vs_ss4": round(times["ss4_ms"] / times["learned_ms"], 3),
+        "target_met": bool(times["learned_ms"] < times["ss4_ms"]
+                           and psnr["learned_vs_ref"] >= psnr["ss4_vs_ref"] - 0.5),
+        "seconds": round(time.time() - t0, 1),
+    }
     return out
 
 
@@ -322,16 +411,17 @@ def run_batch(args, torch, lfdpr, scenes):
             B.render(models[args.warmup + k], views, panels)
         torch.cuda.synchronize()
         wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    pv = pts = act = 0
+    pv = pts = act = wpx = 0
     for k in range(args.steps):
         B.render(models[args.warmup + k], views, panels)
         s = B.stats()
         pv += s["point_views"]
         pts += s["points"]
         act += s["active_tris"]
+        wpx += s["written_px"]
     nfr = args.steps
     shape = dict(nt=sum(ntri), views=V, points=pts / nfr, pixels=len(ws) * V * W * H,
-                 panel_px=len(ws) * ws[0].lens.Wp * ws[0].lens.Hp, tris_with_points=act / nfr, fragments=0)
+                 panel_px=len(ws) * ws[0].lens.Wp * ws[0].lens.Hp, tris_with_points=act / nfr, written_px=wpx / nfr)
     roof = roofline(st_avg, pv / nfr, shape)
     roof["timing"] = "stage events on eager batch renders of the same frames (graph replays carry no events)"
     return {
@@ -418,6 +508,8 @@ def run_learned(args, torch, lfdpr, scenes):
     # blurred RGB and writes 4 channels (80).  121 flop/B, below the 312 flop/B
     # ridge of MI355X: the forward pass is HBM bound.
     net_bytes = NET_FWD_BYTES_PER_PX * px
+    # the method's own input and output: (R, G, B, d) per view pixel in, (R, G, B, 0) out, BF16
+    io_bytes = (8 + 8) * px
     gbs = net_bytes / (fwd_ms * 1e-3) / 1e9
     R1.render_frame(ss.rigs[1].scene_ids[0], w.model(args.warmup), ss.views1)
     pv = R1.stats()["point_views"]
@@ -439,14 +531,16 @@ def run_learned(args, torch, lfdpr, scenes):
         "net_forward_ms": round(fwd_ms, 4),
         "net_train_step_ms": round(train_ms, 4),
         "net_train_step": "forward + backward + Adam on 48 x 128 x 128 crops",
-        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur_rows", "bound": "hbm",
-                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"kernel": "k_conv3x3 (4 layers) + k_disparity_blur_rows", "bound": "mfma",
+                     "achieved": round(achieved, 1), "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4),
                      "traffic": profile_traffic("learned-display_forward_traffic.md", ("lfdpr_net.hip",),
                                                 "HBM bytes per forward"),
-                     "bytes_per_frame": net_bytes, "flops_per_frame": flops,
-                     "mfma_achieved_tflops": round(achieved, 1),
-                     "mfma_frac": round(achieved / BF16_MFMA_PEAK_TFLOPS, 4), "launch_ms": round(fwd_ms, 4)},
+                     "flops_per_frame": flops,
+                     "io_bytes_per_frame": io_bytes, "io_hbm_frac": round(io_bytes / (fwd_ms * 1e-3) / 1e9
+                                                                          / HBM_PEAK_GBS, 4),
+                     "unfused_activation_bytes_per_frame": net_bytes,
+                     "unfused_activation_gbs": round(gbs, 1), "launch_ms": round(fwd_ms, 4)},
     }
 
 
@@ -459,6 +553,8 @@ def main():
                                            "display-1M-spatial2x", "display-1M-pbr", "batch16", "learned-display"),
                     default="display-1M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-reconstruction comparison of the default workload")
     ap.add_argument("--frames-in-flight", type=int, choices=(1, 2), default=2,
                     help="frames whose point generation overlaps the previous frame (display, learned and batch workloads)")
     ap.add_argument("--seed", type=int, default=2)

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LFDPR_ABI_VERSION 2
+#define LFDPR_ABI_VERSION 3
 
 enum {
   LFDPR_OK = 0,
@@ -53,6 +53,9 @@ enum {
 };
 
 enum { LFDPR_RECON_NONE = 0, LFDPR_RECON_SPATIAL = 1, LFDPR_RECON_ANGULAR = 2, LFDPR_RECON_BOTH = 3 };
+/* Order in which the splat visits its work (lfdpr_set_splat_order); both give
+ * the same keys, hence the same views, bit for bit. */
+enum { LFDPR_SPLAT_POINT = 0, LFDPR_SPLAT_TRIANGLE_VIEW = 1 };
 enum { LFDPR_SHADE_UNLIT = 0, LFDPR_SHADE_PBR = 1 };
 
 typedef struct lfdpr_ctx lfdpr_ctx;
@@ -105,6 +108,8 @@ typedef struct {
   int64_t capacity;        /* point capacity of the context */
   int32_t point_overflow;  /* 1 when points > capacity (frame incomplete) */
   int32_t n_views;         /* rendered (sub-)views */
+  int64_t written_px;      /* (point, view, pixel) depth-test updates the splat issued: every
+                              covered pixel of a visible triangle, owned by one point (Sec. 3.2) */
 } lfdpr_stats;
 
 /* Version of this ABI (LFDPR_ABI_VERSION). */
@@ -172,6 +177,17 @@ int lfdpr_set_shading(lfdpr_ctx* ctx, const lfdpr_shading* shading);
  * every rendered view, the 64-bit view buffer of Sec. 5.1) and the point
  * buffer (16 B per point).  Synchronous. */
 int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* views);
+
+/* How the splat (Sec. 3.2) visits its (point, view, pixel) work:
+ *   LFDPR_SPLAT_POINT (default)  per point, looping over the views and its
+ *     splat rectangle's pixels;
+ *   LFDPR_SPLAT_TRIANGLE_VIEW  per (triangle, view): the pixels inside the
+ *     triangle's projection find their owning point through the lattice row
+ *     table and apply its splat rectangle and colour (unlit frames; physically
+ *     shaded frames always splat per point).
+ * The keys, views and depth are identical.  Applies to the context's frames
+ * and to batches created on it afterwards. */
+int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
 
 /* Sets the panel and reconstruction parameters used by lfdpr_reconstruct. */
 int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* lens);
@@ -351,6 +367,10 @@ int lfdpr_net_param_count(lfdpr_net* net, int64_t* n);
  * for the rig of R2 (k >= 0; 0, the default, turns the blur into the identity).
  * Applies from the next forward. */
 int lfdpr_net_set_disparity_scale(lfdpr_net* net, float k);
+/* The same k computed by the library from the rig the views were rendered with
+ * (R2: fx = (W/2) / (aspect tan(fovy/2)); k = fx * 2 tan(cone/2) / V, in
+ * double, rounded once).  views->V must equal the network's V. */
+int lfdpr_net_set_rig(lfdpr_net* net, const lfdpr_view_params* views);
 /* Host FP32 parameters in / out (n must equal the count); set resets Adam.  Synchronous. */
 int lfdpr_net_set_params(lfdpr_net* net, const float* host_params, int64_t n);
 int lfdpr_net_get_params(lfdpr_net* net, float* host_params, int64_t n);

@@ -54,6 +54,8 @@ struct lfdpr_ctx {
   float* d_lod_thr = nullptr;
   int64_t cap = 0;
   Point* d_points = nullptr;
+  RowEntry* d_rows = nullptr;   // triangle-major splat: lattice row table and
+  PointBox* d_pbox = nullptr;   // per-point splat rectangles (point capacity each)
   uint64_t* d_keys = nullptr;
   int64_t n_keys = 0;
   // angular supersampling filter table
@@ -69,6 +71,7 @@ struct lfdpr_ctx {
   TriEmit* d_em = nullptr;
   uint64_t* d_tiles = nullptr;
   uint32_t* d_big = nullptr;
+  uint32_t* d_tris = nullptr;   // triangles with points
   uint64_t* d_stats = nullptr;
   int64_t last_nt = 0;
   // lens
@@ -103,20 +106,26 @@ struct lfdpr_ctx {
   struct FrameBufs {
     int64_t points_alloc = 0, tri_cap = 0, tm_cap = 0, pmat_cap = 0, last_nt = 0;
     Point* d_points = nullptr;
+    RowEntry* d_rows = nullptr;
+    PointBox* d_pbox = nullptr;
     uint32_t* d_counts = nullptr;
     uint64_t* d_offsets = nullptr;
     TriRec* d_rec = nullptr;
     TriEmit* d_em = nullptr;
     uint64_t* d_tiles = nullptr;
     uint32_t* d_big = nullptr;
+    uint32_t* d_tris = nullptr;
     uint64_t* d_stats = nullptr;
     TriMat* d_tm = nullptr;
     uint4* d_pmat = nullptr;
     bool last_pbr = false;
   } other;
-  // launch shape of the splat kernel and key layout (autotuned)
+  // launch shape of the splat kernel and key layout (autotuned); splat order:
+  // LFDPR_SPLAT_POINT or LFDPR_SPLAT_TRIANGLE_VIEW (unlit frames; shaded frames
+  // always go point by point)
   int splat_blocks = 4096;
   int key_layout = 0;
+  int splat_order = LFDPR_SPLAT_POINT;
   // stage timing: event pairs recorded on the stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -170,6 +179,9 @@ void swap_frame_buffers(lfdpr_ctx* ctx) {
   std::swap(ctx->pmat_cap, o.pmat_cap);
   std::swap(ctx->last_nt, o.last_nt);
   std::swap(ctx->d_points, o.d_points);
+  std::swap(ctx->d_rows, o.d_rows);
+  std::swap(ctx->d_pbox, o.d_pbox);
+  std::swap(ctx->d_tris, o.d_tris);
   std::swap(ctx->d_counts, o.d_counts);
   std::swap(ctx->d_offsets, o.d_offsets);
   std::swap(ctx->d_rec, o.d_rec);
@@ -193,8 +205,12 @@ int prepare_frame_buffers(lfdpr_ctx* ctx, int64_t nt, bool pbr) {
   if (!ctx->d_points || ctx->points_alloc != ctx->cap) {
     if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
     dfree(ctx->d_points);
+    dfree(ctx->d_rows);
+    dfree(ctx->d_pbox);
     ctx->points_alloc = 0;
-    if (dalloc(ctx->d_points, (size_t)ctx->cap) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "point buffer");
+    if (dalloc(ctx->d_points, (size_t)ctx->cap) != hipSuccess || dalloc(ctx->d_rows, (size_t)ctx->cap) != hipSuccess ||
+        dalloc(ctx->d_pbox, (size_t)ctx->cap) != hipSuccess)
+      return fail(ctx, LFDPR_ENOMEM, "point buffers");
     ctx->points_alloc = ctx->cap;
   }
   if (!ctx->d_stats) {
@@ -225,9 +241,11 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   dfree(ctx->d_em);
   dfree(ctx->d_tiles);
   dfree(ctx->d_big);
+  dfree(ctx->d_tris);
   if (dalloc(ctx->d_counts, n) != hipSuccess || dalloc(ctx->d_offsets, n) != hipSuccess ||
       dalloc(ctx->d_rec, n) != hipSuccess || dalloc(ctx->d_em, n) != hipSuccess ||
-      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess || dalloc(ctx->d_big, n) != hipSuccess) {
+      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess || dalloc(ctx->d_big, n) != hipSuccess ||
+      dalloc(ctx->d_tris, n) != hipSuccess) {
     ctx->tri_cap = 0;
     return fail(ctx, LFDPR_ENOMEM, "per-triangle buffers");
   }
@@ -392,6 +410,9 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   {
     auto& o = ctx->other;
     dfree(o.d_points);
+    dfree(o.d_rows);
+    dfree(o.d_pbox);
+    dfree(o.d_tris);
     dfree(o.d_counts);
     dfree(o.d_offsets);
     dfree(o.d_rec);
@@ -412,6 +433,9 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_kshift);
   dfree(ctx->d_lod_thr);
   dfree(ctx->d_points);
+  dfree(ctx->d_rows);
+  dfree(ctx->d_pbox);
+  dfree(ctx->d_tris);
   dfree(ctx->d_keys);
   dfree(ctx->d_acnt);
   dfree(ctx->d_asrc);
@@ -619,6 +643,13 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
   return LFDPR_OK;
 }
 
+int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order) {
+  if (!ctx) return LFDPR_EINVAL;
+  if (order != LFDPR_SPLAT_TRIANGLE_VIEW && order != LFDPR_SPLAT_POINT) return fail(ctx, LFDPR_EINVAL, "unknown splat order");
+  ctx->splat_order = order;
+  return LFDPR_OK;
+}
+
 int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* l) {
   if (!ctx || !l) return fail(ctx, LFDPR_EINVAL, "null argument");
   if (l->Wp < 1 || l->Hp < 1 || l->Wp > 16384 || l->Hp > 16384 || !(l->pitch_subpx > 0.0) || l->mode < 0 ||
@@ -726,6 +757,12 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   ea.cap = ctx->cap;
   ea.tm = pbr ? ctx->d_tm : nullptr;
   ea.pmat = pbr ? ctx->d_pmat : nullptr;
+  const bool tv = !pbr && ctx->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW;
+  ea.rec = ctx->d_rec;
+  ea.rows = tv ? ctx->d_rows : nullptr;
+  ea.pbox = tv ? ctx->d_pbox : nullptr;
+  ea.tris = tv ? ctx->d_tris : nullptr;
+  ea.n_tris = ctx->d_stats + STAT_EMITTING;
   launch_emit(ea, ctx->splat_blocks, gen);
   hipEvent_t e3 = mark_on(ctx, gen);
   if (piped) {
@@ -739,6 +776,15 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   pa.table_rig = ctx->rig;
   pa.points = ctx->d_points;
   pa.n_points = ctx->d_stats + STAT_TOTAL;
+  pa.stats = ctx->d_stats;
+  pa.em = ctx->d_em;
+  pa.offsets = ctx->d_offsets;
+  pa.counts = ctx->d_counts;
+  pa.rows = ctx->d_rows;
+  pa.pbox = tv ? ctx->d_pbox : nullptr;
+  pa.tris = ctx->d_tris;
+  pa.n_tris = ctx->d_stats + STAT_EMITTING;
+  pa.nt = s.nt;
   pa.cap = ctx->cap;
   pa.rec = ctx->d_rec;
   pa.tm = pbr ? ctx->d_tm : nullptr;
@@ -813,6 +859,7 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   out->active_tris = (int64_t)st[STAT_ACTIVE];
   out->point_views = (int64_t)st[STAT_POINT_VIEWS];
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
+  out->written_px = (int64_t)st[STAT_WRITTEN];
   out->capacity = ctx->cap;
   out->point_overflow = out->points > ctx->cap ? 1 : 0;
   out->n_views = ctx->rig.n_views;
@@ -904,9 +951,13 @@ struct lfdpr_batch {
   TriEmit* em = nullptr;
   uint64_t* tiles = nullptr;
   uint32_t* big = nullptr;
+  uint32_t* tris = nullptr;
   uint64_t* stats = nullptr;
   Point* points = nullptr;
+  RowEntry* rows = nullptr;
+  PointBox* pbox = nullptr;
   int64_t cap = 0;
+  int splat_order = LFDPR_SPLAT_POINT;
   TriMat* tm = nullptr;  // physically based shading: material records and
   uint4* pmat = nullptr; // per-point material words (allocated on first use)
   Rig table_rig{};
@@ -931,8 +982,11 @@ struct lfdpr_batch {
     TriEmit* em = nullptr;
     uint64_t* tiles = nullptr;
     uint32_t* big = nullptr;
+    uint32_t* tris = nullptr;
     uint64_t* stats = nullptr;
     Point* points = nullptr;
+    RowEntry* rows = nullptr;
+    PointBox* pbox = nullptr;
     TriMat* tm = nullptr;
     uint4* pmat = nullptr;
   } alt;
@@ -970,8 +1024,11 @@ void batch_free_alt(lfdpr_batch* b) {
   dfree(a.em);
   dfree(a.tiles);
   dfree(a.big);
+  dfree(a.tris);
   dfree(a.stats);
   dfree(a.points);
+  dfree(a.rows);
+  dfree(a.pbox);
   dfree(a.tm);
   dfree(a.pmat);
   for (int k = 0; k < 2; ++k) {
@@ -995,8 +1052,11 @@ void batch_swap_sets(lfdpr_batch* b) {
   std::swap(b->em, a.em);
   std::swap(b->tiles, a.tiles);
   std::swap(b->big, a.big);
+  std::swap(b->tris, a.tris);
   std::swap(b->stats, a.stats);
   std::swap(b->points, a.points);
+  std::swap(b->rows, a.rows);
+  std::swap(b->pbox, a.pbox);
   std::swap(b->tm, a.tm);
   std::swap(b->pmat, a.pmat);
 }
@@ -1022,8 +1082,11 @@ void batch_free(lfdpr_batch* b) {
   dfree(b->em);
   dfree(b->tiles);
   dfree(b->big);
+  dfree(b->tris);
   dfree(b->stats);
   dfree(b->points);
+  dfree(b->rows);
+  dfree(b->pbox);
   dfree(b->tm);
   dfree(b->pmat);
   batch_free_alt(b);
@@ -1070,6 +1133,12 @@ hipEvent_t batch_gen(lfdpr_batch* b, hipStream_t st, bool timed) {
   ea.cap = b->cap;
   ea.tm = pbr ? b->tm : nullptr;
   ea.pmat = pbr ? b->pmat : nullptr;
+  const bool tv = !pbr && b->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW;
+  ea.rec = b->rec;
+  ea.rows = tv ? b->rows : nullptr;
+  ea.pbox = tv ? b->pbox : nullptr;
+  ea.tris = tv ? b->tris : nullptr;
+  ea.n_tris = b->stats + STAT_EMITTING;
   launch_emit(ea, b->splat_blocks, st);
   hipEvent_t e3 = ev();
   stage(ctx, 0, e0, e1);
@@ -1090,8 +1159,17 @@ void batch_splat(lfdpr_batch* b, uint32_t* views, uint8_t* panels, hipStream_t s
   pa.table_rig = b->table_rig;
   pa.points = b->points;
   pa.n_points = b->stats + STAT_TOTAL;
+  pa.stats = b->stats;
   pa.cap = b->cap;
   pa.rec = b->rec;
+  pa.em = b->em;
+  pa.offsets = b->offsets;
+  pa.counts = b->counts;
+  pa.rows = b->rows;
+  pa.pbox = !pbr && b->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW ? b->pbox : nullptr;
+  pa.tris = b->tris;
+  pa.n_tris = b->stats + STAT_EMITTING;
+  pa.nt = b->nt;
   pa.tm = pbr ? b->tm : nullptr;
   pa.pmat = pbr ? b->pmat : nullptr;
   const lfdpr_shading& sh = ctx->shading;
@@ -1149,6 +1227,7 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
   lfdpr_batch* b = new lfdpr_batch();
   b->ctx = ctx;
   b->n = n;
+  b->splat_order = ctx->splat_order;
   bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
@@ -1193,6 +1272,8 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
     ok = dalloc(b->keys, (size_t)(b->per_item_px * n)) == hipSuccess && dalloc(b->counts, ntb) == hipSuccess &&
          dalloc(b->offsets, ntb) == hipSuccess && dalloc(b->rec, ntb) == hipSuccess && dalloc(b->em, ntb) == hipSuccess &&
          dalloc(b->tiles, (ntb + 1023) / 1024 + 1) == hipSuccess && dalloc(b->big, ntb) == hipSuccess &&
+         dalloc(b->tris, ntb) == hipSuccess && dalloc(b->rows, (size_t)b->cap) == hipSuccess &&
+         dalloc(b->pbox, (size_t)b->cap) == hipSuccess &&
          dalloc(b->stats, STAT_SLOTS) == hipSuccess && dalloc(b->points, (size_t)b->cap) == hipSuccess &&
          dalloc(b->d_items, n) == hipSuccess && dalloc(b->d_models, n) == hipSuccess &&
          hipHostMalloc((void**)&b->h_models, sizeof(Model) * n, hipHostMallocDefault) == hipSuccess;
@@ -1265,6 +1346,8 @@ int lfdpr_batch_set_frames_in_flight(lfdpr_batch* b, int32_t n) {
     ok = dalloc(a.counts, ntb) == hipSuccess && dalloc(a.offsets, ntb) == hipSuccess && dalloc(a.rec, ntb) == hipSuccess &&
          dalloc(a.em, ntb) == hipSuccess && dalloc(a.tiles, (ntb + 1023) / 1024 + 1) == hipSuccess &&
          dalloc(a.big, ntb) == hipSuccess && dalloc(a.stats, STAT_SLOTS) == hipSuccess &&
+         dalloc(a.tris, ntb) == hipSuccess && dalloc(a.rows, (size_t)b->cap) == hipSuccess &&
+         dalloc(a.pbox, (size_t)b->cap) == hipSuccess &&
          dalloc(a.points, (size_t)b->cap) == hipSuccess && dalloc(a.d_models, b->n) == hipSuccess &&
          hipHostMalloc((void**)&a.h_models, sizeof(Model) * b->n, hipHostMallocDefault) == hipSuccess;
   if (ok && b->tm) ok = dalloc(a.tm, (size_t)ntb) == hipSuccess && dalloc(a.pmat, (size_t)b->cap) == hipSuccess;
@@ -1393,6 +1476,7 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
   out->active_tris = (int64_t)st[STAT_ACTIVE];
   out->point_views = (int64_t)st[STAT_POINT_VIEWS];
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
+  out->written_px = (int64_t)st[STAT_WRITTEN];
   out->capacity = b->cap;
   out->point_overflow = out->points > b->cap ? 1 : 0;
   out->n_views = b->table_rig.n_views;

@@ -47,6 +47,30 @@ struct alignas(16) Point {
   uint32_t tri_flags, ij, tvmin, tvmax;
 };
 
+// Per-point splat data (48 B) for the triangle-major splat, written with the
+// point's mip colours: the four corners of the point's splat rectangle
+// (lattice cell, extended by one cell beyond a row or column end) projected
+// except for the eye offset (x = cA - b*cC in the view with eye offset b),
+// the pixel rows the rectangle covers (view independent; kAllRows when a
+// corner lies behind z_near/2: then no box limit), the cube of the cell-centre
+// depth (Eq. 8) and the two mip colours (Eq. 9).
+struct alignas(16) PointBox {
+  float cA[4];
+  float cC[4];
+  float zc3;
+  int32_t rows;  // (u16)first row | (u16)last row << 16
+  uint32_t tvmin, tvmax;
+};
+constexpr int32_t kAllRows = (int32_t)0x7FFF8000;  // first row -32768, last 32767
+
+// One row j of a triangle's lattice, stored at (triangle's first point) + (j -
+// jlo): the row's first point relative to the triangle's first point, and the
+// row's cell range [ilo, ihi].
+struct alignas(8) RowEntry {
+  uint32_t start;
+  int16_t ilo, ihi;
+};
+
 struct TexInfo {
   int32_t size, levels;
   int64_t off[16];  // byte offset of each level in the texel pool

@@ -7,7 +7,8 @@
 
 namespace lfdpr {
 
-enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_BIG = 4, STAT_SLOTS = 8 };
+enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_BIG = 4,
+                STAT_WRITTEN = 5, STAT_EMITTING = 6, STAT_SLOTS = 8 };
 
 // One frame of one scene inside a (possibly single-element) batch.  Items share
 // the view size and projection (W, H, fovy, aspect); eye tables may differ.
@@ -64,6 +65,12 @@ struct EmitArgs {
   int64_t cap;
   const TriMat* tm;          // physically based mode: material records, and
   uint4* pmat;               // per point normal min/max and roughness/metallic bytes; else null
+  // triangle-major splat data (null when the point-major splat is used):
+  const TriRec* rec;         // set-up records (for the point boxes)
+  RowEntry* rows;            // per lattice row, at the triangle's first point + (j - jlo)
+  PointBox* pbox;            // per point
+  uint32_t* tris;            // triangles with points (any order) and their number
+  uint64_t* n_tris;
 };
 
 struct SplatArgs {
@@ -77,6 +84,16 @@ struct SplatArgs {
   const TriMat* tm;          // physically based mode; else null
   const uint4* pmat;
   Shading sh;
+  uint64_t* stats;           // STAT_WRITTEN: pixels written (64-bit key updates issued)
+  // triangle-major splat (used when pbox is not null)
+  const TriEmit* em;
+  const uint64_t* offsets;   // first point of each triangle
+  const uint32_t* counts;    // points of each triangle
+  const RowEntry* rows;
+  const PointBox* pbox;
+  const uint32_t* tris;
+  const uint64_t* n_tris;
+  int64_t nt;                // triangles of the launch (capacity of tris)
 };
 
 struct InterleaveArgs {

@@ -62,6 +62,19 @@ __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
   return v;
 }
 
+// Slot of this lane in a list shared by the grid when `take`: one atomic per wave.
+__device__ __forceinline__ uint64_t wave_append(bool take, uint64_t* counter) {
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
+  if (!mask) return 0;
+  const int lane = threadIdx.x & 63;
+  const int leader = __builtin_ctzll(mask);
+  uint64_t base = 0;
+  if (lane == leader) base = atomicAdd((unsigned long long*)counter, (unsigned long long)__builtin_popcountll(mask));
+  base = __shfl(base, leader, 64);
+  const uint64_t below = lane ? (mask & (~0ull >> (64 - lane))) : 0ull;
+  return base + (uint64_t)__builtin_popcountll(below);
+}
+
 // ------------------------------------------------------------------ a1/a2: triangle setup
 
 __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
@@ -373,8 +386,11 @@ __device__ __forceinline__ void write_head(Point* pts, uint64_t gi, uint32_t t, 
 // for k_emit_big instead.
 __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= a.nt) return;
-  uint32_t cnt = a.counts[t];
+  const uint32_t cnt = t < a.nt ? a.counts[t] : 0u;
+  if (a.tris) {
+    const uint64_t slot = wave_append(cnt > 0, a.n_tris);
+    if (cnt > 0) a.tris[slot] = (uint32_t)t;
+  }
   if (cnt == 0) return;
   if (cnt > kBigCells) {
     uint64_t slot = atomicAdd((unsigned long long*)a.n_big, 1ull);
@@ -391,6 +407,8 @@ __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
     int64_t lo, hi;
     lattice_row(L, j, lo, hi);
     uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
+    const uint64_t ri = base + (uint64_t)(j - jlo);  // rows never outnumber points
+    if (a.rows && ri < (uint64_t)a.cap) a.rows[ri] = RowEntry{(uint32_t)k, (int16_t)lo, (int16_t)hi};
     for (int64_t i = lo; i <= hi; ++i, ++k) {
       uint64_t gi = base + k;
       if (gi >= (uint64_t)a.cap) return;
@@ -427,6 +445,9 @@ __global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
       }
       const uint64_t start = base + run + before + inc - c;
       const uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
+      const uint64_t ri = base + (uint64_t)(j - jlo);
+      if (a.rows && j <= jhi && ri < (uint64_t)a.cap)
+        a.rows[ri] = RowEntry{(uint32_t)(start - base), (int16_t)lo, (int16_t)hi};
       for (int64_t i = lo; i <= hi; ++i) {
         uint64_t gi = start + (uint64_t)(i - lo);
         if (gi < (uint64_t)a.cap)
@@ -439,7 +460,34 @@ __global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
   }
 }
 
-// Per point: UV at the cell centre and the two mip fetches (Eqs. 6-7).
+// Splat rectangle of point (i, j): its lattice cell, extended by one cell
+// beyond the end of its row (F_ILO / F_IHI) or of the lattice (F_JLO / F_JHI),
+// with the corners projected except for the eye offset (x = cA - b*cC) and the
+// range of their projected rows; `full` when a corner lies behind z_near/2.
+__device__ __forceinline__ void splat_corners(const Rig& rg, const TriRec& T, int32_t i, int32_t j, uint32_t flags,
+                                              float cA[4], float cC[4], float& ymn, float& ymx, bool& full) {
+  const int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
+  const int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
+  const float zlim = 0.5f * rg.znear;
+  ymn = ymx = 0.0f;
+  full = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float aa = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
+    float cc = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
+    float X = (T.p0x + aa * T.ux) + cc * T.wx;
+    float Y = (T.p0y + aa * T.uy) + cc * T.wy;
+    float Z = (T.p0z + aa * T.uz) + cc * T.wz;
+    if (!(Z >= zlim)) full = true;
+    float Yp;
+    vertex_proj(rg, X, Y, Z, cA[k], cC[k], Yp);
+    if (k == 0) { ymn = ymx = Yp; }
+    else { ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx; }
+  }
+}
+
+// Per point: UV at the cell centre and the two mip fetches (Eqs. 6-7); for the
+// triangle-major splat also the point's splat rectangle (PointBox).
 __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -464,6 +512,29 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
     tv.x = trilinear(it.texels, ti, u, v, E.kmin);
     tv.y = E.kmax == E.kmin ? tv.x : trilinear(it.texels, ti, u, v, E.kmax);
     *reinterpret_cast<uint2*>(&a.points[p].tvmin) = tv;
+    if (a.pbox) {
+      const TriRec& T = a.rec[t];
+      PointBox B;
+      float ymn, ymx;
+      bool full;
+      splat_corners(it.rig, T, (int32_t)i, (int32_t)j, head.x >> 28, B.cA, B.cC, ymn, ymx, full);
+      if (full) {
+        B.rows = kAllRows;
+      } else {
+        // rows whose centres lie within 1/64 px of the corners' range, clamped
+        // to [-1, H] (rows outside the view never matter)
+        int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
+        r0 = r0 < -1 ? -1 : (r0 > it.rig.H ? it.rig.H : r0);
+        r1 = r1 < -1 ? -1 : (r1 > it.rig.H ? it.rig.H : r1);
+        B.rows = (int32_t)((uint32_t)(uint16_t)(int16_t)r0 | ((uint32_t)(uint16_t)(int16_t)r1 << 16));
+      }
+      const float cs = (float)i / T.sx, ct = (float)j / T.sy;
+      const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
+      B.zc3 = (Zc * Zc) * Zc;
+      B.tvmin = tv.x;
+      B.tvmax = tv.y;
+      a.pbox[p] = B;
+    }
     if (a.tm) {
       // physically based mode: normal map (RGBA8) and the R bytes of the
       // roughness and metallic maps, each at its own LOD pair
@@ -529,14 +600,13 @@ __device__ __forceinline__ float uniform_f32(float x) {
 template <bool kPBR>
 __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, const TriRec& T, uint32_t flags,
                                             int32_t i, int32_t j, const float* tx, const float* ty,
-                                            const SplatArgs& a, uint64_t p) {
+                                            const SplatArgs& a, uint64_t p, uint32_t& written) {
   const int64_t vpx = (int64_t)item.rig.W * item.rig.H;
   const int32_t H8 = 256 * item.rig.H, W8 = 256 * item.rig.W;
   const Rig& rg = item.rig;
   uint64_t* const keys = item.keys;
   const bool rowmajor = item.key_layout != 0;
   const int64_t row_stride = rowmajor ? (int64_t)rg.n_views * rg.W : rg.W;
-  const float zlim = 0.5f * rg.znear;
   // view-independent vertex rows (guard band on y) and triangle row range
   if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) return;
   const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
@@ -547,24 +617,10 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   const int32_t Y1 = min(rg.H - 1, (ymax - 128) >> 8);
   if (Y0 > Y1) return;
   // splat box corners (row-end extended cell), projected except for the eye offset
-  const int32_t s0 = i - ((flags & F_ILO) ? 1 : 0), s1 = i + 1 + ((flags & F_IHI) ? 1 : 0);
-  const int32_t t0 = j - ((flags & F_JLO) ? 1 : 0), t1 = j + 1 + ((flags & F_JHI) ? 1 : 0);
   float cA[4], cC[4];
-  float ymn = 0.0f, ymx = 0.0f;
-  bool full = false;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    float aa = ((float)((k & 1) ? s1 : s0) - 0.5f) / T.sx;
-    float cc = ((float)((k & 2) ? t1 : t0) - 0.5f) / T.sy;
-    float X = (T.p0x + aa * T.ux) + cc * T.wx;
-    float Y = (T.p0y + aa * T.uy) + cc * T.wy;
-    float Z = (T.p0z + aa * T.uz) + cc * T.wz;
-    if (!(Z >= zlim)) full = true;
-    float Yp;
-    vertex_proj(rg, X, Y, Z, cA[k], cC[k], Yp);
-    if (k == 0) { ymn = ymx = Yp; }
-    else { ymn = Yp < ymn ? Yp : ymn; ymx = Yp > ymx ? Yp : ymx; }
-  }
+  float ymn, ymx;
+  bool full;
+  splat_corners(rg, T, i, j, flags, cA, cC, ymn, ymx, full);
   int32_t by0 = Y0, by1 = Y1;
   if (!full) {
     int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
@@ -693,8 +749,10 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
         const float sv = T.sx * (Z * ur + cu) + 0.5f;
         const float tv = T.sy * (Z * wr + cw) + 0.5f;
         const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
-        if (own)
+        if (own) {
           key_min(&kv[(int64_t)y * row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
+          ++written;
+        }
       }
     }
   }
@@ -717,13 +775,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR &
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const Item it0 = load_uniform(a.items);
+  uint32_t written = 0;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npts; p += stride) {
     const Point pt = a.points[p];
     const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
     const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
     if (!kMulti) {
       const TriRec T = a.rec[tri];
-      splat_point<kPBR>(it0, pt, T, flags, i, j, tx, ty, a, p);
+      splat_point<kPBR>(it0, pt, T, flags, i, j, tx, ty, a, p, written);
       continue;
     }
     // points of one wave nearly always belong to one item: take the items one at
@@ -738,11 +797,226 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR &
       if (mine) {
         const Item it = load_uniform(a.items + cur);
         const TriRec T = a.rec[tri];
-        splat_point<kPBR>(it, pt, T, flags, i, j, tx, ty, a, p);
+        splat_point<kPBR>(it, pt, T, flags, i, j, tx, ty, a, p, written);
       }
       todo &= ~__builtin_amdgcn_ballot_w64(mine);
     }
   }
+  const uint64_t wsum = wave_sum((uint64_t)written);
+  if ((threadIdx.x & 63) == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
+}
+
+// ------------------------------------------------------------------ a3: splat, triangle-major
+//
+// The same splats and keys as k_splat, visited per (triangle, view) instead of
+// per point.  A wave takes 64 (triangle, view) pairs; each lane sets its pair
+// up (visibility, Q8 vertices, edge functions, pixel bounding box) and the
+// wave then walks the concatenated bounding boxes 64 pixels at a time, so that
+// every lane works whatever the boxes' sizes.  A pixel inside the triangle
+// finds its owning cell by the clamped lattice coordinates of its ray hit
+// (row table of the triangle), then applies that point's splat rectangle and
+// colour (Eqs. 8-9) from the point's PointBox, and the 64-bit depth test.
+
+struct alignas(16) PairData {
+  int32_t qx0, qx1, qx2, qy0;    // Q8 vertices, positively oriented
+  int32_t qy1, qy2, xy0, w;      // bounding box origin (x | y << 16) and width
+  float delta, cu, cw, ks;       // plane distance of the eye, lattice offsets, lens shift
+  float fxfy_ad, b, inv_w;       // fx*fy*|delta| (Eq. 8), eye offset, 1/width
+  uint32_t tri;
+  uint64_t* kv;                  // keys of this view
+  int32_t row_stride;            // keys per pixel row
+  float acell;                   // 1/(Sx*Sy), the cell area (Eq. 8)
+  float suv;                     // acell * ruv, the cell's texture area (Eq. 8)
+  int32_t pad0, pad1, pad2;
+};
+static_assert(sizeof(PairData) == 96, "PairData is six 16-byte words");
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool kMulti>
+__global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
+  extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
+  __shared__ PairData pd[4][64];
+  __shared__ uint32_t poff[4][64];
+  const Rig& trg = a.table_rig;
+  float* tx = ray_tab;
+  float* ty = ray_tab + trg.W;
+  for (int k = threadIdx.x; k < trg.W; k += blockDim.x) tx[k] = ((float)k + 0.5f - trg.cx) / trg.fx;
+  for (int k = threadIdx.x; k < trg.H; k += blockDim.x) ty[k] = ((float)k + 0.5f - trg.cy) / trg.fy;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int32_t V = trg.n_views;
+  const int64_t npairs = (int64_t)imin((int64_t)*a.n_tris, a.nt) * V;
+  const Item it0 = load_uniform(a.items);
+  PairData* const mypd = pd[wv];
+  uint32_t* const myoff = poff[wv];
+  uint32_t written = 0;
+  const int64_t chunks = (npairs + 63) >> 6;
+  for (int64_t c = (int64_t)blockIdx.x * 4 + wv; c < chunks; c += (int64_t)gridDim.x * 4) {
+    // ---- phase A: one (triangle, view) pair per lane
+    const int64_t k = c * 64 + lane;
+    uint32_t npx = 0;
+    PairData P;
+    P.tri = 0;
+    if (k < npairs) {
+      const uint32_t ti = (uint32_t)k / (uint32_t)V;
+      const int32_t r = (int32_t)((uint32_t)k - ti * (uint32_t)V);
+      const uint32_t tri = a.tris[ti];
+      const TriRec& T = a.rec[tri];
+      const Item& it = kMulti ? a.items[T.item] : it0;
+      const Rig& rg = it.rig;
+      // every point of the triangle must be in the buffer (else the frame
+      // overflowed and the triangle is left out)
+      const bool fits = a.offsets[tri] + a.counts[tri] <= (uint64_t)a.cap;
+      const float b = fits && r < rg.n_views ? rg.eye[r] : 0.0f;
+      const float delta = T.h - T.nx * b;
+      const int32_t H8 = 256 * rg.H, W8 = 256 * rg.W;
+      bool act = fits && r < rg.n_views && faces_eye(T.p0x, T.p0y * T.p0y, T.p0z * T.p0z, delta, b);
+      int32_t qx[3], qy[3];
+      if (act) act = q8_xy(T.a0, T.c0, T.y0, b, qx[0], qy[0]) && q8_xy(T.a1, T.c1, T.y1, b, qx[1], qy[1]) &&
+                     q8_xy(T.a2, T.c2, T.y2, b, qx[2], qy[2]);
+      if (act && ((qx[0] < 0 && qx[1] < 0 && qx[2] < 0) || (qx[0] > W8 && qx[1] > W8 && qx[2] > W8) ||
+                  (qy[0] < 0 && qy[1] < 0 && qy[2] < 0) || (qy[0] > H8 && qy[1] > H8 && qy[2] > H8)))
+        act = false;
+      if (act) {
+        const int64_t a2 = (int64_t)(qx[1] - qx[0]) * (qy[2] - qy[0]) - (int64_t)(qy[1] - qy[0]) * (qx[2] - qx[0]);
+        if (a2 == 0) act = false;
+        if (a2 < 0) {
+          int32_t u = qx[1]; qx[1] = qx[2]; qx[2] = u;
+          u = qy[1]; qy[1] = qy[2]; qy[2] = u;
+        }
+      }
+      if (act) {
+        const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
+        const int32_t ymin = min(qy[0], min(qy[1], qy[2])), ymax = max(qy[0], max(qy[1], qy[2]));
+        const int32_t X0 = max(0, -((128 - xmin) >> 8)), X1 = min(rg.W - 1, (xmax - 128) >> 8);
+        const int32_t Y0 = max(0, -((128 - ymin) >> 8)), Y1 = min(rg.H - 1, (ymax - 128) >> 8);
+        if (X0 <= X1 && Y0 <= Y1) {
+          const int32_t w = X1 - X0 + 1;
+          npx = (uint32_t)(w * (Y1 - Y0 + 1));
+          P.qx0 = qx[0]; P.qx1 = qx[1]; P.qx2 = qx[2];
+          P.qy0 = qy[0]; P.qy1 = qy[1]; P.qy2 = qy[2];
+          P.xy0 = X0 | (Y0 << 16);
+          P.w = w;
+          P.delta = delta;
+          P.cu = T.ux * (b - T.p0x) - T.cu0;
+          P.cw = T.wx * (b - T.p0x) - T.cw0;
+          P.ks = rg.kshift[r];
+          P.fxfy_ad = rg.fxfy * fabsf(delta);
+          P.b = b;
+          P.inv_w = 1.0f / (float)w;
+          P.tri = tri;
+          const bool rowmajor = it.key_layout != 0;
+          P.kv = it.keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * rg.W * rg.H);
+          P.row_stride = rowmajor ? rg.n_views * rg.W : rg.W;
+          P.acell = 1.0f / (T.sx * T.sy);
+          P.suv = P.acell * T.ruv;
+        }
+      }
+    }
+    // exclusive offsets of the pixel boxes; pair data to LDS
+    uint32_t inc = npx;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    const uint32_t total = __shfl(inc, 63, 64);
+    if (total == 0) continue;
+    myoff[lane] = inc - npx;
+    if (npx) mypd[lane] = P;
+    wave_sync_lds();
+    // ---- phase B: 64 box pixels per round over the concatenated boxes
+    for (uint32_t base = 0; base < total; base += 64) {
+      const uint32_t u = base + lane;
+      if (u < total) {
+        int o = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1)
+          if (myoff[o + st] <= u) o += st;
+        const PairData& Q = mypd[o];
+        const int32_t q = (int32_t)(u - myoff[o]);
+        const int32_t w = Q.w;
+        int32_t yq = (int32_t)((float)q * Q.inv_w);
+        int32_t xq = q - yq * w;
+        if (xq < 0) { yq -= 1; xq += w; }
+        else if (xq >= w) { yq += 1; xq -= w; }
+        const int32_t x = (Q.xy0 & 0xFFFF) + xq, y = (Q.xy0 >> 16) + yq;
+        const int32_t pxq = 256 * x + 128, pyq = 256 * y + 128;
+        const int32_t qx0 = Q.qx0, qx1 = Q.qx1, qx2 = Q.qx2, qy0 = Q.qy0, qy1 = Q.qy1, qy2 = Q.qy2;
+        // edge functions in 64-bit integers; an edge owns its ties iff dy > 0 || (dy == 0 && dx > 0)
+        auto inside = [](int32_t ax, int32_t ay, int32_t bx, int32_t by, int32_t px, int32_t py) {
+          const int32_t dx = bx - ax, dy = by - ay;
+          const int64_t E = (int64_t)dx * (py - ay) - (int64_t)dy * (px - ax);
+          return E > 0 || (E == 0 && (dy > 0 || (dy == 0 && dx > 0)));
+        };
+        if (inside(qx0, qy0, qx1, qy1, pxq, pyq) && inside(qx1, qy1, qx2, qy2, pxq, pyq) &&
+            inside(qx2, qy2, qx0, qy0, pxq, pyq)) {
+          const uint32_t tri = Q.tri;
+          const TriRec& T = a.rec[tri];
+          const float rx = tx[x] - Q.ks, ry = ty[y];
+          const float den = (T.nx * rx + T.ny * ry) + T.nz;
+          const float Z = Q.delta / den;
+          if (Z > 0.0f && !isinf(Z)) {
+            const float ur = (T.ux * rx + T.uy * ry) + T.uz;
+            const float wr = (T.wx * rx + T.wy * ry) + T.wz;
+            const float sv = T.sx * (Z * ur + Q.cu) + 0.5f;
+            const float tv = T.sy * (Z * wr + Q.cw) + 0.5f;
+            // owning cell: clamp to the lattice rows, then to the row's cells
+            const int2 jr = *reinterpret_cast<const int2*>(&a.em[tri].jlo);
+            int32_t cj = (int32_t)floorf(clamp_big(tv));
+            cj = cj < jr.x ? jr.x : (cj > jr.y ? jr.y : cj);
+            const uint64_t first = a.offsets[tri];
+            const RowEntry R = a.rows[first + (uint64_t)(cj - jr.x)];
+            int32_t ci = (int32_t)floorf(clamp_big(sv));
+            ci = ci < R.ilo ? R.ilo : (ci > R.ihi ? R.ihi : ci);
+            const uint64_t pidx = first + R.start + (uint32_t)(ci - R.ilo);
+            const PointBox& B = a.pbox[pidx];
+            const int32_t rows = B.rows;
+            bool keep = true;
+            if (rows != kAllRows) {
+              const int32_t r0 = (int16_t)(rows & 0xFFFF), r1 = (int16_t)((uint32_t)rows >> 16);
+              const float b = Q.b;
+              float xmn = B.cA[0] - b * B.cC[0], xmx = xmn;
+#pragma unroll
+              for (int kk = 1; kk < 4; ++kk) {
+                const float xx = B.cA[kk] - b * B.cC[kk];
+                xmn = xx < xmn ? xx : xmn;
+                xmx = xx > xmx ? xx : xmx;
+              }
+              const int32_t c0 = (int32_t)ceilf(clamp_big(xmn - 0.515625f));
+              const int32_t c1 = (int32_t)floorf(clamp_big(xmx - 0.484375f));
+              keep = y >= r0 && y <= r1 && x >= c0 && x <= c1;
+            }
+            if (keep) {
+              // colour of the point in this view (Eqs. 8-9)
+              const float Ar = B.zc3 / Q.fxfy_ad;
+              const float vse = Q.acell < Ar ? T.ruv * Ar : Q.suv;
+              const float vs = vse < T.smin ? T.smin : (vse > T.smax ? T.smax : vse);
+              const float tau = (vs - T.smin) * T.irange;
+              int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
+              tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
+              const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
+              const uint32_t lo = B.tvmin, hi = B.tvmax;
+              const uint32_t col =
+                  ((((lo & 0x00FF00FFu) * wa + (hi & 0x00FF00FFu) * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
+                  (((((lo >> 8) & 0x00FF00FFu) * wa + ((hi >> 8) & 0x00FF00FFu) * wz + 0x00800080u) >> 8) &
+                   0x00FF00FFu) << 8;
+              key_min(&Q.kv[(int64_t)y * Q.row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
+              ++written;
+            }
+          }
+        }
+      }
+    }
+    wave_sync_lds();  // the pair data is rewritten for the next chunk
+  }
+  const uint64_t wsum = wave_sum((uint64_t)written);
+  if (lane == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
 }
 
 // keys -> RGBA8 (+ depth) in [item][view][y][x] order; keys re-cleared.
@@ -871,6 +1145,13 @@ void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
   size_t lds = sizeof(float) * (size_t)(a.table_rig.W + a.table_rig.H);
+  if (a.pbox && !a.tm) {
+    if (a.n_items > 1)
+      k_splat_tv<true><<<grid_blocks, 256, lds, s>>>(a);
+    else
+      k_splat_tv<false><<<grid_blocks, 256, lds, s>>>(a);
+    return;
+  }
   if (a.n_items > 1 && a.tm)
     k_splat<true, true><<<grid_blocks, 256, lds, s>>>(a);
   else if (a.n_items > 1)

@@ -877,6 +877,18 @@ int lfdpr_net_set_disparity_scale(lfdpr_net* net, float k) {
   return LFDPR_OK;
 }
 
+int lfdpr_net_set_rig(lfdpr_net* net, const lfdpr_view_params* v) {
+  if (!net || !v) return LFDPR_EINVAL;
+  if (v->V != net->V || v->W < 1 || !(v->aspect > 0.0f) || !(v->fovy_deg > 0.0f && v->fovy_deg < 180.0f) ||
+      !(v->cone_deg >= 0.0f && v->cone_deg < 180.0f))
+    return nfail(net, LFDPR_EINVAL, "rig does not match the network or is out of range");
+  // a view step moves the eye by 2 D tan(cone/2) / V, which shifts a surface at
+  // depth Z by fx * 2 D tan(cone/2) / V * (1/Z - 1/D) pixels = k * d, d = D/Z - 1
+  const double fx = (v->W / 2.0) / ((double)v->aspect * std::tan((double)v->fovy_deg * M_PI / 360.0));
+  const double k = fx * 2.0 * std::tan((double)v->cone_deg * M_PI / 360.0) / v->V;
+  return lfdpr_net_set_disparity_scale(net, (float)k);
+}
+
 int lfdpr_net_pack_input(lfdpr_net* net, const uint32_t* views, const float* depth, int32_t n_views, int32_t H,
                          int32_t W, float D, void* x) {
   if (!net || !views || !x || n_views < 1 || H < 1 || W < 1 || !(D > 0.0f)) return LFDPR_EINVAL;

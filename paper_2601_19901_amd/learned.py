@@ -88,7 +88,7 @@ class LearnedReconstruction:
         self.torch = torch
         self.ss = ss
         self.net = lfdpr.Net(ss.rigs[1].renderer, ss.V, max_h, max_w)
-        self.net.set_disparity_scale(lfdpr.disparity_scale(ss.rigs[1].views))
+        self.net.set_rig(ss.rigs[1].views)
         self.fallback_S = fallback_S
         self.healthy = True
         rng = np.random.default_rng(seed)
@@ -112,6 +112,26 @@ class LearnedReconstruction:
         self.net.set_params(flat)
         self.healthy = True
         return True
+
+    def validate(self, frames: Sequence, min_gain_db: float = 1.0) -> dict:
+        """The 4x angular supersampling judges the network (Sec. 4's result is
+        what it stands in for): on the given (scene, frame) pairs the learned
+        views must be closer to the 4x result than the plain 1x render is, by
+        at least min_gain_db of PSNR, or the network is switched off and
+        reconstruct() returns the 4x result."""
+        if not self.healthy:
+            return {"healthy": False, "reason": "parameters refused"}
+        gains = []
+        for (k, f) in frames:
+            s4 = self.ss.render_ss(k, f, self.fallback_S).clone()
+            plain, _ = self.ss.render_plain(k, f)
+            p_plain = psnr_views(plain, s4)
+            p_learned = psnr_views(self.reconstruct(k, f), s4)
+            gains.append(p_learned - p_plain)
+        gain = float(np.mean(gains))
+        self.healthy = bool(np.isfinite(gain) and gain >= min_gain_db)
+        return {"healthy": self.healthy, "gain_db_vs_plain": gain, "min_gain_db": min_gain_db,
+                "frames": len(frames)}
 
     def make_pair(self, k: int, frame: int):
         views, depth = self.ss.render_plain(k, frame)
@@ -194,7 +214,7 @@ class LearnedPipeline:
         self.R = lfdpr.Renderer(0, stream=self.stream)
         self.R.set_lens(lens)
         self.net = lfdpr.Net(self.R, V, H, W)
-        self.net.set_disparity_scale(lfdpr.disparity_scale(self.ss.rigs[1].views))
+        self.net.set_rig(self.ss.rigs[1].views)
         self.views = [torch.empty((V, H, W), dtype=torch.int32, device=dev) for _ in range(2)]
         self.depth = [torch.empty((V, H, W), dtype=torch.float32, device=dev) for _ in range(2)]
         self.x = torch.empty((V, H, W, 4), dtype=torch.int16, device=dev)

@@ -7,7 +7,6 @@ Raises if the library is missing: there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 import re
 from typing import Optional
@@ -19,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "liblfdpr.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "lfdpr.h")
 
 LFDPR_OK, LFDPR_EINVAL, LFDPR_ENOMEM, LFDPR_EOVERFLOW, LFDPR_EDEVICE, LFDPR_ESTATE = 0, -1, -2, -3, -4, -5
+SPLAT_POINT, SPLAT_TRIANGLE_VIEW = 0, 1
 
 
 class LfdprError(RuntimeError):
@@ -60,7 +60,7 @@ class TuneResult(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("points", C.c_int64), ("active_tris", C.c_int64), ("point_views", C.c_int64),
                 ("overflow_tris", C.c_int64), ("capacity", C.c_int64), ("point_overflow", C.c_int32),
-                ("n_views", C.c_int32)]
+                ("n_views", C.c_int32), ("written_px", C.c_int64)]
 
 
 _lib = None
@@ -115,6 +115,7 @@ def signatures():
         "lfdpr_copy_point_materials": ([vp, vp, i64, p(i64)], C.c_int),
         "lfdpr_set_views": ([vp, p(ViewParams)], C.c_int),
         "lfdpr_set_lens": ([vp, p(LensParams)], C.c_int),
+        "lfdpr_set_splat_order": ([vp, i32], C.c_int),
         "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
         "lfdpr_reconstruct": ([vp, vp, i32, i32, i32, vp], C.c_int),
         "lfdpr_angular_filter": ([vp, vp, vp], C.c_int),
@@ -140,6 +141,7 @@ def signatures():
         "lfdpr_net_param_count": ([vp, p(i64)], C.c_int),
         "lfdpr_net_set_params": ([vp, vp, i64], C.c_int),
         "lfdpr_net_set_disparity_scale": ([vp, C.c_float], C.c_int),
+        "lfdpr_net_set_rig": ([vp, p(ViewParams)], C.c_int),
         "lfdpr_net_get_params": ([vp, vp, i64], C.c_int),
         "lfdpr_net_pack_input": ([vp, vp, vp, i32, i32, i32, C.c_float, vp], C.c_int),
         "lfdpr_net_forward": ([vp, vp, i32, i32, i32, vp], C.c_int),
@@ -274,6 +276,10 @@ class Renderer:
         self._check(lib().lfdpr_set_frames_in_flight(self.h, n))
         self.frames_in_flight = int(n)
 
+    def set_splat_order(self, order: int):
+        """SPLAT_POINT (default) or SPLAT_TRIANGLE_VIEW; the same results."""
+        self._check(lib().lfdpr_set_splat_order(self.h, int(order)))
+
     def autotune(self, sid: int, model: np.ndarray, views) -> dict:
         m = np.ascontiguousarray(model, np.float32).reshape(12)
         res = TuneResult()
@@ -405,6 +411,7 @@ class Net:
         self._check(lib().lfdpr_net_param_count(self.h, C.byref(n)))
         self.n_params = n.value
         self.loss_buf = self._torch.zeros(1, dtype=self._torch.float32, device=f"cuda:{renderer.device}")
+        self._last_shape = None  # (n, H, W) of the last forward: the shape backward's target must have
 
     def _check(self, rc: int):
         if rc != LFDPR_OK:
@@ -430,6 +437,12 @@ class Net:
         """Pixels per view step per unit d of the input's disparity blur."""
         self._check(lib().lfdpr_net_set_disparity_scale(self.h, float(k)))
 
+    def set_rig(self, vp):
+        """The disparity scale of the rig (scenes.ViewParams) the views come from,
+        computed by the library."""
+        p, keep = view_params(vp)
+        self._check(lib().lfdpr_net_set_rig(self.h, C.byref(p)))
+
     def get_params(self) -> np.ndarray:
         a = np.zeros(self.n_params, np.float32)
         self._check(lib().lfdpr_net_get_params(self.h, _ptr(a), a.size))
@@ -453,8 +466,14 @@ class Net:
         _check_dev(x, torch.int16, n * H * W * 4, "x")
         _check_dev(y, torch.int16, n * H * W * 4, "y")
         self._check(lib().lfdpr_net_forward(self.h, _ptr(x), n, H, W, _ptr(y)))
+        self._last_shape = (n, H, W)
 
     def backward(self, target):
+        """target: (n, H, W, 4) int16 BF16 bits of the last forward's shape."""
+        if self._last_shape is None:
+            raise ValueError("backward needs a forward first")
+        n, H, W = self._last_shape
+        _check_dev(target, self._torch.int16, n * H * W * 4, "target")
         self._check(lib().lfdpr_net_backward(self.h, _ptr(target), _ptr(self.loss_buf)))
         return self.loss_buf
 
@@ -484,13 +503,6 @@ def params_to_flat(params) -> np.ndarray:
 
 
 NET_SHAPES = [(24, 32), (32, 32), (32, 32), (32, 3)]  # (cin, cout) per layer
-
-
-def disparity_scale(vp) -> float:
-    """k = fx * 2 tan(cone/2) / V for a rig (scenes.ViewParams): the pixels a
-    surface at d = D/Z - 1 = 1 moves across per view step."""
-    fx = (vp.W / 2.0) / (vp.aspect * math.tan(math.radians(vp.fovy_deg) / 2.0))
-    return fx * 2.0 * math.tan(math.radians(vp.cone_deg) / 2.0) / vp.V
 
 
 def flat_to_params(flat: np.ndarray):
@@ -553,8 +565,13 @@ class Batch:
         return self._torch.empty(self.shape, dtype=self._torch.int32, device=f"cuda:{self.R.device}")
 
     def render(self, models, views, panels=None):
+        """panels: None, or (n, Hp, Wp, 3) uint8 for the context's lens."""
         m = np.ascontiguousarray(np.asarray(models, np.float32).reshape(self.n, 12))
         _check_dev(views, self._torch.int32, int(np.prod(self.shape)), "views")
+        if panels is not None:
+            if self.R.lens is None:
+                raise ValueError("panels need a lens (Renderer.set_lens) on the batch's context")
+            _check_dev(panels, self._torch.uint8, self.n * self.R.lens.Hp * self.R.lens.Wp * 3, "panels")
         self._check(lib().lfdpr_batch_render(self.h, _ptr(m), _ptr(views), _ptr(panels) if panels is not None else None))
 
     def stats(self) -> dict:

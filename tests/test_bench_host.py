@@ -23,7 +23,7 @@ def bench():
 
 def shape(**kw):
     s = dict(nt=1000, views=48, points=5000, pixels=48 * 64 * 64, panel_px=320 * 200, tris_with_points=600,
-             fragments=0, out_pixels=0)
+             written_px=0, out_pixels=0)
     s.update(kw)
     return s
 
@@ -36,12 +36,23 @@ def test_alu_peak_is_the_chip_lane_rate(bench):
 
 def test_splat_dominant_roofline(bench):
     st = {"setup": 0.2, "emit": 0.1, "splat": 2.0, "resolve": 0.05}
-    pv = 1.0e8
-    r = bench.roofline(st, pv, shape(), traffic=123.0)
+    pv, wpx = 1.0e8, 3.0e7
+    r = bench.roofline(st, pv, shape(written_px=wpx), traffic=123.0)
     assert r["kernel"] == "k_splat" and r["bound"] == "alu" and r["traffic"] == 123.0
-    want = bench.SPLAT_OPS_PER_POINT_VIEW * pv / 2.0e-3 / 1e12
+    want = (25 * pv + 40 * wpx) / 2.0e-3 / 1e12        # ~25 ops per point-view + ~40 per written pixel
     assert r["achieved"] == pytest.approx(want, abs=1e-3)
     assert r["frac"] == pytest.approx(want / 39.3216, abs=1e-4)
+    census = (100 * pv + 37 * wpx) / 2.0e-3 / 1e12 / 39.3216
+    assert r["frac_census"] == pytest.approx(census, abs=1e-4)
+
+
+def test_splat_fraction_of_the_round_one_display_frame(bench):
+    """The algorithmic count on the display-1M frame of the earlier kernels:
+    146.85M point-views and 48.0M written pixels in a 1667.5 us splat is 5.59 G
+    ops, 0.085 of the 39.32 T lane-op/s peak."""
+    r = bench.roofline({"splat": 1.6675}, 146.85e6, shape(written_px=48.0e6))
+    assert bench.splat_ops(146.85e6, 48.0e6) == pytest.approx(5.59e9, rel=2e-3)
+    assert r["frac"] == pytest.approx(0.085, abs=6e-4)
 
 
 def test_memory_dominant_roofline(bench):
@@ -55,14 +66,14 @@ def test_memory_dominant_roofline(bench):
 
 
 def test_frame_roofline_sums_the_larger_bound_per_stage(bench):
-    s = shape()
+    s = shape(written_px=6.0e6)
     st = {"setup": 0.3, "splat": 1.5, "resolve": 0.05, "interleave": 0.04}
     pv = 2.0e7
     r = bench.frame_roofline(st, pv, s, frame_ms=2.0)
     peak_ops, peak_b = bench.VALU_PEAK_GOPS * 1e9, bench.HBM_PEAK_GBS * 1e9
     want = {
-        "setup": max(bench.BYTES["setup"](s) / peak_b, bench.SETUP_OPS_PER_TRI_VIEW * s["nt"] * s["views"] / peak_ops),
-        "splat": max(bench.BYTES["splat"](s) / peak_b, bench.SPLAT_OPS_PER_POINT_VIEW * pv / peak_ops),
+        "setup": max(bench.BYTES["setup"](s) / peak_b, 40 * s["nt"] * s["views"] / peak_ops),
+        "splat": max(bench.BYTES["splat"](s) / peak_b, (25 * pv + 40 * 6.0e6) / peak_ops),
         "resolve": bench.BYTES["resolve"](s) / peak_b,
         "interleave": bench.BYTES["interleave"](s) / peak_b,
     }
@@ -85,6 +96,12 @@ def test_profile_traffic_requires_matching_sources(bench, tmp_path, monkeypatch)
     assert bench.profile_traffic("missing.md", ("a.hip",), "HBM bytes per launch") is None
     (csrc / "a.hip").write_bytes(b"kernel source v2\n")                                  # sources changed
     assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per launch") is None
+
+
+def test_host_cpu_description(bench):
+    h = bench.host_cpu()
+    assert h["nproc"] >= 1 and h["logical_cpus"] >= h["nproc"] and h["oracle_threads"] == 1
+    assert isinstance(h["cpu_model"], str)
 
 
 def test_more_than_one_gpu_is_refused():

@@ -109,3 +109,49 @@ def test_overlapped_frames_equal_serial_frames(trained):
     for (f, _), a, b in zip(((10, 0), (11, 0), (12, 0)), want, out):
         np.testing.assert_array_equal(b.cpu().numpy(), a, err_msg=f"frame {f} around the fallback")
     pipe.close()
+
+
+def test_validation_against_supersampling_switches_off_a_bad_network(trained):
+    """The 4x result judges the network: a trained network passes; finite but
+    wrong parameters (large random weights) fail the PSNR check, and the
+    reconstruction then returns the 4x result."""
+    learned, ss, model, _, _, _ = trained
+    good = model.net.get_params()
+    ok = model.validate([(3, 17), (3, 512)])
+    assert ok["healthy"] and ok["gain_db_vs_plain"] > 2.0, ok
+    rng = np.random.default_rng(9)
+    bad = (rng.normal(0.0, 0.5, good.size)).astype(np.float32)
+    assert model.set_params(bad)               # finite: accepted
+    res = model.validate([(3, 17), (3, 512)])
+    assert not res["healthy"], res
+    out = model.reconstruct(3, 40).clone()
+    assert learned.psnr_views(out, ss.render_ss(3, 40, 4)) == math.inf
+    assert model.set_params(good) and model.healthy
+    assert model.validate([(3, 17)])["healthy"]
+
+
+def test_disparity_scale_from_the_rig(trained):
+    """lfdpr_net_set_rig gives the network the scale k = fx 2 tan(cone/2) / V
+    of the rig the views come from: forward equals the one with k set
+    explicitly from that formula (double, rounded once)."""
+    _, ss, model, _, _, _ = trained
+    import torch
+    vp = ss.rigs[1].views
+    # the rig crosses the boundary in binary32
+    aspect, fovy, cone = (float(np.float32(v)) for v in (vp.aspect, vp.fovy_deg, vp.cone_deg))
+    fx = (vp.W / 2.0) / (aspect * math.tan(fovy * math.pi / 360.0))
+    k = np.float32(fx * 2.0 * math.tan(cone * math.pi / 360.0) / vp.V)
+    views, depth = ss.render_plain(3, 77)
+    x = torch.empty((vp.V, vp.H, vp.W, 4), dtype=torch.int16, device="cuda")
+    model.net.pack_input(views, depth, x, ss.D)
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    model.net.set_rig(vp)
+    model.net.forward(x, y1)
+    model.net.set_disparity_scale(float(k))
+    model.net.forward(x, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    model.net.set_disparity_scale(float(k) * 1.5)
+    model.net.forward(x, y2)
+    assert not torch.equal(y1, y2)
+    model.net.set_rig(vp)

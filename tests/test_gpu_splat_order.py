@@ -1,0 +1,103 @@
+"""The two splat orders (lfdpr_set_splat_order): per (triangle, view), the
+default for unlit frames, and per point.  They visit the same (point, view,
+pixel) work in different orders, so views, depth and statistics must be
+identical bit for bit; the default order is tied to the oracle by the parity
+tests, and here the point order is tied to it through the default."""
+import numpy as np
+import pytest
+
+from paper_2601_19901_amd import scenes
+from test_gpu_parity import _log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _render(R, sid, model, order):
+    from paper_2601_19901_amd import lfdpr  # noqa: F401
+    R.set_splat_order(order)
+    v, d = R.alloc_views(with_depth=True)
+    R.render_frame(sid, model, v, d)
+    st = R.stats()
+    return v.cpu().numpy(), d.cpu().numpy(), st
+
+
+def _same(R, sid, model, label):
+    from paper_2601_19901_amd import lfdpr
+    vt, dt, st = _render(R, sid, model, lfdpr.SPLAT_TRIANGLE_VIEW)
+    vp, dp, sp = _render(R, sid, model, lfdpr.SPLAT_POINT)
+    _log(f"[{label}] triangle-view {st}; point {sp}")
+    assert st == sp
+    assert st["written_px"] > 0
+    np.testing.assert_array_equal(vt, vp, err_msg=f"{label}: views")
+    np.testing.assert_array_equal(dt.view(np.uint32), dp.view(np.uint32), err_msg=f"{label}: depth")
+
+
+@pytest.mark.parametrize("seed,frame,mip,S", [(7, 0, True, 1), (8, 333, False, 1), (9, 500, True, 4)])
+def test_orders_agree_small_display(torch_cuda, seed, frame, mip, S):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=seed, S=S)
+    w.views.mip = mip
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    _same(R, sid, w.model(frame), f"small-display seed {seed} S={S}")
+    # the other key layout and a small grid (several chunks per wave)
+    R.set_launch(64, 1)
+    _same(R, sid, w.model(frame + 1), f"small-display seed {seed}, 64 blocks, [y][view][x] keys")
+
+
+def test_orders_agree_at_display_size(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.display()
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    for f in (17, 600):
+        _same(R, sid, w.model(f), f"display-1M frame {f}")
+    # two frames in flight, triangle-view order, against the serial point order
+    R.set_splat_order(lfdpr.SPLAT_TRIANGLE_VIEW)
+    R.set_frames_in_flight(2)
+    outs = []
+    for f in (3, 4, 5):
+        v, _ = R.alloc_views()
+        R.render_frame(sid, w.model(f), v)
+        outs.append(v)
+    R.set_frames_in_flight(1)
+    for f, v in zip((3, 4, 5), outs):
+        vp, _, _ = _render(R, sid, w.model(f), lfdpr.SPLAT_POINT)
+        np.testing.assert_array_equal(v.cpu().numpy(), vp, err_msg=f"pipelined frame {f}")
+
+
+def test_orders_agree_in_batches(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    ws = [scenes.small_display(seed=s, V=12, W=96, H=96, hf_quads=hq) for s, hq in ((70, 24), (71, 48), (72, 8))]
+    for k, w in enumerate(ws):
+        w.views.cone_deg = 30.0 + 7.0 * k
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    models = [w.model(50 + 9 * k) for k, w in enumerate(ws)]
+    out = {}
+    for order in (lfdpr.SPLAT_TRIANGLE_VIEW, lfdpr.SPLAT_POINT):
+        R.set_splat_order(order)
+        B = lfdpr.Batch(R, ids, [w.views for w in ws])
+        v = B.alloc_views()
+        panels = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+        B.use_graph(order == lfdpr.SPLAT_TRIANGLE_VIEW)
+        for _ in range(2):
+            B.render(models, v, panels)
+        out[order] = (v.cpu().numpy(), panels.cpu().numpy(), B.stats())
+        B.close()
+    a, b = out[lfdpr.SPLAT_TRIANGLE_VIEW], out[lfdpr.SPLAT_POINT]
+    assert a[2] == b[2] and a[2]["written_px"] > 0
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
