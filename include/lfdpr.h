@@ -202,6 +202,27 @@ int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* lens);
  * 64 B per triangle and 16 B per point of material buffers (synchronous). */
 int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views_rgba, float* depth);
 
+/* lfdpr_render_frame for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with every per-frame buffer
+ * (triangle records, counts, offsets, points and their splat data, 64-bit
+ * keys, statistics) in one 65.5 MiB array of the library's device image that
+ * each GPU holds until the process ends.  This call allocates nothing.
+ *   model, views_rgba, depth  as for lfdpr_render_frame;
+ *   stats  device, 6 int64 (points, active triangles, point-views, overflowed
+ *          triangles, written pixels, point capacity), or NULL.
+ * Limits: unlit shading (LFDPR_ESTATE with LFDPR_SHADE_PBR), one frame in
+ * flight (LFDPR_ESTATE otherwise), at most 65,536 triangles and V*S*H*W at
+ * most 2,097,152 (LFDPR_EINVAL beyond), at most 524,288 points (more leave
+ * the frame incomplete: stats[0] > stats[5]).  Asynchronous.  All calls on one
+ * GPU share the array, so calls that overlap in time on one GPU (other
+ * streams, other contexts) race; calls ordered on one stream do not.
+ * lfdpr_get_stats / lfdpr_copy_points keep describing the last
+ * lfdpr_render_frame.  LFDPR_EDEVICE when the array's address could not be
+ * resolved for the device at lfdpr_create. */
+int lfdpr_render_frame_noalloc(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views_rgba,
+                               float* depth, int64_t* stats);
+
 /* Interleaves n_views views of W x H (device, [view][row][col] RGBA8) into the
  * lenticular panel (device, Hp*Wp*3 bytes) with the lens and reconstruction
  * mode of lfdpr_set_lens (Sec. 4).  Asynchronous. */

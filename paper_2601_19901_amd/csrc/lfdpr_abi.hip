@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <utility>
 #include <string>
 #include <vector>
@@ -35,11 +36,61 @@ void dfree(T*& p) {
   p = nullptr;
 }
 
+// Scratch of lfdpr_render_frame_noalloc: every per-frame buffer of one
+// unlit frame of at most kNoAllocTris triangles, kNoAllocPoints points and
+// kNoAllocKeys keys (views x H x W), at 256-byte aligned offsets.
+constexpr int64_t kNoAllocTris = 65536;
+constexpr int64_t kNoAllocPoints = 1 << 19;
+constexpr int64_t kNoAllocKeys = 1 << 21;
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kOffItem = 0;
+constexpr size_t kOffStats = kOffItem + align256(sizeof(Item));
+constexpr size_t kOffCounts = kOffStats + align256(8 * STAT_SLOTS);
+constexpr size_t kOffOffsets = kOffCounts + align256(4 * kNoAllocTris);
+constexpr size_t kOffTiles = kOffOffsets + align256(8 * kNoAllocTris);
+constexpr size_t kOffRec = kOffTiles + align256(8 * (kNoAllocTris / 1024 + 1));
+constexpr size_t kOffEm = kOffRec + align256(sizeof(TriRec) * kNoAllocTris);
+constexpr size_t kOffBig = kOffEm + align256(sizeof(TriEmit) * kNoAllocTris);
+constexpr size_t kOffTris = kOffBig + align256(4 * kNoAllocTris);
+constexpr size_t kOffPoints = kOffTris + align256(4 * kNoAllocTris);
+constexpr size_t kOffRows = kOffPoints + align256(sizeof(Point) * kNoAllocPoints);
+constexpr size_t kOffPbox = kOffRows + align256(sizeof(RowEntry) * kNoAllocPoints);
+constexpr size_t kOffKeys = kOffPbox + align256(sizeof(PointBox) * kNoAllocPoints);
+constexpr size_t kScratchBytes = kOffKeys + 8 * kNoAllocKeys;  // 65.5 MiB
+static_assert(kScratchBytes <= (66u << 20), "no-allocation scratch stays within 66 MiB");
+
+}  // namespace
+
+// One copy per device, held until the process ends.  Host code never uses this
+// name as an address: the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the current device), resolved once.
+void* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device] && g_scratch_err[device] == hipSuccess) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    else g_scratch_ptr[device] = p;
+  }
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 struct lfdpr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  void* scratch = nullptr;  // device address of this device's no-allocation scratch
   std::string err;
   std::map<int32_t, SceneDev> scenes;
   int32_t next_scene = 1;
@@ -378,6 +429,7 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
   ctx = new lfdpr_ctx();
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
+  ctx->scratch = scratch_on(device);  // null: lfdpr_render_frame_noalloc reports LFDPR_EDEVICE
   if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess || dalloc(ctx->d_item1, 1) != hipSuccess) {
     dfree(ctx->d_stats);
     delete ctx;
@@ -808,6 +860,120 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   stage(ctx, 4, e4, e5);
   ctx->last_nt = s.nt;
   ctx->last_pbr = pbr;
+  return LFDPR_OK;
+}
+
+int lfdpr_render_frame_noalloc(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, float* depth,
+                               int64_t* stats) {
+  if (!ctx || !model || !views) return fail(ctx, LFDPR_EINVAL, "null argument");
+  if (!ctx->views_set) return fail(ctx, LFDPR_ESTATE, "lfdpr_set_views first");
+  if (ctx->frames_in_flight != 1) return fail(ctx, LFDPR_ESTATE, "one frame in flight only");
+  if (ctx->shading.mode == LFDPR_SHADE_PBR)
+    return fail(ctx, LFDPR_ESTATE, "physically based shading needs lfdpr_render_frame");
+  auto it = ctx->scenes.find(scene_id);
+  if (it == ctx->scenes.end()) return fail(ctx, LFDPR_EINVAL, "unknown scene id");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(model[k])) return fail(ctx, LFDPR_EINVAL, "non-finite model matrix");
+  const SceneDev& s = it->second;
+  if (s.nt > kNoAllocTris) return fail(ctx, LFDPR_EINVAL, "scene above the no-allocation limit of 65,536 triangles");
+  const int64_t nkeys = (int64_t)ctx->rig.n_views * ctx->rig.W * ctx->rig.H;
+  if (nkeys > kNoAllocKeys)
+    return fail(ctx, LFDPR_EINVAL, "views x H x W above the no-allocation limit of 2,097,152 keys");
+  if (!ctx->scratch) return fail(ctx, LFDPR_EDEVICE, "no-allocation scratch unavailable on this device");
+  HIPOK(hipSetDevice(ctx->device));
+  unsigned char* base = (unsigned char*)ctx->scratch;
+  Item* d_item = (Item*)(base + kOffItem);
+  uint64_t* d_st = (uint64_t*)(base + kOffStats);
+  uint32_t* d_counts = (uint32_t*)(base + kOffCounts);
+  uint64_t* d_offsets = (uint64_t*)(base + kOffOffsets);
+  uint64_t* d_tiles = (uint64_t*)(base + kOffTiles);
+  TriRec* d_rec = (TriRec*)(base + kOffRec);
+  TriEmit* d_em = (TriEmit*)(base + kOffEm);
+  uint32_t* d_big = (uint32_t*)(base + kOffBig);
+  uint32_t* d_tris = (uint32_t*)(base + kOffTris);
+  Point* d_points = (Point*)(base + kOffPoints);
+  RowEntry* d_rows = (RowEntry*)(base + kOffRows);
+  PointBox* d_pbox = (PointBox*)(base + kOffPbox);
+  uint64_t* d_keys = (uint64_t*)(base + kOffKeys);
+  hipStream_t st = ctx->stream;
+  Item one;
+  std::memset(&one, 0, sizeof one);
+  one.pos = s.pos;
+  one.uv = s.uv;
+  one.idx = s.idx;
+  one.tex = s.tex;
+  one.texinfo = s.texinfo;
+  one.texels = s.texels;
+  one.tri_base = 0;
+  one.nt = s.nt;
+  one.rig = ctx->rig;
+  one.keys = d_keys;
+  one.key_layout = ctx->key_layout;
+  one.mat = nullptr;
+  // the scratch keeps the last call's contents: statistics start at 0, keys at ~0
+  launch_store_item(one, d_item, st);
+  launch_fill_u64(d_st, STAT_SLOTS, 0ull, st);
+  launch_fill_u64(d_keys, nkeys, ~0ull, st);
+  SetupArgs sa{};
+  sa.items = d_item;
+  sa.n_items = 1;
+  sa.nt = s.nt;
+  std::memcpy(sa.model.m, model, sizeof sa.model.m);
+  sa.models = nullptr;
+  sa.lod_thr = ctx->d_lod_thr;
+  sa.counts = d_counts;
+  sa.rec = d_rec;
+  sa.em = d_em;
+  sa.dbgf = nullptr;
+  sa.dbgi = nullptr;
+  sa.stats = d_st;
+  sa.tm = nullptr;
+  launch_tri_setup(sa, st);
+  launch_scan(d_counts, s.nt, d_tiles, d_offsets, d_st + STAT_TOTAL, st);
+  EmitArgs ea{};
+  ea.items = d_item;
+  ea.nt = s.nt;
+  ea.counts = d_counts;
+  ea.offsets = d_offsets;
+  ea.em = d_em;
+  ea.points = d_points;
+  ea.n_points = d_st + STAT_TOTAL;
+  ea.big = d_big;
+  ea.n_big = d_st + STAT_BIG;
+  ea.cap = kNoAllocPoints;
+  ea.tm = nullptr;
+  ea.pmat = nullptr;
+  const bool tv = ctx->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW;
+  ea.rec = d_rec;
+  ea.rows = tv ? d_rows : nullptr;
+  ea.pbox = tv ? d_pbox : nullptr;
+  ea.tris = tv ? d_tris : nullptr;
+  ea.n_tris = d_st + STAT_EMITTING;
+  launch_emit(ea, ctx->splat_blocks, st);
+  SplatArgs pa{};
+  pa.items = d_item;
+  pa.n_items = 1;
+  pa.table_rig = ctx->rig;
+  pa.points = d_points;
+  pa.n_points = d_st + STAT_TOTAL;
+  pa.cap = kNoAllocPoints;
+  pa.rec = d_rec;
+  pa.tm = nullptr;
+  pa.pmat = nullptr;
+  pa.sh = Shading{};
+  pa.stats = d_st;
+  pa.em = d_em;
+  pa.offsets = d_offsets;
+  pa.counts = d_counts;
+  pa.rows = d_rows;
+  pa.pbox = tv ? d_pbox : nullptr;
+  pa.tris = d_tris;
+  pa.n_tris = d_st + STAT_EMITTING;
+  pa.nt = s.nt;
+  launch_splat(pa, ctx->splat_blocks, st);
+  launch_resolve(d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st);
+  if (stats) launch_export_stats(d_st, kNoAllocPoints, stats, st);
+  HIPOK(hipGetLastError());
   return LFDPR_OK;
 }
 

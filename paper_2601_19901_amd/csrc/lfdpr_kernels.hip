@@ -28,6 +28,24 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
   for (; i < n; i += stride) p[i] = v;
 }
 
+// The single-frame item table, written from a kernel argument (no host staging).
+__global__ void k_store_item(Item it, Item* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = it;
+}
+
+// Frame statistics for the caller: points, active triangles, point-views,
+// overflowed triangles, written pixels, point capacity.
+__global__ void k_export_stats(const uint64_t* __restrict__ st, int64_t cap, int64_t* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = (int64_t)st[STAT_TOTAL];
+    out[1] = (int64_t)st[STAT_ACTIVE];
+    out[2] = (int64_t)st[STAT_POINT_VIEWS];
+    out[3] = (int64_t)st[STAT_OVERFLOW];
+    out[4] = (int64_t)st[STAT_WRITTEN];
+    out[5] = cap;
+  }
+}
+
 __global__ void k_build_mip(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int s) {
   int h = s >> 1;
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1105,6 +1123,12 @@ void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
   if (n <= 0) return;
   unsigned g = (unsigned)imin(nblk(n, 256), 256 * 64);
   k_fill_u64<<<g, 256, 0, s>>>(p, n, v);
+}
+
+void launch_store_item(const Item& it, Item* dst, hipStream_t s) { k_store_item<<<1, 64, 0, s>>>(it, dst); }
+
+void launch_export_stats(const uint64_t* st, int64_t cap, int64_t* out, hipStream_t s) {
+  k_export_stats<<<1, 64, 0, s>>>(st, cap, out);
 }
 
 void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st) {

@@ -117,6 +117,7 @@ def signatures():
         "lfdpr_set_lens": ([vp, p(LensParams)], C.c_int),
         "lfdpr_set_splat_order": ([vp, i32], C.c_int),
         "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
+        "lfdpr_render_frame_noalloc": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "lfdpr_reconstruct": ([vp, vp, i32, i32, i32, vp], C.c_int),
         "lfdpr_angular_filter": ([vp, vp, vp], C.c_int),
         "lfdpr_get_stats": ([vp, p(Stats)], C.c_int),
@@ -320,6 +321,24 @@ class Renderer:
                 _check_dev(depth, torch.float32, n, "depth")
         m = np.ascontiguousarray(model, np.float32).reshape(12)
         self._check(lib().lfdpr_render_frame(self.h, sid, _ptr(m), _ptr(views), _ptr(depth) if depth is not None else None))
+
+    def render_frame_noalloc(self, sid: int, model: np.ndarray, views, depth=None, stats=None):
+        """lfdpr_render_frame_noalloc: the frame with the library's static
+        scratch (no device allocation); stats: None or a device int64 tensor
+        of >= 6 elements (points, active triangles, point-views, overflowed
+        triangles, written pixels, point capacity)."""
+        torch = self._torch
+        if self.vp is not None:
+            n = self.n_views * self.vp.H * self.vp.W
+            _check_dev(views, torch.int32, n, "views")
+            if depth is not None:
+                _check_dev(depth, torch.float32, n, "depth")
+        if stats is not None:
+            _check_dev(stats, torch.int64, 6, "stats")
+        m = np.ascontiguousarray(model, np.float32).reshape(12)
+        self._check(lib().lfdpr_render_frame_noalloc(self.h, sid, _ptr(m), _ptr(views),
+                                                     _ptr(depth) if depth is not None else None,
+                                                     _ptr(stats) if stats is not None else None))
 
     def reconstruct(self, views, panel, n_views: Optional[int] = None, W: Optional[int] = None,
                     H: Optional[int] = None):
