@@ -203,6 +203,7 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     R.set_lens(lens)
     R.set_shading(w.shading)
     R.set_frames_in_flight(args.frames_in_flight)
+    R.set_splat_order(lfdpr.SPLAT_TRIANGLE_VIEW if args.splat_order == "triangle-view" else lfdpr.SPLAT_POINT)
     views, _ = R.alloc_views()
     filtered = (torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0")
                 if kind == "display-4M-ss4" else None)
@@ -296,6 +297,7 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         "frame_ms_p99": round(float(np.percentile(intervals, 99)), 4),
         "frames_per_s": round(1e3 / wall_ms, 2),
         "frames_in_flight": args.frames_in_flight,
+        "splat_order": args.splat_order,
         "frame_ms_one_in_flight": round(serial_ms if serial_ms is not None else wall_ms, 4),
         "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
         "written_px_per_frame": int(wpx / nfr), "active_tris_per_frame": int(act / nfr),
@@ -558,6 +560,8 @@ def main():
     ap.add_argument("--frames-in-flight", type=int, choices=(1, 2), default=2,
                     help="frames whose point generation overlaps the previous frame (display, learned and batch workloads)")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--splat-order", choices=("point", "triangle-view"), default="point",
+                    help="how the splat visits its work (the same results)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
