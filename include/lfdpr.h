@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LFDPR_ABI_VERSION 3
+#define LFDPR_ABI_VERSION 4
 
 enum {
   LFDPR_OK = 0,
@@ -110,6 +110,8 @@ typedef struct {
   int32_t n_views;         /* rendered (sub-)views */
   int64_t written_px;      /* (point, view, pixel) depth-test updates the splat issued: every
                               covered pixel of a visible triangle, owned by one point (Sec. 3.2) */
+  int32_t splat_order;     /* LFDPR_SPLAT_* the last frame's splat used */
+  int32_t reserved;
 } lfdpr_stats;
 
 /* Version of this ABI (LFDPR_ABI_VERSION). */

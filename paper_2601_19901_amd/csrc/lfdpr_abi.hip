@@ -177,6 +177,7 @@ struct lfdpr_ctx {
   int splat_blocks = 4096;
   int key_layout = 0;
   int splat_order = LFDPR_SPLAT_POINT;
+  int last_order = LFDPR_SPLAT_POINT;  // the order the last frame's splat used
   // stage timing: event pairs recorded on the stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -253,7 +254,7 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt);
 int prepare_frame_buffers(lfdpr_ctx* ctx, int64_t nt, bool pbr) {
   int rc = ensure_tri_buffers(ctx, nt);
   if (rc) return rc;
-  if (!ctx->d_points || ctx->points_alloc != ctx->cap) {
+  if (!ctx->d_points || !ctx->d_rows || !ctx->d_pbox || ctx->points_alloc != ctx->cap) {
     if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
     dfree(ctx->d_points);
     dfree(ctx->d_rows);
@@ -663,13 +664,20 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
       dalloc(ctx->d_awt, (size_t)v->V * maxe) != hipSuccess)
     return fail(ctx, LFDPR_ENOMEM, "rig tables");
   if (cap != ctx->cap || !ctx->d_points) {
+    // the point buffer with the splat data sized like it (row table, point rectangles)
     dfree(ctx->d_points);
+    dfree(ctx->d_rows);
+    dfree(ctx->d_pbox);
     ctx->cap = ctx->points_alloc = 0;
-    if (dalloc(ctx->d_points, (size_t)cap) != hipSuccess) return fail(ctx, LFDPR_ENOMEM, "point buffer");
+    if (dalloc(ctx->d_points, (size_t)cap) != hipSuccess || dalloc(ctx->d_rows, (size_t)cap) != hipSuccess ||
+        dalloc(ctx->d_pbox, (size_t)cap) != hipSuccess)
+      return fail(ctx, LFDPR_ENOMEM, "point buffers");
     ctx->cap = ctx->points_alloc = cap;
   }
   if (ctx->other.points_alloc != cap) {  // the second set (two frames in flight) follows on first use
     dfree(ctx->other.d_points);
+    dfree(ctx->other.d_rows);
+    dfree(ctx->other.d_pbox);
     ctx->other.points_alloc = 0;
   }
   if (nkeys != ctx->n_keys || !ctx->d_keys) {
@@ -845,6 +853,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
                   sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
   launch_splat(pa, ctx->splat_blocks, st);
+  ctx->last_order = pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT;
   if (piped) {
     HIPOK(hipEventRecord(ctx->ev_splatted[sl], st));
     ctx->splatted_pending[sl] = true;
@@ -1026,6 +1035,7 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   out->point_views = (int64_t)st[STAT_POINT_VIEWS];
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
   out->written_px = (int64_t)st[STAT_WRITTEN];
+  out->splat_order = ctx->last_order;
   out->capacity = ctx->cap;
   out->point_overflow = out->points > ctx->cap ? 1 : 0;
   out->n_views = ctx->rig.n_views;
@@ -1124,6 +1134,7 @@ struct lfdpr_batch {
   PointBox* pbox = nullptr;
   int64_t cap = 0;
   int splat_order = LFDPR_SPLAT_POINT;
+  int last_order = LFDPR_SPLAT_POINT;
   TriMat* tm = nullptr;  // physically based shading: material records and
   uint4* pmat = nullptr; // per-point material words (allocated on first use)
   Rig table_rig{};
@@ -1342,6 +1353,7 @@ void batch_splat(lfdpr_batch* b, uint32_t* views, uint8_t* panels, hipStream_t s
   pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
                   sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
   launch_splat(pa, b->splat_blocks, st);
+  b->last_order = pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT;
   hipEvent_t e4 = ev();
   launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st);
   hipEvent_t e5 = ev();
@@ -1643,6 +1655,7 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
   out->point_views = (int64_t)st[STAT_POINT_VIEWS];
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
   out->written_px = (int64_t)st[STAT_WRITTEN];
+  out->splat_order = b->last_order;
   out->capacity = b->cap;
   out->point_overflow = out->points > b->cap ? 1 : 0;
   out->n_views = b->table_rig.n_views;

@@ -12,9 +12,10 @@
 //                 inside-triangle test, cell ownership, Eqs. 8-9, 64-bit
 //                 atomicMin of (depth, colour)                (Sec. 3.2, 3.3, 5.1)
 //   k_resolve     keys -> RGBA8 (+ depth), keys re-cleared for the next frame
-//   k_interleave  one lane per panel pixel: tilted-lens phase, view and pixel
-//                 index, optional 8-tap Gaussian reconstruction (Sec. 4)
-//   k_angular_filter  sub-views -> views (angular supersampling, Sec. 4)
+//   k_interleave  one lane per four panel pixels: tilted-lens phase, view and
+//                 pixel index, optional 8-tap Gaussian reconstruction (Sec. 4)
+//   k_angular_filter  sub-views -> views (angular supersampling, Sec. 4), one
+//                 lane per four pixels
 #include "lfdpr_device.h"
 #include "lfdpr_internal.h"
 
@@ -835,19 +836,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR &
 // (row table of the triangle), then applies that point's splat rectangle and
 // colour (Eqs. 8-9) from the point's PointBox, and the 64-bit depth test.
 
+// Everything the pixel pass needs of one (triangle, view) pair, in LDS.
 struct alignas(16) PairData {
   int32_t qx0, qx1, qx2, qy0;    // Q8 vertices, positively oriented
   int32_t qy1, qy2, xy0, w;      // bounding box origin (x | y << 16) and width
   float delta, cu, cw, ks;       // plane distance of the eye, lattice offsets, lens shift
-  float fxfy_ad, b, inv_w;       // fx*fy*|delta| (Eq. 8), eye offset, 1/width
-  uint32_t tri;
+  float fxfy_ad, b, inv_w, acell;  // fx*fy*|delta| (Eq. 8), eye offset, 1/width, 1/(Sx*Sy)
   uint64_t* kv;                  // keys of this view
   int32_t row_stride;            // keys per pixel row
-  float acell;                   // 1/(Sx*Sy), the cell area (Eq. 8)
-  float suv;                     // acell * ruv, the cell's texture area (Eq. 8)
-  int32_t pad0, pad1, pad2;
+  float suv;                     // acell * ruv (Eq. 8)
+  float nx, ny, nz, ux;          // the triangle's plane and lattice axes
+  float uy, uz, wx, wy;
+  float wz, sx, sy, ruv;
+  float smin, smax, irange;      // Eqs. 4-5, 9
+  int32_t jlo;                   // first lattice row
+  uint64_t first;                // the triangle's first point
+  int32_t jhi, pad;
 };
-static_assert(sizeof(PairData) == 96, "PairData is six 16-byte words");
+static_assert(sizeof(PairData) == 160, "PairData is ten 16-byte words");
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -855,11 +861,62 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One covered pixel of pair Q: ray hit, owning cell, its splat rectangle and
+// colour (Eqs. 8-9), the 64-bit depth test.  Returns 1 when a key was written.
+__device__ __forceinline__ uint32_t splat_fragment(const PairData& Q, int32_t x, int32_t y, const float* tx,
+                                                   const float* ty, const RowEntry* __restrict__ rows,
+                                                   const PointBox* __restrict__ pbox) {
+  const float rx = tx[x] - Q.ks, ry = ty[y];
+  const float den = (Q.nx * rx + Q.ny * ry) + Q.nz;
+  const float Z = Q.delta / den;
+  if (!(Z > 0.0f) || isinf(Z)) return 0;
+  const float ur = (Q.ux * rx + Q.uy * ry) + Q.uz;
+  const float wr = (Q.wx * rx + Q.wy * ry) + Q.wz;
+  const float sv = Q.sx * (Z * ur + Q.cu) + 0.5f;
+  const float tv = Q.sy * (Z * wr + Q.cw) + 0.5f;
+  // owning cell: clamp to the lattice rows, then to the row's cells
+  int32_t cj = (int32_t)floorf(clamp_big(tv));
+  cj = cj < Q.jlo ? Q.jlo : (cj > Q.jhi ? Q.jhi : cj);
+  const RowEntry R = rows[Q.first + (uint64_t)(cj - Q.jlo)];
+  int32_t ci = (int32_t)floorf(clamp_big(sv));
+  ci = ci < R.ilo ? R.ilo : (ci > R.ihi ? R.ihi : ci);
+  const PointBox& B = pbox[Q.first + R.start + (uint32_t)(ci - R.ilo)];
+  const int32_t rws = B.rows;
+  if (rws != kAllRows) {
+    const int32_t r0 = (int16_t)(rws & 0xFFFF), r1 = (int16_t)((uint32_t)rws >> 16);
+    if (y < r0 || y > r1) return 0;
+    const float b = Q.b;
+    float xmn = B.cA[0] - b * B.cC[0], xmx = xmn;
+#pragma unroll
+    for (int kk = 1; kk < 4; ++kk) {
+      const float xx = B.cA[kk] - b * B.cC[kk];
+      xmn = xx < xmn ? xx : xmn;
+      xmx = xx > xmx ? xx : xmx;
+    }
+    if (x < (int32_t)ceilf(clamp_big(xmn - 0.515625f)) || x > (int32_t)floorf(clamp_big(xmx - 0.484375f))) return 0;
+  }
+  // colour of the point in this view (Eqs. 8-9)
+  const float Ar = B.zc3 / Q.fxfy_ad;
+  const float vse = Q.acell < Ar ? Q.ruv * Ar : Q.suv;
+  const float vs = vse < Q.smin ? Q.smin : (vse > Q.smax ? Q.smax : vse);
+  const float tau = (vs - Q.smin) * Q.irange;
+  int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
+  tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
+  const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
+  const uint32_t lo = B.tvmin, hi = B.tvmax;
+  const uint32_t col =
+      ((((lo & 0x00FF00FFu) * wa + (hi & 0x00FF00FFu) * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
+      (((((lo >> 8) & 0x00FF00FFu) * wa + ((hi >> 8) & 0x00FF00FFu) * wz + 0x00800080u) >> 8) & 0x00FF00FFu) << 8;
+  key_min(&Q.kv[(int64_t)y * Q.row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
+  return 1;
+}
+
 template <bool kMulti>
 __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
   __shared__ PairData pd[4][64];
   __shared__ uint32_t poff[4][64];
+  __shared__ uint32_t fq[4][128];     // covered pixels waiting: pair | x << 6 | y << 19
   const Rig& trg = a.table_rig;
   float* tx = ray_tab;
   float* ty = ray_tab + trg.W;
@@ -867,11 +924,13 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
   for (int k = threadIdx.x; k < trg.H; k += blockDim.x) ty[k] = ((float)k + 0.5f - trg.cy) / trg.fy;
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int32_t V = trg.n_views;
   const int64_t npairs = (int64_t)imin((int64_t)*a.n_tris, a.nt) * V;
   const Item it0 = load_uniform(a.items);
   PairData* const mypd = pd[wv];
   uint32_t* const myoff = poff[wv];
+  uint32_t* const myq = fq[wv];
   uint32_t written = 0;
   const int64_t chunks = (npairs + 63) >> 6;
   for (int64_t c = (int64_t)blockIdx.x * 4 + wv; c < chunks; c += (int64_t)gridDim.x * 4) {
@@ -879,7 +938,6 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
     const int64_t k = c * 64 + lane;
     uint32_t npx = 0;
     PairData P;
-    P.tri = 0;
     if (k < npairs) {
       const uint32_t ti = (uint32_t)k / (uint32_t)V;
       const int32_t r = (int32_t)((uint32_t)k - ti * (uint32_t)V);
@@ -889,7 +947,8 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
       const Rig& rg = it.rig;
       // every point of the triangle must be in the buffer (else the frame
       // overflowed and the triangle is left out)
-      const bool fits = a.offsets[tri] + a.counts[tri] <= (uint64_t)a.cap;
+      const uint64_t first = a.offsets[tri];
+      const bool fits = first + a.counts[tri] <= (uint64_t)a.cap;
       const float b = fits && r < rg.n_views ? rg.eye[r] : 0.0f;
       const float delta = T.h - T.nx * b;
       const int32_t H8 = 256 * rg.H, W8 = 256 * rg.W;
@@ -927,12 +986,21 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
           P.fxfy_ad = rg.fxfy * fabsf(delta);
           P.b = b;
           P.inv_w = 1.0f / (float)w;
-          P.tri = tri;
           const bool rowmajor = it.key_layout != 0;
           P.kv = it.keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * rg.W * rg.H);
           P.row_stride = rowmajor ? rg.n_views * rg.W : rg.W;
           P.acell = 1.0f / (T.sx * T.sy);
           P.suv = P.acell * T.ruv;
+          P.nx = T.nx; P.ny = T.ny; P.nz = T.nz;
+          P.ux = T.ux; P.uy = T.uy; P.uz = T.uz;
+          P.wx = T.wx; P.wy = T.wy; P.wz = T.wz;
+          P.sx = T.sx; P.sy = T.sy; P.ruv = T.ruv;
+          P.smin = T.smin; P.smax = T.smax; P.irange = T.irange;
+          const int2 jr = *reinterpret_cast<const int2*>(&a.em[tri].jlo);
+          P.jlo = jr.x;
+          P.jhi = jr.y;
+          P.first = first;
+          P.pad = 0;
         }
       }
     }
@@ -948,9 +1016,13 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
     myoff[lane] = inc - npx;
     if (npx) mypd[lane] = P;
     wave_sync_lds();
-    // ---- phase B: 64 box pixels per round over the concatenated boxes
+    // ---- phase B: 64 box pixels per round over the concatenated boxes; the
+    // covered ones queue up and are splatted 64 at a time
+    uint32_t qn = 0;
     for (uint32_t base = 0; base < total; base += 64) {
       const uint32_t u = base + lane;
+      bool cov = false;
+      uint32_t entry = 0;
       if (u < total) {
         int o = 0;
 #pragma unroll
@@ -972,66 +1044,34 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
           const int64_t E = (int64_t)dx * (py - ay) - (int64_t)dy * (px - ax);
           return E > 0 || (E == 0 && (dy > 0 || (dy == 0 && dx > 0)));
         };
-        if (inside(qx0, qy0, qx1, qy1, pxq, pyq) && inside(qx1, qy1, qx2, qy2, pxq, pyq) &&
-            inside(qx2, qy2, qx0, qy0, pxq, pyq)) {
-          const uint32_t tri = Q.tri;
-          const TriRec& T = a.rec[tri];
-          const float rx = tx[x] - Q.ks, ry = ty[y];
-          const float den = (T.nx * rx + T.ny * ry) + T.nz;
-          const float Z = Q.delta / den;
-          if (Z > 0.0f && !isinf(Z)) {
-            const float ur = (T.ux * rx + T.uy * ry) + T.uz;
-            const float wr = (T.wx * rx + T.wy * ry) + T.wz;
-            const float sv = T.sx * (Z * ur + Q.cu) + 0.5f;
-            const float tv = T.sy * (Z * wr + Q.cw) + 0.5f;
-            // owning cell: clamp to the lattice rows, then to the row's cells
-            const int2 jr = *reinterpret_cast<const int2*>(&a.em[tri].jlo);
-            int32_t cj = (int32_t)floorf(clamp_big(tv));
-            cj = cj < jr.x ? jr.x : (cj > jr.y ? jr.y : cj);
-            const uint64_t first = a.offsets[tri];
-            const RowEntry R = a.rows[first + (uint64_t)(cj - jr.x)];
-            int32_t ci = (int32_t)floorf(clamp_big(sv));
-            ci = ci < R.ilo ? R.ilo : (ci > R.ihi ? R.ihi : ci);
-            const uint64_t pidx = first + R.start + (uint32_t)(ci - R.ilo);
-            const PointBox& B = a.pbox[pidx];
-            const int32_t rows = B.rows;
-            bool keep = true;
-            if (rows != kAllRows) {
-              const int32_t r0 = (int16_t)(rows & 0xFFFF), r1 = (int16_t)((uint32_t)rows >> 16);
-              const float b = Q.b;
-              float xmn = B.cA[0] - b * B.cC[0], xmx = xmn;
-#pragma unroll
-              for (int kk = 1; kk < 4; ++kk) {
-                const float xx = B.cA[kk] - b * B.cC[kk];
-                xmn = xx < xmn ? xx : xmn;
-                xmx = xx > xmx ? xx : xmx;
-              }
-              const int32_t c0 = (int32_t)ceilf(clamp_big(xmn - 0.515625f));
-              const int32_t c1 = (int32_t)floorf(clamp_big(xmx - 0.484375f));
-              keep = y >= r0 && y <= r1 && x >= c0 && x <= c1;
-            }
-            if (keep) {
-              // colour of the point in this view (Eqs. 8-9)
-              const float Ar = B.zc3 / Q.fxfy_ad;
-              const float vse = Q.acell < Ar ? T.ruv * Ar : Q.suv;
-              const float vs = vse < T.smin ? T.smin : (vse > T.smax ? T.smax : vse);
-              const float tau = (vs - T.smin) * T.irange;
-              int32_t tq = (int32_t)floorf(tau * 256.0f + 0.5f);
-              tq = tq < 0 ? 0 : (tq > 256 ? 256 : tq);
-              const uint32_t wa = (uint32_t)(256 - tq), wz = (uint32_t)tq;
-              const uint32_t lo = B.tvmin, hi = B.tvmax;
-              const uint32_t col =
-                  ((((lo & 0x00FF00FFu) * wa + (hi & 0x00FF00FFu) * wz + 0x00800080u) >> 8) & 0x00FF00FFu) |
-                  (((((lo >> 8) & 0x00FF00FFu) * wa + ((hi >> 8) & 0x00FF00FFu) * wz + 0x00800080u) >> 8) &
-                   0x00FF00FFu) << 8;
-              key_min(&Q.kv[(int64_t)y * Q.row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
-              ++written;
-            }
-          }
-        }
+        cov = inside(qx0, qy0, qx1, qy1, pxq, pyq) && inside(qx1, qy1, qx2, qy2, pxq, pyq) &&
+              inside(qx2, qy2, qx0, qy0, pxq, pyq);
+        entry = (uint32_t)o | ((uint32_t)x << 6) | ((uint32_t)y << 19);
+      }
+      const uint64_t m = __builtin_amdgcn_ballot_w64(cov);
+      if (cov) myq[qn + (uint32_t)__builtin_popcountll(m & below)] = entry;
+      qn += (uint32_t)__builtin_popcountll(m);
+      if (qn >= 64) {
+        wave_sync_lds();
+        const uint32_t e = myq[lane];
+        written += splat_fragment(mypd[e & 63], (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx, ty, a.rows,
+                                  a.pbox);
+        const uint32_t rest = qn - 64;
+        const uint32_t moved = lane < rest ? myq[64 + lane] : 0u;
+        wave_sync_lds();
+        if (lane < rest) myq[lane] = moved;
+        qn = rest;
       }
     }
-    wave_sync_lds();  // the pair data is rewritten for the next chunk
+    if (qn) {
+      wave_sync_lds();
+      if ((uint32_t)lane < qn) {
+        const uint32_t e = myq[lane];
+        written += splat_fragment(mypd[e & 63], (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx, ty, a.rows,
+                                  a.pbox);
+      }
+    }
+    wave_sync_lds();  // the pair data and the queue are rewritten for the next chunk
   }
   const uint64_t wsum = wave_sum((uint64_t)written);
   if (lane == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
@@ -1061,58 +1101,125 @@ __global__ void k_resolve(uint64_t* __restrict__ keys, int64_t n, int32_t nv, in
 
 // ------------------------------------------------------------------ a4: interleave + reconstruction
 
-__global__ void __launch_bounds__(256) k_interleave(InterleaveArgs a) {
-  int64_t X = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t Y = blockIdx.y;
-  if (X >= a.Wp) return;
-  int64_t xq = ((2 * X + 1) * (int64_t)a.Wv * 128) / a.Wp;
-  int64_t yq = ((2 * Y + 1) * (int64_t)a.Hv * 128) / a.Hp;
-  uint8_t out[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    uint32_t phi = (uint32_t)(3 * X + c) * a.K1 + (uint32_t)Y * a.Ky + a.K0;
-    uint64_t U = (uint64_t)phi * (uint64_t)a.V;
-    uint32_t val;
-    if (a.mode == 0) {
-      int64_t v = (int64_t)(U >> 32);
-      val = (a.views[(v * a.Hv + (yq >> 8)) * a.Wv + (xq >> 8)] >> (8 * c)) & 255u;
-    } else {
-      uint32_t sum = 0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        int64_t v = ((int64_t)U + a.du[k]) >> 32;
-        int64_t x = (xq + a.dx[k]) >> 8, y = (yq + a.dy[k]) >> 8;
-        v = v < 0 ? 0 : (v > a.V - 1 ? a.V - 1 : v);
-        x = x < 0 ? 0 : (x > a.Wv - 1 ? a.Wv - 1 : x);
-        y = y < 0 ? 0 : (y > a.Hv - 1 ? a.Hv - 1 : y);
-        sum += (a.views[(v * a.Hv + y) * a.Wv + x] >> (8 * c)) & 255u;
-      }
-      val = (sum + 4u) >> 3;
-    }
-    out[c] = (uint8_t)val;
-  }
-  uint8_t* dst = a.panel + (Y * a.Wp + X) * 3;
-  dst[0] = out[0]; dst[1] = out[1]; dst[2] = out[2];
+// Logical block of a 1-D launch of nb blocks such that the blocks the
+// hardware places on one XCD (round robin over 8) take one contiguous eighth
+// of the logical order: neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb / 8, extra = nb % 8, xcd = b % 8, k = b / 8;
+  // XCD x takes per (+1 for the first `extra`) consecutive logical blocks
+  return xcd * per + (xcd < extra ? xcd : extra) + k;
 }
 
-__global__ void __launch_bounds__(256) k_angular_filter(AngularArgs a) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int v = blockIdx.y;
-  int64_t npx = (int64_t)a.W * a.H;
-  if (p >= npx) return;
-  int n = a.cnt[v];
-  uint64_t acc[4] = {0, 0, 0, 0}, ws = 0;
-  for (int e = 0; e < n; ++e) {
-    uint64_t w = a.wt[v * a.maxe + e];
-    uint32_t c = a.sub[(int64_t)a.src[v * a.maxe + e] * npx + p];
-    ws += w;
+// One lane per four consecutive panel pixels (12 bytes, written as three
+// 32-bit words when they are aligned and whole).  Panel rows are spread over
+// the XCDs in contiguous bands so that each view row is fetched into one L2.
+__global__ void __launch_bounds__(256) k_interleave(InterleaveArgs a, uint32_t blocks_per_row, uint32_t nblocks) {
+  const uint32_t L = xcd_block(blockIdx.x, nblocks);
+  const int64_t Y = L / blocks_per_row;
+  const int64_t X0 = ((int64_t)(L % blocks_per_row) * blockDim.x + threadIdx.x) * 4;
+  if (Y >= a.Hp || X0 >= a.Wp) return;
+  const int64_t yq = ((2 * Y + 1) * (int64_t)a.Hv * 128) / a.Hp;
+  uint32_t bytes[12];
+  const int nx = a.Wp - X0 < 4 ? (int)(a.Wp - X0) : 4;
 #pragma unroll
-    for (int ch = 0; ch < 4; ++ch) acc[ch] += w * ((c >> (8 * ch)) & 255u);
+  for (int k = 0; k < 4; ++k) {
+    const int64_t X = X0 + k;
+    const int64_t xq = ((2 * X + 1) * (int64_t)a.Wv * 128) / a.Wp;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      uint32_t val = 0;
+      if (k < nx) {
+        const uint32_t phi = (uint32_t)(3 * X + c) * a.K1 + (uint32_t)Y * a.Ky + a.K0;
+        const uint64_t U = (uint64_t)phi * (uint64_t)a.V;
+        if (a.mode == 0) {
+          const int64_t v = (int64_t)(U >> 32);
+          val = (a.views[(v * a.Hv + (yq >> 8)) * a.Wv + (xq >> 8)] >> (8 * c)) & 255u;
+        } else {
+          uint32_t sum = 0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            int64_t v = ((int64_t)U + a.du[t]) >> 32;
+            int64_t x = (xq + a.dx[t]) >> 8, y = (yq + a.dy[t]) >> 8;
+            v = v < 0 ? 0 : (v > a.V - 1 ? a.V - 1 : v);
+            x = x < 0 ? 0 : (x > a.Wv - 1 ? a.Wv - 1 : x);
+            y = y < 0 ? 0 : (y > a.Hv - 1 ? a.Hv - 1 : y);
+            sum += (a.views[(v * a.Hv + y) * a.Wv + x] >> (8 * c)) & 255u;
+          }
+          val = (sum + 4u) >> 3;
+        }
+      }
+      bytes[3 * k + c] = val;
+    }
   }
-  uint32_t o = 0;
+  uint8_t* dst = a.panel + (Y * a.Wp + X0) * 3;
+  if (nx == 4 && ((uintptr_t)dst & 3) == 0) {
+    uint32_t* d32 = reinterpret_cast<uint32_t*>(dst);
+    d32[0] = bytes[0] | (bytes[1] << 8) | (bytes[2] << 16) | (bytes[3] << 24);
+    d32[1] = bytes[4] | (bytes[5] << 8) | (bytes[6] << 16) | (bytes[7] << 24);
+    d32[2] = bytes[8] | (bytes[9] << 8) | (bytes[10] << 16) | (bytes[11] << 24);
+  } else {
+    for (int k = 0; k < 3 * nx; ++k) dst[k] = (uint8_t)bytes[k];
+  }
+}
+
+// Angular supersampling filter, one lane per four consecutive pixels of an
+// output view (16-byte loads and stores where whole).  Per channel the
+// weighted sum fits 32 bits (weights < 2^16, at most 3S sub-views); the
+// rounded quotient (acc + ws/2) div ws is taken exactly from a double
+// reciprocal and one integer correction step.
+__global__ void __launch_bounds__(256) k_angular_filter(AngularArgs a) {
+  const int v = blockIdx.y;
+  const int64_t npx = (int64_t)a.W * a.H;
+  const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (p0 >= npx) return;
+  const int n = a.cnt[v];
+  uint32_t ws = 0;
+  for (int e = 0; e < n; ++e) ws += a.wt[v * a.maxe + e];
+  const double rcp = 1.0 / (double)ws;
+  const uint32_t half = ws / 2;
+  const bool whole = p0 + 4 <= npx && (npx & 3) == 0;
+  uint32_t acc[4][4];
 #pragma unroll
-  for (int ch = 0; ch < 4; ++ch) o |= (uint32_t)((acc[ch] + ws / 2) / ws) << (8 * ch);
-  a.out[(int64_t)v * npx + p] = o;
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[k][c] = 0u;
+  for (int e = 0; e < n; ++e) {
+    const uint32_t w = a.wt[v * a.maxe + e];
+    const uint32_t* row = a.sub + (int64_t)a.src[v * a.maxe + e] * npx + p0;
+    uint32_t px[4];
+    if (whole) {
+      const uint4 q = *reinterpret_cast<const uint4*>(row);
+      px[0] = q.x; px[1] = q.y; px[2] = q.z; px[3] = q.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) px[k] = p0 + k < npx ? row[k] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[k][c] += w * ((px[k] >> (8 * c)) & 255u);
+  }
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o[k] = 0u;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t num = acc[k][c] + half;
+      uint32_t q = (uint32_t)((double)num * rcp);
+      const int64_t r = (int64_t)num - (int64_t)q * ws;
+      if (r >= (int64_t)ws) q += 1;
+      else if (r < 0) q -= 1;
+      o[k] |= q << (8 * c);
+    }
+  }
+  uint32_t* dst = a.out + (int64_t)v * npx + p0;
+  if (whole) {
+    *reinterpret_cast<uint4*>(dst) = make_uint4(o[0], o[1], o[2], o[3]);
+  } else {
+    for (int k = 0; k < 4; ++k)
+      if (p0 + k < npx) dst[k] = o[k];
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1194,12 +1301,13 @@ void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H,
 }
 
 void launch_interleave(const InterleaveArgs& a, hipStream_t s) {
-  dim3 g(nblk(a.Wp, 256), (unsigned)a.Hp);
-  k_interleave<<<g, 256, 0, s>>>(a);
+  const uint32_t per_row = nblk(a.Wp, 256 * 4);
+  const uint32_t nb = per_row * (uint32_t)a.Hp;
+  k_interleave<<<nb, 256, 0, s>>>(a, per_row, nb);
 }
 
 void launch_angular_filter(const AngularArgs& a, hipStream_t s) {
-  dim3 g(nblk((int64_t)a.W * a.H, 256), (unsigned)a.V);
+  dim3 g(nblk(((int64_t)a.W * a.H + 3) / 4, 256), (unsigned)a.V);
   k_angular_filter<<<g, 256, 0, s>>>(a);
 }
 

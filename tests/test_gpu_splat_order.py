@@ -34,6 +34,8 @@ def _same(R, sid, model, label):
     vt, dt, st = _render(R, sid, model, lfdpr.SPLAT_TRIANGLE_VIEW)
     vp, dp, sp = _render(R, sid, model, lfdpr.SPLAT_POINT)
     _log(f"[{label}] triangle-view {st}; point {sp}")
+    # each frame ran the splat of the order asked for
+    assert st.pop("splat_order") == lfdpr.SPLAT_TRIANGLE_VIEW and sp.pop("splat_order") == lfdpr.SPLAT_POINT
     assert st == sp
     assert st["written_px"] > 0
     np.testing.assert_array_equal(vt, vp, err_msg=f"{label}: views")
@@ -70,6 +72,7 @@ def test_orders_agree_at_display_size(torch_cuda):
         v, _ = R.alloc_views()
         R.render_frame(sid, w.model(f), v)
         outs.append(v)
+    assert R.stats()["splat_order"] == lfdpr.SPLAT_TRIANGLE_VIEW
     R.set_frames_in_flight(1)
     for f, v in zip((3, 4, 5), outs):
         vp, _, _ = _render(R, sid, w.model(f), lfdpr.SPLAT_POINT)
@@ -95,7 +98,9 @@ def test_orders_agree_in_batches(torch_cuda):
         B.use_graph(order == lfdpr.SPLAT_TRIANGLE_VIEW)
         for _ in range(2):
             B.render(models, v, panels)
-        out[order] = (v.cpu().numpy(), panels.cpu().numpy(), B.stats())
+        st = B.stats()
+        assert st.pop("splat_order") == order
+        out[order] = (v.cpu().numpy(), panels.cpu().numpy(), st)
         B.close()
     a, b = out[lfdpr.SPLAT_TRIANGLE_VIEW], out[lfdpr.SPLAT_POINT]
     assert a[2] == b[2] and a[2]["written_px"] > 0
