@@ -854,6 +854,23 @@ struct alignas(16) PairData {
   int32_t jhi, pad;
 };
 static_assert(sizeof(PairData) == 160, "PairData is ten 16-byte words");
+constexpr int kPairWords = 10;
+
+// The pair records of a wave are kept in LDS word-major: word g of pair o at
+// [g][o], so that lanes reading consecutive pairs hit consecutive banks.
+__device__ __forceinline__ void store_pair(uint4 (*pw)[64], int o, const PairData& P) {
+  const uint4* w = reinterpret_cast<const uint4*>(&P);
+#pragma unroll
+  for (int g = 0; g < kPairWords; ++g) pw[g][o] = w[g];
+}
+
+__device__ __forceinline__ PairData load_pair(const uint4 (*pw)[64], int o) {
+  PairData P;
+  uint4* w = reinterpret_cast<uint4*>(&P);
+#pragma unroll
+  for (int g = 0; g < kPairWords; ++g) w[g] = pw[g][o];
+  return P;
+}
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -914,7 +931,7 @@ __device__ __forceinline__ uint32_t splat_fragment(const PairData& Q, int32_t x,
 template <bool kMulti>
 __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
-  __shared__ PairData pd[4][64];
+  __shared__ uint4 pd[4][kPairWords][64];
   __shared__ uint32_t poff[4][64];
   __shared__ uint32_t fq[4][128];     // covered pixels waiting: pair | x << 6 | y << 19
   const Rig& trg = a.table_rig;
@@ -928,7 +945,7 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
   const int32_t V = trg.n_views;
   const int64_t npairs = (int64_t)imin((int64_t)*a.n_tris, a.nt) * V;
   const Item it0 = load_uniform(a.items);
-  PairData* const mypd = pd[wv];
+  uint4 (*const mypd)[64] = pd[wv];
   uint32_t* const myoff = poff[wv];
   uint32_t* const myq = fq[wv];
   uint32_t written = 0;
@@ -1014,7 +1031,7 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
     const uint32_t total = __shfl(inc, 63, 64);
     if (total == 0) continue;
     myoff[lane] = inc - npx;
-    if (npx) mypd[lane] = P;
+    if (npx) store_pair(mypd, lane, P);
     wave_sync_lds();
     // ---- phase B: 64 box pixels per round over the concatenated boxes; the
     // covered ones queue up and are splatted 64 at a time
@@ -1028,16 +1045,18 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
 #pragma unroll
         for (int st = 32; st >= 1; st >>= 1)
           if (myoff[o + st] <= u) o += st;
-        const PairData& Q = mypd[o];
+        const uint4 g0 = mypd[0][o], g1 = mypd[1][o];
+        const float inv_w = __uint_as_float(mypd[3][o].z);
         const int32_t q = (int32_t)(u - myoff[o]);
-        const int32_t w = Q.w;
-        int32_t yq = (int32_t)((float)q * Q.inv_w);
+        const int32_t w = (int32_t)g1.w, xy0 = (int32_t)g1.z;
+        int32_t yq = (int32_t)((float)q * inv_w);
         int32_t xq = q - yq * w;
         if (xq < 0) { yq -= 1; xq += w; }
         else if (xq >= w) { yq += 1; xq -= w; }
-        const int32_t x = (Q.xy0 & 0xFFFF) + xq, y = (Q.xy0 >> 16) + yq;
+        const int32_t x = (xy0 & 0xFFFF) + xq, y = (xy0 >> 16) + yq;
         const int32_t pxq = 256 * x + 128, pyq = 256 * y + 128;
-        const int32_t qx0 = Q.qx0, qx1 = Q.qx1, qx2 = Q.qx2, qy0 = Q.qy0, qy1 = Q.qy1, qy2 = Q.qy2;
+        const int32_t qx0 = (int32_t)g0.x, qx1 = (int32_t)g0.y, qx2 = (int32_t)g0.z, qy0 = (int32_t)g0.w,
+                      qy1 = (int32_t)g1.x, qy2 = (int32_t)g1.y;
         // edge functions in 64-bit integers; an edge owns its ties iff dy > 0 || (dy == 0 && dx > 0)
         auto inside = [](int32_t ax, int32_t ay, int32_t bx, int32_t by, int32_t px, int32_t py) {
           const int32_t dx = bx - ax, dy = by - ay;
@@ -1054,8 +1073,8 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
       if (qn >= 64) {
         wave_sync_lds();
         const uint32_t e = myq[lane];
-        written += splat_fragment(mypd[e & 63], (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx, ty, a.rows,
-                                  a.pbox);
+        written += splat_fragment(load_pair(mypd, (int)(e & 63)), (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx,
+                                  ty, a.rows, a.pbox);
         const uint32_t rest = qn - 64;
         const uint32_t moved = lane < rest ? myq[64 + lane] : 0u;
         wave_sync_lds();
@@ -1067,8 +1086,8 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
       wave_sync_lds();
       if ((uint32_t)lane < qn) {
         const uint32_t e = myq[lane];
-        written += splat_fragment(mypd[e & 63], (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx, ty, a.rows,
-                                  a.pbox);
+        written += splat_fragment(load_pair(mypd, (int)(e & 63)), (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx,
+                                  ty, a.rows, a.pbox);
       }
     }
     wave_sync_lds();  // the pair data and the queue are rewritten for the next chunk
