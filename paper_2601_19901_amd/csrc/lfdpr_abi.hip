@@ -9,6 +9,7 @@
 #include <mutex>
 #include <utility>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/lfdpr.h"
@@ -361,6 +362,8 @@ void build_rig(const lfdpr_view_params& v, Rig& rg, std::vector<float>& eye, std
   rg.rD = (float)(1.0 / D);
   rg.znear = v.znear;
   rg.fxfy = rg.fx * rg.fy;
+  rg.eye_lo = *std::min_element(eye.begin(), eye.end());
+  rg.eye_hi = *std::max_element(eye.begin(), eye.end());
 }
 
 bool view_params_ok(const lfdpr_view_params* v) {

@@ -96,6 +96,7 @@ struct Shading {
 struct Rig {
   int32_t n_views, W, H, mip;
   float fx, fy, cx, cy, rD, znear, fxfy;
+  float eye_lo, eye_hi;  // smallest and largest eye offset of the table
   const float* eye;     // n_views
   const float* kshift;  // n_views
 };

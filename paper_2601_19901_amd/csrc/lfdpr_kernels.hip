@@ -96,6 +96,9 @@ __device__ __forceinline__ uint64_t wave_append(bool take, uint64_t* counter) {
 
 // ------------------------------------------------------------------ a1/a2: triangle setup
 
+// kMulti: triangles of several items (a batch), each lane finds its own; else
+// every triangle belongs to items[0], whose rig then sits in scalar registers.
+template <bool kMulti>
 __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t act_cnt = 0, ovf_cnt = 0, pv_cnt = 0;
@@ -104,7 +107,7 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
     if (a.dbgf) {
       for (int k = 0; k < 8; ++k) { a.dbgf[t * 8 + k] = 0.0f; a.dbgi[t * 8 + k] = 0; }
     }
-    const int item = find_item(a.items, a.n_items, t);
+    const int item = kMulti ? find_item(a.items, a.n_items, t) : 0;
     const Item& it = a.items[item];
     const int64_t lt = t - it.tri_base;
     const Rig rg = it.rig;  // in registers: the view loop reads it every iteration
@@ -134,10 +137,37 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       vertex_proj(rg, P1.x, P1.y, P1.z, R.a1, R.c1, R.y1);
       vertex_proj(rg, P2.x, P2.y, P2.z, R.a2, R.c2, R.y2);
     }
+    // triangles that no view can see, told from the two ends of the eye range
+    // (the plane distance delta = h - nx*b and each projected x = a - b*c are
+    // monotone in b, also after rounding; the projected rows do not depend on
+    // b): behind the plane for every eye, rows off the view or outside the
+    // guard band, all vertices left of or right of the view for every eye.
+    // They skip the view loop, which would find no active view.
+    bool seen = ok;
+    if (ok) {
+      if (R.h - R.nx * rg.eye_lo >= 0.0f && R.h - R.nx * rg.eye_hi >= 0.0f) seen = false;
+      if (!(fabsf(R.y0) < kGuard) || !(fabsf(R.y1) < kGuard) || !(fabsf(R.y2) < kGuard)) {
+        seen = false;
+      } else {
+        const int32_t H8 = 256 * rg.H;
+        const int32_t qy0 = (int32_t)rintf(R.y0 * 256.0f), qy1 = (int32_t)rintf(R.y1 * 256.0f),
+                      qy2 = (int32_t)rintf(R.y2 * 256.0f);
+        if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) seen = false;
+      }
+      // x * 256 < -0.5 rounds below 0; x * 256 > W8 + 0.5 rounds above W8
+      const float W8h = (float)(256 * rg.W) + 0.5f;
+      const float xl0 = R.a0 - rg.eye_lo * R.c0, xh0 = R.a0 - rg.eye_hi * R.c0;
+      const float xl1 = R.a1 - rg.eye_lo * R.c1, xh1 = R.a1 - rg.eye_hi * R.c1;
+      const float xl2 = R.a2 - rg.eye_lo * R.c2, xh2 = R.a2 - rg.eye_hi * R.c2;
+      if (fmaxf(xl0, xh0) * 256.0f < -0.5f && fmaxf(xl1, xh1) * 256.0f < -0.5f && fmaxf(xl2, xh2) * 256.0f < -0.5f)
+        seen = false;
+      if (fminf(xl0, xh0) * 256.0f > W8h && fminf(xl1, xh1) * 256.0f > W8h && fminf(xl2, xh2) * 256.0f > W8h)
+        seen = false;
+    }
     // visibility in each view + LFD-biased densities over the active views
     int nact = 0;
     float lxmin = INFINITY, lymin = INFINITY, Amin = INFINITY, admin = INFINITY, admax = 0.0f;
-    if (ok) {
+    if (seen) {
       // the next view's eye offset is fetched one iteration ahead
       float b_next = rg.eye[0];
       for (int r = 0; r < rg.n_views; ++r) {
@@ -1264,7 +1294,10 @@ void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st)
 
 void launch_tri_setup(const SetupArgs& a, hipStream_t s) {
   if (a.nt <= 0) return;
-  k_tri_setup<<<nblk(a.nt, 256), 256, 0, s>>>(a);
+  if (a.n_items > 1)
+    k_tri_setup<true><<<nblk(a.nt, 256), 256, 0, s>>>(a);
+  else
+    k_tri_setup<false><<<nblk(a.nt, 256), 256, 0, s>>>(a);
 }
 
 void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_stride, int64_t panel_stride,
