@@ -116,6 +116,17 @@ LF_HD int64_t floor_div(int64_t a, int64_t b) {  // b > 0
   if ((a % b) != 0 && a < 0) q -= 1;
   return q;
 }
+// floor(a / b) for b > 0 and |a| < 2^53, b < 2^53: the correctly rounded double
+// quotient is within one of the floor (|a / b| < 2^48 here, so its error is
+// below 1/32), and one integer check settles it; q * b stays near a.  Much
+// cheaper on the GPU than a 64-bit integer division.
+LF_HD int64_t floor_div_53(int64_t a, int64_t b) {
+  int64_t q = (int64_t)floor((double)a / (double)b);
+  const int64_t r = a - q * b;
+  if (r < 0) q -= 1;
+  else if (r >= b) q += 1;
+  return q;
+}
 
 LF_HD int64_t imin(int64_t a, int64_t b) { return a < b ? a : b; }
 LF_HD int64_t imax(int64_t a, int64_t b) { return a > b ? a : b; }
@@ -222,6 +233,9 @@ LF_HD void lattice_init(Lattice& L, int32_t s1, int32_t t1, int32_t s2, int32_t 
 }
 
 // Emitted i-range [lo, hi] of row j (empty when lo > hi).
+// Cell range [lo, hi] of lattice row j.  Magnitudes: Q8 vertices below 2^22
+// (|s|, |t| < 16384 cells), so edge coefficients stay below 2^23, the row's
+// edge offsets below 2^48 and the divisors below 2^31 (floor_div_53's range).
 LF_HD void lattice_row(const Lattice& L, int64_t j, int64_t& lo, int64_t& hi) {
   lo = L.iA;
   hi = L.iB;
@@ -236,13 +250,13 @@ LF_HD void lattice_row(const Lattice& L, int64_t j, int64_t& lo, int64_t& hi) {
     int64_t c = beta * (beta > 0 ? y1 : y0) + gamma;
     if (alpha > 0) {
       // alpha*(256 i + 260) + c > 0
-      lo = imax(lo, floor_div(-c - (256 + kEpsQ8) * alpha, 256 * alpha) + 1);
+      lo = imax(lo, floor_div_53(-c - (256 + kEpsQ8) * alpha, 256 * alpha) + 1);
     } else if (alpha < 0) {
       // -a'*(256 i - 4) + c > 0  <=>  256 a' i < c + 4 a'
       int64_t ap = -alpha;
       int64_t num = c + kEpsQ8 * ap;
       // i < num / (256 ap)  <=>  i <= ceil(num / (256 ap)) - 1
-      hi = imin(hi, floor_div(num - 1, 256 * ap));
+      hi = imin(hi, floor_div_53(num - 1, 256 * ap));
     } else if (!(c > 0)) {
       lo = 1;
       hi = 0;
