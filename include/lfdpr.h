@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LFDPR_ABI_VERSION 4
+#define LFDPR_ABI_VERSION 5
 
 enum {
   LFDPR_OK = 0,
@@ -112,6 +112,16 @@ typedef struct {
                               covered pixel of a visible triangle, owned by one point (Sec. 3.2) */
   int32_t splat_order;     /* LFDPR_SPLAT_* the last frame's splat used */
   int32_t reserved;
+  /* Hole census (Sec. 3.2), observed by the triangle-view splat order only (-1
+   * under the point order, which never visits a pixel no point covers):
+   * covered_px counts the pixels inside an active (triangle, view) pair's Q8
+   * triangle, over the triangles that have points; missed_px those that no point
+   * writes -- the eye ray meets the plane behind the eye, or the pixel lies
+   * outside the splat box of the point owning its cell.  A triangle without
+   * points (an orphan: only an overflowed lattice, counted in overflow_tris) is
+   * not visited. */
+  int64_t covered_px;
+  int64_t missed_px;
 } lfdpr_stats;
 
 /* Version of this ABI (LFDPR_ABI_VERSION). */

@@ -1039,6 +1039,8 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
   out->written_px = (int64_t)st[STAT_WRITTEN];
   out->splat_order = ctx->last_order;
+  out->covered_px = ctx->last_order == LFDPR_SPLAT_TRIANGLE_VIEW ? (int64_t)st[STAT_COVERED] : -1;
+  out->missed_px = out->covered_px >= 0 ? out->covered_px - out->written_px : -1;
   out->capacity = ctx->cap;
   out->point_overflow = out->points > ctx->cap ? 1 : 0;
   out->n_views = ctx->rig.n_views;
@@ -1659,6 +1661,8 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
   out->overflow_tris = (int64_t)st[STAT_OVERFLOW];
   out->written_px = (int64_t)st[STAT_WRITTEN];
   out->splat_order = b->last_order;
+  out->covered_px = b->last_order == LFDPR_SPLAT_TRIANGLE_VIEW ? (int64_t)st[STAT_COVERED] : -1;
+  out->missed_px = out->covered_px >= 0 ? out->covered_px - out->written_px : -1;
   out->capacity = b->cap;
   out->point_overflow = out->points > b->cap ? 1 : 0;
   out->n_views = b->table_rig.n_views;

@@ -8,7 +8,7 @@
 namespace lfdpr {
 
 enum StatSlot { STAT_ACTIVE = 0, STAT_OVERFLOW = 1, STAT_POINT_VIEWS = 2, STAT_TOTAL = 3, STAT_BIG = 4,
-                STAT_WRITTEN = 5, STAT_EMITTING = 6, STAT_SLOTS = 8 };
+                STAT_WRITTEN = 5, STAT_EMITTING = 6, STAT_COVERED = 7, STAT_SLOTS = 8 };
 
 // One frame of one scene inside a (possibly single-element) batch.  Items share
 // the view size and projection (W, H, fovy, aspect); eye tables may differ.
@@ -84,7 +84,8 @@ struct SplatArgs {
   const TriMat* tm;          // physically based mode; else null
   const uint4* pmat;
   Shading sh;
-  uint64_t* stats;           // STAT_WRITTEN: pixels written (64-bit key updates issued)
+  uint64_t* stats;           // STAT_WRITTEN: pixels written (64-bit key updates issued);
+                             // STAT_COVERED: covered pixels visited (triangle-view order)
   // triangle-major splat (used when pbox is not null)
   const TriEmit* em;
   const uint64_t* offsets;   // first point of each triangle

@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
   uint4 (*const mypd)[64] = pd[wv];
   uint32_t* const myoff = poff[wv];
   uint32_t* const myq = fq[wv];
-  uint32_t written = 0;
+  uint32_t written = 0, covered = 0;  // key updates; covered pixels visited (the hole census)
   const int64_t chunks = (npairs + 63) >> 6;
   for (int64_t c = (int64_t)blockIdx.x * 4 + wv; c < chunks; c += (int64_t)gridDim.x * 4) {
     // ---- phase A: one (triangle, view) pair per lane
@@ -1103,6 +1103,7 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
       if (qn >= 64) {
         wave_sync_lds();
         const uint32_t e = myq[lane];
+        covered += 1;
         written += splat_fragment(load_pair(mypd, (int)(e & 63)), (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx,
                                   ty, a.rows, a.pbox);
         const uint32_t rest = qn - 64;
@@ -1116,14 +1117,16 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
       wave_sync_lds();
       if ((uint32_t)lane < qn) {
         const uint32_t e = myq[lane];
+        covered += 1;
         written += splat_fragment(load_pair(mypd, (int)(e & 63)), (int32_t)((e >> 6) & 0x1FFF), (int32_t)(e >> 19), tx,
                                   ty, a.rows, a.pbox);
       }
     }
     wave_sync_lds();  // the pair data and the queue are rewritten for the next chunk
   }
-  const uint64_t wsum = wave_sum((uint64_t)written);
+  const uint64_t wsum = wave_sum((uint64_t)written), csum = wave_sum((uint64_t)covered);
   if (lane == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
+  if (lane == 0 && csum) atomicAdd((unsigned long long*)&a.stats[STAT_COVERED], (unsigned long long)csum);
 }
 
 // keys -> RGBA8 (+ depth) in [item][view][y][x] order; keys re-cleared.

@@ -61,7 +61,7 @@ class Stats(C.Structure):
     _fields_ = [("points", C.c_int64), ("active_tris", C.c_int64), ("point_views", C.c_int64),
                 ("overflow_tris", C.c_int64), ("capacity", C.c_int64), ("point_overflow", C.c_int32),
                 ("n_views", C.c_int32), ("written_px", C.c_int64), ("splat_order", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("covered_px", C.c_int64), ("missed_px", C.c_int64)]
 
 
 _lib = None

@@ -36,6 +36,9 @@ def _same(R, sid, model, label):
     _log(f"[{label}] triangle-view {st}; point {sp}")
     # each frame ran the splat of the order asked for
     assert st.pop("splat_order") == lfdpr.SPLAT_TRIANGLE_VIEW and sp.pop("splat_order") == lfdpr.SPLAT_POINT
+    # the hole census is observed by the triangle-view order only
+    assert sp.pop("covered_px") == -1 and sp.pop("missed_px") == -1
+    assert st.pop("covered_px") >= st["written_px"] and st.pop("missed_px") >= 0
     assert st == sp
     assert st["written_px"] > 0
     np.testing.assert_array_equal(vt, vp, err_msg=f"{label}: views")
@@ -100,9 +103,35 @@ def test_orders_agree_in_batches(torch_cuda):
             B.render(models, v, panels)
         st = B.stats()
         assert st.pop("splat_order") == order
+        cov, mis = st.pop("covered_px"), st.pop("missed_px")
+        if order == lfdpr.SPLAT_POINT:
+            assert cov == -1 and mis == -1
+        else:  # the batch's census: every covered pixel written
+            assert cov == st["written_px"] and mis == 0
         out[order] = (v.cpu().numpy(), panels.cpu().numpy(), st)
         B.close()
     a, b = out[lfdpr.SPLAT_TRIANGLE_VIEW], out[lfdpr.SPLAT_POINT]
     assert a[2] == b[2] and a[2]["written_px"] > 0
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("kind,seed,frame", [("tiny", 3, 0), ("small", 7, 0), ("small", 8, 40), ("display", 2, 17)])
+def test_hole_census_matches_the_oracle(torch_cuda, kind, seed, frame):
+    """Under the triangle-view order the splat counts the pixels inside every
+    active (triangle, view) pair's Q8 triangle and, of those, the ones no point
+    writes (Sec. 3.2's holes); both equal the oracle's own census, which
+    rasterises the triangles independently (display-1M frame 17 had one hole
+    before the grazing-margin and zero-area rules)."""
+    from oracle import oracle as O
+    from paper_2601_19901_amd import lfdpr
+    w = {"tiny": scenes.tiny, "small": scenes.small_display, "display": scenes.display}[kind](seed=seed)
+    o = O.render(w.scene, w.views, w.model(frame))["stats"]
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    _, _, st = _render(R, sid, w.model(frame), lfdpr.SPLAT_TRIANGLE_VIEW)
+    _log(f"[census {kind} {seed} f{frame}] gpu covered {st['covered_px']} missed {st['missed_px']}; oracle {o}")
+    assert o["overflow_tris"] == 0 and o["orphans"] == 0
+    assert st["covered_px"] == o["fragments"] and st["missed_px"] == o["misses"]
+    assert st["written_px"] == o["fragments"] - o["misses"]
