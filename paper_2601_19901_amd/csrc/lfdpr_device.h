@@ -182,6 +182,34 @@ LF_HD F3 sub3(F3 a, F3 b) { return F3{a.x - b.x, a.y - b.y, a.z - b.z}; }
 LF_HD float dot3(F3 a, F3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
 LF_HD F3 axpy3(F3 a, float s, F3 d) { return F3{a.x + s * d.x, a.y + s * d.y, a.z + s * d.z}; }
 
+// False only for a triangle that no view of the rig can see (view_active is
+// false for every eye offset in [eye_lo, eye_hi]), told from the two ends of
+// the range: the plane distance delta = h - nx*b and each projected x = a - b*c
+// are monotone in b (a product with a fixed factor and a difference with a
+// fixed term keep their order under rounding), and the projected rows do not
+// depend on b.  So the triangle is behind its plane for every eye, or its rows
+// are off the view or outside the guard band, or all its vertices are left of
+// (right of) the view at both ends and hence for every eye.  The record needs
+// h, nx, a/c/y of the three vertices.
+LF_HD bool may_be_seen(const Rig& rg, const TriRec& R) {
+  if (R.h - R.nx * rg.eye_lo >= 0.0f && R.h - R.nx * rg.eye_hi >= 0.0f) return false;
+  if (!(fabsf(R.y0) < kGuard) || !(fabsf(R.y1) < kGuard) || !(fabsf(R.y2) < kGuard)) return false;
+  const int32_t H8 = 256 * rg.H;
+  const int32_t qy0 = (int32_t)rintf(R.y0 * 256.0f), qy1 = (int32_t)rintf(R.y1 * 256.0f),
+                qy2 = (int32_t)rintf(R.y2 * 256.0f);
+  if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) return false;
+  // x * 256 < -0.5 rounds below 0; x * 256 > W8 + 0.5 rounds above W8
+  const float W8h = (float)(256 * rg.W) + 0.5f;
+  const float xl0 = R.a0 - rg.eye_lo * R.c0, xh0 = R.a0 - rg.eye_hi * R.c0;
+  const float xl1 = R.a1 - rg.eye_lo * R.c1, xh1 = R.a1 - rg.eye_hi * R.c1;
+  const float xl2 = R.a2 - rg.eye_lo * R.c2, xh2 = R.a2 - rg.eye_hi * R.c2;
+  if (fmaxf(xl0, xh0) * 256.0f < -0.5f && fmaxf(xl1, xh1) * 256.0f < -0.5f && fmaxf(xl2, xh2) * 256.0f < -0.5f)
+    return false;
+  if (fminf(xl0, xh0) * 256.0f > W8h && fminf(xl1, xh1) * 256.0f > W8h && fminf(xl2, xh2) * 256.0f > W8h)
+    return false;
+  return true;
+}
+
 // Point of triangle abc nearest to p, by the Voronoi regions of its vertices,
 // edges and face (Ericson, Real-Time Collision Detection, Sec. 5.1.5).
 LF_HD F3 nearest_on_triangle(F3 p, F3 a, F3 b, F3 c) {

@@ -137,33 +137,8 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       vertex_proj(rg, P1.x, P1.y, P1.z, R.a1, R.c1, R.y1);
       vertex_proj(rg, P2.x, P2.y, P2.z, R.a2, R.c2, R.y2);
     }
-    // triangles that no view can see, told from the two ends of the eye range
-    // (the plane distance delta = h - nx*b and each projected x = a - b*c are
-    // monotone in b, also after rounding; the projected rows do not depend on
-    // b): behind the plane for every eye, rows off the view or outside the
-    // guard band, all vertices left of or right of the view for every eye.
-    // They skip the view loop, which would find no active view.
-    bool seen = ok;
-    if (ok) {
-      if (R.h - R.nx * rg.eye_lo >= 0.0f && R.h - R.nx * rg.eye_hi >= 0.0f) seen = false;
-      if (!(fabsf(R.y0) < kGuard) || !(fabsf(R.y1) < kGuard) || !(fabsf(R.y2) < kGuard)) {
-        seen = false;
-      } else {
-        const int32_t H8 = 256 * rg.H;
-        const int32_t qy0 = (int32_t)rintf(R.y0 * 256.0f), qy1 = (int32_t)rintf(R.y1 * 256.0f),
-                      qy2 = (int32_t)rintf(R.y2 * 256.0f);
-        if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) seen = false;
-      }
-      // x * 256 < -0.5 rounds below 0; x * 256 > W8 + 0.5 rounds above W8
-      const float W8h = (float)(256 * rg.W) + 0.5f;
-      const float xl0 = R.a0 - rg.eye_lo * R.c0, xh0 = R.a0 - rg.eye_hi * R.c0;
-      const float xl1 = R.a1 - rg.eye_lo * R.c1, xh1 = R.a1 - rg.eye_hi * R.c1;
-      const float xl2 = R.a2 - rg.eye_lo * R.c2, xh2 = R.a2 - rg.eye_hi * R.c2;
-      if (fmaxf(xl0, xh0) * 256.0f < -0.5f && fmaxf(xl1, xh1) * 256.0f < -0.5f && fmaxf(xl2, xh2) * 256.0f < -0.5f)
-        seen = false;
-      if (fminf(xl0, xh0) * 256.0f > W8h && fminf(xl1, xh1) * 256.0f > W8h && fminf(xl2, xh2) * 256.0f > W8h)
-        seen = false;
-    }
+    // triangles that no view can see skip the view loop (see may_be_seen)
+    const bool seen = ok && may_be_seen(rg, R);
     // visibility in each view + LFD-biased densities over the active views
     int nact = 0;
     float lxmin = INFINITY, lymin = INFINITY, Amin = INFINITY, admin = INFINITY, admax = 0.0f;
