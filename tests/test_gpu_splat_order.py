@@ -1,8 +1,8 @@
-"""The two splat orders (lfdpr_set_splat_order): per (triangle, view), the
-default for unlit frames, and per point.  They visit the same (point, view,
+"""The two splat orders (lfdpr_set_splat_order): per point, the default, and
+per (triangle, view) for unlit frames.  They visit the same (point, view,
 pixel) work in different orders, so views, depth and statistics must be
 identical bit for bit; the default order is tied to the oracle by the parity
-tests, and here the point order is tied to it through the default."""
+tests, and here the triangle-view order is tied to it through the default."""
 import numpy as np
 import pytest
 
