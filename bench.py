@@ -69,8 +69,12 @@ BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
     "scan": lambda s: s["nt"] * (4 + 4 + 8),
     "emit": lambda s: s["tris_with_points"] * 76 + s["points"] * (16 + 2 * 16),
-    "splat": lambda s: s["points"] * (16 + 112) + s["written_px"] * 8,
-    "resolve": lambda s: s["pixels"] * (8 + 8 + 4),
+    # point order: points and records in, one 8 B key per written pixel; quilt:
+    # points, records and splat rectangles in, the views (4 B per pixel) out
+    "splat": lambda s: (s["points"] * (16 + 112 + 48) + s["pixels"] * 4 if s.get("quilt")
+                        else s["points"] * (16 + 112) + s["written_px"] * 8),
+    "resolve": lambda s: 0 if s.get("quilt") else s["pixels"] * (8 + 8 + 4),
+    "quilt_bin": lambda s: s["points"] * (4 + 4 + 4),
     "interleave": lambda s: s["panel_px"] * 3 + s["panel_px"] * 3 * 4,
     "angular_filter": lambda s: s["pixels"] * 4 + s["out_pixels"] * 4,
 }
@@ -98,7 +102,8 @@ def roofline(stage_ms: dict, pv_per_frame: float, shape: dict, traffic=None, pbr
         ops = splat_ops(pv_per_frame, wpx, pbr)
         achieved = ops / (dom_ms * 1e-3) / 1e12
         census = splat_ops_census(pv_per_frame, wpx, pbr) / (dom_ms * 1e-3) / 1e12
-        return {"kernel": "k_splat", "bound": "alu", "achieved": round(achieved, 3),
+        return {"kernel": "k_splat_quilt" if shape.get("quilt") else "k_splat", "bound": "alu",
+                "achieved": round(achieved, 3),
                 "peak": round(peak_t, 2), "unit": "Tops/s",
                 "frac": round(achieved / peak_t, 4), "traffic": traffic,
                 "ops": f"{SPLAT_OPS_PER_POINT_VIEW_ALG} per point-view + "
@@ -155,10 +160,31 @@ def profile_traffic(name: str, sources, label: str):
     return float(t.group(1))
 
 
-def splat_traffic():
-    """HBM bytes per k_splat launch on display-1M (see profile_traffic)."""
-    return profile_traffic("display-1M_splat_traffic.md", ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"),
-                           "HBM bytes per launch")
+def splat_traffic(quilt: bool = False):
+    """HBM bytes per k_splat (or k_splat_quilt) launch on display-1M (see
+    profile_traffic)."""
+    return profile_traffic("display-1M_quilt_traffic.md" if quilt else "display-1M_splat_traffic.md",
+                           ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"), "HBM bytes per launch")
+
+
+ORDER_NAMES = {0: "point", 1: "triangle-view", 2: "quilt"}
+
+
+def choose_splat_order(args, lfdpr, R, sid, model, views) -> dict:
+    """The splat order of the run: the library's autotuner (point order under
+    each launch shape and key layout, the quilt under each band height) or the
+    one asked for.  Returns what was chosen."""
+    if args.splat_order == "auto":
+        tune = R.autotune(sid, model, views)
+        b = tune["best"]
+        log(f"autotune: {b}")
+        return {"order": ORDER_NAMES[b["splat_order"]], "quilt_tile": [b["quilt_rows"], b["quilt_views"]],
+                "splat_blocks": b["splat_blocks"], "key_layout": b["key_layout"], "autotuned": True,
+                "candidates_ms": {f"{ORDER_NAMES[e['splat_order']]} {e['splat_blocks']}/{e['key_layout']}/"
+                                  f"{e['quilt_rows']}x{e['quilt_views']}": round(e["ms"], 4) for e in tune["entries"]}}
+    R.set_splat_order({"point": lfdpr.SPLAT_POINT, "triangle-view": lfdpr.SPLAT_TRIANGLE_VIEW,
+                       "quilt": lfdpr.SPLAT_QUILT}[args.splat_order])
+    return {"order": args.splat_order, "autotuned": False}
 
 
 def host_cpu() -> dict:
@@ -203,12 +229,12 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     R.set_lens(lens)
     R.set_shading(w.shading)
     R.set_frames_in_flight(args.frames_in_flight)
-    R.set_splat_order(lfdpr.SPLAT_TRIANGLE_VIEW if args.splat_order == "triangle-view" else lfdpr.SPLAT_POINT)
     views, _ = R.alloc_views()
+    models = [w.model(f) for f in range(args.warmup + args.steps)]
+    chosen = choose_splat_order(args, lfdpr, R, sid, models[0], views)
     filtered = (torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda:0")
                 if kind == "display-4M-ss4" else None)
     panel = torch.empty((lens.Hp, lens.Wp, 3), dtype=torch.uint8, device="cuda:0")
-    models = [w.model(f) for f in range(args.warmup + args.steps)]
 
     def frame(f):
         R.render_frame(sid, models[f], views)
@@ -258,12 +284,17 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         act += s["active_tris"]
         wpx += s["written_px"]
     nfr = args.steps
+    quilt = s["splat_order"] == lfdpr.SPLAT_QUILT
+    chosen["order"] = ORDER_NAMES[s["splat_order"]]
+    if quilt:
+        chosen["quilt_tile"] = [s["quilt_rows"], s["quilt_views"]]
+        chosen["quilt_entries_per_frame"] = s["quilt_entries"]
     n_rendered = w.views.V * w.views.S
     pbr = kind == "display-1M-pbr"
     shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
                  out_pixels=w.views.V * w.views.W * w.views.H,
-                 panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, written_px=wpx / nfr)
-    roof = roofline(st_avg, pv / nfr, shape, splat_traffic() if kind == "display-1M" else None, pbr)
+                 panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, written_px=wpx / nfr, quilt=quilt)
+    roof = roofline(st_avg, pv / nfr, shape, splat_traffic(quilt) if kind == "display-1M" else None, pbr)
     names = {
         "display-1M": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
                       "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene",
@@ -297,7 +328,7 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
         "frame_ms_p99": round(float(np.percentile(intervals, 99)), 4),
         "frames_per_s": round(1e3 / wall_ms, 2),
         "frames_in_flight": args.frames_in_flight,
-        "splat_order": args.splat_order,
+        "splat_order": chosen,
         "frame_ms_one_in_flight": round(serial_ms if serial_ms is not None else wall_ms, 4),
         "points_per_frame": int(pts / nfr), "point_views_per_frame": int(pv / nfr),
         "written_px_per_frame": int(wpx / nfr), "active_tris_per_frame": int(act / nfr),
@@ -560,8 +591,9 @@ def main():
     ap.add_argument("--frames-in-flight", type=int, choices=(1, 2), default=2,
                     help="frames whose point generation overlaps the previous frame (display, learned and batch workloads)")
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--splat-order", choices=("point", "triangle-view"), default="point",
-                    help="how the splat visits its work (the same results)")
+    ap.add_argument("--splat-order", choices=("auto", "point", "triangle-view", "quilt"), default="auto",
+                    help="how the splat visits its work (the same results); auto: the library's autotuner "
+                         "picks the point order's launch shape or the quilt's tile (display workloads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LFDPR_ABI_VERSION 5
+#define LFDPR_ABI_VERSION 6
 
 enum {
   LFDPR_OK = 0,
@@ -53,9 +53,9 @@ enum {
 };
 
 enum { LFDPR_RECON_NONE = 0, LFDPR_RECON_SPATIAL = 1, LFDPR_RECON_ANGULAR = 2, LFDPR_RECON_BOTH = 3 };
-/* Order in which the splat visits its work (lfdpr_set_splat_order); both give
+/* Order in which the splat visits its work (lfdpr_set_splat_order); all give
  * the same keys, hence the same views, bit for bit. */
-enum { LFDPR_SPLAT_POINT = 0, LFDPR_SPLAT_TRIANGLE_VIEW = 1 };
+enum { LFDPR_SPLAT_POINT = 0, LFDPR_SPLAT_TRIANGLE_VIEW = 1, LFDPR_SPLAT_QUILT = 2 };
 enum { LFDPR_SHADE_UNLIT = 0, LFDPR_SHADE_PBR = 1 };
 
 typedef struct lfdpr_ctx lfdpr_ctx;
@@ -122,6 +122,14 @@ typedef struct {
    * not visited. */
   int64_t covered_px;
   int64_t missed_px;
+  /* Row-band quilt (LFDPR_SPLAT_QUILT): the last frame's tile (pixel rows x
+   * views per LDS tile; 0 under the other orders) and its band-list entries,
+   * one per (point, band of quilt_rows rows its splat reaches) (-1 under the
+   * other orders).  When the entries exceed the context's list capacity the
+   * frame is splatted per point instead and splat_order says so. */
+  int32_t quilt_rows;
+  int32_t quilt_views;
+  int64_t quilt_entries;
 } lfdpr_stats;
 
 /* Version of this ABI (LFDPR_ABI_VERSION). */
@@ -192,14 +200,35 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* views);
 
 /* How the splat (Sec. 3.2) visits its (point, view, pixel) work:
  *   LFDPR_SPLAT_POINT (default)  per point, looping over the views and its
- *     splat rectangle's pixels;
+ *     splat rectangle's pixels, 64-bit atomicMin into the key buffer in HBM;
  *   LFDPR_SPLAT_TRIANGLE_VIEW  per (triangle, view): the pixels inside the
  *     triangle's projection find their owning point through the lattice row
  *     table and apply its splat rectangle and colour (unlit frames; physically
- *     shaded frames always splat per point).
+ *     shaded frames always splat per point);
+ *   LFDPR_SPLAT_QUILT  per tile of the views' key space (a band of pixel rows
+ *     of a subset of the views, all columns; lfdpr_set_quilt_tile): the tile's
+ *     64-bit keys (Sec. 5.1) stay in LDS while the points whose splat reaches
+ *     its rows are splatted into it, then it is written out as the views
+ *     (unlit and physically shaded frames; batches and
+ *     lfdpr_render_frame_noalloc splat per point under this order).
  * The keys, views and depth are identical.  Applies to the context's frames
  * and to batches created on it afterwards. */
 int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
+
+/* Tile of the quilt order: `rows` pixel rows of `views` views, all W columns,
+ * 8 B per key in LDS (plus 4 B per view column and row for the ray slopes).
+ * 0, 0 (the default) chooses per rig: 4 rows, else 2, else 1, with the most
+ * views that fit the device's LDS per workgroup, spread evenly over the
+ * subsets.  A shape whose keys do not fit is refused by the frame
+ * (LFDPR_EINVAL).  Results do not depend on it. */
+int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
+
+/* Capacity of the quilt's band lists in entries (4 B each; one entry per
+ * point and band of rows its splat reaches); 0 (the default) = twice the
+ * point capacity + 65536.  A frame with more entries is splatted per point
+ * into the key buffer instead (same results; lfdpr_get_stats reports it).
+ * Reallocated by the next quilt frame. */
+int lfdpr_set_quilt_capacity(lfdpr_ctx* ctx, int64_t entries);
 
 /* Sets the panel and reconstruction parameters used by lfdpr_reconstruct. */
 int lfdpr_set_lens(lfdpr_ctx* ctx, const lfdpr_lens_params* lens);
@@ -297,10 +326,11 @@ int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n);
  * stage.  lfdpr_get_timings() synchronises the stream and writes, per stage,
  * the summed milliseconds and the number of recorded launches (host arrays of
  * LFDPR_N_STAGES); stages: 0 triangle set-up, 1 scan, 2 emission, 3 splat,
- * 4 resolve, 5 interleave, 6 angular filter.  Batch renders on the context
- * that are not replayed from a graph record their stages the same way (on the
- * batch's stream).  lfdpr_timing(ctx, 0) stops. */
-#define LFDPR_N_STAGES 7
+ * 4 resolve, 5 interleave, 6 angular filter, 7 the quilt's band lists (quilt
+ * frames; their splat stage is then the tile kernel alone).  Batch renders on
+ * the context that are not replayed from a graph record their stages the same
+ * way (on the batch's stream).  lfdpr_timing(ctx, 0) stops. */
+#define LFDPR_N_STAGES 8
 int lfdpr_timing(lfdpr_ctx* ctx, int enable);
 int lfdpr_get_timings(lfdpr_ctx* ctx, double* ms_sum, int64_t* n_launches);
 
@@ -311,6 +341,8 @@ typedef struct {
   int32_t splat_blocks;  /* workgroups of the splat and fetch launches */
   int32_t key_layout;    /* 0: 64-bit keys [view][y][x]; 1: [y][view][x] (a row of every view adjacent) */
   float ms;              /* measured time of one frame (or one batch) */
+  int32_t splat_order;   /* LFDPR_SPLAT_POINT or LFDPR_SPLAT_QUILT (single frames) */
+  int32_t quilt_rows, quilt_views;  /* the quilt tile (0, 0 under the point order) */
 } lfdpr_tune_entry;
 typedef struct {
   int32_t n, best;       /* entries tried; index of the fastest (now in use) */

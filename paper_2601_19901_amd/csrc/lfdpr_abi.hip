@@ -108,6 +108,7 @@ struct lfdpr_ctx {
   Point* d_points = nullptr;
   RowEntry* d_rows = nullptr;   // triangle-major splat: lattice row table and
   PointBox* d_pbox = nullptr;   // per-point splat rectangles (point capacity each)
+  uint32_t* d_prows = nullptr;  // quilt: per point its splat's pixel rows (first | last << 16, or ~0)
   uint64_t* d_keys = nullptr;
   int64_t n_keys = 0;
   // angular supersampling filter table
@@ -160,6 +161,7 @@ struct lfdpr_ctx {
     Point* d_points = nullptr;
     RowEntry* d_rows = nullptr;
     PointBox* d_pbox = nullptr;
+    uint32_t* d_prows = nullptr;
     uint32_t* d_counts = nullptr;
     uint64_t* d_offsets = nullptr;
     TriRec* d_rec = nullptr;
@@ -170,6 +172,9 @@ struct lfdpr_ctx {
     uint64_t* d_stats = nullptr;
     TriMat* d_tm = nullptr;
     uint4* d_pmat = nullptr;
+    uint32_t* d_qentries = nullptr;
+    uint32_t* d_qband = nullptr;
+    int64_t q_entry_cap = 0;
     bool last_pbr = false;
   } other;
   // launch shape of the splat kernel and key layout (autotuned); splat order:
@@ -179,6 +184,18 @@ struct lfdpr_ctx {
   int key_layout = 0;
   int splat_order = LFDPR_SPLAT_POINT;
   int last_order = LFDPR_SPLAT_POINT;  // the order the last frame's splat used
+  // row-band quilt: tile shape asked for (0, 0: chosen per rig), the last
+  // frame's, the device's LDS per workgroup, and the band lists (a per-frame
+  // buffer, built with the point generation): the entries, and per band
+  // counts | offsets (+1) | cursors | order, then the overflow flag and the
+  // number of entries
+  int quilt_rows = 0, quilt_views = 0;
+  int64_t quilt_cap_req = 0;  // band-list entries asked for (0: twice the point capacity + 65536)
+  int last_qrows = 0, last_qviews = 0;
+  int max_lds = 65536;
+  uint32_t* d_qentries = nullptr;
+  uint32_t* d_qband = nullptr;
+  int64_t q_entry_cap = 0;
   // stage timing: event pairs recorded on the stream
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -234,6 +251,7 @@ void swap_frame_buffers(lfdpr_ctx* ctx) {
   std::swap(ctx->d_points, o.d_points);
   std::swap(ctx->d_rows, o.d_rows);
   std::swap(ctx->d_pbox, o.d_pbox);
+  std::swap(ctx->d_prows, o.d_prows);
   std::swap(ctx->d_tris, o.d_tris);
   std::swap(ctx->d_counts, o.d_counts);
   std::swap(ctx->d_offsets, o.d_offsets);
@@ -244,25 +262,74 @@ void swap_frame_buffers(lfdpr_ctx* ctx) {
   std::swap(ctx->d_stats, o.d_stats);
   std::swap(ctx->d_tm, o.d_tm);
   std::swap(ctx->d_pmat, o.d_pmat);
+  std::swap(ctx->d_qentries, o.d_qentries);
+  std::swap(ctx->d_qband, o.d_qband);
+  std::swap(ctx->q_entry_cap, o.q_entry_cap);
   std::swap(ctx->last_pbr, o.last_pbr);
   ctx->slot ^= 1;
 }
 
 int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt);
 
+constexpr int kQBandCap = 4096;  // bands per frame (H <= 4096)
+
+// The quilt tile for the context's rig: the shape asked for, clipped to the
+// rig, or the automatic one (4 rows, else 2, else 1, as long as at least
+// min(8, views) views fit; the views spread evenly over the subsets).  False
+// when the keys do not fit the device's LDS.
+bool quilt_shape(const lfdpr_ctx* ctx, int& rows, int& views) {
+  const Rig& rg = ctx->rig;
+  auto fits = [&](int r, int v) { return quilt_lds_bytes(r, v, rg.W, rg.H) <= (size_t)ctx->max_lds; };
+  if (ctx->quilt_rows > 0) {
+    rows = std::min(ctx->quilt_rows, rg.H);
+    views = std::min(ctx->quilt_views, rg.n_views);
+    return fits(rows, views);
+  }
+  for (int r : {4, 2, 1}) {
+    if (r > rg.H && r > 1) continue;
+    int vmax = 0;
+    while (vmax < rg.n_views && fits(r, vmax + 1)) ++vmax;
+    if (vmax >= std::min(8, rg.n_views) || (r == 1 && vmax >= 1)) {
+      const int subsets = (rg.n_views + vmax - 1) / vmax;
+      rows = r;
+      views = (rg.n_views + subsets - 1) / subsets;
+      return true;
+    }
+  }
+  return false;
+}
+
+// Band lists sized for the context's point capacity: twice as many entries
+// as points unless set (a frame that needs more is splatted per point).
+int ensure_quilt_buffers(lfdpr_ctx* ctx) {
+  const int64_t ecap = ctx->quilt_cap_req > 0 ? ctx->quilt_cap_req : 2 * ctx->cap + 65536;
+  if (ctx->d_qentries && ctx->q_entry_cap == ecap) return LFDPR_OK;
+  if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
+  dfree(ctx->d_qentries);
+  dfree(ctx->d_qband);
+  ctx->q_entry_cap = 0;
+  if (dalloc(ctx->d_qentries, (size_t)ecap) != hipSuccess || dalloc(ctx->d_qband, (size_t)(4 * kQBandCap + 8)) != hipSuccess)
+    return fail(ctx, LFDPR_ENOMEM, "quilt band lists");
+  if (hipMemset(ctx->d_qband, 0, (4 * kQBandCap + 8) * sizeof(uint32_t)) != hipSuccess)
+    return fail(ctx, LFDPR_EDEVICE, "clearing the quilt band counts");
+  ctx->q_entry_cap = ecap;
+  return LFDPR_OK;
+}
+
 // Per-frame buffers of the set in the context's fields, sized for a frame of
 // nt triangles (material buffers only for physically based shading).
 int prepare_frame_buffers(lfdpr_ctx* ctx, int64_t nt, bool pbr) {
   int rc = ensure_tri_buffers(ctx, nt);
   if (rc) return rc;
-  if (!ctx->d_points || !ctx->d_rows || !ctx->d_pbox || ctx->points_alloc != ctx->cap) {
+  if (!ctx->d_points || !ctx->d_rows || !ctx->d_pbox || !ctx->d_prows || ctx->points_alloc != ctx->cap) {
     if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
     dfree(ctx->d_points);
     dfree(ctx->d_rows);
     dfree(ctx->d_pbox);
+    dfree(ctx->d_prows);
     ctx->points_alloc = 0;
     if (dalloc(ctx->d_points, (size_t)ctx->cap) != hipSuccess || dalloc(ctx->d_rows, (size_t)ctx->cap) != hipSuccess ||
-        dalloc(ctx->d_pbox, (size_t)ctx->cap) != hipSuccess)
+        dalloc(ctx->d_pbox, (size_t)ctx->cap) != hipSuccess || dalloc(ctx->d_prows, (size_t)ctx->cap) != hipSuccess)
       return fail(ctx, LFDPR_ENOMEM, "point buffers");
     ctx->points_alloc = ctx->cap;
   }
@@ -434,6 +501,9 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
   ctx->scratch = scratch_on(device);  // null: lfdpr_render_frame_noalloc reports LFDPR_EDEVICE
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    ctx->max_lds = lds;
   if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess || dalloc(ctx->d_item1, 1) != hipSuccess) {
     dfree(ctx->d_stats);
     delete ctx;
@@ -468,6 +538,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
     dfree(o.d_points);
     dfree(o.d_rows);
     dfree(o.d_pbox);
+    dfree(o.d_prows);
     dfree(o.d_tris);
     dfree(o.d_counts);
     dfree(o.d_offsets);
@@ -478,6 +549,8 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
     dfree(o.d_stats);
     dfree(o.d_tm);
     dfree(o.d_pmat);
+    dfree(o.d_qentries);
+    dfree(o.d_qband);
   }
   for (int k = 0; k < 2; ++k) {
     if (ctx->ev_emitted[k]) (void)hipEventDestroy(ctx->ev_emitted[k]);
@@ -491,6 +564,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_points);
   dfree(ctx->d_rows);
   dfree(ctx->d_pbox);
+  dfree(ctx->d_prows);
   dfree(ctx->d_tris);
   dfree(ctx->d_keys);
   dfree(ctx->d_acnt);
@@ -506,6 +580,8 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
   dfree(ctx->d_item1);
   dfree(ctx->d_tm);
   dfree(ctx->d_pmat);
+  dfree(ctx->d_qentries);
+  dfree(ctx->d_qband);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
   return LFDPR_OK;
@@ -671,9 +747,10 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
     dfree(ctx->d_points);
     dfree(ctx->d_rows);
     dfree(ctx->d_pbox);
+    dfree(ctx->d_prows);
     ctx->cap = ctx->points_alloc = 0;
     if (dalloc(ctx->d_points, (size_t)cap) != hipSuccess || dalloc(ctx->d_rows, (size_t)cap) != hipSuccess ||
-        dalloc(ctx->d_pbox, (size_t)cap) != hipSuccess)
+        dalloc(ctx->d_pbox, (size_t)cap) != hipSuccess || dalloc(ctx->d_prows, (size_t)cap) != hipSuccess)
       return fail(ctx, LFDPR_ENOMEM, "point buffers");
     ctx->cap = ctx->points_alloc = cap;
   }
@@ -681,6 +758,7 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
     dfree(ctx->other.d_points);
     dfree(ctx->other.d_rows);
     dfree(ctx->other.d_pbox);
+    dfree(ctx->other.d_prows);
     ctx->other.points_alloc = 0;
   }
   if (nkeys != ctx->n_keys || !ctx->d_keys) {
@@ -708,8 +786,25 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* v) {
 
 int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order) {
   if (!ctx) return LFDPR_EINVAL;
-  if (order != LFDPR_SPLAT_TRIANGLE_VIEW && order != LFDPR_SPLAT_POINT) return fail(ctx, LFDPR_EINVAL, "unknown splat order");
+  if (order != LFDPR_SPLAT_TRIANGLE_VIEW && order != LFDPR_SPLAT_POINT && order != LFDPR_SPLAT_QUILT)
+    return fail(ctx, LFDPR_EINVAL, "unknown splat order");
   ctx->splat_order = order;
+  return LFDPR_OK;
+}
+
+int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views) {
+  if (!ctx) return LFDPR_EINVAL;
+  if (!((rows == 0 && views == 0) || (rows >= 1 && rows <= 4096 && views >= 1 && views <= 1024)))
+    return fail(ctx, LFDPR_EINVAL, "quilt tile: rows in [1, 4096] and views in [1, 1024], or both 0");
+  ctx->quilt_rows = rows;
+  ctx->quilt_views = views;
+  return LFDPR_OK;
+}
+
+int lfdpr_set_quilt_capacity(lfdpr_ctx* ctx, int64_t entries) {
+  if (!ctx) return LFDPR_EINVAL;
+  if (entries < 0 || entries > 0xFFFFFFFFll) return fail(ctx, LFDPR_EINVAL, "quilt capacity in [0, 2^32 - 1]");
+  ctx->quilt_cap_req = entries;
   return LFDPR_OK;
 }
 
@@ -749,10 +844,14 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   const bool pbr = ctx->shading.mode == LFDPR_SHADE_PBR;
   if (pbr && s.nt > 0 && !s.mat) return fail(ctx, LFDPR_ESTATE, "physically based shading needs lfdpr_scene_set_materials");
   HIPOK(hipSetDevice(ctx->device));
+  const bool quilt = ctx->splat_order == LFDPR_SPLAT_QUILT;
+  int qrows = 0, qviews = 0;
+  if (quilt && !quilt_shape(ctx, qrows, qviews)) return fail(ctx, LFDPR_EINVAL, "quilt tile does not fit the device's LDS");
   // two frames in flight: this frame takes the other set of per-frame buffers
   const bool piped = ctx->frames_in_flight == 2;
   if (piped) swap_frame_buffers(ctx);
   int rc = prepare_frame_buffers(ctx, s.nt, pbr);
+  if (!rc && quilt) rc = ensure_quilt_buffers(ctx);
   if (rc) {
     if (piped) swap_frame_buffers(ctx);
     return rc;
@@ -823,16 +922,36 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   const bool tv = !pbr && ctx->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW;
   ea.rec = ctx->d_rec;
   ea.rows = tv ? ctx->d_rows : nullptr;
-  ea.pbox = tv ? ctx->d_pbox : nullptr;
+  ea.pbox = tv || quilt ? ctx->d_pbox : nullptr;
+  ea.prows = quilt ? ctx->d_prows : nullptr;
   ea.tris = tv ? ctx->d_tris : nullptr;
   ea.n_tris = ctx->d_stats + STAT_EMITTING;
   launch_emit(ea, ctx->splat_blocks, gen);
   hipEvent_t e3 = mark_on(ctx, gen);
+  QuiltBinArgs qa{};
+  if (quilt) {
+    // the quilt's band lists, built with the point generation
+    uint32_t* qb = ctx->d_qband;
+    qa.n_points = ctx->d_stats + STAT_TOTAL;
+    qa.cap = ctx->cap;
+    qa.prows = ctx->d_prows;
+    qa.rows = qrows;
+    qa.bands = (ctx->rig.H + qrows - 1) / qrows;
+    qa.band_cnt = qb;
+    qa.band_off = qb + kQBandCap;
+    qa.band_cur = qb + 2 * kQBandCap + 1;
+    qa.order = qb + 3 * kQBandCap + 1;
+    qa.entries = ctx->d_qentries;
+    qa.entry_cap = ctx->q_entry_cap;
+    qa.state = qb + 4 * kQBandCap + 1;
+    launch_quilt_bin(qa, gen);
+  }
+  hipEvent_t ebin = quilt ? mark_on(ctx, gen) : e3;
   if (piped) {
     HIPOK(hipEventRecord(ctx->ev_emitted[sl], gen));
     HIPOK(hipStreamWaitEvent(st, ctx->ev_emitted[sl], 0));
   }
-  hipEvent_t e3s = piped ? mark(ctx) : e3;
+  hipEvent_t e3s = piped ? mark(ctx) : ebin;
   SplatArgs pa{};
   pa.items = ctx->d_item1;
   pa.n_items = 1;
@@ -855,19 +974,47 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   const lfdpr_shading& sh = ctx->shading;
   pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
                   sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
-  launch_splat(pa, ctx->splat_blocks, st);
-  ctx->last_order = pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT;
+  const uint32_t* qstate = nullptr;
+  if (quilt) {
+    // the tiles, which write the views; the point splat and the resolve
+    // below run only if the band lists overflowed
+    SplatArgs qp = pa;
+    qp.pbox = ctx->d_pbox;
+    qp.q_entries = qa.entries;
+    qp.q_band_off = qa.band_off;
+    qp.q_order = qa.order;
+    qp.q_state = qa.state;
+    qp.q_rows = qrows;
+    qp.q_views = qviews;
+    qp.q_bands = qa.bands;
+    qp.q_subsets = (ctx->rig.n_views + qviews - 1) / qviews;
+    // two tiles per CU when their LDS allows (the device's per-workgroup
+    // figure is the CU's LDS on this architecture)
+    qp.q_block = 2 * quilt_lds_bytes(qrows, qviews, ctx->rig.W, ctx->rig.H) <= (size_t)ctx->max_lds ? 512 : 1024;
+    qp.out_rgba = views;
+    qp.out_depth = depth;
+    HIPOK(launch_splat_quilt(qp, st));
+    qstate = qa.state;
+    pa.gate = qstate;
+  }
+  // under the quilt this is the overflow fallback, which nearly always exits at once: a small grid
+  launch_splat(pa, quilt ? 256 : ctx->splat_blocks, st);
+  ctx->last_order = quilt ? LFDPR_SPLAT_QUILT : (pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT);
+  ctx->last_qrows = qrows;
+  ctx->last_qviews = qviews;
+  hipEvent_t e4 = mark(ctx);
+  launch_resolve(ctx->d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st, qstate);
+  hipEvent_t e5 = mark(ctx);
   if (piped) {
+    // after the resolve, which reads this set's overflow flag under the quilt
     HIPOK(hipEventRecord(ctx->ev_splatted[sl], st));
     ctx->splatted_pending[sl] = true;
   }
-  hipEvent_t e4 = mark(ctx);
-  launch_resolve(ctx->d_keys, 1, ctx->rig.n_views, ctx->rig.H, ctx->rig.W, ctx->key_layout, views, depth, st);
-  hipEvent_t e5 = mark(ctx);
   HIPOK(hipGetLastError());
   stage(ctx, 0, e0, e1);
   stage(ctx, 1, e1, e2);
   stage(ctx, 2, e2, e3);
+  if (quilt) stage(ctx, 7, e3, ebin);
   stage(ctx, 3, e3s, e4);
   stage(ctx, 4, e4, e5);
   ctx->last_nt = s.nt;
@@ -1041,6 +1188,15 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   out->splat_order = ctx->last_order;
   out->covered_px = ctx->last_order == LFDPR_SPLAT_TRIANGLE_VIEW ? (int64_t)st[STAT_COVERED] : -1;
   out->missed_px = out->covered_px >= 0 ? out->covered_px - out->written_px : -1;
+  out->quilt_entries = -1;
+  if (ctx->last_order == LFDPR_SPLAT_QUILT) {
+    uint32_t qs[2];
+    HIPOK(hipMemcpy(qs, ctx->d_qband + 4 * kQBandCap + 1, sizeof qs, hipMemcpyDeviceToHost));
+    out->quilt_rows = ctx->last_qrows;
+    out->quilt_views = ctx->last_qviews;
+    out->quilt_entries = (int64_t)qs[1];
+    if (qs[0]) out->splat_order = LFDPR_SPLAT_POINT;  // the lists overflowed: splatted per point
+  }
   out->capacity = ctx->cap;
   out->point_overflow = out->points > ctx->cap ? 1 : 0;
   out->n_views = ctx->rig.n_views;
@@ -1663,6 +1819,7 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
   out->splat_order = b->last_order;
   out->covered_px = b->last_order == LFDPR_SPLAT_TRIANGLE_VIEW ? (int64_t)st[STAT_COVERED] : -1;
   out->missed_px = out->covered_px >= 0 ? out->covered_px - out->written_px : -1;
+  out->quilt_entries = -1;
   out->capacity = b->cap;
   out->point_overflow = out->points > b->cap ? 1 : 0;
   out->n_views = b->table_rig.n_views;
@@ -1697,6 +1854,7 @@ int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, l
       e.splat_blocks = kBlocks[bi];
       e.key_layout = layout;
       e.ms = ms / 3.0f;
+      e.splat_order = b->last_order;
       if (e.ms < best) {
         best = e.ms;
         res->best = res->n - 1;
@@ -1713,38 +1871,77 @@ int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, l
 int lfdpr_autotune(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, lfdpr_tune_result* res) {
   if (!ctx || !model || !views || !res) return fail(ctx, LFDPR_EINVAL, "null argument");
   static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
+  static const int kQuiltRows[] = {1, 2, 4, 8};
+  // candidates: the per-point (or per triangle-view) order under every launch
+  // shape and key layout, then the quilt under each band height with the most
+  // views that fit
+  struct Cand {
+    int order, blocks, layout, qrows, qviews;
+  };
+  std::vector<Cand> cands;
+  const int base_order = ctx->splat_order == LFDPR_SPLAT_QUILT ? LFDPR_SPLAT_POINT : ctx->splat_order;
+  for (int layout = 0; layout < 2; ++layout)
+    for (int blocks : kBlocks) cands.push_back({base_order, blocks, layout, 0, 0});
+  if (ctx->views_set)
+    for (int r : kQuiltRows) {
+      if (r > ctx->rig.H) continue;
+      int v = 0;
+      while (v < ctx->rig.n_views && quilt_lds_bytes(r, v + 1, ctx->rig.W, ctx->rig.H) <= (size_t)ctx->max_lds) ++v;
+      if (v == 0) continue;
+      const int subsets = (ctx->rig.n_views + v - 1) / v;
+      cands.push_back({LFDPR_SPLAT_QUILT, ctx->splat_blocks, ctx->key_layout, r, (ctx->rig.n_views + subsets - 1) / subsets});
+    }
+  const int saved[5] = {ctx->splat_order, ctx->splat_blocks, ctx->key_layout, ctx->quilt_rows, ctx->quilt_views};
   hipEvent_t t0, t1;
   HIPOK(hipEventCreate(&t0));
   HIPOK(hipEventCreate(&t1));
   std::memset(res, 0, sizeof *res);
   float best = INFINITY;
   int rc = LFDPR_OK;
-  for (int layout = 0; layout < 2 && !rc; ++layout)
-    for (int bi = 0; bi < 5 && !rc; ++bi) {
-      ctx->splat_blocks = kBlocks[bi];
-      ctx->key_layout = layout;
-      for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
-      if (rc) break;
-      (void)hipEventRecord(t0, ctx->stream);
-      for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
-      (void)hipEventRecord(t1, ctx->stream);
-      (void)hipEventSynchronize(t1);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      lfdpr_tune_entry& e = res->entries[res->n++];
-      e.splat_blocks = kBlocks[bi];
-      e.key_layout = layout;
-      e.ms = ms / 3.0f;
-      if (e.ms < best) {
-        best = e.ms;
-        res->best = res->n - 1;
-      }
+  for (const Cand& c : cands) {
+    if (res->n >= (int)(sizeof res->entries / sizeof res->entries[0])) break;
+    ctx->splat_order = c.order;
+    ctx->splat_blocks = c.blocks;
+    ctx->key_layout = c.layout;
+    ctx->quilt_rows = c.qrows;
+    ctx->quilt_views = c.qviews;
+    for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
+    if (rc) break;
+    (void)hipEventRecord(t0, ctx->stream);
+    for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_render_frame(ctx, scene_id, model, views, nullptr);
+    (void)hipEventRecord(t1, ctx->stream);
+    (void)hipEventSynchronize(t1);
+    if (rc) break;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    lfdpr_tune_entry& e = res->entries[res->n++];
+    e.splat_blocks = c.blocks;
+    e.key_layout = c.layout;
+    e.ms = ms / 3.0f;
+    e.splat_order = c.order;
+    e.quilt_rows = c.qrows;
+    e.quilt_views = c.qviews;
+    if (e.ms < best) {
+      best = e.ms;
+      res->best = res->n - 1;
     }
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  if (rc) return rc;
-  ctx->splat_blocks = res->entries[res->best].splat_blocks;
-  ctx->key_layout = res->entries[res->best].key_layout;
+  if (rc || res->n == 0) {
+    ctx->splat_order = saved[0];
+    ctx->splat_blocks = saved[1];
+    ctx->key_layout = saved[2];
+    ctx->quilt_rows = saved[3];
+    ctx->quilt_views = saved[4];
+    return rc ? rc : fail(ctx, LFDPR_ESTATE, "no candidate ran");
+  }
+  const lfdpr_tune_entry& b = res->entries[res->best];
+  ctx->splat_order = b.splat_order;
+  ctx->splat_blocks = b.splat_blocks;
+  ctx->key_layout = b.key_layout;
+  ctx->quilt_rows = b.quilt_rows;
+  ctx->quilt_views = b.quilt_views;
   return LFDPR_OK;
 }
 

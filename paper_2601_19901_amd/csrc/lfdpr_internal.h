@@ -71,6 +71,9 @@ struct EmitArgs {
   PointBox* pbox;            // per point
   uint32_t* tris;            // triangles with points (any order) and their number
   uint64_t* n_tris;
+  // row-band quilt: per point the pixel rows its splat can write in any view
+  // (first | last << 16, or ~0 for none); null otherwise
+  uint32_t* prows;
 };
 
 struct SplatArgs {
@@ -95,6 +98,36 @@ struct SplatArgs {
   const uint32_t* tris;
   const uint64_t* n_tris;
   int64_t nt;                // triangles of the launch (capacity of tris)
+  // point-major splat: runs only when gate is null or *gate != 0 (the
+  // quilt's fallback when its band lists overflowed)
+  const uint32_t* gate;
+  // row-band quilt (k_splat_quilt): per-point splat rectangles in pbox, the
+  // band lists, and the views it writes directly
+  const uint32_t* q_entries;   // point indices grouped by band
+  const uint32_t* q_band_off;  // q_bands + 1 offsets into q_entries
+  const uint32_t* q_order;     // bands by decreasing number of entries
+  const uint32_t* q_state;     // [0] != 0: the lists overflowed, the point splat takes the frame
+  int32_t q_rows, q_views, q_bands, q_subsets;  // tile: q_rows rows x q_views views x W
+  int32_t q_block;             // threads per quilt workgroup: 1024, or 512 (two tiles per CU)
+  uint32_t* out_rgba;          // the views, [view][y][x]
+  float* out_depth;            // optional, [view][y][x]
+};
+
+// Band lists of the row-band quilt: every point goes to each band of q_rows
+// pixel rows that its splat can write in some view (its rows do not depend
+// on the eye offset).
+struct QuiltBinArgs {
+  const uint64_t* n_points;  // device count (total emitted)
+  int64_t cap;
+  const uint32_t* prows;     // per point: first row | last row << 16, or ~0 (no rows)
+  int32_t rows, bands;       // rows per band, bands
+  uint32_t* band_cnt;  // entries per band (zero on entry; left zero)
+  uint32_t* band_off;  // bands + 1 exclusive offsets
+  uint32_t* band_cur;  // scatter cursors
+  uint32_t* order;     // bands by decreasing entries, ties by band
+  uint32_t* entries;
+  int64_t entry_cap;
+  uint32_t* state;     // [0]: 1 when the entries exceed entry_cap; [1]: entries
 };
 
 struct InterleaveArgs {
@@ -124,8 +157,13 @@ void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_
                  hipStream_t s);
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s);
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
+// the quilt: band lists (bins), then one workgroup per (band, view subset)
+// tile in decreasing band size; the tile's LDS bytes
+size_t quilt_lds_bytes(int32_t rows, int32_t views, int32_t W, int32_t H);
+void launch_quilt_bin(const QuiltBinArgs& a, hipStream_t s);
+hipError_t launch_splat_quilt(const SplatArgs& a, hipStream_t s);
 void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,
-                    uint32_t* rgba, float* depth, hipStream_t s);
+                    uint32_t* rgba, float* depth, hipStream_t s, const uint32_t* gate = nullptr);
 void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_stride, int64_t panel_stride, hipStream_t s);
 void launch_interleave(const InterleaveArgs& a, hipStream_t s);
 void launch_angular_filter(const AngularArgs& a, hipStream_t s);

@@ -510,8 +510,28 @@ __device__ __forceinline__ void splat_corners(const Rig& rg, const TriRec& T, in
   }
 }
 
+// Rows that splat_point can write for a point in any view: the triangle's rows
+// (guard band, the whole triangle above or below the view) met with the splat
+// rectangle's rows `rows` (PointBox).  False when none.
+__device__ __forceinline__ bool quilt_point_rows(int32_t H, const TriRec& T, int32_t rows, int32_t& r0, int32_t& r1) {
+  if (!(fabsf(T.y0) < kGuard) || !(fabsf(T.y1) < kGuard) || !(fabsf(T.y2) < kGuard)) return false;
+  const int32_t H8 = 256 * H;
+  const int32_t qy0 = (int32_t)rintf(T.y0 * 256.0f), qy1 = (int32_t)rintf(T.y1 * 256.0f),
+                qy2 = (int32_t)rintf(T.y2 * 256.0f);
+  if ((qy0 < 0 && qy1 < 0 && qy2 < 0) || (qy0 > H8 && qy1 > H8 && qy2 > H8)) return false;
+  const int32_t ymin = min(qy0, min(qy1, qy2)), ymax = max(qy0, max(qy1, qy2));
+  r0 = max(0, -((128 - ymin) >> 8));
+  r1 = min(H - 1, (ymax - 128) >> 8);
+  if (rows != kAllRows) {
+    r0 = max(r0, (int32_t)(int16_t)(rows & 0xFFFF));
+    r1 = min(r1, (int32_t)(int16_t)((uint32_t)rows >> 16));
+  }
+  return r0 <= r1;
+}
+
 // Per point: UV at the cell centre and the two mip fetches (Eqs. 6-7); for the
-// triangle-major splat also the point's splat rectangle (PointBox).
+// triangle-major splat and the quilt also the point's splat rectangle
+// (PointBox), for the quilt the pixel rows its splat can write.
 __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -558,6 +578,10 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
       B.tvmin = tv.x;
       B.tvmax = tv.y;
       a.pbox[p] = B;
+      if (a.prows) {
+        int32_t r0, r1;
+        a.prows[p] = quilt_point_rows(it.rig.H, T, B.rows, r0, r1) ? (uint32_t)r0 | ((uint32_t)r1 << 16) : ~0u;
+      }
     }
     if (a.tm) {
       // physically based mode: normal map (RGBA8) and the R bytes of the
@@ -608,6 +632,21 @@ __device__ __forceinline__ void key_min(uint64_t* p, uint64_t v) {
   __hip_atomic_fetch_min((global_u64*)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// 64-bit depth-test update of a key held in LDS (a quilt tile).
+__device__ __forceinline__ void lds_key_min(uint64_t* p, uint64_t v) {
+  typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+  __hip_atomic_fetch_min((lds_u64*)p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// One tile of the row-band quilt: views [r_lo, r_hi) and rows [y_lo, y_hi] of
+// every view, all W columns, as keys[((r - r_lo) * rows + (y - y_lo)) * W + x]
+// in LDS; `box` is the point's splat rectangle written at emission.
+struct QuiltTile {
+  uint64_t* keys;
+  int32_t r_lo, r_hi, y_lo, y_hi, rows;
+  const PointBox* box;
+};
+
 // Element i (wave-uniform) of a table that no kernel of the launch writes, as a
 // scalar-cache read straight into a scalar register.
 __device__ __forceinline__ float table_f32(const float* p, int i) {
@@ -621,10 +660,14 @@ __device__ __forceinline__ float uniform_f32(float x) {
 
 // One point against every view of its item's rig; `item` is wave-uniform.
 // kPBR: the colour is shaded (material record tm[tri], point words pm).
-template <bool kPBR>
+// kQuilt: only the views and rows of tile *qt, keys in its LDS; the splat
+// rectangle's corners, rows and cell-centre depth come from the point's
+// PointBox (the same values, computed at emission).
+template <bool kPBR, bool kQuilt = false>
 __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, const TriRec& T, uint32_t flags,
                                             int32_t i, int32_t j, const float* tx, const float* ty,
-                                            const SplatArgs& a, uint64_t p, uint32_t& written) {
+                                            const SplatArgs& a, uint64_t p, uint32_t& written,
+                                            const QuiltTile* qt = nullptr) {
   const int64_t vpx = (int64_t)item.rig.W * item.rig.H;
   const int32_t H8 = 256 * item.rig.H, W8 = 256 * item.rig.W;
   const Rig& rg = item.rig;
@@ -642,20 +685,44 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   if (Y0 > Y1) return;
   // splat box corners (row-end extended cell), projected except for the eye offset
   float cA[4], cC[4];
-  float ymn, ymx;
   bool full;
-  splat_corners(rg, T, i, j, flags, cA, cC, ymn, ymx, full);
   int32_t by0 = Y0, by1 = Y1;
-  if (!full) {
-    int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
-    by0 = max(r0, by0);
-    by1 = min(r1, by1);
+  if constexpr (kQuilt) {
+    // the stored rows are clamped to [-1, H], which leaves their intersection
+    // with [Y0, Y1] (inside [0, H-1]) unchanged or empty as before
+    const PointBox& B = *qt->box;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cA[k] = B.cA[k];
+      cC[k] = B.cC[k];
+    }
+    full = B.rows == kAllRows;
+    if (!full) {
+      by0 = max((int32_t)(int16_t)(B.rows & 0xFFFF), by0);
+      by1 = min((int32_t)(int16_t)((uint32_t)B.rows >> 16), by1);
+    }
+    by0 = max(by0, qt->y_lo);
+    by1 = min(by1, qt->y_hi);
+  } else {
+    float ymn, ymx;
+    splat_corners(rg, T, i, j, flags, cA, cC, ymn, ymx, full);
+    if (!full) {
+      int32_t r0 = (int32_t)ceilf(clamp_big(ymn - 0.515625f)), r1 = (int32_t)floorf(clamp_big(ymx - 0.484375f));
+      by0 = max(r0, by0);
+      by1 = min(r1, by1);
+    }
   }
   if (by0 > by1) return;
   // cell-centre terms of Eqs. 8-9 and the ownership bounds
-  const float cs = (float)i / T.sx, ct = (float)j / T.sy;
-  const float Zc = (T.p0z + cs * T.uz) + ct * T.wz;
-  const float Zc3 = (Zc * Zc) * Zc;
+  float cs = 0.0f, ct = 0.0f, Zc = 0.0f, Zc3;
+  if (kQuilt && !kPBR) {
+    Zc3 = qt->box->zc3;
+  } else {
+    cs = (float)i / T.sx;
+    ct = (float)j / T.sy;
+    Zc = (T.p0z + cs * T.uz) + ct * T.wz;
+    Zc3 = (Zc * Zc) * Zc;
+  }
   F3 pc{0.0f, 0.0f, Zc}, Tf{0.0f, 0.0f, 0.0f}, Bf{0.0f, 0.0f, 0.0f};
   uint4 pm{0u, 0u, 0u, 0u};
   if constexpr (kPBR) {
@@ -674,10 +741,11 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
   const uint32_t lo02 = pt.tvmin & 0x00FF00FFu, lo13 = (pt.tvmin >> 8) & 0x00FF00FFu;
   const uint32_t hi02 = pt.tvmax & 0x00FF00FFu, hi13 = (pt.tvmax >> 8) & 0x00FF00FFu;
   const float p0y2 = T.p0y * T.p0y, p0z2 = T.p0z * T.p0z;
-  float b_next = table_f32(rg.eye, 0);  // the next view's eye offset, one iteration ahead
-  for (int r = 0; r < rg.n_views; ++r) {
+  const int r_begin = kQuilt ? qt->r_lo : 0, r_end = kQuilt ? qt->r_hi : rg.n_views;
+  float b_next = table_f32(rg.eye, r_begin);  // the next view's eye offset, one iteration ahead
+  for (int r = r_begin; r < r_end; ++r) {
     const float b = b_next;
-    if (r + 1 < rg.n_views) b_next = table_f32(rg.eye, r + 1);
+    if (r + 1 < r_end) b_next = table_f32(rg.eye, r + 1);
     const float delta = T.h - T.nx * b;
     if (!faces_eye(T.p0x, p0y2, p0z2, delta, b)) continue;
     // splat box columns first: empty for about a third of the (point, view) pairs
@@ -709,7 +777,7 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
     const int32_t xmin = min(qx[0], min(qx[1], qx[2])), xmax = max(qx[0], max(qx[1], qx[2]));
     const int32_t bx0 = max(cbx0, -((128 - xmin) >> 8));
     const int32_t bx1 = min(cbx1, (xmax - 128) >> 8);
-    const int32_t ry0 = full ? Y0 : by0, ry1 = full ? Y1 : by1;
+    const int32_t ry0 = kQuilt ? by0 : (full ? Y0 : by0), ry1 = kQuilt ? by1 : (full ? Y1 : by1);
     if (bx0 > bx1 || ry0 > ry1) continue;
     // colour of this point in this view (Eqs. 8-9)
     const float ad = fabsf(delta);
@@ -746,6 +814,7 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
       bias[e] = (dy > 0 || (dy == 0 && dx > 0)) ? 0.5 : 0.0;
     }
     uint64_t* kv = keys + (rowmajor ? (int64_t)r * rg.W : (int64_t)r * vpx);
+    const int32_t kq = kQuilt ? ((r - qt->r_lo) * qt->rows - qt->y_lo) * rg.W : 0;  // tile key of (y, x): kq + y*W + x
     const int32_t pxq0 = 256 * bx0 + 128, pyq0 = 256 * ry0 + 128;
     // edge functions at (bx0, ry0), stepped by whole pixels (all values are
     // integers + 0.5 below 2^51, so every step is exact)
@@ -774,7 +843,10 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
         const float tv = T.sy * (Z * wr + cw) + 0.5f;
         const bool own = (oilo || sv >= fi0) && (oihi || sv < fi1) && (ojlo || tv >= fj0) && (ojhi || tv < fj1);
         if (own) {
-          key_min(&kv[(int64_t)y * row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
+          if constexpr (kQuilt)
+            lds_key_min(qt->keys + (kq + y * rg.W + x), ((uint64_t)__float_as_uint(Z) << 32) | col);
+          else
+            key_min(&kv[(int64_t)y * row_stride + x], ((uint64_t)__float_as_uint(Z) << 32) | col);
           ++written;
         }
       }
@@ -789,6 +861,7 @@ __device__ __forceinline__ void splat_point(const Item& item, const Point& pt, c
 // capped, it spills 40 bytes and slows down.
 template <bool kMulti, bool kPBR>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR && !kMulti ? 4 : 1))) k_splat(SplatArgs a) {
+  if (a.gate && *a.gate == 0) return;
   extern __shared__ float ray_tab[];  // W column slopes, then H row slopes
   const Rig& trg = a.table_rig;
   float* tx = ray_tab;
@@ -828,6 +901,220 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR &
   }
   const uint64_t wsum = wave_sum((uint64_t)written);
   if ((threadIdx.x & 63) == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
+}
+
+// ------------------------------------------------------------------ a3: splat, row-band quilt
+//
+// The keys of one tile -- q_rows pixel rows of q_views views, all W columns --
+// stay in LDS while every point whose splat reaches those rows is splatted
+// into them (64-bit ds_min), and the finished tile is written out as the
+// views' RGBA8 (+ depth): the key buffer in HBM is neither updated nor
+// resolved.  The views differ only by a horizontal eye offset (Sec. 3.2), so a
+// point's pixel rows are the same in every view and each point is binned once
+// per frame, into every band of q_rows rows that its splat can reach.  A
+// workgroup takes one tile; tiles are launched by decreasing band size.
+
+constexpr int kQChunk = 4096;  // points per workgroup pass in the band kernels
+// threads of a quilt workgroup: 1024 (16 waves, one tile per CU), or 512 when
+// two tiles fit the CU's LDS (two workgroups of 8 waves, so that one tile's
+// clearing, writing out and last chunks overlap the other's splatting)
+
+// Pass 1: entries per band (a workgroup histogram in LDS, one global add per
+// band it touched).
+__global__ void __launch_bounds__(256) k_qcount(QuiltBinArgs a) {
+  extern __shared__ uint32_t qhist[];
+  for (int k = threadIdx.x; k < a.bands; k += blockDim.x) qhist[k] = 0u;
+  __syncthreads();
+  const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
+  for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += (uint64_t)gridDim.x * kQChunk) {
+    const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
+    for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
+      const uint32_t pr = a.prows[p];
+      if (pr != ~0u)
+        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
+          atomicAdd(&qhist[b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.bands; k += blockDim.x)
+    if (qhist[k]) atomicAdd(&a.band_cnt[k], qhist[k]);
+}
+
+// Pass 2 (one workgroup): band offsets and cursors, the overflow flag, and
+// the bands sorted by decreasing entries (bitonic sort in LDS) so that the
+// largest tiles start first.  Leaves the band counts at zero.
+__global__ void __launch_bounds__(1024) k_qplan(QuiltBinArgs a) {
+  __shared__ uint64_t sk[4096];
+  __shared__ uint64_t wtot[16];
+  const int nb = a.bands, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t c[4];
+  uint64_t t = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = tid * 4 + k;
+    c[k] = b < nb ? a.band_cnt[b] : 0u;
+    t += c[k];
+  }
+  const uint64_t inc = wave_incl_scan(t);
+  if (lane == 63) wtot[wv] = inc;
+  __syncthreads();
+  uint64_t run = inc - t, total = 0;
+  for (int w = 0; w < 16; ++w) {
+    if (w < wv) run += wtot[w];
+    total += wtot[w];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int b = tid * 4 + k;
+    if (b < nb) {
+      const uint32_t o = run < 0xFFFFFFFFull ? (uint32_t)run : 0xFFFFFFFFu;
+      a.band_off[b] = o;
+      a.band_cur[b] = o;
+      a.band_cnt[b] = 0u;
+      sk[b] = ((uint64_t)c[k] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)b);
+    }
+    run += c[k];
+  }
+  if (tid == 0) {
+    const bool over = total > (uint64_t)a.entry_cap;
+    a.band_off[nb] = over ? 0xFFFFFFFFu : (uint32_t)total;
+    a.state[0] = over ? 1u : 0u;
+    a.state[1] = total < 0xFFFFFFFFull ? (uint32_t)total : 0xFFFFFFFFu;
+  }
+  int n2 = 1;
+  while (n2 < nb) n2 <<= 1;
+  for (int b = nb + tid; b < n2; b += blockDim.x) sk[b] = 0ull;  // below every band's key
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < n2; i += blockDim.x) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const uint64_t x = sk[i], y = sk[j];
+          const bool desc = (i & size) == 0;
+          if (desc ? x < y : x > y) {
+            sk[i] = y;
+            sk[j] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int k = tid; k < nb; k += blockDim.x) a.order[k] = 0xFFFFFFFFu - (uint32_t)sk[k];
+}
+
+// Pass 3: the band lists.  A workgroup counts its points' entries per band in
+// LDS, reserves each band's share with one global add, then places them.
+__global__ void __launch_bounds__(256) k_qscatter(QuiltBinArgs a) {
+  if (a.state[0]) return;  // overflow: the point splat takes the frame
+  extern __shared__ uint32_t qsh[];
+  uint32_t* hist = qsh;
+  uint32_t* base = qsh + a.bands;
+  for (int k = threadIdx.x; k < a.bands; k += blockDim.x) hist[k] = 0u;
+  __syncthreads();
+  const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
+  const uint64_t step = (uint64_t)gridDim.x * kQChunk;
+  for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += step) {
+    const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
+    for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
+      const uint32_t pr = a.prows[p];
+      if (pr != ~0u)
+        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
+          atomicAdd(&hist[b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < a.bands; k += blockDim.x)
+    if (hist[k]) {
+      base[k] = atomicAdd(&a.band_cur[k], hist[k]);
+      hist[k] = 0u;
+    }
+  __syncthreads();
+  for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += step) {
+    const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
+    for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
+      const uint32_t pr = a.prows[p];
+      if (pr != ~0u)
+        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
+          a.entries[base[b] + atomicAdd(&hist[b], 1u)] = (uint32_t)p;
+    }
+  }
+}
+
+// One tile per workgroup: clear the keys, splat the band's points into the
+// tile's views and rows, write the tile out.  kPBR: shaded colours.  Held to
+// 128 VGPRs: four waves per SIMD.
+template <bool kPBR, int kBlock>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_splat_quilt(SplatArgs a) {
+  extern __shared__ uint64_t qtile[];  // the tile's keys, then W column and H row ray slopes
+  __shared__ uint32_t qnext;           // next unclaimed entry of the band
+  if (*a.q_state != 0) return;         // overflow: the point splat takes the frame
+  const Rig& trg = a.table_rig;
+  const int32_t W = trg.W, H = trg.H;
+  // Workgroups go to the 8 XCDs round robin (block b on XCD b % 8).  XCD x
+  // takes the bands of rank x, x + 8, ... (ranks by decreasing size, so the
+  // XCDs get equal shares), each band's view subsets on consecutive blocks of
+  // that XCD: the subsets read the same points through one L2.  The grid is
+  // padded to whole rounds of 8 bands; blocks past the last band exit.
+  const uint32_t xcd = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  const uint32_t rank = (k / (uint32_t)a.q_subsets) * 8u + xcd, sub = k % (uint32_t)a.q_subsets;
+  if (rank >= (uint32_t)a.q_bands) return;
+  const int32_t band = (int32_t)a.q_order[rank];
+  QuiltTile qt;
+  qt.keys = qtile;
+  qt.rows = a.q_rows;
+  qt.y_lo = band * a.q_rows;
+  qt.y_hi = min(H - 1, qt.y_lo + a.q_rows - 1);
+  qt.r_lo = (int32_t)sub * a.q_views;
+  qt.r_hi = min(trg.n_views, qt.r_lo + a.q_views);
+  const int32_t nkeys = a.q_rows * a.q_views * W;
+  float* tx = reinterpret_cast<float*>(qtile + nkeys);
+  float* ty = tx + W;
+  for (int32_t k = threadIdx.x; k < nkeys; k += blockDim.x) qtile[k] = ~0ull;
+  for (int k = threadIdx.x; k < W; k += blockDim.x) tx[k] = ((float)k + 0.5f - trg.cx) / trg.fx;
+  for (int k = threadIdx.x; k < H; k += blockDim.x) ty[k] = ((float)k + 0.5f - trg.cy) / trg.fy;
+  if (threadIdx.x == 0) qnext = 0u;
+  __syncthreads();
+  const uint32_t e0 = a.q_band_off[band], e1 = a.q_band_off[band + 1];
+  const Item it0 = load_uniform(a.items);
+  const int lane = threadIdx.x & 63;
+  uint32_t written = 0;
+  // the band's entries in chunks of 64, one chunk per wave at a time, taken
+  // from an LDS counter as the waves free up: the tile ends when its last
+  // chunk does, whatever the per-point work
+  for (;;) {
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&qnext, 64u);
+    c = (uint32_t)__shfl((int)c, 0, 64);
+    if (c >= e1 - e0) break;
+    const uint32_t e = e0 + c + (uint32_t)lane;
+    if (e < e1) {
+      const uint32_t p = a.q_entries[e];
+      const Point pt = a.points[p];
+      const uint32_t tri = pt.tri_flags & 0x0FFFFFFFu, flags = pt.tri_flags >> 28;
+      const int32_t i = (int16_t)(pt.ij & 0xFFFFu), j = (int16_t)(pt.ij >> 16);
+      const TriRec T = a.rec[tri];
+      qt.box = a.pbox + p;
+      splat_point<kPBR, true>(it0, pt, T, flags, i, j, tx, ty, a, p, written, &qt);
+    }
+  }
+  __syncthreads();
+  // the tile as RGBA8 (+ depth): one pixel row of one view per wave at a time
+  const int32_t nrows = qt.y_hi - qt.y_lo + 1, nvt = qt.r_hi - qt.r_lo;
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int32_t q = wv; q < nvt * nrows; q += nw) {
+    const int32_t rv = q / nrows, yy = q - rv * nrows;
+    const uint64_t* src = qtile + (rv * a.q_rows + yy) * W;
+    const int64_t o = ((int64_t)(qt.r_lo + rv) * H + (qt.y_lo + yy)) * W;
+    for (int32_t x = lane; x < W; x += 64) {
+      const uint64_t key = src[x];
+      const bool empty = key == ~0ull;
+      a.out_rgba[o + x] = empty ? 0u : (uint32_t)key;
+      if (a.out_depth) a.out_depth[o + x] = empty ? __uint_as_float(0x7f800000u) : __uint_as_float((uint32_t)(key >> 32));
+    }
+  }
+  const uint64_t wsum = wave_sum((uint64_t)written);
+  if (lane == 0 && wsum) atomicAdd((unsigned long long*)&a.stats[STAT_WRITTEN], (unsigned long long)wsum);
 }
 
 // ------------------------------------------------------------------ a3: splat, triangle-major
@@ -1106,7 +1393,8 @@ __global__ void __launch_bounds__(256) k_splat_tv(SplatArgs a) {
 
 // keys -> RGBA8 (+ depth) in [item][view][y][x] order; keys re-cleared.
 __global__ void k_resolve(uint64_t* __restrict__ keys, int64_t n, int32_t nv, int32_t H, int32_t W, int32_t layout,
-                          uint32_t* __restrict__ rgba, float* __restrict__ depth) {
+                          uint32_t* __restrict__ rgba, float* __restrict__ depth, const uint32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t per_view = (int64_t)W * H, per_item = per_view * nv;
@@ -1324,10 +1612,41 @@ void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
 }
 
 void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,
-                    uint32_t* rgba, float* depth, hipStream_t s) {
+                    uint32_t* rgba, float* depth, hipStream_t s, const uint32_t* gate) {
   const int64_t n = n_items * n_views * (int64_t)H * W;
-  unsigned g = (unsigned)imin(nblk(n, 256), 256 * 64);
-  k_resolve<<<g, 256, 0, s>>>(keys, n, n_views, H, W, key_layout, rgba, depth);
+  // a gated resolve is a fallback that nearly always exits at once: a small grid
+  unsigned g = (unsigned)imin(nblk(n, 256), gate ? 1024 : 256 * 64);
+  k_resolve<<<g, 256, 0, s>>>(keys, n, n_views, H, W, key_layout, rgba, depth, gate);
+}
+
+constexpr size_t kQuiltStaticLds = 16;  // the workgroup's entry counter
+
+size_t quilt_lds_bytes(int32_t rows, int32_t views, int32_t W, int32_t H) {
+  return (size_t)rows * (size_t)views * (size_t)W * 8u + (size_t)(W + H) * 4u + kQuiltStaticLds;
+}
+
+void launch_quilt_bin(const QuiltBinArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)imin(nblk(a.cap, kQChunk), 1024);
+  k_qcount<<<g, 256, sizeof(uint32_t) * (size_t)a.bands, s>>>(a);
+  k_qplan<<<1, 1024, 0, s>>>(a);
+  k_qscatter<<<g, 256, 2 * sizeof(uint32_t) * (size_t)a.bands, s>>>(a);
+}
+
+template <bool kPBR, int kBlock>
+static hipError_t launch_quilt_kernel(const SplatArgs& a, unsigned g, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_splat_quilt<kPBR, kBlock>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  k_splat_quilt<kPBR, kBlock><<<g, kBlock, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat_quilt(const SplatArgs& a, hipStream_t s) {
+  const size_t lds = quilt_lds_bytes(a.q_rows, a.q_views, a.table_rig.W, a.table_rig.H) - kQuiltStaticLds;
+  const unsigned g = (unsigned)((a.q_bands + 7) / 8) * 8u * (unsigned)a.q_subsets;
+  if (a.q_block == 512)
+    return a.tm ? launch_quilt_kernel<true, 512>(a, g, lds, s) : launch_quilt_kernel<false, 512>(a, g, lds, s);
+  return a.tm ? launch_quilt_kernel<true, 1024>(a, g, lds, s) : launch_quilt_kernel<false, 1024>(a, g, lds, s);
 }
 
 void launch_interleave(const InterleaveArgs& a, hipStream_t s) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "liblfdpr.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "lfdpr.h")
 
 LFDPR_OK, LFDPR_EINVAL, LFDPR_ENOMEM, LFDPR_EOVERFLOW, LFDPR_EDEVICE, LFDPR_ESTATE = 0, -1, -2, -3, -4, -5
-SPLAT_POINT, SPLAT_TRIANGLE_VIEW = 0, 1
+SPLAT_POINT, SPLAT_TRIANGLE_VIEW, SPLAT_QUILT = 0, 1, 2
 
 
 class LfdprError(RuntimeError):
@@ -50,7 +50,8 @@ class ShadingParams(C.Structure):
 
 
 class TuneEntry(C.Structure):
-    _fields_ = [("splat_blocks", C.c_int32), ("key_layout", C.c_int32), ("ms", C.c_float)]
+    _fields_ = [("splat_blocks", C.c_int32), ("key_layout", C.c_int32), ("ms", C.c_float),
+                ("splat_order", C.c_int32), ("quilt_rows", C.c_int32), ("quilt_views", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -61,7 +62,8 @@ class Stats(C.Structure):
     _fields_ = [("points", C.c_int64), ("active_tris", C.c_int64), ("point_views", C.c_int64),
                 ("overflow_tris", C.c_int64), ("capacity", C.c_int64), ("point_overflow", C.c_int32),
                 ("n_views", C.c_int32), ("written_px", C.c_int64), ("splat_order", C.c_int32),
-                ("reserved", C.c_int32), ("covered_px", C.c_int64), ("missed_px", C.c_int64)]
+                ("reserved", C.c_int32), ("covered_px", C.c_int64), ("missed_px", C.c_int64),
+                ("quilt_rows", C.c_int32), ("quilt_views", C.c_int32), ("quilt_entries", C.c_int64)]
 
 
 _lib = None
@@ -117,6 +119,8 @@ def signatures():
         "lfdpr_set_views": ([vp, p(ViewParams)], C.c_int),
         "lfdpr_set_lens": ([vp, p(LensParams)], C.c_int),
         "lfdpr_set_splat_order": ([vp, i32], C.c_int),
+        "lfdpr_set_quilt_tile": ([vp, i32, i32], C.c_int),
+        "lfdpr_set_quilt_capacity": ([vp, i64], C.c_int),
         "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
         "lfdpr_render_frame_noalloc": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "lfdpr_reconstruct": ([vp, vp, i32, i32, i32, vp], C.c_int),
@@ -179,7 +183,9 @@ def view_params(vp, point_capacity: int = 0):
 
 def tune_dict(res) -> dict:
     ents = [dict(splat_blocks=res.entries[k].splat_blocks, key_layout=res.entries[k].key_layout,
-                 ms=float(res.entries[k].ms)) for k in range(res.n)]
+                 ms=float(res.entries[k].ms), splat_order=res.entries[k].splat_order,
+                 quilt_rows=res.entries[k].quilt_rows, quilt_views=res.entries[k].quilt_views)
+            for k in range(res.n)]
     return dict(best=ents[res.best], entries=ents)
 
 
@@ -279,8 +285,16 @@ class Renderer:
         self.frames_in_flight = int(n)
 
     def set_splat_order(self, order: int):
-        """SPLAT_POINT (default) or SPLAT_TRIANGLE_VIEW; the same results."""
+        """SPLAT_POINT (default), SPLAT_TRIANGLE_VIEW or SPLAT_QUILT; the same results."""
         self._check(lib().lfdpr_set_splat_order(self.h, int(order)))
+
+    def set_quilt_tile(self, rows: int = 0, views: int = 0):
+        """Tile of the quilt order: pixel rows x views in LDS (0, 0: chosen per rig)."""
+        self._check(lib().lfdpr_set_quilt_tile(self.h, int(rows), int(views)))
+
+    def set_quilt_capacity(self, entries: int = 0):
+        """Band-list entries of the quilt order (0: twice the point capacity + 65536)."""
+        self._check(lib().lfdpr_set_quilt_capacity(self.h, int(entries)))
 
     def autotune(self, sid: int, model: np.ndarray, views) -> dict:
         m = np.ascontiguousarray(model, np.float32).reshape(12)
@@ -395,7 +409,7 @@ class Renderer:
         self._check(lib().lfdpr_copy_counts(self.h, _ptr(buf), nt))
         return buf[:nt].cpu().numpy().view(np.uint32)
 
-    STAGES = ("setup", "scan", "emit", "splat", "resolve", "interleave", "angular_filter")
+    STAGES = ("setup", "scan", "emit", "splat", "resolve", "interleave", "angular_filter", "quilt_bin")
 
     def timing(self, enable: bool):
         self._check(lib().lfdpr_timing(self.h, int(enable)))

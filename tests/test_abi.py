@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     missing = [s for s in lfdpr.declared_symbols() if not hasattr(L, s)]
     assert not missing, missing
     lib = lfdpr.lib()
-    assert lib.lfdpr_abi_version() == 5
+    assert lib.lfdpr_abi_version() == 6
     assert lib.lfdpr_strerror(-3) == b"point capacity exceeded"
     assert lib.lfdpr_strerror(12345) == b"unknown status"
     assert lib.lfdpr_destroy(None) == 0

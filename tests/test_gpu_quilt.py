@@ -1,0 +1,230 @@
+"""The row-band quilt (lfdpr_set_splat_order(LFDPR_SPLAT_QUILT)): the views'
+64-bit keys (Sec. 5.1) resolved in LDS tiles of q_rows pixel rows x q_views
+views, the views written straight from the tiles.  It does the point order's
+(point, view, pixel) work in another grouping, so views, depth and statistics
+must be identical bit for bit: tied to the oracle directly at small sizes and
+through the point order (itself tied to the oracle) at display size, for
+every tile shape, shaded frames, two frames in flight and the per-point
+fallback taken when the band lists overflow."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2601_19901_amd import scenes
+from test_gpu_parity import _log, assert_parity, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+QUILT_KEYS = ("quilt_rows", "quilt_views", "quilt_entries")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _render(R, sid, model, order):
+    R.set_splat_order(order)
+    v, d = R.alloc_views(with_depth=True)
+    R.render_frame(sid, model, v, d)
+    return v.cpu().numpy(), d.cpu().numpy(), R.stats()
+
+
+def _same_as_point(R, sid, model, label, rows=0, views=0):
+    """Quilt frame (tile rows x views; 0, 0 = automatic) against the point
+    order; returns the quilt's (rows, views, entries)."""
+    from paper_2601_19901_amd import lfdpr
+    R.set_quilt_tile(rows, views)
+    vq, dq, sq = _render(R, sid, model, lfdpr.SPLAT_QUILT)
+    vp, dp, sp = _render(R, sid, model, lfdpr.SPLAT_POINT)
+    _log(f"[{label}] quilt {sq}; point {sp}")
+    assert sq.pop("splat_order") == lfdpr.SPLAT_QUILT and sp.pop("splat_order") == lfdpr.SPLAT_POINT
+    q = tuple(sq.pop(k) for k in QUILT_KEYS)
+    assert tuple(sp.pop(k) for k in QUILT_KEYS) == (0, 0, -1)
+    H, nv = R.vp.H, R.vp.V * R.vp.S
+    assert 1 <= q[0] <= H and 1 <= q[1] <= nv and q[2] >= 0
+    if rows:
+        assert q[:2] == (min(rows, H), min(views, nv))
+    assert sq == sp and sp["written_px"] > 0
+    np.testing.assert_array_equal(vq, vp, err_msg=f"{label}: views")
+    np.testing.assert_array_equal(dq.view(np.uint32), dp.view(np.uint32), err_msg=f"{label}: depth")
+    return q
+
+
+@pytest.mark.parametrize("kind,seed,frame,mip", [("tiny", 1, 0, True), ("tiny", 1, 137, True),
+                                                 ("small", 7, 250, True), ("small", 8, 40, False)])
+def test_quilt_matches_the_oracle(torch_cuda, kind, seed, frame, mip):
+    from paper_2601_19901_amd import lfdpr
+    w = {"tiny": scenes.tiny, "small": scenes.small_display}[kind](seed=seed)
+    w.views.mip = mip
+    o = O.render(w.scene, w.views, w.model(frame))
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_splat_order(lfdpr.SPLAT_QUILT)
+    g = run_gpu(R, sid, w, w.model(frame), w.scene.n_tris)
+    assert g["stats"]["splat_order"] == lfdpr.SPLAT_QUILT
+    assert_parity(g, o, w.scene.n_tris, f"quilt {kind} s{seed} f{frame}")
+    assert g["stats"]["written_px"] == o["stats"]["fragments"] - o["stats"]["misses"]
+
+
+@pytest.mark.parametrize("rows,views", [(0, 0), (1, 1), (3, 5), (4, 12), (8, 2), (96, 2), (200, 2), (7, 11)])
+def test_every_tile_shape_agrees_with_the_point_order(torch_cuda, rows, views):
+    """Tiles of one row and one view up to all rows of two views (96 x 96
+    views); band heights that do not divide H and view counts that do not
+    divide V (partial last band and subset); rows beyond the rig are clipped."""
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=11)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    _same_as_point(R, sid, w.model(77), f"small-display tile {rows}x{views}", rows, views)
+
+
+def test_band_entries_shrink_with_taller_bands(torch_cuda):
+    """Each point is listed once per band its splat's rows reach: taller bands
+    list no more entries, and one band over the whole view lists each point
+    with rows at most once."""
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=12)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    ents = []
+    for rows in (1, 2, 4, 8, w.views.H):
+        ents.append(_same_as_point(R, sid, w.model(5), f"entries at {rows} rows", rows, 1)[2])
+    _log(f"band entries at 1, 2, 4, 8, H rows: {ents}")
+    assert all(a >= b for a, b in zip(ents, ents[1:]))
+    assert 0 < ents[-1] <= R.stats()["points"]
+
+
+def test_a_tile_beyond_the_lds_is_refused(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=11)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_splat_order(lfdpr.SPLAT_QUILT)
+    R.set_quilt_tile(96, 12)  # 96 rows x 12 views x 96 columns x 8 B = 864 KiB
+    v, _ = R.alloc_views()
+    with pytest.raises(lfdpr.LfdprError) as e:
+        R.render_frame(sid, w.model(1), v)
+    assert e.value.code == lfdpr.LFDPR_EINVAL
+    R.set_quilt_tile(0, 0)
+    R.render_frame(sid, w.model(1), v)
+    assert R.stats()["splat_order"] == lfdpr.SPLAT_QUILT
+
+
+@pytest.mark.parametrize("S,mip", [(1, False), (4, True)])
+def test_quilt_with_sub_views(torch_cuda, S, mip):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=13, S=S)
+    w.views.mip = mip
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    _same_as_point(R, sid, w.model(300), f"small-display S={S}")
+    _same_as_point(R, sid, w.model(301), f"small-display S={S}, 2 rows x 5 views", 2, 5)
+
+
+def test_quilt_shaded(torch_cuda):
+    """Physically based shading: the shaded colour per (point, view) is the
+    same in a tile as in the point order."""
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.with_pbr(scenes.small_display(seed=14))
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_shading(w.shading)
+    _same_as_point(R, sid, w.model(42), "small-display PBR")
+    _same_as_point(R, sid, w.model(43), "small-display PBR, 1 row x 3 views", 1, 3)
+
+
+def test_overflowed_band_lists_fall_back_to_the_point_order(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=15)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    m = w.model(9)
+    vp, dp, sp = _render(R, sid, m, lfdpr.SPLAT_POINT)
+    R.set_quilt_capacity(1000)
+    vq, dq, sq = _render(R, sid, m, lfdpr.SPLAT_QUILT)
+    _log(f"quilt with 1000 entries: {sq}")
+    assert sq["splat_order"] == lfdpr.SPLAT_POINT and sq["quilt_entries"] > 1000
+    np.testing.assert_array_equal(vq, vp)
+    np.testing.assert_array_equal(dq.view(np.uint32), dp.view(np.uint32))
+    assert sq["written_px"] == sp["written_px"]
+    # the next frame with room again takes the quilt; then overflow once more
+    R.set_quilt_capacity(0)
+    vq2, dq2, sq2 = _render(R, sid, m, lfdpr.SPLAT_QUILT)
+    assert sq2["splat_order"] == lfdpr.SPLAT_QUILT and sq2["quilt_entries"] == sq["quilt_entries"]
+    np.testing.assert_array_equal(vq2, vp)
+    R.set_quilt_capacity(1000)
+    vq3, _, sq3 = _render(R, sid, m, lfdpr.SPLAT_QUILT)
+    assert sq3["splat_order"] == lfdpr.SPLAT_POINT
+    np.testing.assert_array_equal(vq3, vp)
+
+
+def test_quilt_at_display_size(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.display()
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    for f, (rows, views) in ((17, (0, 0)), (600, (2, 16)), (601, (1, 24))):
+        q = _same_as_point(R, sid, w.model(f), f"display-1M frame {f}", rows, views)
+        _log(f"display-1M frame {f}: tile {q[0]} rows x {q[1]} views, {q[2]} entries")
+    # two frames in flight under the quilt against the serial point order
+    R.set_quilt_tile(0, 0)
+    R.set_splat_order(lfdpr.SPLAT_QUILT)
+    R.set_frames_in_flight(2)
+    outs = []
+    for f in (3, 4, 5):
+        v, _ = R.alloc_views()
+        R.render_frame(sid, w.model(f), v)
+        outs.append(v)
+    assert R.stats()["splat_order"] == lfdpr.SPLAT_QUILT
+    R.set_frames_in_flight(1)
+    for f, v in zip((3, 4, 5), outs):
+        vp, _, _ = _render(R, sid, w.model(f), lfdpr.SPLAT_POINT)
+        np.testing.assert_array_equal(v.cpu().numpy(), vp, err_msg=f"pipelined frame {f}")
+
+
+def test_quilt_shaded_at_display_size(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.with_pbr(scenes.display())
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_shading(w.shading)
+    _same_as_point(R, sid, w.model(17), "display-1M PBR frame 17")
+
+
+def test_autotune_takes_the_quilt_into_account(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    w = scenes.small_display(seed=16)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    v, _ = R.alloc_views()
+    res = R.autotune(sid, w.model(3), v)
+    _log(f"autotune best {res['best']}")
+    orders = {e["splat_order"] for e in res["entries"]}
+    assert orders == {lfdpr.SPLAT_POINT, lfdpr.SPLAT_QUILT}
+    assert all((e["quilt_rows"] > 0) == (e["splat_order"] == lfdpr.SPLAT_QUILT) for e in res["entries"])
+    # whatever it kept, the frame equals the point order's
+    v1, d1, s1 = _render_current(R, sid, w.model(4))
+    assert s1["splat_order"] == res["best"]["splat_order"]
+    vp, dp, _ = _render(R, sid, w.model(4), lfdpr.SPLAT_POINT)
+    np.testing.assert_array_equal(v1, vp)
+    np.testing.assert_array_equal(d1.view(np.uint32), dp.view(np.uint32))
+
+
+def _render_current(R, sid, model):
+    v, d = R.alloc_views(with_depth=True)
+    R.render_frame(sid, model, v, d)
+    return v.cpu().numpy(), d.cpu().numpy(), R.stats()
