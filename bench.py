@@ -160,11 +160,17 @@ def profile_traffic(name: str, sources, label: str):
     return float(t.group(1))
 
 
-def splat_traffic(quilt: bool = False):
-    """HBM bytes per k_splat (or k_splat_quilt) launch on display-1M (see
+SPLAT_TRAFFIC_PROFILES = {"display-1M": "display-1M_splat_traffic.md", "display-4M-ss4": "display-4M-ss4_splat_traffic.md"}
+
+
+def splat_traffic(kind: str, kernel: str):
+    """HBM bytes per launch of the splat kernel that ran (k_splat or
+    k_splat_quilt) on a workload with a committed counter summary (see
     profile_traffic)."""
-    return profile_traffic("display-1M_quilt_traffic.md" if quilt else "display-1M_splat_traffic.md",
-                           ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"), "HBM bytes per launch")
+    if kind not in SPLAT_TRAFFIC_PROFILES:
+        return None
+    return profile_traffic(SPLAT_TRAFFIC_PROFILES[kind], ("lfdpr_kernels.hip", "lfdpr_device.h", "lfdpr_internal.h"),
+                           f"HBM bytes per launch of {kernel}")
 
 
 ORDER_NAMES = {0: "point", 1: "triangle-view", 2: "quilt"}
@@ -294,7 +300,7 @@ def run_display(args, torch, lfdpr, scenes, kind: str):
     shape = dict(nt=w.scene.n_tris, views=n_rendered, points=pts / nfr, pixels=n_rendered * w.views.W * w.views.H,
                  out_pixels=w.views.V * w.views.W * w.views.H,
                  panel_px=w.lens.Wp * w.lens.Hp, tris_with_points=act / nfr, written_px=wpx / nfr, quilt=quilt)
-    roof = roofline(st_avg, pv / nfr, shape, splat_traffic(quilt) if kind == "display-1M" else None, pbr)
+    roof = roofline(st_avg, pv / nfr, shape, splat_traffic(kind, "k_splat_quilt" if quilt else "k_splat"), pbr)
     names = {
         "display-1M": "display-1M: 999,168 tris (512^2-quad heightfield + 200 icospheres), 16 RGBA8 2048^2 textures, "
                       "48 views 512x512 (aspect 1.6, 40 deg cone), 2560x1600 lenticular panel, rotating scene",

@@ -83,6 +83,23 @@ def test_frame_roofline_sums_the_larger_bound_per_stage(bench):
     assert r["frac"] == pytest.approx(r["achievable_ms"] / 2.0, abs=1e-4)
 
 
+def test_quilt_frame_roofline(bench):
+    """Under the quilt the splat writes the views from its LDS tiles (points,
+    records and splat rectangles in, 4 B per view pixel out), the resolve
+    stage has nothing to move, and the band lists read each point's row range
+    twice and write an entry."""
+    s = shape(written_px=6.0e6, quilt=True)
+    st = {"setup": 0.3, "splat": 1.4, "resolve": 0.006, "quilt_bin": 0.07}
+    r = bench.roofline(st, 2.0e7, s)
+    assert r["kernel"] == "k_splat_quilt" and r["bound"] == "alu"
+    assert bench.BYTES["splat"](s) == s["points"] * (16 + 112 + 48) + s["pixels"] * 4
+    assert bench.BYTES["resolve"](s) == 0
+    assert bench.BYTES["quilt_bin"](s) == s["points"] * 12
+    f = bench.frame_roofline(st, 2.0e7, s, frame_ms=2.0)
+    assert f["bound_ms"]["resolve"] == 0.0
+    assert f["bound_ms"]["quilt_bin"] == pytest.approx(s["points"] * 12 / 8e12 * 1e3, abs=1e-4)
+
+
 def test_profile_traffic_requires_matching_sources(bench, tmp_path, monkeypatch):
     csrc = tmp_path / "paper_2601_19901_amd" / "csrc"
     csrc.mkdir(parents=True)
@@ -94,6 +111,12 @@ def test_profile_traffic_requires_matching_sources(bench, tmp_path, monkeypatch)
     assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per launch") == 1.5e9
     assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per forward") is None   # label absent
     assert bench.profile_traffic("missing.md", ("a.hip",), "HBM bytes per launch") is None
+    # one summary can hold the bytes of several kernels, each on its own line
+    (tmp_path / "profiles" / "k.md").write_text(f"HBM bytes per launch of k_splat: 1.0e+09\n"
+                                                f"HBM bytes per launch of k_splat_quilt: 2.5e+08\n\n"
+                                                f"kernel sources sha256: {sha}\n")
+    assert bench.profile_traffic("k.md", ("a.hip",), "HBM bytes per launch of k_splat_quilt") == 2.5e8
+    assert bench.profile_traffic("k.md", ("a.hip",), "HBM bytes per launch of k_splat") == 1.0e9
     (csrc / "a.hip").write_bytes(b"kernel source v2\n")                                  # sources changed
     assert bench.profile_traffic("p.md", ("a.hip",), "HBM bytes per launch") is None
 
