@@ -230,9 +230,29 @@ def display_workload():
     return scenes.display()
 
 
+def _quilt_against_oracle(R, sid, w, model, o, label):
+    """The same frame under the quilt order at its automatic tile (the one the
+    autotuner times): views, depth and written pixels against the oracle."""
+    from paper_2601_19901_amd import lfdpr
+    R.set_splat_order(lfdpr.SPLAT_QUILT)
+    R.set_quilt_tile(0, 0)
+    views, depth = R.alloc_views(with_depth=True)
+    R.render_frame(sid, model, views, depth)
+    st = R.stats()
+    _log(f"[{label} quilt] {st}")
+    assert st["splat_order"] == lfdpr.SPLAT_QUILT
+    np.testing.assert_array_equal(views.cpu().numpy().view(np.uint32), o["rgba"], err_msg=f"{label} quilt: views")
+    np.testing.assert_array_equal(depth.cpu().numpy().view(np.uint32), o["depth"].view(np.uint32),
+                                  err_msg=f"{label} quilt: depth")
+    assert st["written_px"] == o["stats"]["fragments"] - o["stats"]["misses"]
+    R.set_splat_order(lfdpr.SPLAT_POINT)
+    return views
+
+
 def test_display_size_parity(torch_cuda, display_workload):
     """Full display workload (999,168 triangles, 48 views of 512^2) in the
-    launch configuration the benchmark times: everything bit-exact."""
+    launch configurations the benchmark times (the point order and the
+    quilt, between which its autotuner chooses): everything bit-exact."""
     w = display_workload
     frame = 17
     _log("oracle: display frame", frame)
@@ -247,13 +267,15 @@ def test_display_size_parity(torch_cuda, display_workload):
     panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
     R.reconstruct(g["views_t"], panel)
     np.testing.assert_array_equal(panel.cpu().numpy(), O.interleave(o["rgba"], w.lens))
+    _quilt_against_oracle(R, sid, w, w.model(frame), o, "display")
 
 
 def test_display_4m_ss4_parity(torch_cuda):
     """The 4M-triangle workload with 4x angular supersampling (192 rendered
-    views of 512^2) in the benchmark's launch configuration: counts, points,
-    all 192 sub-views with depth, the angular filter to 48 views and the panel,
-    bit-exact against the oracle (the oracle takes about a minute)."""
+    views of 512^2) in the benchmark's launch configurations (its autotuner
+    takes the quilt here): counts, points, all 192 sub-views with depth, the
+    angular filter to 48 views and the panel, bit-exact against the oracle
+    (the oracle takes about a minute)."""
     torch = torch_cuda
     _log("generating display-4M-ss4 scene (3,996,672 triangles)")
     w = scenes.display_4m(seed=3)
@@ -274,6 +296,9 @@ def test_display_4m_ss4_parity(torch_cuda):
     panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
     R.reconstruct(filt, panel)
     np.testing.assert_array_equal(panel.cpu().numpy(), O.interleave(of, w.lens))
+    vq = _quilt_against_oracle(R, sid, w, w.model(frame), o, "display-4M-ss4")
+    R.angular_filter(vq, filt)
+    np.testing.assert_array_equal(filt.cpu().numpy().view(np.uint32), of)
 
 
 def test_spatial_supersampling_parity(torch_cuda):
