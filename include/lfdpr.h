@@ -225,7 +225,7 @@ int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
 
 /* Capacity of the quilt's band lists in entries (4 B each; one entry per
  * point and band of rows its splat reaches); 0 (the default) = twice the
- * point capacity + 65536.  A frame with more entries is splatted per point
+ * point capacity + 65536, at most 2^32 - 1.  A frame with more entries is splatted per point
  * into the key buffer instead (same results; lfdpr_get_stats reports it).
  * Reallocated by the next quilt frame. */
 int lfdpr_set_quilt_capacity(lfdpr_ctx* ctx, int64_t entries);

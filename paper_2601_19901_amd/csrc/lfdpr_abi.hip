@@ -302,7 +302,8 @@ bool quilt_shape(const lfdpr_ctx* ctx, int& rows, int& views) {
 // Band lists sized for the context's point capacity: twice as many entries
 // as points unless set (a frame that needs more is splatted per point).
 int ensure_quilt_buffers(lfdpr_ctx* ctx) {
-  const int64_t ecap = ctx->quilt_cap_req > 0 ? ctx->quilt_cap_req : 2 * ctx->cap + 65536;
+  // entries and band offsets are 32-bit
+  const int64_t ecap = ctx->quilt_cap_req > 0 ? ctx->quilt_cap_req : std::min<int64_t>(2 * ctx->cap + 65536, 0xFFFFFFFFll);
   if (ctx->d_qentries && ctx->q_entry_cap == ecap) return LFDPR_OK;
   if (sync_all(ctx) != hipSuccess) return fail(ctx, LFDPR_EDEVICE, "synchronising before reallocation");
   dfree(ctx->d_qentries);
