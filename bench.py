@@ -474,7 +474,10 @@ def run_batch(args, torch, lfdpr, scenes):
         "config": {"workload": "batch16: 16 independent display-family scenes per batch call, triangle counts "
                                "log-uniform 50k-4M, textures 512^2-2048^2, cones 30-50 deg, 48 views 512x512 each, "
                                "16 2560x1600 panels", "scenes": len(ws), "triangles": ntri,
-                   "autotuned": tune["best"]},
+                   "autotuned": tune["best"],
+                   "autotune_candidates_ms": {f"{ORDER_NAMES[e['splat_order']]} {e['splat_blocks']}/{e['key_layout']}/"
+                                              f"{e['quilt_rows']}x{e['quilt_views']}": round(e["ms"], 4)
+                                              for e in tune["entries"]}},
         "frames_in_flight": args.frames_in_flight,
         "ms_per_step_graph_one_in_flight": round(graph_ms, 4),
         "scene_frames_per_s": round(len(ws) * 1e3 / wall_ms, 2),

@@ -209,8 +209,9 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* views);
  *     of a subset of the views, all columns; lfdpr_set_quilt_tile): the tile's
  *     64-bit keys (Sec. 5.1) stay in LDS while the points whose splat reaches
  *     its rows are splatted into it, then it is written out as the views
- *     (unlit and physically shaded frames; batches and
- *     lfdpr_render_frame_noalloc splat per point under this order).
+ *     (unlit and physically shaded frames and batches, whose band lists
+ *     hold every item's bands; lfdpr_render_frame_noalloc splats per point
+ *     under this order).
  * The keys, views and depth are identical.  Applies to the context's frames
  * and to batches created on it afterwards. */
 int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
@@ -219,8 +220,9 @@ int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
  * 8 B per key in LDS (plus 4 B per view column and row for the ray slopes).
  * 0, 0 (the default) chooses per rig: 4 rows, else 2, else 1, with the most
  * views that fit the device's LDS per workgroup, spread evenly over the
- * subsets.  A shape whose keys do not fit is refused by the frame
- * (LFDPR_EINVAL).  Results do not depend on it. */
+ * subsets.  A shape whose keys do not fit, or a batch whose bands (items x
+ * ceil(H / rows)) exceed 8192, is refused by the frame (LFDPR_EINVAL).
+ * Results do not depend on it.  Batches created afterwards start from it. */
 int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
 
 /* Capacity of the quilt's band lists in entries (4 B each; one entry per
@@ -355,8 +357,11 @@ typedef struct {
 int lfdpr_set_launch(lfdpr_ctx* ctx, int32_t splat_blocks, int32_t key_layout);
 
 /* Renders a scene (model: host 3x4; views: device as in lfdpr_render_frame)
- * under every candidate launch shape and key layout, times each with HIP
- * events on the stream and keeps the fastest.  Synchronous. */
+ * under every candidate: the point order (or the triangle-view order, if
+ * set) under each launch shape and key layout, and the quilt with bands of
+ * 1, 2, 4 and 8 rows (each with the most views that fit); times each with
+ * HIP events on the stream and keeps the fastest (order, shape and tile).
+ * Synchronous. */
 int lfdpr_autotune(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uint32_t* views, lfdpr_tune_result* res);
 
 typedef struct lfdpr_batch lfdpr_batch;

@@ -108,7 +108,7 @@ struct lfdpr_ctx {
   Point* d_points = nullptr;
   RowEntry* d_rows = nullptr;   // triangle-major splat: lattice row table and
   PointBox* d_pbox = nullptr;   // per-point splat rectangles (point capacity each)
-  uint32_t* d_prows = nullptr;  // quilt: per point its splat's pixel rows (first | last << 16, or ~0)
+  uint2* d_prows = nullptr;     // quilt: per point its splat's pixel rows (first, last), or ~0
   uint64_t* d_keys = nullptr;
   int64_t n_keys = 0;
   // angular supersampling filter table
@@ -161,7 +161,7 @@ struct lfdpr_ctx {
     Point* d_points = nullptr;
     RowEntry* d_rows = nullptr;
     PointBox* d_pbox = nullptr;
-    uint32_t* d_prows = nullptr;
+    uint2* d_prows = nullptr;
     uint32_t* d_counts = nullptr;
     uint64_t* d_offsets = nullptr;
     TriRec* d_rec = nullptr;
@@ -271,18 +271,18 @@ void swap_frame_buffers(lfdpr_ctx* ctx) {
 
 int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt);
 
-constexpr int kQBandCap = 4096;  // bands per frame (H <= 4096)
-
 // The quilt tile for the context's rig: the shape asked for, clipped to the
 // rig, or the automatic one (4 rows, else 2, else 1, as long as at least
 // min(8, views) views fit; the views spread evenly over the subsets).  False
 // when the keys do not fit the device's LDS.
-bool quilt_shape(const lfdpr_ctx* ctx, int& rows, int& views) {
-  const Rig& rg = ctx->rig;
-  auto fits = [&](int r, int v) { return quilt_lds_bytes(r, v, rg.W, rg.H) <= (size_t)ctx->max_lds; };
-  if (ctx->quilt_rows > 0) {
-    rows = std::min(ctx->quilt_rows, rg.H);
-    views = std::min(ctx->quilt_views, rg.n_views);
+bool quilt_shape_for(const Rig& rg, int max_lds, int want_rows, int want_views, int n_items, int& rows, int& views) {
+  auto fits = [&](int r, int v) {
+    return quilt_lds_bytes(r, v, rg.W, rg.H) <= (size_t)max_lds &&
+           (int64_t)n_items * ((rg.H + r - 1) / r) <= kQuiltBandCap;
+  };
+  if (want_rows > 0) {
+    rows = std::min(want_rows, rg.H);
+    views = std::min(want_views, rg.n_views);
     return fits(rows, views);
   }
   for (int r : {4, 2, 1}) {
@@ -299,6 +299,10 @@ bool quilt_shape(const lfdpr_ctx* ctx, int& rows, int& views) {
   return false;
 }
 
+bool quilt_shape(const lfdpr_ctx* ctx, int& rows, int& views) {
+  return quilt_shape_for(ctx->rig, ctx->max_lds, ctx->quilt_rows, ctx->quilt_views, 1, rows, views);
+}
+
 // Band lists sized for the context's point capacity: twice as many entries
 // as points unless set (a frame that needs more is splatted per point).
 int ensure_quilt_buffers(lfdpr_ctx* ctx) {
@@ -309,12 +313,56 @@ int ensure_quilt_buffers(lfdpr_ctx* ctx) {
   dfree(ctx->d_qentries);
   dfree(ctx->d_qband);
   ctx->q_entry_cap = 0;
-  if (dalloc(ctx->d_qentries, (size_t)ecap) != hipSuccess || dalloc(ctx->d_qband, (size_t)(4 * kQBandCap + 8)) != hipSuccess)
+  if (dalloc(ctx->d_qentries, (size_t)ecap) != hipSuccess || dalloc(ctx->d_qband, (size_t)(4 * kQuiltBandCap + 8)) != hipSuccess)
     return fail(ctx, LFDPR_ENOMEM, "quilt band lists");
-  if (hipMemset(ctx->d_qband, 0, (4 * kQBandCap + 8) * sizeof(uint32_t)) != hipSuccess)
+  if (hipMemset(ctx->d_qband, 0, (4 * kQuiltBandCap + 8) * sizeof(uint32_t)) != hipSuccess)
     return fail(ctx, LFDPR_EDEVICE, "clearing the quilt band counts");
   ctx->q_entry_cap = ecap;
   return LFDPR_OK;
+}
+
+// Band-list kernels' arguments over the lists at qb (per band counts |
+// offsets (+1) | cursors | order, then the overflow flag and the entries).
+QuiltBinArgs quilt_bin_args(uint32_t* qb, uint32_t* entries, int64_t entry_cap, const uint2* prows,
+                            const uint64_t* n_points, int64_t cap, int H, int rows, int n_items) {
+  QuiltBinArgs qa{};
+  qa.n_points = n_points;
+  qa.cap = cap;
+  qa.prows = prows;
+  qa.H = H;
+  qa.rows = rows;
+  qa.bands_item = (H + rows - 1) / rows;
+  qa.bands = qa.bands_item * n_items;
+  qa.band_cnt = qb;
+  qa.band_off = qb + kQuiltBandCap;
+  qa.band_cur = qb + 2 * kQuiltBandCap + 1;
+  qa.order = qb + 3 * kQuiltBandCap + 1;
+  qa.entries = entries;
+  qa.entry_cap = entry_cap;
+  qa.state = qb + 4 * kQuiltBandCap + 1;
+  return qa;
+}
+
+// The tile kernel's arguments: those of the point splat pa plus the lists.
+SplatArgs quilt_tile_args(const SplatArgs& pa, const QuiltBinArgs& qa, PointBox* pbox, int views, int max_lds,
+                          uint32_t* out_rgba, float* out_depth) {
+  SplatArgs qp = pa;
+  qp.pbox = pbox;
+  qp.q_entries = qa.entries;
+  qp.q_band_off = qa.band_off;
+  qp.q_order = qa.order;
+  qp.q_state = qa.state;
+  qp.q_rows = qa.rows;
+  qp.q_views = views;
+  qp.q_bands = qa.bands;
+  qp.q_bands_item = qa.bands_item;
+  qp.q_subsets = (pa.table_rig.n_views + views - 1) / views;
+  // two tiles per CU when their LDS allows (the device's per-workgroup
+  // figure is the CU's LDS on this architecture)
+  qp.q_block = 2 * quilt_lds_bytes(qa.rows, views, pa.table_rig.W, pa.table_rig.H) <= (size_t)max_lds ? 512 : 1024;
+  qp.out_rgba = out_rgba;
+  qp.out_depth = out_depth;
+  return qp;
 }
 
 // Per-frame buffers of the set in the context's fields, sized for a frame of
@@ -505,6 +553,16 @@ int lfdpr_create(int device, void* stream, lfdpr_ctx** out) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     ctx->max_lds = lds;
+  // the quilt's tile kernels may take that much LDS (set once, outside any
+  // capture); if the device refuses, tiles stay within 64 KiB
+  if (prepare_quilt_kernels((size_t)ctx->max_lds) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->max_lds = 65536;
+    if (prepare_quilt_kernels((size_t)ctx->max_lds) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->max_lds = 0;  // no tile fits: the quilt order is refused
+    }
+  }
   if (dalloc(ctx->d_stats, STAT_SLOTS) != hipSuccess || dalloc(ctx->d_item1, 1) != hipSuccess) {
     dfree(ctx->d_stats);
     delete ctx;
@@ -932,19 +990,8 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   QuiltBinArgs qa{};
   if (quilt) {
     // the quilt's band lists, built with the point generation
-    uint32_t* qb = ctx->d_qband;
-    qa.n_points = ctx->d_stats + STAT_TOTAL;
-    qa.cap = ctx->cap;
-    qa.prows = ctx->d_prows;
-    qa.rows = qrows;
-    qa.bands = (ctx->rig.H + qrows - 1) / qrows;
-    qa.band_cnt = qb;
-    qa.band_off = qb + kQBandCap;
-    qa.band_cur = qb + 2 * kQBandCap + 1;
-    qa.order = qb + 3 * kQBandCap + 1;
-    qa.entries = ctx->d_qentries;
-    qa.entry_cap = ctx->q_entry_cap;
-    qa.state = qb + 4 * kQBandCap + 1;
+    qa = quilt_bin_args(ctx->d_qband, ctx->d_qentries, ctx->q_entry_cap, ctx->d_prows, ctx->d_stats + STAT_TOTAL,
+                        ctx->cap, ctx->rig.H, qrows, 1);
     launch_quilt_bin(qa, gen);
   }
   hipEvent_t ebin = quilt ? mark_on(ctx, gen) : e3;
@@ -979,21 +1026,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   if (quilt) {
     // the tiles, which write the views; the point splat and the resolve
     // below run only if the band lists overflowed
-    SplatArgs qp = pa;
-    qp.pbox = ctx->d_pbox;
-    qp.q_entries = qa.entries;
-    qp.q_band_off = qa.band_off;
-    qp.q_order = qa.order;
-    qp.q_state = qa.state;
-    qp.q_rows = qrows;
-    qp.q_views = qviews;
-    qp.q_bands = qa.bands;
-    qp.q_subsets = (ctx->rig.n_views + qviews - 1) / qviews;
-    // two tiles per CU when their LDS allows (the device's per-workgroup
-    // figure is the CU's LDS on this architecture)
-    qp.q_block = 2 * quilt_lds_bytes(qrows, qviews, ctx->rig.W, ctx->rig.H) <= (size_t)ctx->max_lds ? 512 : 1024;
-    qp.out_rgba = views;
-    qp.out_depth = depth;
+    const SplatArgs qp = quilt_tile_args(pa, qa, ctx->d_pbox, qviews, ctx->max_lds, views, depth);
     HIPOK(launch_splat_quilt(qp, st));
     qstate = qa.state;
     pa.gate = qstate;
@@ -1192,7 +1225,7 @@ int lfdpr_get_stats(lfdpr_ctx* ctx, lfdpr_stats* out) {
   out->quilt_entries = -1;
   if (ctx->last_order == LFDPR_SPLAT_QUILT) {
     uint32_t qs[2];
-    HIPOK(hipMemcpy(qs, ctx->d_qband + 4 * kQBandCap + 1, sizeof qs, hipMemcpyDeviceToHost));
+    HIPOK(hipMemcpy(qs, ctx->d_qband + 4 * kQuiltBandCap + 1, sizeof qs, hipMemcpyDeviceToHost));
     out->quilt_rows = ctx->last_qrows;
     out->quilt_views = ctx->last_qviews;
     out->quilt_entries = (int64_t)qs[1];
@@ -1297,6 +1330,14 @@ struct lfdpr_batch {
   int64_t cap = 0;
   int splat_order = LFDPR_SPLAT_POINT;
   int last_order = LFDPR_SPLAT_POINT;
+  // quilt: tile asked for (0, 0: chosen for the batch), the tile of the
+  // calls being enqueued, and this set's per-point rows and band lists
+  // (allocated on the first quilt call)
+  int quilt_rows = 0, quilt_views = 0, cur_qrows = 0, cur_qviews = 0;
+  uint2* prows = nullptr;
+  uint32_t* qentries = nullptr;
+  uint32_t* qband = nullptr;
+  int64_t q_entry_cap = 0;
   TriMat* tm = nullptr;  // physically based shading: material records and
   uint4* pmat = nullptr; // per-point material words (allocated on first use)
   Rig table_rig{};
@@ -1328,6 +1369,10 @@ struct lfdpr_batch {
     PointBox* pbox = nullptr;
     TriMat* tm = nullptr;
     uint4* pmat = nullptr;
+    uint2* prows = nullptr;
+    uint32_t* qentries = nullptr;
+    uint32_t* qband = nullptr;
+    int64_t q_entry_cap = 0;
   } alt;
   int in_flight = 1, slot = 0;
   hipStream_t gen = nullptr;
@@ -1370,6 +1415,10 @@ void batch_free_alt(lfdpr_batch* b) {
   dfree(a.pbox);
   dfree(a.tm);
   dfree(a.pmat);
+  dfree(a.prows);
+  dfree(a.qentries);
+  dfree(a.qband);
+  a.q_entry_cap = 0;
   for (int k = 0; k < 2; ++k) {
     if (b->ev_gen[k]) (void)hipEventDestroy(b->ev_gen[k]);
     if (b->ev_spl[k]) (void)hipEventDestroy(b->ev_spl[k]);
@@ -1398,6 +1447,10 @@ void batch_swap_sets(lfdpr_batch* b) {
   std::swap(b->pbox, a.pbox);
   std::swap(b->tm, a.tm);
   std::swap(b->pmat, a.pmat);
+  std::swap(b->prows, a.prows);
+  std::swap(b->qentries, a.qentries);
+  std::swap(b->qband, a.qband);
+  std::swap(b->q_entry_cap, a.q_entry_cap);
 }
 
 // Every stream of the batch idle.
@@ -1428,6 +1481,9 @@ void batch_free(lfdpr_batch* b) {
   dfree(b->pbox);
   dfree(b->tm);
   dfree(b->pmat);
+  dfree(b->prows);
+  dfree(b->qentries);
+  dfree(b->qband);
   batch_free_alt(b);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -1473,17 +1529,27 @@ hipEvent_t batch_gen(lfdpr_batch* b, hipStream_t st, bool timed) {
   ea.tm = pbr ? b->tm : nullptr;
   ea.pmat = pbr ? b->pmat : nullptr;
   const bool tv = !pbr && b->splat_order == LFDPR_SPLAT_TRIANGLE_VIEW;
+  const bool quilt = b->splat_order == LFDPR_SPLAT_QUILT;
   ea.rec = b->rec;
   ea.rows = tv ? b->rows : nullptr;
-  ea.pbox = tv ? b->pbox : nullptr;
+  ea.pbox = tv || quilt ? b->pbox : nullptr;
+  ea.prows = quilt ? b->prows : nullptr;
   ea.tris = tv ? b->tris : nullptr;
   ea.n_tris = b->stats + STAT_EMITTING;
   launch_emit(ea, b->splat_blocks, st);
   hipEvent_t e3 = ev();
+  hipEvent_t ebin = e3;
+  if (quilt) {
+    launch_quilt_bin(quilt_bin_args(b->qband, b->qentries, b->q_entry_cap, b->prows, b->stats + STAT_TOTAL, b->cap,
+                                    b->table_rig.H, b->cur_qrows, b->n),
+                     st);
+    ebin = ev();
+    stage(ctx, 7, e3, ebin);
+  }
   stage(ctx, 0, e0, e1);
   stage(ctx, 1, e1, e2);
   stage(ctx, 2, e2, e3);
-  return e3;
+  return ebin;
 }
 
 // Splat, resolve and interleave of a batch frame on stream st; e3 marks the
@@ -1514,10 +1580,22 @@ void batch_splat(lfdpr_batch* b, uint32_t* views, uint8_t* panels, hipStream_t s
   const lfdpr_shading& sh = ctx->shading;
   pa.sh = Shading{sh.light_dir[0], sh.light_dir[1], sh.light_dir[2], sh.light_rgb[0], sh.light_rgb[1],
                   sh.light_rgb[2], sh.ambient_rgb[0], sh.ambient_rgb[1], sh.ambient_rgb[2]};
-  launch_splat(pa, b->splat_blocks, st);
-  b->last_order = pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT;
+  const bool quilt = b->splat_order == LFDPR_SPLAT_QUILT;
+  const uint32_t* qstate = nullptr;
+  if (quilt) {
+    // the tiles write every item's views; the point splat and the resolve
+    // below run only if the band lists overflowed
+    const QuiltBinArgs qa = quilt_bin_args(b->qband, b->qentries, b->q_entry_cap, b->prows, b->stats + STAT_TOTAL,
+                                           b->cap, b->table_rig.H, b->cur_qrows, b->n);
+    (void)launch_splat_quilt(quilt_tile_args(pa, qa, b->pbox, b->cur_qviews, ctx->max_lds, views, nullptr), st);
+    qstate = qa.state;
+    pa.gate = qstate;
+  }
+  launch_splat(pa, quilt ? 256 : b->splat_blocks, st);
+  b->last_order = quilt ? LFDPR_SPLAT_QUILT : (pa.pbox && !pa.tm ? LFDPR_SPLAT_TRIANGLE_VIEW : LFDPR_SPLAT_POINT);
   hipEvent_t e4 = ev();
-  launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st);
+  launch_resolve(b->keys, b->n, b->table_rig.n_views, b->table_rig.H, b->table_rig.W, b->key_layout, views, nullptr, st,
+                 qstate);
   hipEvent_t e5 = ev();
   if (panels) {
     InterleaveArgs ia = interleave_args(b->ctx->lens, views, b->table_rig.n_views, b->table_rig.W, b->table_rig.H, panels);
@@ -1532,6 +1610,40 @@ void batch_splat(lfdpr_batch* b, uint32_t* views, uint8_t* panels, hipStream_t s
 void batch_enqueue(lfdpr_batch* b, uint32_t* views, uint8_t* panels, bool timed) {
   const hipEvent_t e3 = batch_gen(b, b->stream, timed);
   batch_splat(b, views, panels, b->stream, timed, e3);
+}
+
+// Rows and band lists of the batch's buffer set(s) for the quilt (entries:
+// twice the point capacity + 65536, at most 2^32 - 1).
+int ensure_batch_quilt(lfdpr_batch* b) {
+  const int64_t ecap = std::min<int64_t>(2 * b->cap + 65536, 0xFFFFFFFFll);
+  const int64_t nq = 4 * kQuiltBandCap + 8;
+  auto need = [&](uint2* pr) { return pr == nullptr; };
+  if (!need(b->prows) && !(b->in_flight == 2 && need(b->alt.prows))) return LFDPR_OK;
+  BHIP(batch_sync(b));
+  bool ok = true;
+  if (need(b->prows)) {
+    ok = dalloc(b->prows, (size_t)b->cap) == hipSuccess && dalloc(b->qentries, (size_t)ecap) == hipSuccess &&
+         dalloc(b->qband, (size_t)nq) == hipSuccess &&
+         hipMemset(b->qband, 0, (size_t)nq * sizeof(uint32_t)) == hipSuccess;
+    b->q_entry_cap = ecap;
+  }
+  if (ok && b->in_flight == 2 && need(b->alt.prows)) {
+    lfdpr_batch::GenSet& a = b->alt;
+    ok = dalloc(a.prows, (size_t)b->cap) == hipSuccess && dalloc(a.qentries, (size_t)ecap) == hipSuccess &&
+         dalloc(a.qband, (size_t)nq) == hipSuccess &&
+         hipMemset(a.qband, 0, (size_t)nq * sizeof(uint32_t)) == hipSuccess;
+    a.q_entry_cap = ecap;
+  }
+  if (!ok) {
+    dfree(b->prows);
+    dfree(b->qentries);
+    dfree(b->qband);
+    dfree(b->alt.prows);
+    dfree(b->alt.qentries);
+    dfree(b->alt.qband);
+    return bfail(b, LFDPR_ENOMEM, "quilt band lists");
+  }
+  return LFDPR_OK;
 }
 
 int batch_set_shape(lfdpr_batch* b, int splat_blocks, int key_layout) {
@@ -1568,6 +1680,8 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
   b->ctx = ctx;
   b->n = n;
   b->splat_order = ctx->splat_order;
+  b->quilt_rows = ctx->quilt_rows;
+  b->quilt_views = ctx->quilt_views;
   bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) == hipSuccess &&
@@ -1747,6 +1861,16 @@ int lfdpr_batch_render(lfdpr_batch* b, const float* models, uint32_t* views, uin
   if (items_changed || b->g_pbr != pbr ||
       (pbr && std::memcmp(&b->g_sh, &b->ctx->shading, sizeof b->g_sh) != 0))
     b->g_valid = false;
+  if (b->splat_order == LFDPR_SPLAT_QUILT) {
+    int qr = 0, qv = 0;
+    if (!quilt_shape_for(b->table_rig, b->ctx->max_lds, b->quilt_rows, b->quilt_views, b->n, qr, qv))
+      return bfail(b, LFDPR_EINVAL, "quilt tile does not fit the device's LDS or the batch's band lists");
+    if (qr != b->cur_qrows || qv != b->cur_qviews) b->g_valid = false;
+    b->cur_qrows = qr;
+    b->cur_qviews = qv;
+    int rc = ensure_batch_quilt(b);
+    if (rc) return rc;
+  }
   if (b->in_flight == 2) {
     // this call's generation buffers; generation waits only for the splat
     // that last read them, the splat for earlier work on the context's stream
@@ -1821,6 +1945,14 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
   out->covered_px = b->last_order == LFDPR_SPLAT_TRIANGLE_VIEW ? (int64_t)st[STAT_COVERED] : -1;
   out->missed_px = out->covered_px >= 0 ? out->covered_px - out->written_px : -1;
   out->quilt_entries = -1;
+  if (b->last_order == LFDPR_SPLAT_QUILT) {
+    uint32_t qs[2];
+    BHIP(hipMemcpy(qs, b->qband + 4 * kQuiltBandCap + 1, sizeof qs, hipMemcpyDeviceToHost));
+    out->quilt_rows = b->cur_qrows;
+    out->quilt_views = b->cur_qviews;
+    out->quilt_entries = (int64_t)qs[1];
+    if (qs[0]) out->splat_order = LFDPR_SPLAT_POINT;  // the lists overflowed: splatted per point
+  }
   out->capacity = b->cap;
   out->point_overflow = out->points > b->cap ? 1 : 0;
   out->n_views = b->table_rig.n_views;
@@ -1832,6 +1964,27 @@ int lfdpr_batch_stats(lfdpr_batch* b, lfdpr_stats* out) {
 int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, lfdpr_tune_result* res) {
   if (!b || !models || !views || !res) return bfail(b, LFDPR_EINVAL, "null argument");
   static const int kBlocks[] = {1024, 2048, 4096, 8192, 16384};
+  static const int kQuiltRows[] = {1, 2, 4, 8};
+  // candidates: the batch's per-point (or triangle-view) order under every
+  // launch shape and key layout, then the quilt under each band height with
+  // the most views that fit (its band lists hold every item's bands)
+  struct Cand {
+    int order, blocks, layout, qrows, qviews;
+  };
+  std::vector<Cand> cands;
+  const int base_order = b->splat_order == LFDPR_SPLAT_QUILT ? LFDPR_SPLAT_POINT : b->splat_order;
+  for (int layout = 0; layout < 2; ++layout)
+    for (int blocks : kBlocks) cands.push_back({base_order, blocks, layout, 0, 0});
+  for (int r : kQuiltRows) {
+    int qr = 0, qv = 0, v = 0;
+    while (v < b->table_rig.n_views && quilt_lds_bytes(r, v + 1, b->table_rig.W, b->table_rig.H) <= (size_t)b->ctx->max_lds) ++v;
+    if (v == 0) continue;
+    const int subsets = (b->table_rig.n_views + v - 1) / v;
+    if (!quilt_shape_for(b->table_rig, b->ctx->max_lds, r, (b->table_rig.n_views + subsets - 1) / subsets, b->n, qr, qv))
+      continue;
+    cands.push_back({LFDPR_SPLAT_QUILT, b->splat_blocks, b->key_layout, qr, qv});
+  }
+  const int saved[5] = {b->splat_order, b->splat_blocks, b->key_layout, b->quilt_rows, b->quilt_views};
   const bool graph = b->use_graph;
   b->use_graph = false;
   hipEvent_t t0, t1;
@@ -1840,32 +1993,50 @@ int lfdpr_batch_autotune(lfdpr_batch* b, const float* models, uint32_t* views, l
   std::memset(res, 0, sizeof *res);
   float best = INFINITY;
   int rc = LFDPR_OK;
-  for (int layout = 0; layout < 2 && !rc; ++layout)
-    for (int bi = 0; bi < 5 && !rc; ++bi) {
-      rc = batch_set_shape(b, kBlocks[bi], layout);
-      for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
-      if (rc) break;
-      (void)hipEventRecord(t0, b->stream);
-      for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
-      (void)hipEventRecord(t1, b->stream);
-      (void)hipEventSynchronize(t1);
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      lfdpr_tune_entry& e = res->entries[res->n++];
-      e.splat_blocks = kBlocks[bi];
-      e.key_layout = layout;
-      e.ms = ms / 3.0f;
-      e.splat_order = b->last_order;
-      if (e.ms < best) {
-        best = e.ms;
-        res->best = res->n - 1;
-      }
+  for (const Cand& c : cands) {
+    if (res->n >= (int)(sizeof res->entries / sizeof res->entries[0])) break;
+    rc = batch_set_shape(b, c.blocks, c.layout);
+    if (rc) break;
+    b->splat_order = c.order;
+    b->quilt_rows = c.qrows;
+    b->quilt_views = c.qviews;
+    for (int w = 0; w < 2 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
+    if (rc) break;
+    (void)hipEventRecord(t0, b->stream);
+    for (int w = 0; w < 3 && !rc; ++w) rc = lfdpr_batch_render(b, models, views, nullptr);
+    (void)hipEventRecord(t1, b->stream);
+    (void)hipEventSynchronize(t1);
+    if (rc) break;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    lfdpr_tune_entry& e = res->entries[res->n++];
+    e.splat_blocks = c.blocks;
+    e.key_layout = c.layout;
+    e.ms = ms / 3.0f;
+    e.splat_order = b->last_order;
+    e.quilt_rows = c.qrows;
+    e.quilt_views = c.qviews;
+    if (e.ms < best) {
+      best = e.ms;
+      res->best = res->n - 1;
     }
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   b->use_graph = graph;
-  if (rc) return rc;
-  return batch_set_shape(b, res->entries[res->best].splat_blocks, res->entries[res->best].key_layout);
+  b->g_valid = false;
+  if (rc || res->n == 0) {
+    b->splat_order = saved[0];
+    b->quilt_rows = saved[3];
+    b->quilt_views = saved[4];
+    const int rc2 = batch_set_shape(b, saved[1], saved[2]);
+    return rc ? rc : (rc2 ? rc2 : bfail(b, LFDPR_ESTATE, "no candidate ran"));
+  }
+  const lfdpr_tune_entry& e = res->entries[res->best];
+  b->splat_order = e.splat_order == LFDPR_SPLAT_QUILT ? LFDPR_SPLAT_QUILT : base_order;
+  b->quilt_rows = e.quilt_rows;
+  b->quilt_views = e.quilt_views;
+  return batch_set_shape(b, e.splat_blocks, e.key_layout);
 }
 
 // Same search for single frames of one scene on the context.

@@ -71,9 +71,10 @@ struct EmitArgs {
   PointBox* pbox;            // per point
   uint32_t* tris;            // triangles with points (any order) and their number
   uint64_t* n_tris;
-  // row-band quilt: per point the pixel rows its splat can write in any view
-  // (first | last << 16, or ~0 for none); null otherwise
-  uint32_t* prows;
+  // row-band quilt: per point the pixel rows its splat can write in any view,
+  // as rows of the batch's stacked views (item * H + row; first, last), or
+  // (~0, ~0) for none; null otherwise
+  uint2* prows;
 };
 
 struct SplatArgs {
@@ -108,6 +109,7 @@ struct SplatArgs {
   const uint32_t* q_order;     // bands by decreasing number of entries
   const uint32_t* q_state;     // [0] != 0: the lists overflowed, the point splat takes the frame
   int32_t q_rows, q_views, q_bands, q_subsets;  // tile: q_rows rows x q_views views x W
+  int32_t q_bands_item;        // bands per item (q_bands over all items)
   int32_t q_block;             // threads per quilt workgroup: 1024, or 512 (two tiles per CU)
   uint32_t* out_rgba;          // the views, [view][y][x]
   float* out_depth;            // optional, [view][y][x]
@@ -119,8 +121,9 @@ struct SplatArgs {
 struct QuiltBinArgs {
   const uint64_t* n_points;  // device count (total emitted)
   int64_t cap;
-  const uint32_t* prows;     // per point: first row | last row << 16, or ~0 (no rows)
-  int32_t rows, bands;       // rows per band, bands
+  const uint2* prows;        // per point: first and last stacked row (item * H + row), or ~0
+  int32_t H, rows;           // view height, rows per band
+  int32_t bands_item, bands; // bands per item, over all items
   uint32_t* band_cnt;  // entries per band (zero on entry; left zero)
   uint32_t* band_off;  // bands + 1 exclusive offsets
   uint32_t* band_cur;  // scatter cursors
@@ -160,6 +163,10 @@ void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
 // the quilt: band lists (bins), then one workgroup per (band, view subset)
 // tile in decreasing band size; the tile's LDS bytes
 size_t quilt_lds_bytes(int32_t rows, int32_t views, int32_t W, int32_t H);
+constexpr int kQuiltBandCap = 8192;  // bands of a frame or batch frame
+// Lets the tile kernels take up to lds bytes of LDS (once per device, before
+// any launch or graph capture).
+hipError_t prepare_quilt_kernels(size_t lds);
 void launch_quilt_bin(const QuiltBinArgs& a, hipStream_t s);
 hipError_t launch_splat_quilt(const SplatArgs& a, hipStream_t s);
 void launch_resolve(uint64_t* keys, int64_t n_items, int32_t n_views, int32_t H, int32_t W, int32_t key_layout,

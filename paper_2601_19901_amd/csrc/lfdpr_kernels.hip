@@ -580,7 +580,9 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
       a.pbox[p] = B;
       if (a.prows) {
         int32_t r0, r1;
-        a.prows[p] = quilt_point_rows(it.rig.H, T, B.rows, r0, r1) ? (uint32_t)r0 | ((uint32_t)r1 << 16) : ~0u;
+        const uint32_t base = (uint32_t)E.item * (uint32_t)it.rig.H;
+        a.prows[p] = quilt_point_rows(it.rig.H, T, B.rows, r0, r1) ? make_uint2(base + (uint32_t)r0, base + (uint32_t)r1)
+                                                                   : make_uint2(~0u, ~0u);
       }
     }
     if (a.tm) {
@@ -919,6 +921,12 @@ constexpr int kQChunk = 4096;  // points per workgroup pass in the band kernels
 // two tiles fit the CU's LDS (two workgroups of 8 waves, so that one tile's
 // clearing, writing out and last chunks overlap the other's splatting)
 
+// Band (over all items) of stacked row g = item * H + row.
+__device__ __forceinline__ uint32_t quilt_band(const QuiltBinArgs& a, uint32_t g) {
+  const uint32_t item = g / (uint32_t)a.H;
+  return item * (uint32_t)a.bands_item + (g - item * (uint32_t)a.H) / (uint32_t)a.rows;
+}
+
 // Pass 1: entries per band (a workgroup histogram in LDS, one global add per
 // band it touched).
 __global__ void __launch_bounds__(256) k_qcount(QuiltBinArgs a) {
@@ -929,10 +937,9 @@ __global__ void __launch_bounds__(256) k_qcount(QuiltBinArgs a) {
   for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += (uint64_t)gridDim.x * kQChunk) {
     const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
     for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
-      const uint32_t pr = a.prows[p];
-      if (pr != ~0u)
-        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
-          atomicAdd(&qhist[b], 1u);
+      const uint2 pr = a.prows[p];
+      if (pr.x != ~0u)
+        for (uint32_t b = quilt_band(a, pr.x), b1 = quilt_band(a, pr.y); b <= b1; ++b) atomicAdd(&qhist[b], 1u);
     }
   }
   __syncthreads();
@@ -944,14 +951,15 @@ __global__ void __launch_bounds__(256) k_qcount(QuiltBinArgs a) {
 // the bands sorted by decreasing entries (bitonic sort in LDS) so that the
 // largest tiles start first.  Leaves the band counts at zero.
 __global__ void __launch_bounds__(1024) k_qplan(QuiltBinArgs a) {
-  __shared__ uint64_t sk[4096];
+  constexpr int kPer = kQuiltBandCap / 1024;  // bands per thread
+  __shared__ uint64_t sk[kQuiltBandCap];
   __shared__ uint64_t wtot[16];
   const int nb = a.bands, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  uint32_t c[4];
+  uint32_t c[kPer];
   uint64_t t = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int b = tid * 4 + k;
+  for (int k = 0; k < kPer; ++k) {
+    const int b = tid * kPer + k;
     c[k] = b < nb ? a.band_cnt[b] : 0u;
     t += c[k];
   }
@@ -964,8 +972,8 @@ __global__ void __launch_bounds__(1024) k_qplan(QuiltBinArgs a) {
     total += wtot[w];
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int b = tid * 4 + k;
+  for (int k = 0; k < kPer; ++k) {
+    const int b = tid * kPer + k;
     if (b < nb) {
       const uint32_t o = run < 0xFFFFFFFFull ? (uint32_t)run : 0xFFFFFFFFu;
       a.band_off[b] = o;
@@ -1017,10 +1025,9 @@ __global__ void __launch_bounds__(256) k_qscatter(QuiltBinArgs a) {
   for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += step) {
     const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
     for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
-      const uint32_t pr = a.prows[p];
-      if (pr != ~0u)
-        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
-          atomicAdd(&hist[b], 1u);
+      const uint2 pr = a.prows[p];
+      if (pr.x != ~0u)
+        for (uint32_t b = quilt_band(a, pr.x), b1 = quilt_band(a, pr.y); b <= b1; ++b) atomicAdd(&hist[b], 1u);
     }
   }
   __syncthreads();
@@ -1033,9 +1040,9 @@ __global__ void __launch_bounds__(256) k_qscatter(QuiltBinArgs a) {
   for (uint64_t c = (uint64_t)blockIdx.x * kQChunk; c < npts; c += step) {
     const uint64_t end = c + kQChunk < npts ? c + kQChunk : npts;
     for (uint64_t p = c + threadIdx.x; p < end; p += blockDim.x) {
-      const uint32_t pr = a.prows[p];
-      if (pr != ~0u)
-        for (uint32_t b = (pr & 0xFFFFu) / (uint32_t)a.rows; b <= (pr >> 16) / (uint32_t)a.rows; ++b)
+      const uint2 pr = a.prows[p];
+      if (pr.x != ~0u)
+        for (uint32_t b = quilt_band(a, pr.x), b1 = quilt_band(a, pr.y); b <= b1; ++b)
           a.entries[base[b] + atomicAdd(&hist[b], 1u)] = (uint32_t)p;
     }
   }
@@ -1060,10 +1067,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   const uint32_t rank = (k / (uint32_t)a.q_subsets) * 8u + xcd, sub = k % (uint32_t)a.q_subsets;
   if (rank >= (uint32_t)a.q_bands) return;
   const int32_t band = (int32_t)a.q_order[rank];
+  const int32_t item = band / a.q_bands_item, lband = band - item * a.q_bands_item;  // the band within its item
   QuiltTile qt;
   qt.keys = qtile;
   qt.rows = a.q_rows;
-  qt.y_lo = band * a.q_rows;
+  qt.y_lo = lband * a.q_rows;
   qt.y_hi = min(H - 1, qt.y_lo + a.q_rows - 1);
   qt.r_lo = (int32_t)sub * a.q_views;
   qt.r_hi = min(trg.n_views, qt.r_lo + a.q_views);
@@ -1076,7 +1084,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   if (threadIdx.x == 0) qnext = 0u;
   __syncthreads();
   const uint32_t e0 = a.q_band_off[band], e1 = a.q_band_off[band + 1];
-  const Item it0 = load_uniform(a.items);
+  const Item it0 = load_uniform(a.items + item);
   const int lane = threadIdx.x & 63;
   uint32_t written = 0;
   // the band's entries in chunks of 64, one chunk per wave at a time, taken
@@ -1105,7 +1113,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
   for (int32_t q = wv; q < nvt * nrows; q += nw) {
     const int32_t rv = q / nrows, yy = q - rv * nrows;
     const uint64_t* src = qtile + (rv * a.q_rows + yy) * W;
-    const int64_t o = ((int64_t)(qt.r_lo + rv) * H + (qt.y_lo + yy)) * W;
+    const int64_t o = (((int64_t)item * trg.n_views + qt.r_lo + rv) * H + (qt.y_lo + yy)) * W;
     for (int32_t x = lane; x < W; x += 64) {
       const uint64_t key = src[x];
       const bool empty = key == ~0ull;
@@ -1632,21 +1640,28 @@ void launch_quilt_bin(const QuiltBinArgs& a, hipStream_t s) {
   k_qscatter<<<g, 256, 2 * sizeof(uint32_t) * (size_t)a.bands, s>>>(a);
 }
 
-template <bool kPBR, int kBlock>
-static hipError_t launch_quilt_kernel(const SplatArgs& a, unsigned g, size_t lds, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_splat_quilt<kPBR, kBlock>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  k_splat_quilt<kPBR, kBlock><<<g, kBlock, lds, s>>>(a);
-  return hipGetLastError();
+hipError_t prepare_quilt_kernels(size_t lds) {
+  const int dyn = (int)(lds - kQuiltStaticLds);
+  const void* ks[] = {(const void*)k_splat_quilt<false, 512>, (const void*)k_splat_quilt<false, 1024>,
+                      (const void*)k_splat_quilt<true, 512>, (const void*)k_splat_quilt<true, 1024>};
+  for (const void* k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_splat_quilt(const SplatArgs& a, hipStream_t s) {
   const size_t lds = quilt_lds_bytes(a.q_rows, a.q_views, a.table_rig.W, a.table_rig.H) - kQuiltStaticLds;
   const unsigned g = (unsigned)((a.q_bands + 7) / 8) * 8u * (unsigned)a.q_subsets;
-  if (a.q_block == 512)
-    return a.tm ? launch_quilt_kernel<true, 512>(a, g, lds, s) : launch_quilt_kernel<false, 512>(a, g, lds, s);
-  return a.tm ? launch_quilt_kernel<true, 1024>(a, g, lds, s) : launch_quilt_kernel<false, 1024>(a, g, lds, s);
+  if (a.q_block == 512) {
+    if (a.tm) k_splat_quilt<true, 512><<<g, 512, lds, s>>>(a);
+    else k_splat_quilt<false, 512><<<g, 512, lds, s>>>(a);
+  } else {
+    if (a.tm) k_splat_quilt<true, 1024><<<g, 1024, lds, s>>>(a);
+    else k_splat_quilt<false, 1024><<<g, 1024, lds, s>>>(a);
+  }
+  return hipGetLastError();
 }
 
 void launch_interleave(const InterleaveArgs& a, hipStream_t s) {

@@ -147,7 +147,9 @@ def test_autotune_keeps_results(setup):
     ref = views.cpu().numpy().copy()
     res = B.autotune(models, views)
     print("batch autotune:", res["best"], flush=True)
-    assert len(res["entries"]) == 10 and res["best"] in res["entries"]
+    # ten point-order shapes, then the quilt under each band height that fits
+    assert 10 < len(res["entries"]) <= 14 and res["best"] in res["entries"]
+    assert {e["splat_order"] for e in res["entries"][10:]} == {lfdpr.SPLAT_QUILT}
     B.use_graph(True)
     B.render(models, views)
     torch.cuda.synchronize()

@@ -228,3 +228,104 @@ def _render_current(R, sid, model):
     v, d = R.alloc_views(with_depth=True)
     R.render_frame(sid, model, v, d)
     return v.cpu().numpy(), d.cpu().numpy(), R.stats()
+
+
+def _batch_scenes():
+    ws = [scenes.small_display(seed=s, V=12, W=96, H=96, hf_quads=hq) for s, hq in ((70, 24), (71, 48), (72, 8))]
+    for k, w in enumerate(ws):
+        w.views.cone_deg = 30.0 + 7.0 * k
+    return ws
+
+
+def _batch_run(lfdpr, torch, R, ids, ws, order, tile, graph, in_flight, frames):
+    R.set_splat_order(order)
+    R.set_quilt_tile(*tile)
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    B.use_graph(graph)
+    if in_flight == 2:
+        B.set_frames_in_flight(2)
+    outs = []
+    for f in frames:
+        models = [w.model(f + 9 * k) for k, w in enumerate(ws)]
+        v = B.alloc_views()
+        p = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+        B.render(models, v, p)
+        outs.append((v, p))
+    torch.cuda.synchronize()
+    st = B.stats()
+    res = [(v.cpu().numpy(), p.cpu().numpy()) for v, p in outs]
+    B.close()
+    return res, st
+
+
+@pytest.mark.parametrize("tile", [(0, 0), (1, 5), (3, 12)])
+def test_quilt_in_batches(torch_cuda, tile):
+    """A batch of three scenes with different cones under the quilt (every
+    item's bands in one set of lists and one tile launch) against the same
+    batch per point: views, panels and statistics, eager, replayed from a
+    hipGraph and with two calls in flight."""
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    ws = _batch_scenes()
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    frames = [50, 51, 52]
+    want, sp = _batch_run(lfdpr, torch, R, ids, ws, lfdpr.SPLAT_POINT, (0, 0), False, 1, frames)
+    for graph, fif in ((False, 1), (True, 1), (False, 2)):
+        got, sq = _batch_run(lfdpr, torch, R, ids, ws, lfdpr.SPLAT_QUILT, tile, graph, fif, frames)
+        _log(f"[batch quilt {tile} graph={graph} in flight {fif}] {sq}")
+        assert sq.pop("splat_order") == lfdpr.SPLAT_QUILT
+        q = tuple(sq.pop(k) for k in QUILT_KEYS)
+        assert q[0] >= 1 and q[1] >= 1 and q[2] > 0
+        if tile[0]:
+            assert q[:2] == tile
+        p = dict(sp)
+        p.pop("splat_order")
+        for k in QUILT_KEYS:
+            p.pop(k)
+        assert sq == p
+        for f, (wv, wp), (gv, gp) in zip(frames, want, got):
+            np.testing.assert_array_equal(gv, wv, err_msg=f"frame {f} views ({graph}, {fif})")
+            np.testing.assert_array_equal(gp, wp, err_msg=f"frame {f} panels ({graph}, {fif})")
+
+
+def test_quilt_in_shaded_batches(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    ws = [scenes.with_pbr(w) for w in _batch_scenes()]
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    R.set_shading(ws[0].shading)
+    want, _ = _batch_run(lfdpr, torch, R, ids, ws, lfdpr.SPLAT_POINT, (0, 0), False, 1, [7, 8])
+    got, sq = _batch_run(lfdpr, torch, R, ids, ws, lfdpr.SPLAT_QUILT, (0, 0), True, 1, [7, 8])
+    assert sq["splat_order"] == lfdpr.SPLAT_QUILT
+    for (wv, wp), (gv, gp) in zip(want, got):
+        np.testing.assert_array_equal(gv, wv)
+        np.testing.assert_array_equal(gp, wp)
+
+
+def test_batch_autotune_takes_the_quilt_into_account(torch_cuda):
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    ws = _batch_scenes()
+    R = lfdpr.Renderer(0)
+    ids = [R.upload_scene(w.scene) for w in ws]
+    R.set_lens(ws[0].lens)
+    want, _ = _batch_run(lfdpr, torch, R, ids, ws, lfdpr.SPLAT_POINT, (0, 0), False, 1, [60])
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    models = [w.model(60 + 9 * k) for k, w in enumerate(ws)]
+    v = B.alloc_views()
+    res = B.autotune(models, v)
+    _log(f"batch autotune best {res['best']}")
+    assert lfdpr.SPLAT_QUILT in {e["splat_order"] for e in res["entries"]}
+    B.use_graph(True)
+    p = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    for _ in range(2):
+        B.render(models, v, p)
+    torch.cuda.synchronize()
+    assert B.stats()["splat_order"] == res["best"]["splat_order"]
+    np.testing.assert_array_equal(v.cpu().numpy(), want[0][0])
+    np.testing.assert_array_equal(p.cpu().numpy(), want[0][1])
+    B.close()
