@@ -7,10 +7,18 @@
 //   k_emit        one lane per triangle: its cells in deterministic order;
 //   k_emit_big    triangles with many cells: one workgroup each, rows over lanes
 //   k_fetch       one lane per point: UV at the cell centre, two trilinear
-//                 mip fetches (tv_min, tv_max)                (Sec. 3.3)
+//                 mip fetches (tv_min, tv_max)                (Sec. 3.3); for
+//                 the triangle-view order and the quilt also the point's
+//                 splat rectangle (and, for the quilt, its pixel rows)
 //   k_splat       one lane per point, looping over the views: splat box,
 //                 inside-triangle test, cell ownership, Eqs. 8-9, 64-bit
 //                 atomicMin of (depth, colour)                (Sec. 3.2, 3.3, 5.1)
+//   k_qcount, k_qplan, k_qscatter   the quilt's band lists: points binned by
+//                 the pixel rows their splat reaches           (Sec. 3.2)
+//   k_splat_quilt one workgroup per tile (a band of rows x a subset of the
+//                 views): the same splat with the 64-bit keys in LDS, the
+//                 tile written out as RGBA8 (+ depth)          (Sec. 3.2, 5.1)
+//   k_splat_tv    per (triangle, view): covered pixels find their owning point
 //   k_resolve     keys -> RGBA8 (+ depth), keys re-cleared for the next frame
 //   k_interleave  one lane per four panel pixels: tilted-lens phase, view and
 //                 pixel index, optional 8-tap Gaussian reconstruction (Sec. 4)
@@ -913,13 +921,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPBR &
 // views' RGBA8 (+ depth): the key buffer in HBM is neither updated nor
 // resolved.  The views differ only by a horizontal eye offset (Sec. 3.2), so a
 // point's pixel rows are the same in every view and each point is binned once
-// per frame, into every band of q_rows rows that its splat can reach.  A
-// workgroup takes one tile; tiles are launched by decreasing band size.
+// per frame, into every band of q_rows rows that its splat can reach (in a
+// batch, the bands of its own item).  A workgroup takes one tile; tiles are
+// launched by decreasing band size.  Workgroups have 1024 threads (16 waves,
+// one tile per CU), or 512 when two tiles fit the CU's LDS.
 
 constexpr int kQChunk = 4096;  // points per workgroup pass in the band kernels
-// threads of a quilt workgroup: 1024 (16 waves, one tile per CU), or 512 when
-// two tiles fit the CU's LDS (two workgroups of 8 waves, so that one tile's
-// clearing, writing out and last chunks overlap the other's splatting)
 
 // Band (over all items) of stacked row g = item * H + row.
 __device__ __forceinline__ uint32_t quilt_band(const QuiltBinArgs& a, uint32_t g) {
@@ -1049,8 +1056,8 @@ __global__ void __launch_bounds__(256) k_qscatter(QuiltBinArgs a) {
 }
 
 // One tile per workgroup: clear the keys, splat the band's points into the
-// tile's views and rows, write the tile out.  kPBR: shaded colours.  Held to
-// 128 VGPRs: four waves per SIMD.
+// tile's views and rows, write the tile out into its item's views.  kPBR:
+// shaded colours.  Held to 128 VGPRs: four waves per SIMD.
 template <bool kPBR, int kBlock>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_splat_quilt(SplatArgs a) {
   extern __shared__ uint64_t qtile[];  // the tile's keys, then W column and H row ray slopes
