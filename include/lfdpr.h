@@ -225,6 +225,16 @@ int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
  * Results do not depend on it.  Batches created afterwards start from it. */
 int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
 
+/* The tile a frame (n_items = 1) or a batch of n_items would use for views of
+ * W x H pixels, n_views (sub-)views, with max_lds bytes of LDS per
+ * workgroup, when rows x views is asked for (0, 0: the automatic choice
+ * described above); a tile takes rows * views * W * 8 + (W + H) * 4 + 16
+ * bytes.  Host only (no device, no context).  LFDPR_EINVAL when no tile fits
+ * or an argument is out of range (W, H in [1, 4096], n_views in [1, 1024],
+ * n_items in [1, 256]). */
+int lfdpr_quilt_tile(int32_t W, int32_t H, int32_t n_views, int32_t n_items, int32_t max_lds, int32_t rows,
+                     int32_t views, int32_t* out_rows, int32_t* out_views);
+
 /* Capacity of the quilt's band lists in entries (4 B each; one entry per
  * point and band of rows its splat reaches); 0 (the default) = twice the
  * point capacity + 65536, at most 2^32 - 1.  A frame with more entries is splatted per point

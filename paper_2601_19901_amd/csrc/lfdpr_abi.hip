@@ -860,6 +860,22 @@ int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views) {
   return LFDPR_OK;
 }
 
+int lfdpr_quilt_tile(int32_t W, int32_t H, int32_t n_views, int32_t n_items, int32_t max_lds, int32_t rows,
+                     int32_t views, int32_t* out_rows, int32_t* out_views) {
+  if (!out_rows || !out_views || W < 1 || H < 1 || W > 4096 || H > 4096 || n_views < 1 || n_views > 1024 ||
+      n_items < 1 || n_items > 256 || max_lds < 0 || !((rows == 0 && views == 0) || (rows >= 1 && views >= 1)))
+    return LFDPR_EINVAL;
+  Rig rg{};
+  rg.W = W;
+  rg.H = H;
+  rg.n_views = n_views;
+  int r = 0, v = 0;
+  if (!quilt_shape_for(rg, max_lds, rows, views, n_items, r, v)) return LFDPR_EINVAL;
+  *out_rows = r;
+  *out_views = v;
+  return LFDPR_OK;
+}
+
 int lfdpr_set_quilt_capacity(lfdpr_ctx* ctx, int64_t entries) {
   if (!ctx) return LFDPR_EINVAL;
   if (entries < 0 || entries > 0xFFFFFFFFll) return fail(ctx, LFDPR_EINVAL, "quilt capacity in [0, 2^32 - 1]");

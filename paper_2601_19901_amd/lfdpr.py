@@ -121,6 +121,7 @@ def signatures():
         "lfdpr_set_splat_order": ([vp, i32], C.c_int),
         "lfdpr_set_quilt_tile": ([vp, i32, i32], C.c_int),
         "lfdpr_set_quilt_capacity": ([vp, i64], C.c_int),
+        "lfdpr_quilt_tile": ([i32, i32, i32, i32, i32, i32, i32, p(i32), p(i32)], C.c_int),
         "lfdpr_render_frame": ([vp, i32, vp, vp, vp], C.c_int),
         "lfdpr_render_frame_noalloc": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "lfdpr_reconstruct": ([vp, vp, i32, i32, i32, vp], C.c_int),
@@ -179,6 +180,16 @@ def view_params(vp, point_capacity: int = 0):
     p = ViewParams(vp.V, vp.S, vp.W, vp.H, vp.fovy_deg, vp.aspect, vp.D, vp.cone_deg, vp.znear,
                    _ptr(jit) if jit is not None else None, int(vp.mip), int(point_capacity))
     return p, jit
+
+
+def quilt_tile(W: int, H: int, n_views: int, n_items: int = 1, max_lds: int = 160 * 1024, rows: int = 0,
+               views: int = 0):
+    """The quilt tile (rows, views) the library uses for this rig, or None when
+    none fits (host only)."""
+    r, v = C.c_int32(), C.c_int32()
+    rc = lib().lfdpr_quilt_tile(int(W), int(H), int(n_views), int(n_items), int(max_lds), int(rows), int(views),
+                                C.byref(r), C.byref(v))
+    return (r.value, v.value) if rc == LFDPR_OK else None
 
 
 def tune_dict(res) -> dict:
