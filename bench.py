@@ -16,6 +16,12 @@ replay after the launch autotuner.
 --workload learned-display: display-1M rendered once plus the learned
 angular reconstruction, beside the plain and 4x angular-SS frames.
 
+Before the timed frames the library's autotuner chooses the splat order
+(--splat-order auto, the default): the point order under each launch shape
+and key layout, or the row-band quilt (keys resolved in LDS tiles) under each
+band height; the line's splat_order holds the choice and every candidate's
+time.
+
 Prints one JSON line: value = point-view splats per second of whole-step
 time (sum over points of the views their triangle is active in, divided by
 step time), ms_per_step; per-stage ms, the roofline of the dominant kernel
