@@ -329,3 +329,28 @@ def test_batch_autotune_takes_the_quilt_into_account(torch_cuda):
     np.testing.assert_array_equal(v.cpu().numpy(), want[0][0])
     np.testing.assert_array_equal(p.cpu().numpy(), want[0][1])
     B.close()
+
+
+def test_random_rigs_and_tiles(torch_cuda):
+    """Twelve seeded rigs (odd view sizes, one to twenty views, sub-views) and
+    tiles (bands that do not divide H, subsets that do not divide the views,
+    bands taller than the view): the quilt equals the point order bit for
+    bit, with depth and statistics."""
+    from paper_2601_19901_amd import lfdpr
+    rng = np.random.default_rng(2026)
+    for case in range(12):
+        W, H = int(rng.integers(17, 161)), int(rng.integers(5, 161))
+        S = int(rng.choice([1, 1, 2]))
+        V = int(rng.integers(1, 21))
+        w = scenes.small_display(seed=100 + case, S=S, V=V, W=W, H=H, hf_quads=int(rng.choice([8, 24, 48])))
+        nv = V * S
+        rows = int(rng.choice([0, 1, 2, 3, 5, 8, H + 3]))
+        views = 0 if rows == 0 else int(rng.integers(1, nv + 3))
+        if rows and lfdpr.quilt_tile(W, H, nv, rows=rows, views=views) is None:
+            rows, views = 0, 0
+        R = lfdpr.Renderer(0)
+        sid = R.upload_scene(w.scene)
+        R.set_views(w.views)
+        q = _same_as_point(R, sid, w.model(int(rng.integers(0, 1000))),
+                           f"random rig {case}: {V}x{S} views of {W}x{H}, tile {rows}x{views}", rows, views)
+        assert q[:2] == lfdpr.quilt_tile(W, H, nv, rows=rows, views=views)
