@@ -216,12 +216,15 @@ int lfdpr_set_views(lfdpr_ctx* ctx, const lfdpr_view_params* views);
  * and to batches created on it afterwards. */
 int lfdpr_set_splat_order(lfdpr_ctx* ctx, int32_t order);
 
-/* Tile of the quilt order: `rows` pixel rows of `views` views, all W columns,
- * 8 B per key in LDS (plus 4 B per view column and row for the ray slopes).
- * 0, 0 (the default) chooses per rig: 4 rows, else 2, else 1, with the most
- * views that fit the device's LDS per workgroup, spread evenly over the
- * subsets.  A shape whose keys do not fit, or a batch whose bands (items x
- * ceil(H / rows)) exceed 8192, is refused by the frame (LFDPR_EINVAL).
+/* Tile of the quilt order (the 64-bit view buffers of Sec. 5.1, a tile at a
+ * time): `rows` pixel rows of `views` views, all W columns, 8 B per key in
+ * LDS (plus 4 B per view column and row for the ray slopes).  0, 0 (the
+ * default) chooses per rig: 4 rows, else 2, else 1, with the most views that
+ * fit the device's LDS per workgroup, spread evenly over the subsets.  rows
+ * and views beyond the rig are clipped to it.  Host only; returns
+ * LFDPR_EINVAL for rows outside [1, 4096] or views outside [1, 1024] (unless
+ * both are 0).  A shape whose keys do not fit, or a batch whose bands (items
+ * x ceil(H / rows)) exceed 8192, is refused by the frame (LFDPR_EINVAL).
  * Results do not depend on it.  Batches created afterwards start from it. */
 int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
 
@@ -235,11 +238,13 @@ int lfdpr_set_quilt_tile(lfdpr_ctx* ctx, int32_t rows, int32_t views);
 int lfdpr_quilt_tile(int32_t W, int32_t H, int32_t n_views, int32_t n_items, int32_t max_lds, int32_t rows,
                      int32_t views, int32_t* out_rows, int32_t* out_views);
 
-/* Capacity of the quilt's band lists in entries (4 B each; one entry per
- * point and band of rows its splat reaches); 0 (the default) = twice the
- * point capacity + 65536, at most 2^32 - 1.  A frame with more entries is splatted per point
- * into the key buffer instead (same results; lfdpr_get_stats reports it).
- * Reallocated by the next quilt frame. */
+/* Capacity of the quilt's band lists in entries (4 B each, device memory
+ * the context owns, one set per frame in flight; one entry per point and
+ * band of rows its splat reaches, Sec. 3.2); 0 (the default) = twice the
+ * point capacity + 65536, at most 2^32 - 1; LFDPR_EINVAL outside [0, 2^32 -
+ * 1].  A frame with more entries is splatted per point into the key buffer
+ * instead (same results; lfdpr_get_stats reports it).  Reallocated by the
+ * next quilt frame (which synchronises then). */
 int lfdpr_set_quilt_capacity(lfdpr_ctx* ctx, int64_t entries);
 
 /* Sets the panel and reconstruction parameters used by lfdpr_reconstruct. */
