@@ -1668,7 +1668,8 @@ hipError_t launch_splat_quilt(const SplatArgs& a, hipStream_t s) {
     if (a.tm) k_splat_quilt<true, 1024><<<g, 1024, lds, s>>>(a);
     else k_splat_quilt<false, 1024><<<g, 1024, lds, s>>>(a);
   }
-  return hipGetLastError();
+  // the error stays set for callers that check it after the frame's launches
+  return hipPeekAtLastError();
 }
 
 void launch_interleave(const InterleaveArgs& a, hipStream_t s) {
