@@ -977,7 +977,7 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   sa.stats = ctx->d_stats;
   sa.tm = pbr ? ctx->d_tm : nullptr;
   hipEvent_t e0 = mark_on(ctx, gen);
-  launch_tri_setup(sa, gen);
+  launch_tri_setup(sa, quilt, gen);
   hipEvent_t e1 = mark_on(ctx, gen);
   launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, gen);
   hipEvent_t e2 = mark_on(ctx, gen);
@@ -1137,7 +1137,7 @@ int lfdpr_render_frame_noalloc(lfdpr_ctx* ctx, int32_t scene_id, const float* mo
   sa.dbgi = nullptr;
   sa.stats = d_st;
   sa.tm = nullptr;
-  launch_tri_setup(sa, st);
+  launch_tri_setup(sa, false, st);
   launch_scan(d_counts, s.nt, d_tiles, d_offsets, d_st + STAT_TOTAL, st);
   EmitArgs ea{};
   ea.items = d_item;
@@ -1527,7 +1527,7 @@ hipEvent_t batch_gen(lfdpr_batch* b, hipStream_t st, bool timed) {
   sa.em = b->em;
   sa.stats = b->stats;
   sa.tm = pbr ? b->tm : nullptr;
-  launch_tri_setup(sa, st);
+  launch_tri_setup(sa, b->splat_order == LFDPR_SPLAT_QUILT, st);
   hipEvent_t e1 = ev();
   launch_scan(b->counts, b->nt, b->tiles, b->offsets, b->stats + STAT_TOTAL, st);
   hipEvent_t e2 = ev();

@@ -155,7 +155,9 @@ void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 void launch_store_item(const Item& it, Item* dst, hipStream_t s);
 void launch_export_stats(const uint64_t* st, int64_t cap, int64_t* out, hipStream_t s);
 void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st);
-void launch_tri_setup(const SetupArgs& a, hipStream_t s);
+// lean: the set-up form that stores its records before the lattice count
+// (fewer registers; used beside the quilt splat)
+void launch_tri_setup(const SetupArgs& a, bool lean, hipStream_t s);
 void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
                  hipStream_t s);
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s);

@@ -106,7 +106,16 @@ __device__ __forceinline__ uint64_t wave_append(bool take, uint64_t* counter) {
 
 // kMulti: triangles of several items (a batch), each lane finds its own; else
 // every triangle belongs to items[0], whose rig then sits in scalar registers.
-template <bool kMulti>
+// kLean: the triangle's records are stored before its lattice count (only the
+// row range after it), so none of them is held in registers across the row
+// loop: 88 VGPRs (5 waves per SIMD) instead of 158 (3 waves).  A triangle
+// whose count then overflows keeps records that nothing reads.  Which form
+// makes the faster frame depends on the splat that runs beside the next
+// frame's set-up: next to the quilt's whole-CU tiles the set-up gets whole
+// CUs between tiles and the lean form is faster; next to the point splat,
+// whose workgroups retire one at a time, the lean form fits into each freed
+// slot and then slows the splat more than it gains.
+template <bool kMulti, bool kLean>
 __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t act_cnt = 0, ovf_cnt = 0, pv_cnt = 0;
@@ -293,7 +302,17 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       }
       int64_t count = 0, jfirst = 0, jlast = -1;
       Lattice L;
+      TriEmit E;
+      E.uv0u = uv0u; E.uv0v = uv0v; E.du1 = du1; E.dv1 = dv1; E.du2 = du2; E.dv2 = dv2;
+      E.s1 = sq[1]; E.t1 = tq[1]; E.s2 = sq[2]; E.t2 = tq[2];
+      E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item;
+      E.jlo = 0; E.jhi = -1;
       if (!ovf) {
+        if constexpr (kLean) {
+          a.rec[t] = R;
+          if (pbr) a.tm[t] = M;
+          a.em[t] = E;
+        }
         lattice_init(L, sq[1], tq[1], sq[2], tq[2]);
         int64_t nb = (L.iB - L.iA + 1) * (L.jB - L.jA + 1);
         if (nb > kBoxCap) {
@@ -319,14 +338,15 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
       cnt = (uint32_t)count;
       pv_cnt = (uint64_t)count * (uint64_t)nact;
       if (cnt > 0) {
-        a.rec[t] = R;
-        TriEmit E;
-        E.uv0u = uv0u; E.uv0v = uv0v; E.du1 = du1; E.dv1 = dv1; E.du2 = du2; E.dv2 = dv2;
-        E.s1 = sq[1]; E.t1 = tq[1]; E.s2 = sq[2]; E.t2 = tq[2];
-        E.kmin = kmin; E.kmax = kmax; E.tex = tex; E.item = item;
-        E.jlo = (int32_t)jfirst; E.jhi = (int32_t)jlast;
-        a.em[t] = E;
-        if (pbr) a.tm[t] = M;
+        if constexpr (kLean) {
+          *reinterpret_cast<int2*>(&a.em[t].jlo) = make_int2((int32_t)jfirst, (int32_t)jlast);
+        } else {
+          E.jlo = (int32_t)jfirst;
+          E.jhi = (int32_t)jlast;
+          a.rec[t] = R;
+          a.em[t] = E;
+          if (pbr) a.tm[t] = M;
+        }
       }
     }
     a.counts[t] = cnt;
@@ -1573,12 +1593,17 @@ void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st)
   k_build_mip<<<nblk(n, 256), 256, 0, st>>>(src, dst, s);
 }
 
-void launch_tri_setup(const SetupArgs& a, hipStream_t s) {
+void launch_tri_setup(const SetupArgs& a, bool lean, hipStream_t s) {
   if (a.nt <= 0) return;
-  if (a.n_items > 1)
-    k_tri_setup<true><<<nblk(a.nt, 256), 256, 0, s>>>(a);
+  const unsigned g = nblk(a.nt, 256);
+  if (a.n_items > 1 && lean)
+    k_tri_setup<true, true><<<g, 256, 0, s>>>(a);
+  else if (a.n_items > 1)
+    k_tri_setup<true, false><<<g, 256, 0, s>>>(a);
+  else if (lean)
+    k_tri_setup<false, true><<<g, 256, 0, s>>>(a);
   else
-    k_tri_setup<false><<<nblk(a.nt, 256), 256, 0, s>>>(a);
+    k_tri_setup<false, false><<<g, 256, 0, s>>>(a);
 }
 
 void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_stride, int64_t panel_stride,
