@@ -49,7 +49,7 @@ constexpr size_t kOffStats = kOffItem + align256(sizeof(Item));
 constexpr size_t kOffCounts = kOffStats + align256(8 * STAT_SLOTS);
 constexpr size_t kOffOffsets = kOffCounts + align256(4 * kNoAllocTris);
 constexpr size_t kOffTiles = kOffOffsets + align256(8 * kNoAllocTris);
-constexpr size_t kOffRec = kOffTiles + align256(8 * (kNoAllocTris / 1024 + 1));
+constexpr size_t kOffRec = kOffTiles + align256(8 * (kNoAllocTris / 256 + 1));
 constexpr size_t kOffEm = kOffRec + align256(sizeof(TriRec) * kNoAllocTris);
 constexpr size_t kOffBig = kOffEm + align256(sizeof(TriEmit) * kNoAllocTris);
 constexpr size_t kOffTris = kOffBig + align256(4 * kNoAllocTris);
@@ -413,7 +413,7 @@ int ensure_tri_buffers(lfdpr_ctx* ctx, int64_t nt) {
   dfree(ctx->d_tris);
   if (dalloc(ctx->d_counts, n) != hipSuccess || dalloc(ctx->d_offsets, n) != hipSuccess ||
       dalloc(ctx->d_rec, n) != hipSuccess || dalloc(ctx->d_em, n) != hipSuccess ||
-      dalloc(ctx->d_tiles, (n + 1023) / 1024 + 1) != hipSuccess || dalloc(ctx->d_big, n) != hipSuccess ||
+      dalloc(ctx->d_tiles, (n + 255) / 256 + 1) != hipSuccess || dalloc(ctx->d_big, n) != hipSuccess ||
       dalloc(ctx->d_tris, n) != hipSuccess) {
     ctx->tri_cap = 0;
     return fail(ctx, LFDPR_ENOMEM, "per-triangle buffers");
@@ -976,15 +976,19 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   sa.dbgi = ctx->dbgi;
   sa.stats = ctx->d_stats;
   sa.tm = pbr ? ctx->d_tm : nullptr;
+  sa.tile_sum = ctx->d_tiles;
+  sa.big = ctx->d_big;
+  sa.n_big = ctx->d_stats + STAT_BIG;
   hipEvent_t e0 = mark_on(ctx, gen);
   launch_tri_setup(sa, quilt, gen);
   hipEvent_t e1 = mark_on(ctx, gen);
-  launch_scan(ctx->d_counts, s.nt, ctx->d_tiles, ctx->d_offsets, ctx->d_stats + STAT_TOTAL, gen);
+  launch_scan(ctx->d_tiles, s.nt, ctx->d_stats + STAT_TOTAL, gen);
   hipEvent_t e2 = mark_on(ctx, gen);
   EmitArgs ea{};
   ea.items = ctx->d_item1;
   ea.nt = s.nt;
   ea.counts = ctx->d_counts;
+  ea.tile_base = ctx->d_tiles;
   ea.offsets = ctx->d_offsets;
   ea.em = ctx->d_em;
   ea.points = ctx->d_points;
@@ -1137,12 +1141,16 @@ int lfdpr_render_frame_noalloc(lfdpr_ctx* ctx, int32_t scene_id, const float* mo
   sa.dbgi = nullptr;
   sa.stats = d_st;
   sa.tm = nullptr;
+  sa.tile_sum = d_tiles;
+  sa.big = d_big;
+  sa.n_big = d_st + STAT_BIG;
   launch_tri_setup(sa, false, st);
-  launch_scan(d_counts, s.nt, d_tiles, d_offsets, d_st + STAT_TOTAL, st);
+  launch_scan(d_tiles, s.nt, d_st + STAT_TOTAL, st);
   EmitArgs ea{};
   ea.items = d_item;
   ea.nt = s.nt;
   ea.counts = d_counts;
+  ea.tile_base = d_tiles;
   ea.offsets = d_offsets;
   ea.em = d_em;
   ea.points = d_points;
@@ -1527,14 +1535,18 @@ hipEvent_t batch_gen(lfdpr_batch* b, hipStream_t st, bool timed) {
   sa.em = b->em;
   sa.stats = b->stats;
   sa.tm = pbr ? b->tm : nullptr;
+  sa.tile_sum = b->tiles;
+  sa.big = b->big;
+  sa.n_big = b->stats + STAT_BIG;
   launch_tri_setup(sa, b->splat_order == LFDPR_SPLAT_QUILT, st);
   hipEvent_t e1 = ev();
-  launch_scan(b->counts, b->nt, b->tiles, b->offsets, b->stats + STAT_TOTAL, st);
+  launch_scan(b->tiles, b->nt, b->stats + STAT_TOTAL, st);
   hipEvent_t e2 = ev();
   EmitArgs ea{};
   ea.items = b->d_items;
   ea.nt = b->nt;
   ea.counts = b->counts;
+  ea.tile_base = b->tiles;
   ea.offsets = b->offsets;
   ea.em = b->em;
   ea.points = b->points;
@@ -1741,7 +1753,7 @@ int lfdpr_batch_create(lfdpr_ctx* ctx, int32_t n, const int32_t* scene_ids, cons
   if (ok)
     ok = dalloc(b->keys, (size_t)(b->per_item_px * n)) == hipSuccess && dalloc(b->counts, ntb) == hipSuccess &&
          dalloc(b->offsets, ntb) == hipSuccess && dalloc(b->rec, ntb) == hipSuccess && dalloc(b->em, ntb) == hipSuccess &&
-         dalloc(b->tiles, (ntb + 1023) / 1024 + 1) == hipSuccess && dalloc(b->big, ntb) == hipSuccess &&
+         dalloc(b->tiles, (ntb + 255) / 256 + 1) == hipSuccess && dalloc(b->big, ntb) == hipSuccess &&
          dalloc(b->tris, ntb) == hipSuccess && dalloc(b->rows, (size_t)b->cap) == hipSuccess &&
          dalloc(b->pbox, (size_t)b->cap) == hipSuccess &&
          dalloc(b->stats, STAT_SLOTS) == hipSuccess && dalloc(b->points, (size_t)b->cap) == hipSuccess &&
@@ -1814,7 +1826,7 @@ int lfdpr_batch_set_frames_in_flight(lfdpr_batch* b, int32_t n) {
          hipEventCreateWithFlags(&b->ev_spl[k], hipEventDisableTiming) == hipSuccess;
   if (ok)
     ok = dalloc(a.counts, ntb) == hipSuccess && dalloc(a.offsets, ntb) == hipSuccess && dalloc(a.rec, ntb) == hipSuccess &&
-         dalloc(a.em, ntb) == hipSuccess && dalloc(a.tiles, (ntb + 1023) / 1024 + 1) == hipSuccess &&
+         dalloc(a.em, ntb) == hipSuccess && dalloc(a.tiles, (ntb + 255) / 256 + 1) == hipSuccess &&
          dalloc(a.big, ntb) == hipSuccess && dalloc(a.stats, STAT_SLOTS) == hipSuccess &&
          dalloc(a.tris, ntb) == hipSuccess && dalloc(a.rows, (size_t)b->cap) == hipSuccess &&
          dalloc(a.pbox, (size_t)b->cap) == hipSuccess &&

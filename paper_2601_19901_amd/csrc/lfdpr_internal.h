@@ -50,15 +50,19 @@ struct SetupArgs {
   int32_t* dbgi;   // optional nt*8
   uint64_t* stats;
   TriMat* tm;      // physically based mode: per-triangle material records; else null
+  uint64_t* tile_sum;  // per workgroup (256 triangles): the sum of their counts
+  uint32_t* big;       // triangles with more than kBigCells cells (capacity nt)
+  uint64_t* n_big;     // and their number
 };
 
 struct EmitArgs {
   const Item* items;
   int64_t nt;
-  uint32_t* big;             // triangles emitted cooperatively (capacity nt)
-  uint64_t* n_big;
+  const uint32_t* big;       // triangles emitted cooperatively, queued by the set-up
+  const uint64_t* n_big;
   const uint32_t* counts;
-  const uint64_t* offsets;
+  const uint64_t* tile_base;  // exclusive point offset of each tile of 256 triangles
+  uint64_t* offsets;          // written: first point of each triangle
   const TriEmit* em;
   Point* points;
   const uint64_t* n_points;  // device count (total emitted)
@@ -158,8 +162,8 @@ void launch_build_mip(const uint32_t* src, uint32_t* dst, int s, hipStream_t st)
 // lean: the set-up form that stores its records before the lattice count
 // (fewer registers; used beside the quilt splat)
 void launch_tri_setup(const SetupArgs& a, bool lean, hipStream_t s);
-void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
-                 hipStream_t s);
+// tile sums (written by the set-up) -> exclusive tile bases, and the total
+void launch_scan(uint64_t* tile_sum, int64_t nt, uint64_t* total, hipStream_t s);
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s);
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s);
 // the quilt: band lists (bins), then one workgroup per (band, view subset)

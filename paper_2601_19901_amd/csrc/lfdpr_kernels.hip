@@ -2,10 +2,12 @@
 //
 //   k_tri_setup   one lane per triangle: frame transform, visibility in every
 //                 LFD view, T_align frame, LFD-biased H/V densities, Eqs. 1-7,
-//                 lattice snap and cell count                (Sec. 3, 3.1, 3.3)
-//   k_scan_*      wave64 prefix sum of the counts -> point offsets
-//   k_emit        one lane per triangle: its cells in deterministic order;
-//   k_emit_big    triangles with many cells: one workgroup each, rows over lanes
+//                 lattice snap and cell count; each workgroup's count sum
+//                 and the list of triangles with many cells    (Sec. 3, 3.1, 3.3)
+//   k_scan_top    one workgroup: the workgroups' count sums -> point offset bases
+//   k_emit        one lane per triangle: its point offset and its cells in
+//                 deterministic order; triangles with many cells: one
+//                 workgroup each, rows over lanes (same launch)
 //   k_fetch       one lane per point: UV at the cell centre, two trilinear
 //                 mip fetches (tv_min, tv_max)                (Sec. 3.3); for
 //                 the triangle-view order and the quilt also the point's
@@ -119,8 +121,8 @@ template <bool kMulti, bool kLean>
 __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t act_cnt = 0, ovf_cnt = 0, pv_cnt = 0;
+  uint32_t cnt = 0;
   if (t < a.nt) {
-    uint32_t cnt = 0;
     if (a.dbgf) {
       for (int k = 0; k < 8; ++k) { a.dbgf[t * 8 + k] = 0.0f; a.dbgi[t * 8 + k] = 0; }
     }
@@ -351,6 +353,14 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
     }
     a.counts[t] = cnt;
   }
+  // triangles with more cells than one lane emits go to the workgroup list
+  const bool big = cnt > kBigCells;
+  const uint64_t bslot = wave_append(big, a.n_big);
+  if (big) a.big[bslot] = (uint32_t)t;
+  // this workgroup's point count (its 256 triangles form one scan tile)
+  __shared__ uint64_t tsum[4];
+  const uint64_t wcnt = wave_sum((uint64_t)cnt);
+  if ((threadIdx.x & 63) == 0) tsum[threadIdx.x >> 6] = wcnt;
   // per-wave statistics, one atomic per wave
   act_cnt = wave_sum(act_cnt);
   ovf_cnt = wave_sum(ovf_cnt);
@@ -360,26 +370,18 @@ __global__ void __launch_bounds__(256) k_tri_setup(SetupArgs a) {
     if (ovf_cnt) atomicAdd((unsigned long long*)&a.stats[STAT_OVERFLOW], (unsigned long long)ovf_cnt);
     if (pv_cnt) atomicAdd((unsigned long long*)&a.stats[STAT_POINT_VIEWS], (unsigned long long)pv_cnt);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = (tsum[0] + tsum[1]) + (tsum[2] + tsum[3]);
 }
 
 // ------------------------------------------------------------------ scan (counts -> offsets)
-// Three passes over 1024-element tiles: tile sums, one-block scan of the tile
-// sums (also writes the grand total), tile-local scans plus the tile base.
+// The point offsets are an exclusive prefix sum of the per-triangle counts over
+// tiles of 256 triangles: the set-up writes each tile's sum (one tile per
+// set-up workgroup), k_scan_top turns the tile sums into tile bases (one
+// workgroup; also the grand total), and the emission kernel, whose workgroups
+// take the same tiles, adds the prefix within its tile.
 
-constexpr int kScanTile = 1024;  // 256 lanes x 4 items
-
-__global__ void __launch_bounds__(256) k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
-                                                      uint64_t* __restrict__ tile_sum) {
-  __shared__ uint64_t ws[4];
-  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
-  uint64_t s = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) s += base + k < n ? cnt[base + k] : 0u;
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
-}
+constexpr int kScanTile = 256;  // triangles per tile: one set-up / emission workgroup
 
 __global__ void __launch_bounds__(1024) k_scan_top(uint64_t* __restrict__ tile_sum, int64_t ntiles,
                                                     uint64_t* __restrict__ total) {
@@ -404,27 +406,6 @@ __global__ void __launch_bounds__(1024) k_scan_top(uint64_t* __restrict__ tile_s
   if (threadIdx.x == 0) *total = carry;
 }
 
-__global__ void __launch_bounds__(256) k_scan_apply(const uint32_t* __restrict__ cnt, int64_t n,
-                                                     const uint64_t* __restrict__ tile_base,
-                                                     uint64_t* __restrict__ off) {
-  __shared__ uint64_t ws[4];
-  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
-  uint64_t v[4], s = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) { v[k] = base + k < n ? cnt[base + k] : 0u; s += v[k]; }
-  uint64_t inc = wave_incl_scan(s);
-  if ((threadIdx.x & 63) == 63) ws[threadIdx.x >> 6] = inc;
-  __syncthreads();
-  uint64_t wbase = 0;
-  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wbase += ws[w];
-  uint64_t run = tile_base[blockIdx.x] + wbase + inc - s;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < n) off[base + k] = run;
-    run += v[k];
-  }
-}
-
 // ------------------------------------------------------------------ a1/a2: emission
 
 __device__ __forceinline__ void write_head(Point* pts, uint64_t gi, uint32_t t, uint32_t f, int64_t i, int64_t j) {
@@ -434,23 +415,90 @@ __device__ __forceinline__ void write_head(Point* pts, uint64_t gi, uint32_t t, 
   *reinterpret_cast<uint2*>(&pts[gi]) = head;
 }
 
-// One lane per triangle; triangles with more than kBigCells cells are queued
-// for k_emit_big instead.
+// Exclusive prefix of v over the 256 lanes of the workgroup (every lane calls).
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* ws4) {
+  const uint64_t inc = wave_incl_scan(v);
+  if ((threadIdx.x & 63) == 63) ws4[threadIdx.x >> 6] = inc;
+  __syncthreads();
+  uint64_t before = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) before += ws4[w];
+  __syncthreads();  // ws4 may be rewritten after this
+  return before + inc - v;
+}
+
+// Emission, one launch: workgroups [0, kEmitBigBlocks) take the queued
+// triangles with more than kBigCells cells, one triangle per workgroup at a
+// time (lanes take rows, a block scan places them); the others take the
+// set-up's tiles of 256 triangles: each lane writes its triangle's point offset
+// (tile base + prefix within the tile) and emits the points of a small
+// triangle.
+constexpr unsigned kEmitBigBlocks = 1024;
+
+__device__ __forceinline__ void emit_big(const EmitArgs& a, uint64_t* ws4) {
+  const uint64_t nbig = *a.n_big;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (uint64_t b = blockIdx.x; b < nbig; b += kEmitBigBlocks) {
+    const uint32_t t = a.big[b];
+    const TriEmit& E = a.em[t];
+    // the triangle's first point: the tile base plus the earlier counts in the tile
+    const int64_t t0 = (int64_t)t - (int64_t)t % kScanTile;
+    const int64_t u = t0 + threadIdx.x;
+    const uint64_t cu = u < (int64_t)t ? a.counts[u] : 0u;
+    uint64_t wsum = wave_sum(cu);
+    if (lane == 0) ws4[wv] = wsum;
+    __syncthreads();
+    const uint64_t base = a.tile_base[t0 / kScanTile] + (ws4[0] + ws4[1]) + (ws4[2] + ws4[3]);
+    __syncthreads();
+    Lattice L;
+    lattice_init(L, E.s1, E.t1, E.s2, E.t2);
+    const int64_t jlo = E.jlo, jhi = E.jhi;  // rows with cells, found by the set-up
+    uint64_t run = 0;
+    for (int64_t j0 = jlo; j0 <= jhi; j0 += blockDim.x) {
+      const int64_t j = j0 + threadIdx.x;
+      int64_t lo = 1, hi = 0;
+      if (j <= jhi) lattice_row(L, j, lo, hi);
+      const uint64_t c = hi >= lo ? (uint64_t)(hi - lo + 1) : 0;
+      uint64_t inc = wave_incl_scan(c);
+      if (lane == 63) ws4[wv] = inc;
+      __syncthreads();
+      uint64_t before = 0, total = 0;
+      for (int w = 0; w < 4; ++w) {
+        if (w < wv) before += ws4[w];
+        total += ws4[w];
+      }
+      const uint64_t start = base + run + before + inc - c;
+      const uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
+      const uint64_t ri = base + (uint64_t)(j - jlo);
+      if (a.rows && j <= jhi && ri < (uint64_t)a.cap)
+        a.rows[ri] = RowEntry{(uint32_t)(start - base), (int16_t)lo, (int16_t)hi};
+      for (int64_t i = lo; i <= hi; ++i) {
+        uint64_t gi = start + (uint64_t)(i - lo);
+        if (gi < (uint64_t)a.cap)
+          write_head(a.points, gi, t, fj | (i == lo ? F_ILO : 0u) | (i == hi ? F_IHI : 0u), i, j);
+      }
+      run += total;
+      __syncthreads();  // the wave sums are rewritten by the next pass
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint64_t ws4[4];
+  if (blockIdx.x < kEmitBigBlocks) {
+    emit_big(a, ws4);
+    return;
+  }
+  const int64_t tile = (int64_t)blockIdx.x - kEmitBigBlocks;
+  const int64_t t = tile * kScanTile + threadIdx.x;
   const uint32_t cnt = t < a.nt ? a.counts[t] : 0u;
+  const uint64_t base = a.tile_base[tile] + block_excl_scan(cnt, ws4);
+  if (t < a.nt) a.offsets[t] = base;
   if (a.tris) {
     const uint64_t slot = wave_append(cnt > 0, a.n_tris);
     if (cnt > 0) a.tris[slot] = (uint32_t)t;
   }
-  if (cnt == 0) return;
-  if (cnt > kBigCells) {
-    uint64_t slot = atomicAdd((unsigned long long*)a.n_big, 1ull);
-    a.big[slot] = (uint32_t)t;
-    return;
-  }
+  if (cnt == 0 || cnt > kBigCells) return;  // the big ones are queued by the set-up
   const TriEmit& E = a.em[t];
-  uint64_t base = a.offsets[t];
   Lattice L;
   lattice_init(L, E.s1, E.t1, E.s2, E.t2);
   const int64_t jlo = E.jlo, jhi = E.jhi;  // rows with cells, found by the set-up
@@ -466,49 +514,6 @@ __global__ void __launch_bounds__(256) k_emit(EmitArgs a) {
       if (gi >= (uint64_t)a.cap) return;
       write_head(a.points, gi, (uint32_t)t, fj | (i == lo ? F_ILO : 0u) | (i == hi ? F_IHI : 0u), i, j);
     }
-  }
-}
-
-// One workgroup per queued triangle: lanes take rows, a block scan places them.
-__global__ void __launch_bounds__(256) k_emit_big(EmitArgs a) {
-  __shared__ uint64_t wsum[4];
-  const uint64_t nbig = *a.n_big;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-    const uint32_t t = a.big[b];
-    const TriEmit& E = a.em[t];
-    const uint64_t base = a.offsets[t];
-    Lattice L;
-    lattice_init(L, E.s1, E.t1, E.s2, E.t2);
-    const int64_t jlo = E.jlo, jhi = E.jhi;  // rows with cells, found by the set-up
-    uint64_t run = 0;
-    for (int64_t j0 = jlo; j0 <= jhi; j0 += blockDim.x) {
-      const int64_t j = j0 + threadIdx.x;
-      int64_t lo = 1, hi = 0;
-      if (j <= jhi) lattice_row(L, j, lo, hi);
-      const uint64_t c = hi >= lo ? (uint64_t)(hi - lo + 1) : 0;
-      uint64_t inc = wave_incl_scan(c);
-      if (lane == 63) wsum[wv] = inc;
-      __syncthreads();
-      uint64_t before = 0, total = 0;
-      for (int w = 0; w < 4; ++w) {
-        if (w < wv) before += wsum[w];
-        total += wsum[w];
-      }
-      const uint64_t start = base + run + before + inc - c;
-      const uint32_t fj = (j == jlo ? F_JLO : 0u) | (j == jhi ? F_JHI : 0u);
-      const uint64_t ri = base + (uint64_t)(j - jlo);
-      if (a.rows && j <= jhi && ri < (uint64_t)a.cap)
-        a.rows[ri] = RowEntry{(uint32_t)(start - base), (int16_t)lo, (int16_t)hi};
-      for (int64_t i = lo; i <= hi; ++i) {
-        uint64_t gi = start + (uint64_t)(i - lo);
-        if (gi < (uint64_t)a.cap)
-          write_head(a.points, gi, t, fj | (i == lo ? F_ILO : 0u) | (i == hi ? F_IHI : 0u), i, j);
-      }
-      run += total;
-      __syncthreads();
-    }
-    __syncthreads();  // the wave sums are rewritten for the next triangle
   }
 }
 
@@ -1616,19 +1621,13 @@ void launch_interleave_batch(const InterleaveArgs& a, int n_items, int64_t view_
   }
 }
 
-void launch_scan(const uint32_t* cnt, int64_t n, uint64_t* tile_scratch, uint64_t* off, uint64_t* total,
-                 hipStream_t s) {
-  int64_t ntiles = (n + kScanTile - 1) / kScanTile;
-  if (ntiles == 0) ntiles = 1;
-  k_scan_reduce<<<(unsigned)ntiles, 256, 0, s>>>(cnt, n, tile_scratch);
-  k_scan_top<<<1, 1024, 0, s>>>(tile_scratch, ntiles, total);
-  k_scan_apply<<<(unsigned)ntiles, 256, 0, s>>>(cnt, n, tile_scratch, off);
+void launch_scan(uint64_t* tile_sum, int64_t nt, uint64_t* total, hipStream_t s) {
+  k_scan_top<<<1, 1024, 0, s>>>(tile_sum, (nt + kScanTile - 1) / kScanTile, total);
 }
 
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
   if (a.nt <= 0) return;
-  k_emit<<<nblk(a.nt, 256), 256, 0, s>>>(a);
-  k_emit_big<<<1024, 256, 0, s>>>(a);
+  k_emit<<<kEmitBigBlocks + nblk(a.nt, kScanTile), 256, 0, s>>>(a);
   k_fetch<<<fetch_blocks, 256, 0, s>>>(a);
 }
 
