@@ -73,8 +73,10 @@ SETUP_OPS_PER_TRI_VIEW = 40        # visibility and the density terms per (trian
 NET_FWD_BYTES_PER_PX = 16 + 80 + 128 + 128 + 80   # blur + four convolution layers, BF16
 BYTES = {
     "setup": lambda s: s["nt"] * 78 + s["tris_with_points"] * 176,
-    "scan": lambda s: s["nt"] * (4 + 4 + 8),
-    "emit": lambda s: s["tris_with_points"] * 76 + s["points"] * (16 + 2 * 16),
+    # the tile sums of 256 triangles each (8 B) in, their bases out
+    "scan": lambda s: -(-s["nt"] // 256) * 16,
+    # counts in, offsets out; emission records in; points out, texels in
+    "emit": lambda s: s["nt"] * (4 + 8) + s["tris_with_points"] * 76 + s["points"] * (16 + 2 * 16),
     # point order: points and records in, one 8 B key per written pixel; quilt:
     # points, records and splat rectangles in, the views (4 B per pixel) out
     "splat": lambda s: (s["points"] * (16 + 112 + 48) + s["pixels"] * 4 if s.get("quilt")

@@ -563,8 +563,11 @@ __device__ __forceinline__ bool quilt_point_rows(int32_t H, const TriRec& T, int
 }
 
 // Per point: UV at the cell centre and the two mip fetches (Eqs. 6-7); for the
-// triangle-major splat and the quilt also the point's splat rectangle
-// (PointBox), for the quilt the pixel rows its splat can write.
+// triangle-major splat and the quilt (kBox) also the point's splat rectangle
+// (PointBox), for the quilt the pixel rows its splat can write; kPBR: the
+// material fetches.  The plain form holds 46 VGPRs (8 waves per SIMD, for a
+// kernel that waits on its texel gathers) instead of the 75 of all branches.
+template <bool kBox, bool kPBR>
 __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
   const uint64_t npts = imin((int64_t)*a.n_points, a.cap);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -589,7 +592,7 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
     tv.x = trilinear(it.texels, ti, u, v, E.kmin);
     tv.y = E.kmax == E.kmin ? tv.x : trilinear(it.texels, ti, u, v, E.kmax);
     *reinterpret_cast<uint2*>(&a.points[p].tvmin) = tv;
-    if (a.pbox) {
+    if constexpr (kBox) {
       const TriRec& T = a.rec[t];
       PointBox B;
       float ymn, ymx;
@@ -618,7 +621,7 @@ __global__ void __launch_bounds__(256) k_fetch(EmitArgs a) {
                                                                    : make_uint2(~0u, ~0u);
       }
     }
-    if (a.tm) {
+    if constexpr (kPBR) {
       // physically based mode: normal map (RGBA8) and the R bytes of the
       // roughness and metallic maps, each at its own LOD pair
       const TriMat& M = a.tm[t];
@@ -1628,7 +1631,14 @@ void launch_scan(uint64_t* tile_sum, int64_t nt, uint64_t* total, hipStream_t s)
 void launch_emit(const EmitArgs& a, int fetch_blocks, hipStream_t s) {
   if (a.nt <= 0) return;
   k_emit<<<kEmitBigBlocks + nblk(a.nt, kScanTile), 256, 0, s>>>(a);
-  k_fetch<<<fetch_blocks, 256, 0, s>>>(a);
+  if (a.pbox && a.tm)
+    k_fetch<true, true><<<fetch_blocks, 256, 0, s>>>(a);
+  else if (a.pbox)
+    k_fetch<true, false><<<fetch_blocks, 256, 0, s>>>(a);
+  else if (a.tm)
+    k_fetch<false, true><<<fetch_blocks, 256, 0, s>>>(a);
+  else
+    k_fetch<false, false><<<fetch_blocks, 256, 0, s>>>(a);
 }
 
 void launch_splat(const SplatArgs& a, int grid_blocks, hipStream_t s) {
