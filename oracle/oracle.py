@@ -125,15 +125,21 @@ def subview_positions(vp) -> np.ndarray:
 
 def view_table(vp) -> Dict[str, object]:
     """Parallel off-axis cameras sharing one orientation and the focal plane
-    Z = D; eye r sits at (b_r, 0, 0) with b = D tan(cone/2) (2q/V - 1)."""
-    B = vp.D * math.tan(math.radians(vp.cone_deg) / 2.0)
+    Z = D; eye r sits at (b_r, 0, 0) with b = D tan(cone/2) (2q/V - 1) (Sec. 3.1,
+    reading R2).  The rig is given by binary32 parameters, as the library's
+    interface takes them: the double evaluation starts from D, cone, field of
+    view and aspect rounded to binary32, degrees taken to radians as
+    deg * (pi / 180)."""
+    D, cone = float(np.float32(vp.D)), float(np.float32(vp.cone_deg))
+    fovy, aspect = float(np.float32(vp.fovy_deg)), float(np.float32(vp.aspect))
+    B = D * math.tan(cone * (math.pi / 180.0) / 2.0)
     q = subview_positions(vp)
     b = B * (2.0 * q / vp.V - 1.0)
-    t = math.tan(math.radians(vp.fovy_deg) / 2.0)
+    t = math.tan(fovy * (math.pi / 180.0) / 2.0)
     return dict(
-        fx=np.float32((vp.W / 2.0) / (vp.aspect * t)), fy=np.float32((vp.H / 2.0) / t),
-        cx=np.float32(vp.W / 2.0), cy=np.float32(vp.H / 2.0), rD=np.float32(1.0 / vp.D),
-        znear=np.float32(vp.znear), eye=b.astype(np.float32), kshift=(b / vp.D).astype(np.float32),
+        fx=np.float32((vp.W / 2.0) / (aspect * t)), fy=np.float32((vp.H / 2.0) / t),
+        cx=np.float32(vp.W / 2.0), cy=np.float32(vp.H / 2.0), rD=np.float32(1.0 / D),
+        znear=np.float32(vp.znear), eye=b.astype(np.float32), kshift=(b / D).astype(np.float32),
         q=q)
 
 

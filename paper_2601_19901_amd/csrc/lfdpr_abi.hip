@@ -453,8 +453,9 @@ void build_rig(const lfdpr_view_params& v, Rig& rg, std::vector<float>& eye, std
                std::vector<double>& q) {
   const int64_t nviews = (int64_t)v.V * v.S;
   const double D = v.D;
-  const double B = D * std::tan((double)v.cone_deg * M_PI / 180.0 / 2.0);
-  const double tf = std::tan((double)v.fovy_deg * M_PI / 180.0 / 2.0);
+  // degrees to radians as deg * (pi / 180), then halved
+  const double B = D * std::tan((double)v.cone_deg * (M_PI / 180.0) / 2.0);
+  const double tf = std::tan((double)v.fovy_deg * (M_PI / 180.0) / 2.0);
   eye.assign(nviews, 0.0f);
   ks.assign(nviews, 0.0f);
   q.assign(nviews, 0.0);

@@ -1,9 +1,11 @@
 """Batched rendering (one launch per stage for several scenes, hipGraph replay)
 and the autotuner: every result bit-identical to single-scene renders, which
-the other GPU tests tie to the oracle."""
+the other GPU tests tie to the oracle, and, for some items, to the oracle
+directly."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_2601_19901_amd import scenes
 
 pytestmark = pytest.mark.gpu
@@ -55,6 +57,32 @@ def test_batch_matches_single_renders(setup, graph):
             tot_pts += st["points"]
         assert bst["points"] == tot_pts
         print(f"frame {frame}: {bst['points']} points over {len(ws)} scenes, graph={graph}", flush=True)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_items_match_oracle(setup, graph):
+    """Every item of a batch frame (scenes of different sizes, cones and eye
+    distances) against the oracle's render of that scene: views, panel (the
+    context's lens) and the point and point-view totals."""
+    torch, lfdpr, R, ws, ids = setup
+    B = lfdpr.Batch(R, ids, [w.views for w in ws])
+    B.use_graph(graph)
+    views = B.alloc_views()
+    panels = torch.empty((len(ws), ws[0].lens.Hp, ws[0].lens.Wp, 3), dtype=torch.uint8, device="cuda")
+    models = [w.model(211 + 29 * k) for k, w in enumerate(ws)]
+    for _ in range(2 if graph else 1):   # graph: capture, then a replay
+        B.render(models, views, panels)
+    torch.cuda.synchronize()
+    bv, bp, bst = views.cpu().numpy(), panels.cpu().numpy(), B.stats()
+    pts = pv = 0
+    for k, w in enumerate(ws):
+        o = O.render(w.scene, w.views, models[k])
+        np.testing.assert_array_equal(bv[k].view(np.uint32), o["rgba"], err_msg=f"item {k} views")
+        np.testing.assert_array_equal(bp[k], O.interleave(o["rgba"], ws[0].lens), err_msg=f"item {k} panel")
+        pts += o["n_points"]
+        pv += o["stats"]["point_views"]
+    assert bst["points"] == pts and bst["point_views"] == pv
+    B.close()
 
 
 def test_graph_replays_with_interleaved_eager_work(setup):
@@ -208,6 +236,13 @@ def test_batch16_full_size_matches_single_renders():
         tot += R.stats()["point_views"]
     assert bst["point_views"] == tot
     print(f"batch16: {bst['points']} points, {tot} point-views, all scenes identical", flush=True)
+    # the two smallest scenes (about 55k triangles, 48 views of 512^2 each)
+    # straight against the oracle
+    for k in sorted(range(len(ws)), key=lambda k: ws[k].scene.n_tris)[:2]:
+        o = O.render(ws[k].scene, ws[k].views, models[k])
+        np.testing.assert_array_equal(bv[k].view(np.uint32), o["rgba"], err_msg=f"scene {k} views vs oracle")
+        np.testing.assert_array_equal(bp[k], O.interleave(o["rgba"], ws[0].lens), err_msg=f"scene {k} panel vs oracle")
+        print(f"batch16 scene {k} ({ws[k].scene.n_tris} triangles): equal to the oracle", flush=True)
     # two batch calls in flight: another frame, then this one, equal to the replay
     B.set_frames_in_flight(2)
     other = B.alloc_views()
