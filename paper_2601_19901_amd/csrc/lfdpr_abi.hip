@@ -156,6 +156,11 @@ struct lfdpr_ctx {
   hipEvent_t ev_emitted[2] = {nullptr, nullptr}, ev_splatted[2] = {nullptr, nullptr};
   hipEvent_t ev_caller = nullptr;  // the caller's stream, for debug records written on `side`
   bool splatted_pending[2] = {false, false};
+  // the library stream at the start of the last frame: after the caller's
+  // work on the frame before it (its presentation), which the next frame's
+  // point generation waits for
+  hipEvent_t ev_start = nullptr;
+  bool start_pending = false;
   struct FrameBufs {
     int64_t points_alloc = 0, tri_cap = 0, tm_cap = 0, pmat_cap = 0, last_nt = 0;
     Point* d_points = nullptr;
@@ -617,6 +622,7 @@ int lfdpr_destroy(lfdpr_ctx* ctx) {
     if (ctx->ev_splatted[k]) (void)hipEventDestroy(ctx->ev_splatted[k]);
   }
   if (ctx->ev_caller) (void)hipEventDestroy(ctx->ev_caller);
+  if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
   dfree(ctx->d_eye);
   dfree(ctx->d_kshift);
@@ -938,6 +944,14 @@ int lfdpr_render_frame(lfdpr_ctx* ctx, int32_t scene_id, const float* model, uin
   hipStream_t gen = piped ? ctx->side : st;
   const int sl = ctx->slot;
   if (piped && ctx->splatted_pending[sl]) HIPOK(hipStreamWaitEvent(gen, ctx->ev_splatted[sl], 0));
+  if (piped) {
+    // and for the caller's work queued before the previous frame began (the
+    // frame before it presented: filter, panel), so that this generation does
+    // not take the CUs that work needs while the previous frame waits on it
+    if (ctx->start_pending) HIPOK(hipStreamWaitEvent(gen, ctx->ev_start, 0));
+    HIPOK(hipEventRecord(ctx->ev_start, st));
+    ctx->start_pending = true;
+  }
   if (piped && ctx->dbgf) {
     // the set-up writes the caller's debug record buffers: after the caller's earlier work
     HIPOK(hipEventRecord(ctx->ev_caller, st));
@@ -2153,9 +2167,9 @@ int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n) {
   if (n == 2 && !ctx->side) {
     // created together or not at all: the context keeps them only on success
     hipStream_t side = nullptr;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool ok = hipStreamCreateWithFlags(&side, hipStreamNonBlocking) == hipSuccess;
-    for (int k = 0; k < 5 && ok; ++k) ok = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 6 && ok; ++k) ok = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
       for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -2168,9 +2182,11 @@ int lfdpr_set_frames_in_flight(lfdpr_ctx* ctx, int32_t n) {
     ctx->ev_splatted[0] = ev[2];
     ctx->ev_splatted[1] = ev[3];
     ctx->ev_caller = ev[4];
+    ctx->ev_start = ev[5];
   }
   ctx->frames_in_flight = n;
   ctx->splatted_pending[0] = ctx->splatted_pending[1] = false;
+  ctx->start_pending = false;
   return LFDPR_OK;
 }
 
