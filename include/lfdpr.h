@@ -327,10 +327,13 @@ int lfdpr_set_debug_records(lfdpr_ctx* ctx, float* dst_f, int32_t* dst_i, int64_
  * resolve of each frame stay on the context's stream, ordered after that
  * frame's point generation, so the views are complete when the context's
  * stream reaches them (as with 1).  Point generation reads only the scene,
- * the model matrix (passed by value) and the rig, and does not wait for work
- * the caller enqueued on the context's stream (except while debug records
- * are enabled: the set-up writes those caller buffers, so it then waits); it
- * waits for the splat that last read its buffers.  Statistics, copies and debug records refer to the
+ * the model matrix (passed by value) and the rig.  It waits for the splat
+ * that last read its buffers and for the work the caller enqueued on the
+ * context's stream before the previous render_frame call (typically the
+ * presentation of the frame before: filter, panel), so that it does not
+ * compete with that work for the GPU; not for work enqueued after it (except
+ * while debug records are enabled: the set-up writes those caller buffers,
+ * so it then waits for all of it).  Statistics, copies and debug records refer to the
  * last frame as before.  A render_frame enqueued while a stream is being
  * captured into a hipGraph needs 1.  The second set of buffers is allocated
  * on first use (per-triangle records, point buffer, statistics).
