@@ -536,6 +536,29 @@ def test_rig_pin_catches_a_planted_cone_error(monkeypatch):
         _check_rig(V=8, D=4.0, cone=40.0)
 
 
+def test_rig_takes_binary32_parameters():
+    """Reading R2: the rig is given by binary32 parameters (as the C ABI holds
+    them): a cone, distance, field of view or aspect that is not a binary32
+    value gives the tables of its binary32 rounding, and the next binary32
+    value gives different eye offsets; the double evaluation uses
+    deg * (pi / 180) for the radians."""
+    base = rig(V=48, W=512, H=512, aspect=1.6, D=10.0, cone=48.89048503827306, fovy=30.0)
+    r32 = rig(V=48, W=512, H=512, aspect=float(np.float32(1.6)), D=10.0,
+              cone=float(np.float32(48.89048503827306)), fovy=30.0)
+    t, t32 = O.view_table(base), O.view_table(r32)
+    for k in ("eye", "kshift", "fx", "fy", "rD"):
+        assert np.array_equal(np.asarray(t[k]).view(np.uint32), np.asarray(t32[k]).view(np.uint32)), k
+    # the binary32 value above it: one ulp of the cone moves some eyes
+    up = rig(V=48, W=512, H=512, aspect=1.6, D=10.0,
+             cone=float(np.nextafter(np.float32(48.89048503827306), np.float32(90))), fovy=30.0)
+    assert not np.array_equal(O.view_table(up)["eye"], t["eye"])
+    # the eye offsets from that definition, written out in double
+    c = float(np.float32(48.89048503827306))
+    B = 10.0 * math.tan(c * (math.pi / 180.0) / 2.0)
+    q = np.arange(48) + 0.5
+    assert np.array_equal(t["eye"], (B * (2.0 * q / 48 - 1.0)).astype(np.float32))
+
+
 def test_multiview_mip_setup_closed_form():
     """Eqs. 4-7 for a fronto-parallel triangle at depth Z: every view's pixel
     footprint on it is Z^2/(fx fy), so size_min = size_max = Z^2/(fx fy) A_ts/A_ws."""
