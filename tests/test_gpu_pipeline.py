@@ -146,3 +146,39 @@ def test_pipelined_display_frames_equal_serial_renders(torch_cuda):
         np.testing.assert_array_equal(res[1][k][0], res[2][k][0], err_msg=f"views, frame {f}")
         np.testing.assert_array_equal(res[1][k][1], res[2][k][1], err_msg=f"panel, frame {f}")
     assert res["stats1"] == res["stats2"]
+
+
+@pytest.mark.parametrize("order", ["point", "quilt"])
+def test_pipelined_supersampled_frames_with_presentation_match_the_oracle(torch_cuda, order):
+    """The benchmark's supersampled loop at a small size: each frame renders
+    4x sub-views with two frames in flight, then the angular filter and the
+    panel pass are queued on the context's stream before the next frame (so
+    the next frame's point generation waits for them); one sub-view buffer
+    serves every frame.  Every filtered frame and panel equals the oracle."""
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    w = scenes.small_display(seed=21, S=4, V=8)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    R.set_lens(w.lens)
+    R.set_splat_order(lfdpr.SPLAT_QUILT if order == "quilt" else lfdpr.SPLAT_POINT)
+    R.set_frames_in_flight(2)
+    sub = _views(torch, w)
+    frames = [2, 3, 4, 90, 91]
+    outs = []
+    for f in frames:
+        R.render_frame(sid, w.model(f), sub)
+        filt = torch.empty((w.views.V, w.views.H, w.views.W), dtype=torch.int32, device="cuda")
+        panel = torch.empty((w.lens.Hp, w.lens.Wp, 3), dtype=torch.uint8, device="cuda")
+        R.angular_filter(sub, filt)
+        R.reconstruct(filt, panel)
+        outs.append((filt, panel))
+    torch.cuda.synchronize()
+    assert R.stats()["splat_order"] == (lfdpr.SPLAT_QUILT if order == "quilt" else lfdpr.SPLAT_POINT)
+    for f, (filt, panel) in zip(frames, outs):
+        o = O.render(w.scene, w.views, w.model(f))
+        of = O.angular_filter(o["rgba"], w.views)
+        np.testing.assert_array_equal(filt.cpu().numpy().view(np.uint32), of, err_msg=f"{order} frame {f} filtered")
+        np.testing.assert_array_equal(panel.cpu().numpy(), O.interleave(of, w.lens), err_msg=f"{order} frame {f} panel")
+    R.close()
