@@ -354,3 +354,47 @@ def test_random_rigs_and_tiles(torch_cuda):
         q = _same_as_point(R, sid, w.model(int(rng.integers(0, 1000))),
                            f"random rig {case}: {V}x{S} views of {W}x{H}, tile {rows}x{views}", rows, views)
         assert q[:2] == lfdpr.quilt_tile(W, H, nv, rows=rows, views=views)
+
+
+@pytest.mark.parametrize("pbr", [False, True])
+def test_lean_setup_records_equal_the_late_form(torch_cuda, pbr):
+    """The quilt order runs the set-up form that stores a triangle's records
+    before its lattice count; the point order the form that stores them at
+    the end.  Same frame: set-up debug records, counts, points (with the
+    material words when shaded) and views identical."""
+    from paper_2601_19901_amd import lfdpr
+    torch = torch_cuda
+    w = scenes.small_display(seed=33, V=12, W=96, H=96)
+    if pbr:
+        w = scenes.with_pbr(w)
+    R = lfdpr.Renderer(0)
+    sid = R.upload_scene(w.scene)
+    R.set_views(w.views)
+    if pbr:
+        R.set_shading(w.shading)
+    nt = w.scene.n_tris
+    out = {}
+    for order in (lfdpr.SPLAT_POINT, lfdpr.SPLAT_QUILT):
+        df = torch.zeros((nt, 8), dtype=torch.float32, device="cuda")
+        di = torch.zeros((nt, 8), dtype=torch.int32, device="cuda")
+        R.set_debug_records(df, di)
+        R.set_splat_order(order)
+        v, d = R.alloc_views(with_depth=True)
+        R.render_frame(sid, w.model(44), v, d)
+        st = R.stats()
+        assert st["splat_order"] == order
+        out[order] = dict(f=df.cpu().numpy(), i=di.cpu().numpy(), counts=R.counts(nt), points=R.points(),
+                          mats=R.point_materials() if pbr else None, v=v.cpu().numpy(), pts=st["points"])
+        R.set_debug_records(None, None)
+    a, b = out[lfdpr.SPLAT_POINT], out[lfdpr.SPLAT_QUILT]
+    np.testing.assert_array_equal(a["f"].view(np.uint32), b["f"].view(np.uint32))
+    np.testing.assert_array_equal(a["i"], b["i"])
+    np.testing.assert_array_equal(a["counts"], b["counts"])
+    assert a["pts"] == b["pts"] > 0
+    for k in a["points"]:
+        np.testing.assert_array_equal(a["points"][k], b["points"][k], err_msg=f"points.{k}")
+    if pbr:
+        for k in a["mats"]:
+            np.testing.assert_array_equal(a["mats"][k], b["mats"][k], err_msg=f"materials.{k}")
+    np.testing.assert_array_equal(a["v"], b["v"])
+    R.close()
